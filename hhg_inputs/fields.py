@@ -1,0 +1,79 @@
+"""Coefficient fields, manufactured solutions and seeded random vectors.
+
+Every function takes node coordinates xyz (n, 3) and returns values there.
+Random streams use NumPy's PCG64 (`numpy.random.default_rng(seed)`), drawn in
+the order documented per function.
+"""
+import numpy as np
+
+
+def smooth_k(xyz):
+    """k = 1 + 0.5 sin(2 pi x) sin(2 pi y) sin(2 pi z), in [0.5, 1.5]."""
+    x, y, z = xyz[:, 0], xyz[:, 1], xyz[:, 2]
+    return 1.0 + 0.5 * np.sin(2 * np.pi * x) * np.sin(2 * np.pi * y) * np.sin(2 * np.pi * z)
+
+
+def affine_k(xyz, c=(2.0, 3.0, 5.0), c0=1.0):
+    """k = 2x + 3y + 5z + 1 (the affine coefficient of the reproduction example)."""
+    return c0 + xyz @ np.asarray(c, dtype=np.float64)
+
+
+def sigmoid_k(xyz, eta, m=50.0):
+    """k = eta / (1 + exp(-m (y - x - 0.2))) + 1, the steep coefficient the paper
+    uses for its pre-asymptotic counter example, evaluated in 3D."""
+    x, y = xyz[:, 0], xyz[:, 1]
+    return eta / (1.0 + np.exp(-m * (y - x - 0.2))) + 1.0
+
+
+def lognormal_params(seed, sigma=None, corr_len=None, modes=32):
+    """Random Fourier modes of a Gaussian field with covariance
+    sigma^2 exp(-|r|^2 / (2 corr_len^2)).  Draw order from default_rng(seed):
+    [sigma ~ U(0.5, 2), corr_len ~ U(0.05, 0.3) when not given], omega
+    (modes x 3, N(0, corr_len^-2)), phi (modes, U(0, 2 pi))."""
+    rng = np.random.default_rng(seed)
+    if sigma is None:
+        sigma = rng.uniform(0.5, 2.0)
+    if corr_len is None:
+        corr_len = rng.uniform(0.05, 0.3)
+    omega = rng.normal(0.0, 1.0 / corr_len, size=(modes, 3))
+    phi = rng.uniform(0.0, 2 * np.pi, size=modes)
+    return dict(sigma=float(sigma), corr_len=float(corr_len), omega=omega, phi=phi, rng=rng)
+
+
+def lognormal_k(xyz, params, chunk=1 << 20):
+    """k = exp(g), g = sigma sqrt(2/M) sum_m cos(omega_m . x + phi_m)."""
+    om, ph, s = params["omega"], params["phi"], params["sigma"]
+    M = om.shape[0]
+    out = np.empty(xyz.shape[0])
+    for a in range(0, xyz.shape[0], chunk):
+        g = np.cos(xyz[a:a + chunk] @ om.T + ph).sum(axis=1)
+        out[a:a + chunk] = np.exp(s * np.sqrt(2.0 / M) * g)
+    return out
+
+
+def uniform_vector(n, seed=None, rng=None, lo=-1.0, hi=1.0):
+    """n values uniform in [lo, hi) from default_rng(seed) (or a given stream)."""
+    if rng is None:
+        rng = np.random.default_rng(seed)
+    return rng.uniform(lo, hi, size=n)
+
+
+def manufactured_u(xyz):
+    """u* = sin(pi x) sin(pi y) sin(pi z) (vanishes on the unit cube's boundary)."""
+    x, y, z = xyz[:, 0], xyz[:, 1], xyz[:, 2]
+    return np.sin(np.pi * x) * np.sin(np.pi * y) * np.sin(np.pi * z)
+
+
+def manufactured_f(xyz):
+    """f = -div(k grad u*) for k = smooth_k and u* = manufactured_u."""
+    x, y, z = xyz[:, 0], xyz[:, 1], xyz[:, 2]
+    p = np.pi
+    sx, sy, sz = np.sin(p * x), np.sin(p * y), np.sin(p * z)
+    cx, cy, cz = np.cos(p * x), np.cos(p * y), np.cos(p * z)
+    s2x, s2y, s2z = np.sin(2 * p * x), np.sin(2 * p * y), np.sin(2 * p * z)
+    c2x, c2y, c2z = np.cos(2 * p * x), np.cos(2 * p * y), np.cos(2 * p * z)
+    k = 1.0 + 0.5 * s2x * s2y * s2z
+    gk = 0.5 * 2 * p * np.stack([c2x * s2y * s2z, s2x * c2y * s2z, s2x * s2y * c2z], axis=1)
+    gu = p * np.stack([cx * sy * sz, sx * cy * sz, sx * sy * cz], axis=1)
+    lap_u = -3 * p * p * sx * sy * sz
+    return -(np.sum(gk * gu, axis=1) + k * lap_u)

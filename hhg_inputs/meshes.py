@@ -1,0 +1,69 @@
+"""Macro meshes of the workloads.
+
+Each function returns (X, T): X float64 (nv, 3) vertex coordinates and T int32
+(nt, 4) vertex ids per tetrahedron.  The vertex order inside a tetrahedron is
+significant: uniform refinement cuts each octahedron along the line through
+the midpoints of edges (x0,x2) and (x1,x3), so the order fixes the refined mesh.
+"""
+import itertools
+import numpy as np
+
+
+def unit_tet():
+    """The unit reference tetrahedron (0,0,0),(1,0,0),(0,1,0),(0,0,1)."""
+    X = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], dtype=np.float64)
+    return X, np.array([[0, 1, 2, 3]], dtype=np.int32)
+
+
+def regular_tet():
+    """The regular tetrahedron of the paper's Fig. 5 (B)."""
+    s = 1.0 / np.sqrt(2.0)
+    X = np.array([[1, 0, -s], [-1, 0, -s], [0, 1, s], [0, -1, s]], dtype=np.float64)
+    return X, np.array([[0, 1, 2, 3]], dtype=np.int32)
+
+
+def flat_tet():
+    """A flat macro tetrahedron with obtuse dihedral angles (its refined Laplacian
+    has several positive off-diagonal stencil entries)."""
+    X = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0.35, 0.35, 0.15]], dtype=np.float64)
+    return X, np.array([[0, 1, 2, 3]], dtype=np.int32)
+
+
+def _kuhn_tets(vid):
+    """Six Kuhn tetrahedra of a cube whose corner (a,b,c) in {0,1}^3 has id
+    vid(a,b,c); each is ordered along its monotone path 0 -> e_p -> e_p+e_q -> 1."""
+    tets = []
+    for perm in itertools.permutations(range(3)):
+        p = [0, 0, 0]
+        path = [vid(*p)]
+        for ax in perm:
+            p[ax] = 1
+            path.append(vid(*p))
+        tets.append(path)
+    return tets
+
+
+def kuhn_cube():
+    """Unit cube split into 6 Kuhn tetrahedra sharing the main diagonal."""
+    X = np.array([[a, b, c] for c in (0, 1) for b in (0, 1) for a in (0, 1)], dtype=np.float64)
+    T = _kuhn_tets(lambda a, b, c: a + 2 * b + 4 * c)
+    return X, np.array(T, dtype=np.int32)
+
+
+def kuhn_cube_2x2x2():
+    """Unit cube split into 2x2x2 sub-cubes, each into 6 Kuhn tetrahedra (48)."""
+    X = np.array([[a / 2, b / 2, c / 2] for c in range(3) for b in range(3) for a in range(3)],
+                 dtype=np.float64)
+    T = []
+    for oz, oy, ox in itertools.product(range(2), repeat=3):
+        T += _kuhn_tets(lambda a, b, c: (ox + a) + 3 * (oy + b) + 9 * (oz + c))
+    return X, np.array(T, dtype=np.int32)
+
+
+MESHES = {
+    "unit_tet": unit_tet,
+    "regular_tet": regular_tet,
+    "flat_tet": flat_tet,
+    "kuhn_cube": kuhn_cube,
+    "kuhn_cube_2x2x2": kuhn_cube_2x2x2,
+}

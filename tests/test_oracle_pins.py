@@ -1,0 +1,307 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: printed
+values (Fig. 5), the paper's lemmas (exactness for constant k, equality of the
+scaled and nodal forms for affine k, O(h^2) consistency, positivity, optimal
+convergence rates), literal evaluation of the defining formulas, closed forms
+(Chebyshev polynomials, exact quadrature, linear reproduction).
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from hhg_inputs import (unit_tet, regular_tet, flat_tet, kuhn_cube, kuhn_cube_2x2x2, smooth_k,
+                        affine_k, sigmoid_k, manufactured_u, manufactured_f,
+                        lognormal_params, lognormal_k)
+from oracle import oracle as O
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _lattice_offset(mesh, T, c, j):
+    """tet-local lattice offset of node j relative to node c in macro tet T."""
+    X = mesh.X[mesh.T[T]]
+    E = np.stack([X[1] - X[0], X[2] - X[0], X[3] - X[0]], axis=1)
+    n = 2 ** mesh.level
+    return tuple(np.rint(np.linalg.solve(E, mesh.xyz[j] - mesh.xyz[c]) * n).astype(int))
+
+
+def _two_sig(x):
+    return float(f"{x:.1e}")
+
+
+def test_fig5_reference_stencils_match_printed_values():
+    """Fig. 5: level-2 interior stencils of the unit and the regular tetrahedron."""
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "fig5_stencils.txt"))
+            if l.strip() and not l.startswith("#")]
+    for panel, fn in (("A", unit_tet), ("B", regular_tet)):
+        X, T = fn()
+        m = O.Mesh(X, T, 2)
+        A = O.assemble(m, np.ones(m.n_nodes)).toarray()
+        c = m.unknowns[0]               # the single interior node at level 2
+        got = {}
+        for j in np.flatnonzero(A[c]):
+            got[_lattice_offset(m, 0, c, j)] = A[c, j]
+        want = {(int(r[1]), int(r[2]), int(r[3])): float(r[4]) for r in rows if r[0] == panel}
+        assert set(got) == set(want), panel
+        for d, v in want.items():
+            assert _two_sig(got[d]) == pytest.approx(v, rel=1e-12), (panel, d, got[d], v)
+
+
+@pytest.mark.parametrize("mesh_fn,level", [(unit_tet, 3), (kuhn_cube, 2), (kuhn_cube_2x2x2, 2)])
+def test_constant_k_is_exact(mesh_fn, level):
+    """k constant: scaled = nodal = k * Laplacian (Sec. 2.1: a_h = a for constant k)."""
+    X, T = mesh_fn()
+    m = O.Mesh(X, T, level)
+    lap = O.assemble(m, np.ones(m.n_nodes), "nodal").toarray()
+    k = np.full(m.n_nodes, 2.75)
+    As = O.assemble(m, k, "scaled").toarray()
+    An = O.assemble(m, k, "nodal").toarray()
+    s = np.abs(lap).max()
+    assert np.abs(As - 2.75 * lap).max() <= 1e-14 * s
+    assert np.abs(An - 2.75 * lap).max() <= 1e-14 * s
+
+
+@pytest.mark.parametrize("mesh_fn,level", [(unit_tet, 3), (regular_tet, 3), (kuhn_cube_2x2x2, 2)])
+def test_zero_row_sum_and_symmetry(mesh_fn, level):
+    """Row sums vanish and the matrices are symmetric (Sec. 2.2, eq. (zerosum), Lemma 3.2)."""
+    X, T = mesh_fn()
+    m = O.Mesh(X, T, level)
+    k = smooth_k(m.xyz) + m.xyz[:, 0]
+    for kind in ("scaled", "nodal"):
+        A = O.assemble(m, k, kind)
+        s = abs(A).max()
+        assert np.abs(A @ np.ones(m.n_nodes)).max() <= 1e-14 * s * 15
+        assert abs(A - A.T).max() <= 1e-15 * s * 4
+
+
+@pytest.mark.parametrize("mesh_fn,level", [(unit_tet, 2), (kuhn_cube, 1), (regular_tet, 2)])
+def test_brute_force_definitions(mesh_fn, level):
+    """eq. (discrete) and eq. (standardfe) evaluated literally over node pairs /
+    quadrature points equal the element-loop assembly (Lemma 3.2)."""
+    X, T = mesh_fn()
+    m = O.Mesh(X, T, level)
+    k = 1.0 + m.xyz[:, 0] ** 2 + np.sin(3 * m.xyz[:, 1]) ** 2 + 0.3 * m.xyz[:, 2]
+    As = O.assemble(m, k, "scaled").toarray()
+    Bs = O.brute_force_scaled(m, k)
+    assert np.abs(As - Bs).max() <= 1e-14 * np.abs(As).max()
+    An = O.assemble(m, k, "nodal").toarray()
+    Bn = O.brute_force_nodal(m, k)
+    assert np.abs(An - Bn).max() <= 1e-14 * np.abs(An).max()
+
+
+def _tet_interior_mask(m):
+    """Nodes strictly inside a macro tet: the last block of the canonical order."""
+    n = 2 ** m.level
+    per = (n - 1) * (n - 2) * (n - 3) // 6
+    mask = np.zeros(m.n_nodes, dtype=bool)
+    mask[m.n_nodes - per * m.T.shape[0]:] = True
+    return mask
+
+
+@pytest.mark.parametrize("mesh_fn,level", [(unit_tet, 3), (unit_tet, 4), (regular_tet, 3), (kuhn_cube, 3)])
+def test_affine_k_scaled_equals_nodal_on_volume_rows(mesh_fn, level):
+    """k affine: the point-reflection argument of Lemma 3.3 (and Lemma 5.1) makes
+    the scaled and nodal rows of macro-interior nodes identical."""
+    X, T = mesh_fn()
+    m = O.Mesh(X, T, level)
+    k = affine_k(m.xyz)
+    As = O.assemble(m, k, "scaled")
+    An = O.assemble(m, k, "nodal")
+    v = _tet_interior_mask(m)
+    D = (As - An).tocsr()[v]
+    assert abs(D).max() <= 1e-14 * abs(An).max()
+
+
+def test_consistency_gap_is_second_order():
+    """A3 / Lemma 3.3: for smooth k the scaled-vs-nodal entry gap on macro-interior
+    rows shrinks like h^2 relative to the entries."""
+    X, T = unit_tet()
+    gaps = []
+    for L in (4, 5, 6):
+        m = O.Mesh(X, T, L)
+        k = smooth_k(m.xyz)
+        As = O.assemble(m, k, "scaled")
+        An = O.assemble(m, k, "nodal")
+        v = _tet_interior_mask(m)
+        gaps.append(abs((As - An).tocsr()[v]).max() / abs(An.tocsr()[v]).max())
+    r1, r2 = gaps[0] / gaps[1], gaps[1] / gaps[2]
+    assert 3.0 < r1 < 5.0 and 3.5 < r2 < 4.5, gaps
+
+
+def test_m_matrix_mesh_gives_positive_operator():
+    """Lemma 4.1: Kuhn macro tets give an M-matrix Laplacian, so the scaled form
+    stays positive (definite on the unknowns) even for a steep coefficient."""
+    X, T = kuhn_cube()
+    m = O.Mesh(X, T, 2)
+    k = sigmoid_k(m.xyz, eta=1000.0)
+    op = O.make_operator(m, k, "scaled")
+    assert np.linalg.eigvalsh(op.A.toarray()).min() > 0
+    mods, info = O.modification_factors(m, k)
+    assert info["n_candidates"] == 0 and not mods
+
+
+def test_modification_properties():
+    """Sec. 4.1 read for 3D: no trigger for constant k; k_emin < k_mod < k_e on
+    triggered edges; the modification restores positivity where the plain
+    scaled matrix of an M-matrix-free mesh is indefinite."""
+    X, T = unit_tet()
+    m = O.Mesh(X, T, 3)
+    mods, info = O.modification_factors(m, np.full(m.n_nodes, 3.0))
+    assert info["n_candidates"] > 0 and not mods
+    # lambda_min^T / a_plus is a property of the macro tet, independent of the level
+    ratios = []
+    for L in (2, 3):
+        mm = O.Mesh(X, T, L)
+        _, inf = O.modification_factors(mm, np.ones(mm.n_nodes))
+        ratios.append(inf["lam_T"][0] / inf["a_plus"].max())
+    assert ratios[0] == pytest.approx(ratios[1], rel=1e-12)
+    found_indefinite = False
+    X, T = flat_tet()
+    for L in (2, 3):
+        mm = O.Mesh(X, T, L)
+        if len(mm.unknowns) == 0:
+            continue
+        for eta in (100.0, 1000.0):
+            k = sigmoid_k(mm.xyz, eta)
+            mods, inf = O.modification_factors(mm, k)
+            if inf["n_triggered"]:
+                assert np.all(inf["k_emin"] < inf["k_mod"]) and np.all(inf["k_mod"] < inf["k_e"])
+            plain = O.make_operator(mm, k, "scaled").A.toarray()
+            fixed = O.make_operator(mm, k, "scaled", modification=True).A.toarray()
+            if np.linalg.eigvalsh(plain).min() < 0:
+                found_indefinite = True
+            assert np.linalg.eigvalsh(fixed).min() > 0, (L, eta)
+    assert found_indefinite, "the steep coefficient should break positivity somewhere"
+
+
+def test_prolongation_reproduces_affine_functions():
+    for fn, L in ((unit_tet, 2), (kuhn_cube_2x2x2, 1)):
+        X, T = fn()
+        mc, mf = O.Mesh(X, T, L), O.Mesh(X, T, L + 1)
+        P = O.prolongation(mc, mf)
+        g = lambda x: 0.3 + 2 * x[:, 0] - x[:, 1] + 4 * x[:, 2]
+        assert np.abs(P @ g(mc.xyz) - g(mf.xyz)).max() < 1e-13
+        c2f = O.coarse_to_fine(mc, mf)
+        assert np.abs(mf.xyz[c2f] - mc.xyz).max() < 1e-15
+
+
+def test_quadrature_and_mass_are_exact():
+    """Stroud conical rule integrates monomials of degree <= 5 exactly on the unit
+    tet (int x^a y^b z^c = a! b! c! / (a+b+c+3)!); the mass matrix sums to |Omega|."""
+    bary, w = O._conical_rule(4)
+    pts = bary[:, 1:]
+    for a, b, c in [(0, 0, 0), (1, 2, 2), (5, 0, 0), (2, 1, 2), (0, 3, 2)]:
+        exact = math.factorial(a) * math.factorial(b) * math.factorial(c) / math.factorial(a + b + c + 3)
+        assert np.sum(w * pts[:, 0] ** a * pts[:, 1] ** b * pts[:, 2] ** c) == pytest.approx(exact, rel=1e-13)
+    X, T = kuhn_cube()
+    m = O.Mesh(X, T, 2)
+    M = O.assemble_mass(m)
+    assert M.sum() == pytest.approx(1.0, rel=1e-14)
+
+
+def test_rows_one_by_one_match_full_assembly():
+    for fn, L in ((unit_tet, 3), (kuhn_cube_2x2x2, 2)):
+        X, T = fn()
+        m = O.Mesh(X, T, L)
+        k = smooth_k(m.xyz) + 0.5
+        for kind in ("scaled", "nodal"):
+            A = O.assemble(m, k, kind).tocsr()
+            nodes = np.random.default_rng(0).choice(m.n_nodes, 25, replace=False)
+            for p, (c, v) in zip(nodes, O.rows(m, k, nodes, kind)):
+                ref = A[p].toarray().ravel()
+                got = np.zeros(m.n_nodes)
+                got[c] = v
+                assert np.abs(ref - got).max() <= 1e-14 * np.abs(ref).max()
+
+
+def test_chebyshev_matches_closed_form():
+    """On D^{-1}A with known spectrum the error is multiplied by
+    T_s((theta - lam)/delta) / T_s(theta/delta) per eigen-component."""
+    class Diag:
+        pass
+    lam = np.linspace(0.05, 2.0, 40)
+    import scipy.sparse as sp
+    from types import SimpleNamespace
+    mesh = SimpleNamespace(n_nodes=40, unknowns=np.arange(40), dirichlet=np.zeros(40, bool))
+    op = SimpleNamespace(mesh=mesh, A=sp.diags(lam).tocsr(), diag=np.ones(40))
+    op.apply = lambda x: op.A @ x
+    op.residual = lambda f, x: f - op.A @ x
+    e0 = np.ones(40)
+    lmax = 2.0
+    for s in (1, 2, 3, 4):
+        u = O.chebyshev(op, np.zeros(40), e0, s, lmax)
+        a, b = 0.1 * lmax, 1.0 * lmax
+        th, de = (a + b) / 2, (b - a) / 2
+        Ts = lambda x: np.cosh(s * np.arccosh(x)) if np.all(np.abs(x) >= 1) else np.cos(s * np.arccos(np.clip(x, -1, 1)))
+        Tx = np.array([np.polynomial.chebyshev.chebval((th - l) / de, [0] * s + [1]) for l in lam])
+        ref = Tx / np.polynomial.chebyshev.chebval(th / de, [0] * s + [1])
+        assert np.abs(u - ref).max() < 1e-12
+
+
+def test_jacobi_fixed_point_and_multigrid_solution():
+    X, T = kuhn_cube()
+    mg = O.Multigrid(X, T, 4, 2, kfun=smooth_k)
+    m = mg.meshes[4]
+    op = mg.ops[4]
+    f = np.zeros(m.n_nodes)
+    f[m.unknowns] = np.random.default_rng(3).uniform(-1, 1, len(m.unknowns))
+    ref = np.zeros(m.n_nodes)
+    ref[m.unknowns] = spla.spsolve(op.A.tocsc(), f[m.unknowns])
+    u, hist = mg.solve(f, tol=1e-10)
+    assert all(h2 < h1 for h1, h2 in zip(hist, hist[1:]))
+    assert np.abs(u - ref).max() <= 1e-8 * np.abs(ref).max()
+    rho = (hist[-1] / hist[1]) ** (1.0 / (len(hist) - 2))
+    assert rho < 0.35
+    # Gershgorin bound of D^-1 A for the 7-point-type Kuhn stencil is exactly 2
+    assert O.gershgorin_lambda(op) == pytest.approx(2.0, rel=1e-12) or O.gershgorin_lambda(op) <= 2.0 + 1e-12
+    # Jacobi keeps the exact solution fixed
+    uj = O.jacobi(op, f, ref, 3)
+    assert np.abs(uj - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.slow
+def test_convergence_rates_manufactured_solution():
+    """Lemma 3.1: O(h^2) in L2 and O(h) in H1 for the scaled form (and the
+    nodal form), 6-tet Kuhn cube, u = sin sin sin, k = smooth_k, b = M I_h f."""
+    X, T = kuhn_cube()
+    res = {"scaled": [], "nodal": []}
+    grad = lambda x: np.pi * np.stack([
+        np.cos(np.pi * x[:, 0]) * np.sin(np.pi * x[:, 1]) * np.sin(np.pi * x[:, 2]),
+        np.sin(np.pi * x[:, 0]) * np.cos(np.pi * x[:, 1]) * np.sin(np.pi * x[:, 2]),
+        np.sin(np.pi * x[:, 0]) * np.sin(np.pi * x[:, 1]) * np.cos(np.pi * x[:, 2])], axis=1)
+    for L in (2, 3, 4, 5):
+        m = O.Mesh(X, T, L)
+        b = O.assemble_mass(m) @ manufactured_f(m.xyz)
+        k = smooth_k(m.xyz)
+        for kind in res:
+            op = O.make_operator(m, k, kind)
+            uh = np.zeros(m.n_nodes)
+            uh[m.unknowns] = spla.spsolve(op.A.tocsc(), b[m.unknowns])
+            res[kind].append(O.errors(m, uh, manufactured_u, grad))
+    for kind, errs in res.items():
+        eoc_l2 = [np.log2(a["L2"] / b["L2"]) for a, b in zip(errs, errs[1:])]
+        eoc_h1 = [np.log2(a["H1"] / b["H1"]) for a, b in zip(errs, errs[1:])]
+        eoc_nd = [np.log2(a["nodal_L2"] / b["nodal_L2"]) for a, b in zip(errs, errs[1:])]
+        assert abs(eoc_l2[-1] - 2.0) < 0.15, (kind, eoc_l2)
+        assert abs(eoc_nd[-1] - 2.0) < 0.15, (kind, eoc_nd)
+        assert abs(eoc_h1[-1] - 1.0) < 0.1, (kind, eoc_h1)
+    ratio = res["scaled"][-1]["nodal_L2"] / res["nodal"][-1]["nodal_L2"]
+    assert 0.3 < ratio < 3.0
+
+
+def test_canonical_order_convention():
+    """Canonical numbering: macro vertices first, then edge, face and tet-interior nodes."""
+    X, T = unit_tet()
+    m = O.Mesh(X, T, 2)
+    assert np.allclose(m.xyz[:4], X)
+    # edge (0,1): nodes at 1/4, 2/4, 3/4 along x
+    assert np.allclose(m.xyz[4:7], [[0.25, 0, 0], [0.5, 0, 0], [0.75, 0, 0]])
+    # the only interior node of the level-2 tet is last
+    assert np.allclose(m.xyz[-1], [0.25, 0.25, 0.25]) and m.unknowns.tolist() == [m.n_nodes - 1]
+    X, T = kuhn_cube_2x2x2()
+    m = O.Mesh(X, T, 1)
+    assert len(m.unknowns) == 27 and m.n_nodes == 125
