@@ -1,0 +1,206 @@
+/*
+ * hhg.h -- C ABI of the stencil-scaling operator library for MI355X (gfx950).
+ *
+ * The library applies the variable-coefficient P1 Darcy operator -div(k grad u)
+ * with homogeneous Dirichlet data on hierarchical hybrid grids: a tetrahedral
+ * macro mesh refined uniformly (Bey's rule, Sec. 2.1 of Bauer et al.,
+ * "A stencil scaling approach for accelerating matrix-free finite element
+ * implementations", arXiv 1709.06793).  Two discrete operators are offered:
+ *   - the scaled-stencil operator a_h of eq. (discrete): off-diagonal stencil
+ *     entry (k_i + k_j)/2 times the constant-coefficient reference entry, the
+ *     diagonal as minus the row sum (Sec. 2.1, Sec. 6.1), optionally with the
+ *     pre-asymptotic modification of Sec. 4.1 (read for 3D, see flags);
+ *   - the classical nodal-integration operator of eq. (standardfe), assembled
+ *     on the fly from six element matrices per macro tet (Sec. 6.2).
+ * Around them: residual with norm, Jacobi / Chebyshev smoothing, geometric
+ * multigrid V-cycles, FP32 V-cycles inside FP64 iterative refinement, and a
+ * learned smoothing correction.
+ *
+ * Conventions for every call
+ *   - Return value: hhg_status, 0 on success, < 0 on error (nothing is
+ *     launched then), > 0 a warning.  hhg_last_error() gives the message.
+ *     No C++ exception crosses this ABI.
+ *   - Vectors: device pointers (hipMalloc / PyTorch CUDA memory) in the
+ *     context's SLOT layout, owned by the caller.  One slot array per level:
+ *     for each macro tet t (input order) a closed tetrahedral lattice of
+ *     (n+1)(n+2)(n+3)/6 slots, n = 2^level, padded to a multiple of 64 slots,
+ *     slot of lattice point (i,j,k) (i,j,k >= 0, i+j+k <= n) inside tet t:
+ *       S(n) - S(n-k) + j (n-k+1) - j (j-1)/2 + i,  S(m) = (m+1)(m+2)(m+3)/6,
+ *     where (i,j,k) are the barycentric weights of t's vertices 1,2,3 times n.
+ *     A node on a macro face/edge/vertex appears in every tet holding it; input
+ *     vectors must hold the same value in all copies ("consistent"), and all
+ *     outputs are consistent.  Dirichlet slots (nodes on the domain boundary)
+ *     must hold 0 in inputs and are written 0 in outputs; padding slots are
+ *     never read.  hhg_to_canonical / hhg_from_canonical convert to and from
+ *     the canonical unique-node order (from_canonical writes the 0s).
+ *   - dtype selects double or float buffers (HHG_F64 / HHG_F32).
+ *   - Streams: `stream` is a hipStream_t (NULL = the context's stream).  Calls
+ *     are asynchronous and stream-ordered unless they return a host scalar
+ *     (then they synchronise that stream).
+ *   - The context owns all internal device memory; it allocates at creation
+ *     and in hhg_set_coefficient only.  Calls on one context must not overlap
+ *     (they share work vectors).
+ *
+ * Canonical node order (unique nodes, including Dirichlet nodes):
+ *   1. macro vertices used by some tet, by increasing vertex id;
+ *   2. macro edges {a<b} in lexicographic order, nodes by the weight s of b,
+ *      s = 1..n-1;
+ *   3. macro faces {a<b<c} in lexicographic order, nodes with weights
+ *      (n-s-t, s, t) on (a,b,c), s,t >= 1, s+t <= n-1, t outer, s inner;
+ *   4. macro tets in input order, interior nodes (i,j,k >= 1, i+j+k <= n-1),
+ *      k outer, then j, then i.
+ */
+#ifndef HHG_H
+#define HHG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t hhg_status;
+#define HHG_OK          0
+#define HHG_EINVAL     (-1)   /* bad argument: level, dtype, null pointer, size */
+#define HHG_EMESH      (-2)   /* degenerate tet, non-manifold or non-conforming macro mesh */
+#define HHG_ECOEF      (-3)   /* coefficient not positive / not finite */
+#define HHG_EHIP       (-4)   /* a HIP runtime call failed (message kept) */
+#define HHG_ESTATE     (-5)   /* call needs state that is not there (no coefficient, no weights) */
+#define HHG_ENOMEM     (-6)   /* device allocation failed */
+#define HHG_WFALLBACK   1     /* warning: the learned smoother fell back to the plain one */
+
+typedef struct hhg_ctx_s *hhg_ctx;
+
+typedef enum { HHG_F64 = 0, HHG_F32 = 1 } hhg_dtype;
+typedef enum { HHG_JACOBI = 0, HHG_CHEBYSHEV = 1, HHG_LEARNED = 2 } hhg_smoother;
+typedef enum { HHG_SOLVE_F64 = 0, HHG_SOLVE_MIXED = 1, HHG_SOLVE_LEARNED = 2 } hhg_solve_mode;
+
+/* flags of hhg_create_macro */
+#define HHG_FLAG_NO_MODIFICATION 1u  /* disable the Sec. 4.1 modification (on by default) */
+
+/* Build the context for a macro mesh (Sec. 2.1: macro triangulation T_H refined
+ * uniformly up to max_level, 0 <= max_level <= 10).
+ *   vert_xyz  host, n_vert x 3 doubles (row-major).
+ *   tet_vert  host, n_tet x 4 vertex ids.  The ORDER inside a tet matters: the
+ *             refinement cuts each octahedron along the line through the
+ *             midpoints of edges (v0,v2) and (v1,v3) (the "gray" edge of Fig. 5).
+ *   flags     HHG_FLAG_* bits.
+ *   hip_stream the context's default stream (NULL = null stream).
+ *   out       receives the context; NULL on failure.
+ * Errors: HHG_EINVAL (null pointers, n_tet <= 0, ids out of range, level),
+ * HHG_EMESH (zero-volume tet, a face shared by more than two tets),
+ * HHG_ENOMEM / HHG_EHIP.  Host setup computes, per macro tet and level, the
+ * 15 primitive reference stencils (Sec. 2.2, Remark 2.1), the six element
+ * matrices of the nodal kernel (Sec. 6.2) and the inter-tet node tables. */
+hhg_status hhg_create_macro(const double *vert_xyz, int32_t n_vert,
+                            const int32_t *tet_vert, int32_t n_tet,
+                            int32_t max_level, uint32_t flags,
+                            void *hip_stream, hhg_ctx *out);
+hhg_status hhg_destroy(hhg_ctx ctx);
+/* Message of the last error on this context (or of the last failed create when
+ * ctx is NULL).  Owned by the library; valid until the next call. */
+const char *hhg_last_error(hhg_ctx ctx);
+
+/* Sizes at a level: n_slots = length of a slot vector (elements),
+ * n_unknowns = non-Dirichlet unique nodes, n_nodes = all unique nodes
+ * (length of a canonical vector).  Any pointer may be NULL. */
+hhg_status hhg_vector_size(hhg_ctx ctx, int32_t level, int64_t *n_slots,
+                           int64_t *n_unknowns, int64_t *n_nodes);
+/* Coordinates of all unique nodes in canonical order into host memory
+ * (n_nodes x 3 doubles), and (if not NULL) a Dirichlet flag per node. */
+hhg_status hhg_node_coords(hhg_ctx ctx, int32_t level, double *xyz, uint8_t *dirichlet);
+
+/* Convert between slot layout and canonical order at a level (device to
+ * device, dtype elements).  from_canonical fills every copy of a node and
+ * writes 0 to Dirichlet slots; to_canonical reads one copy per node. */
+hhg_status hhg_to_canonical(hhg_ctx ctx, int32_t level, hhg_dtype dtype,
+                            const void *v_slots, void *v_canon, void *stream);
+hhg_status hhg_from_canonical(hhg_ctx ctx, int32_t level, hhg_dtype dtype,
+                              const void *v_canon, void *v_slots, void *stream);
+
+/* Nodal coefficient k > 0 at the finest level (max_level), canonical order,
+ * double; on_device = 1 for a device pointer, 0 for host memory.  Coarser
+ * levels sample k at their own nodes (the nested nodes, Sec. 2.2: k is stored
+ * per node).  Computes per level: FP32 copies, the Jacobi diagonal, the
+ * Chebyshev bound, the modification corrections and the coarse-grid inverse.
+ * Synchronises the stream.  Errors: HHG_ECOEF (k <= 0 or not finite). */
+hhg_status hhg_set_coefficient(hhg_ctx ctx, const double *k_canonical, int on_device,
+                               void *stream);
+
+/* Coarsest multigrid level (default: the largest level with at most 1000
+ * unknowns).  Recomputes the coarse inverse if a coefficient is set. */
+hhg_status hhg_set_coarse_level(hhg_ctx ctx, int32_t level);
+/* Per-level solver data: Chebyshev bound of D^{-1}A (Gershgorin), number of
+ * modification corrections (edges whose factor was replaced), coarse level. */
+hhg_status hhg_level_info(hhg_ctx ctx, int32_t level, double *lambda_max,
+                          int64_t *n_modified_edges, int32_t *coarse_level);
+
+/* y = A u with the scaled-stencil operator (eq. (discrete), Sec. 6.1:
+ * s_ij = (k_i + k_j)/2 shat_ij, s_ii = -sum_j s_ij; plus the modification of
+ * Sec. 4.1 where triggered).  u, y: device slot vectors of dtype; u != y. */
+hhg_status hhg_apply_scaled(hhg_ctx ctx, int32_t level, hhg_dtype dtype,
+                            const void *u, void *y, void *stream);
+/* y = A~ u with the nodal-integration operator (eq. (standardfe), Sec. 6.2). */
+hhg_status hhg_apply_nodal(hhg_ctx ctx, int32_t level, hhg_dtype dtype,
+                           const void *u, void *y, void *stream);
+/* r = f - A u (scaled operator).  If norm2_out is not NULL it receives the
+ * Euclidean norm of r over the unknowns (each unique node once, accumulated
+ * in double) and the stream is synchronised.  r may alias neither f nor u. */
+hhg_status hhg_residual(hhg_ctx ctx, int32_t level, hhg_dtype dtype, const void *f,
+                        const void *u, void *r, double *norm2_out, void *stream);
+/* In-place smoothing of A u = f: `sweeps` steps of weighted Jacobi
+ * u <- u + omega D^{-1}(f - A u) (HHG_JACOBI), or a Chebyshev polynomial of
+ * degree `sweeps` in D^{-1}A on [0.1, 1] x lambda_max (HHG_CHEBYSHEV; omega
+ * ignored), or that Chebyshev step plus the learned correction
+ * (HHG_LEARNED).  f, u: device slot vectors. */
+hhg_status hhg_smooth(hhg_ctx ctx, int32_t level, hhg_dtype dtype, hhg_smoother smoother,
+                      int32_t sweeps, double omega, const void *f, void *u, void *stream);
+/* One V(pre,post) cycle from `level` down to the coarse level: smoothing,
+ * residual, restriction (transpose of P1 interpolation), exact coarse solve
+ * (FP64), interpolation, smoothing; rediscretised coarse operators.  u is
+ * updated in place.  rel_res_out (nullable): |f - A u| / |f| afterwards. */
+hhg_status hhg_vcycle(hhg_ctx ctx, int32_t level, hhg_dtype dtype, int32_t pre, int32_t post,
+                      hhg_smoother smoother, const void *f, void *u, double *rel_res_out,
+                      void *stream);
+
+typedef struct {
+    int32_t iterations;        /* outer iterations (V-cycles) performed */
+    int32_t fallback;          /* learned smoother fell back (1) or not (0) */
+    double rel_residual;       /* final |f - A u| / |f| in FP64 */
+    double rho;                /* asymptotic rate (r_last / r_5)^(1/(last-5)), or the mean rate */
+    double seconds;            /* wall time of the solve loop */
+} hhg_solve_stats;
+
+/* Solve A u = f at `level` to |f - A u| / |f| <= tol (FP64 residual):
+ *   HHG_SOLVE_F64     FP64 V(pre,post) Chebyshev cycles;
+ *   HHG_SOLVE_MIXED   FP64 residual, one FP32 V-cycle on the correction,
+ *                     FP64 update (iterative refinement);
+ *   HHG_SOLVE_LEARNED as MIXED with the learned smoother on the finest level,
+ *                     falling back to Chebyshev when the contraction worsens.
+ * f, u: FP64 device slot vectors; u holds the start value and the result.
+ * Returns HHG_WFALLBACK (> 0) if the learned smoother fell back. */
+hhg_status hhg_solve(hhg_ctx ctx, int32_t level, hhg_solve_mode mode, int32_t pre, int32_t post,
+                     double tol, int32_t max_iter, const double *f, double *u,
+                     hhg_solve_stats *stats, void *stream);
+
+/* Learned smoothing correction (not in the paper).  Per node i a network maps
+ * the 15-point neighbourhood features [r_{i+d}/s_i] and [log k_{i+d} - log k_i]
+ * (15 + 15, padded to 32) through 32 -> 16 -> 16 -> 1 (ReLU), BF16 weights,
+ * FP32 accumulation, to c_i; the correction is delta_i = s_i c_i / D_i with
+ * s_i = max |r| over the neighbourhood + 1e-30.  Weight vector layout (FP32):
+ * W1[16][32], b1[16], W2[16][16], b2[16], w3[16], b3  (801 values). */
+#define HHG_LEARNED_NPARAM 801
+hhg_status hhg_learned_set_weights(hhg_ctx ctx, const float *w_host, int64_t n);
+/* c_out[slot] = network output c_i (FP32, consistent slot vector; 0 on
+ * Dirichlet slots).  r: FP32 slot vector. */
+hhg_status hhg_learned_forward(hhg_ctx ctx, int32_t level, const float *r, float *c_out,
+                               void *stream);
+/* Gradient of sum_i g_i c_i with respect to the 801 parameters (FP32 host
+ * array), g = dL/dc given as an FP32 slot vector; synchronises the stream. */
+hhg_status hhg_learned_backward(hhg_ctx ctx, int32_t level, const float *r, const float *g,
+                                float *dw_host, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HHG_H */

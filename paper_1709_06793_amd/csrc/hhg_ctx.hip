@@ -1,0 +1,1452 @@
+// hhg_ctx.hip -- host side of the library: macro-mesh topology, per-level
+// tables (reference stencils, element matrices, inter-tet node lists, the
+// Sec. 4.1 modification), coefficient set-up, and the C ABI of include/hhg.h
+// including the multigrid drivers.  All numerical work on vectors runs in the
+// kernels of hhg_kernels.hip (and hhg_learned.hip); the host only sets up
+// tables and sequences launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/hhg.h"
+#include "hhg_internal.h"
+#include "hhg_lattice.h"
+#include "hhg_learned.h"
+
+using namespace hhg;
+
+namespace {
+
+// ---------------------------------------------------------------- small linear algebra
+struct Mat3 {
+    double a[3][3];
+};
+
+double det3(const Mat3 &m)
+{
+    return m.a[0][0] * (m.a[1][1] * m.a[2][2] - m.a[1][2] * m.a[2][1]) -
+           m.a[0][1] * (m.a[1][0] * m.a[2][2] - m.a[1][2] * m.a[2][0]) +
+           m.a[0][2] * (m.a[1][0] * m.a[2][1] - m.a[1][1] * m.a[2][0]);
+}
+
+// 4x4 element matrix int_t grad phi_a . grad phi_b of the tet with vertices p[4]
+bool element_matrix(const double p[4][3], double E[4][4])
+{
+    Mat3 J;  // columns p1-p0, p2-p0, p3-p0
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) J.a[r][c] = p[c + 1][r] - p[0][r];
+    const double det = det3(J);
+    if (!(std::fabs(det) > 0.0)) return false;
+    // rows of J^{-1} = gradients of barycentric coordinates 1..3 (cofactors)
+    double G[4][3];
+    const auto &a = J.a;
+    double inv[3][3] = {
+        {a[1][1] * a[2][2] - a[1][2] * a[2][1], a[0][2] * a[2][1] - a[0][1] * a[2][2],
+         a[0][1] * a[1][2] - a[0][2] * a[1][1]},
+        {a[1][2] * a[2][0] - a[1][0] * a[2][2], a[0][0] * a[2][2] - a[0][2] * a[2][0],
+         a[0][2] * a[1][0] - a[0][0] * a[1][2]},
+        {a[1][0] * a[2][1] - a[1][1] * a[2][0], a[0][1] * a[2][0] - a[0][0] * a[2][1],
+         a[0][0] * a[1][1] - a[0][1] * a[1][0]}};
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) G[r + 1][c] = inv[r][c] / det;
+    for (int c = 0; c < 3; ++c) G[0][c] = -(G[1][c] + G[2][c] + G[3][c]);
+    const double vol = std::fabs(det) / 6.0;
+    for (int x = 0; x < 4; ++x)
+        for (int y = 0; y < 4; ++y)
+            E[x][y] = vol * (G[x][0] * G[y][0] + G[x][1] * G[y][1] + G[x][2] * G[y][2]);
+    return true;
+}
+
+// eigenvalues of a symmetric 3x3 matrix (cyclic Jacobi rotations)
+void sym3_eigs(double A[3][3], double ev[3])
+{
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        double off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
+        if (off < 1e-300) break;
+        for (int p = 0; p < 2; ++p)
+            for (int q = p + 1; q < 3; ++q) {
+                if (A[p][q] == 0.0) continue;
+                const double theta = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
+                const double t = (theta >= 0 ? 1.0 : -1.0) /
+                                 (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+                const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+                for (int k = 0; k < 3; ++k) {  // A <- A G (columns p,q)
+                    const double akp = A[k][p], akq = A[k][q];
+                    A[k][p] = c * akp - s * akq;
+                    A[k][q] = s * akp + c * akq;
+                }
+                for (int k = 0; k < 3; ++k) {  // A <- G^T A (rows p,q)
+                    const double apk = A[p][k], aqk = A[q][k];
+                    A[p][k] = c * apk - s * aqk;
+                    A[q][k] = s * apk + c * aqk;
+                }
+            }
+    }
+    for (int i = 0; i < 3; ++i) ev[i] = A[i][i];
+}
+
+// smallest non-zero eigenvalue of E x = lambda (4I - 11^T) x: on the complement
+// of the constants (orthonormal basis B) the right-hand form is 4I
+double lambda_min_element(const double E[4][4])
+{
+    const double r2 = std::sqrt(2.0), r6 = std::sqrt(6.0), r12 = std::sqrt(12.0);
+    const double B[4][3] = {{1 / r2, 1 / r6, 1 / r12},
+                            {-1 / r2, 1 / r6, 1 / r12},
+                            {0, -2 / r6, 1 / r12},
+                            {0, 0, -3 / r12}};
+    double R[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double s = 0;
+            for (int a = 0; a < 4; ++a)
+                for (int b = 0; b < 4; ++b) s += B[a][i] * E[a][b] * B[b][j];
+            R[i][j] = s;
+        }
+    double ev[3];
+    sym3_eigs(R, ev);
+    return std::min(ev[0], std::min(ev[1], ev[2])) / 4.0;
+}
+
+// dense inverse with partial pivoting (Gauss-Jordan), in place; false if singular
+bool invert_dense(std::vector<double> &A, int n)
+{
+    std::vector<double> I((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) I[(size_t)i * n + i] = 1.0;
+    for (int c = 0; c < n; ++c) {
+        int p = c;
+        for (int r = c + 1; r < n; ++r)
+            if (std::fabs(A[(size_t)r * n + c]) > std::fabs(A[(size_t)p * n + c])) p = r;
+        if (!(std::fabs(A[(size_t)p * n + c]) > 0.0)) return false;
+        if (p != c)
+            for (int k = 0; k < n; ++k) {
+                std::swap(A[(size_t)p * n + k], A[(size_t)c * n + k]);
+                std::swap(I[(size_t)p * n + k], I[(size_t)c * n + k]);
+            }
+        const double piv = A[(size_t)c * n + c];
+        for (int k = 0; k < n; ++k) {
+            A[(size_t)c * n + k] /= piv;
+            I[(size_t)c * n + k] /= piv;
+        }
+        for (int r = 0; r < n; ++r) {
+            if (r == c) continue;
+            const double f = A[(size_t)r * n + c];
+            if (f == 0.0) continue;
+            for (int k = 0; k < n; ++k) {
+                A[(size_t)r * n + k] -= f * A[(size_t)c * n + k];
+                I[(size_t)r * n + k] -= f * I[(size_t)c * n + k];
+            }
+        }
+    }
+    A.swap(I);
+    return true;
+}
+
+int popcount4(int z) { return (z & 1) + ((z >> 1) & 1) + ((z >> 2) & 1) + ((z >> 3) & 1); }
+
+// ---------------------------------------------------------------- topology
+struct Topology {
+    int nv = 0, nt = 0;
+    std::vector<double> X;
+    std::vector<int> tet;
+    std::vector<int> vpos;                      // vertex id -> canonical index, -1 unused
+    int nvu = 0;
+    std::vector<std::array<int, 2>> edges;      // sorted
+    std::vector<std::array<int, 3>> faces;      // sorted
+    std::vector<int> v_val, e_val, f_val;       // number of tets holding the primitive
+    std::vector<uint8_t> v_bnd, e_bnd, f_bnd;
+
+    int find_edge(int a, int b) const
+    {
+        std::array<int, 2> key = {std::min(a, b), std::max(a, b)};
+        auto it = std::lower_bound(edges.begin(), edges.end(), key);
+        return (it != edges.end() && *it == key) ? (int)(it - edges.begin()) : -1;
+    }
+    int find_face(int a, int b, int c) const
+    {
+        std::array<int, 3> key = {a, b, c};
+        std::sort(key.begin(), key.end());
+        auto it = std::lower_bound(faces.begin(), faces.end(), key);
+        return (it != faces.end() && *it == key) ? (int)(it - faces.begin()) : -1;
+    }
+    // global primitive of tet t's local primitive with zero pattern zp:
+    // returns dimension (0 vertex .. 3 tet) and its index
+    void primitive(int t, int zp, int &dim, int &idx, std::vector<int> *verts = nullptr) const
+    {
+        int v[4], c = 0;
+        for (int a = 0; a < 4; ++a)
+            if (!((zp >> a) & 1)) v[c++] = tet[4 * t + a];
+        dim = c - 1;
+        if (verts) verts->assign(v, v + c);
+        if (c == 4) idx = t;
+        else if (c == 3) idx = find_face(v[0], v[1], v[2]);
+        else if (c == 2) idx = find_edge(v[0], v[1]);
+        else idx = v[0];
+    }
+    int valence(int t, int zp) const
+    {
+        int dim, idx;
+        primitive(t, zp, dim, idx);
+        return dim == 3 ? 1 : dim == 2 ? f_val[idx] : dim == 1 ? e_val[idx] : v_val[idx];
+    }
+    bool dirichlet(int t, int zp) const
+    {
+        int dim, idx;
+        primitive(t, zp, dim, idx);
+        return dim == 3 ? false : dim == 2 ? f_bnd[idx] : dim == 1 ? e_bnd[idx] : v_bnd[idx];
+    }
+};
+
+// ---------------------------------------------------------------- per-level data
+template <typename T>
+struct DBuf {
+    T *p = nullptr;
+    int64_t n = 0;
+};
+
+struct Level {
+    int l = 0, n = 0, S = 0, bpt = 0;
+    int64_t Spad = 0, n_slots = 0, n_nodes = 0, n_unknowns = 0;
+    // per-tet tables
+    std::vector<double> h_sten, h_emat, h_rstw;
+    std::vector<uint16_t> h_dmask, h_smask;
+    double *sten64 = nullptr, *emat64 = nullptr, *rstw64 = nullptr;
+    float *sten32 = nullptr, *emat32 = nullptr, *rstw32 = nullptr;
+    uint16_t *dmask = nullptr, *smask = nullptr;
+    // shared nodes
+    int n_shared = 0;
+    std::vector<int32_t> h_sh_off;
+    std::vector<uint64_t> h_sh_copy;
+    int32_t *sh_off = nullptr;
+    uint64_t *sh_copy = nullptr;
+    // coefficient dependent
+    double *k64 = nullptr, *invd64 = nullptr;
+    float *k32 = nullptr, *invd32 = nullptr;
+    double lam = 0.0;
+    // work vectors
+    double *r64 = nullptr, *d64 = nullptr, *f64 = nullptr, *u64 = nullptr;
+    float *r32 = nullptr, *d32 = nullptr, *f32 = nullptr, *u32 = nullptr;
+    // modification corrections
+    int n_corr_rows = 0;
+    int64_t n_corr = 0;
+    int32_t *c_off = nullptr, *p_off = nullptr;
+    int64_t *c_self = nullptr, *c_nb = nullptr, *p_slot = nullptr;
+    double *c_d64 = nullptr, *c_base = nullptr;
+    float *c_d32 = nullptr;
+    uint8_t *c_nbdir = nullptr;
+    // canonical maps (built on first use); slot2canon holds -(c+1) for a
+    // Dirichlet slot of node c
+    int32_t *slot2canon = nullptr;
+    int64_t *canon2slot = nullptr;
+    std::vector<int64_t> h_poff;  // interior nodes in planes 1..k-1
+};
+
+}  // namespace
+
+struct hhg_ctx_s {
+    Topology topo;
+    int max_level = 0, coarse = 0;
+    uint32_t flags = 0;
+    hipStream_t stream = nullptr;
+    std::vector<Level> lv;
+    bool have_k = false;
+    std::vector<void *> allocs;
+    double *partial = nullptr;
+    int64_t partial_cap = 0;
+    double *dscalar = nullptr;  // device scalars
+    double *hscalar = nullptr;  // pinned host scalars
+    int *dflag = nullptr;
+    // coarse solve
+    int cu = 0;
+    double *ainv = nullptr;
+    int64_t *cgather = nullptr;
+    int32_t *ccoff = nullptr;
+    int64_t *ccslot = nullptr;
+    std::string err;
+    // learned correction
+    LearnedState learned;
+};
+
+namespace {
+
+thread_local std::string g_create_error;
+
+hhg_status fail(hhg_ctx c, hhg_status code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    else g_create_error = buf;
+    return code;
+}
+
+#define HIPCHK(ctx, ...)                                                                    \
+    do {                                                                                    \
+        hipError_t e_ = (__VA_ARGS__);                                                      \
+        if (e_ != hipSuccess)                                                               \
+            return fail((ctx), HHG_EHIP, "%s failed: %s", #__VA_ARGS__,                     \
+                        hipGetErrorString(e_));                                             \
+    } while (0)
+
+// free memory that dalloc/upload gave out
+void dfree(hhg_ctx c, void *p)
+{
+    if (!p) return;
+    auto it = std::find(c->allocs.begin(), c->allocs.end(), p);
+    if (it != c->allocs.end()) c->allocs.erase(it);
+    (void)hipFree(p);
+}
+
+template <typename T>
+hhg_status dalloc(hhg_ctx c, T **p, int64_t n)
+{
+    *p = nullptr;
+    if (n <= 0) n = 1;
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, (size_t)n * sizeof(T));
+    if (e != hipSuccess) return fail(c, HHG_ENOMEM, "hipMalloc of %lld bytes failed: %s",
+                                     (long long)(n * sizeof(T)), hipGetErrorString(e));
+    c->allocs.push_back(q);
+    *p = (T *)q;
+    return HHG_OK;
+}
+
+template <typename T>
+hhg_status upload(hhg_ctx c, T **p, const std::vector<T> &h)
+{
+    hhg_status s = dalloc(c, p, (int64_t)h.size());
+    if (s) return s;
+    if (!h.empty()) HIPCHK(c, hipMemcpy(*p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+    return HHG_OK;
+}
+
+hipStream_t pick(hhg_ctx c, void *s) { return s ? (hipStream_t)s : c->stream; }
+
+#define TRY(expr)                      \
+    do {                               \
+        hhg_status s_ = (expr);        \
+        if (s_ < 0) return s_;         \
+    } while (0)
+
+// element-shape pairs (t, a, b) whose edge a->b runs along direction d
+struct EdgeUse {
+    int t, a, b;
+};
+std::vector<EdgeUse> g_edge_use[NDIR];
+void init_edge_use()
+{
+    if (!g_edge_use[0].empty()) return;
+    for (int t = 0; t < NTYPE; ++t)
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b) {
+                if (a == b) continue;
+                const int d = dir_index(TYPE_OFF[t][b][0] - TYPE_OFF[t][a][0],
+                                        TYPE_OFF[t][b][1] - TYPE_OFF[t][a][1],
+                                        TYPE_OFF[t][b][2] - TYPE_OFF[t][a][2]);
+                g_edge_use[d].push_back({t, a, b});
+            }
+}
+
+// physical coordinates of lattice point (i,j,k) of tet t at n intervals
+void lattice_point(const Topology &tp, int t, int n, double i, double j, double k, double x[3])
+{
+    const double *v0 = &tp.X[3 * tp.tet[4 * t]], *v1 = &tp.X[3 * tp.tet[4 * t + 1]],
+                 *v2 = &tp.X[3 * tp.tet[4 * t + 2]], *v3 = &tp.X[3 * tp.tet[4 * t + 3]];
+    for (int c = 0; c < 3; ++c)
+        x[c] = v0[c] + (i * (v1[c] - v0[c]) + j * (v2[c] - v0[c]) + k * (v3[c] - v0[c])) / n;
+}
+
+// the six element matrices of tet t at n intervals
+bool type_matrices(const Topology &tp, int t, int n, double E[NTYPE][4][4])
+{
+    for (int ty = 0; ty < NTYPE; ++ty) {
+        double p[4][3];
+        for (int a = 0; a < 4; ++a)
+            lattice_point(tp, t, n, TYPE_OFF[ty][a][0], TYPE_OFF[ty][a][1], TYPE_OFF[ty][a][2], p[a]);
+        if (!element_matrix(p, E[ty])) return false;
+    }
+    return true;
+}
+
+// representative lattice point (with nrep = 8 intervals) of the primitive with
+// zero pattern zp: every non-zero barycentric weight is at least 2
+void representative(int zp, int &i, int &j, int &k)
+{
+    int w[4] = {0, 0, 0, 0}, idx[4], c = 0;
+    for (int a = 0; a < 4; ++a)
+        if (!((zp >> a) & 1)) idx[c++] = a;
+    for (int q = 0; q < 8; ++q) w[idx[q % c]] += 1;
+    i = w[1]; j = w[2]; k = w[3];
+}
+
+bool element_valid(int n, int bi, int bj, int bk, int t)
+{
+    for (int v = 0; v < 4; ++v)
+        if (!in_lattice(n, bi + TYPE_OFF[t][v][0], bj + TYPE_OFF[t][v][1], bk + TYPE_OFF[t][v][2]))
+            return false;
+    return true;
+}
+
+// canonical index of lattice point (i,j,k) of tet t at n intervals; poff[k] =
+// number of tet-interior nodes in planes 1..k-1
+int64_t canon_index(const Topology &tp, int t, int n, int i, int j, int k, const int64_t *poff)
+{
+    const int w[4] = {n - i - j - k, i, j, k};
+    int vid[4], ww[4], c = 0;
+    for (int a = 0; a < 4; ++a)
+        if (w[a] > 0) { vid[c] = tp.tet[4 * t + a]; ww[c] = w[a]; ++c; }
+    const int64_t N = n, EN = N - 1, FN = (N - 1) * (N - 2) / 2, TN = (N - 1) * (N - 2) * (N - 3) / 6;
+    const int64_t off_e = tp.nvu, off_f = off_e + (int64_t)tp.edges.size() * EN,
+                  off_t = off_f + (int64_t)tp.faces.size() * FN;
+    if (c == 4) {
+        // interior: k outer, then j, then i; row jj of plane k holds M - jj
+        // points, M = n-1-k
+        const int64_t M = N - 1 - k;
+        const int64_t loc = poff[k] + (int64_t)(j - 1) * M - (int64_t)(j - 1) * j / 2;
+        return off_t + (int64_t)t * TN + loc + (i - 1);
+    }
+    for (int a = 1; a < c; ++a)  // sort by vertex id
+        for (int b = a; b > 0 && vid[b - 1] > vid[b]; --b) {
+            std::swap(vid[b - 1], vid[b]);
+            std::swap(ww[b - 1], ww[b]);
+        }
+    if (c == 1) return tp.vpos[vid[0]];
+    if (c == 2) return off_e + (int64_t)tp.find_edge(vid[0], vid[1]) * EN + (ww[1] - 1);
+    const int64_t s = ww[1], tt = ww[2];
+    return off_f + (int64_t)tp.find_face(vid[0], vid[1], vid[2]) * FN + (tt - 1) * (N - 1) -
+           (tt - 1) * tt / 2 + (s - 1);
+}
+
+template <typename T>
+LevelView<T> view(const hhg_ctx c, int l);
+
+template <>
+LevelView<double> view<double>(const hhg_ctx c, int l)
+{
+    const Level &L = c->lv[l];
+    LevelView<double> v;
+    v.n = L.n; v.n_tet = c->topo.nt; v.S = L.S; v.Spad = L.Spad; v.bpt = L.bpt;
+    v.sten = L.sten64; v.emat = L.emat64; v.rstw = L.rstw64;
+    v.dmask = L.dmask; v.smask = L.smask; v.kap = L.k64;
+    v.n_shared = L.n_shared; v.sh_off = L.sh_off; v.sh_copy = L.sh_copy;
+    return v;
+}
+template <>
+LevelView<float> view<float>(const hhg_ctx c, int l)
+{
+    const Level &L = c->lv[l];
+    LevelView<float> v;
+    v.n = L.n; v.n_tet = c->topo.nt; v.S = L.S; v.Spad = L.Spad; v.bpt = L.bpt;
+    v.sten = L.sten32; v.emat = L.emat32; v.rstw = L.rstw32;
+    v.dmask = L.dmask; v.smask = L.smask; v.kap = L.k32;
+    v.n_shared = L.n_shared; v.sh_off = L.sh_off; v.sh_copy = L.sh_copy;
+    return v;
+}
+
+template <typename T>
+CorrView<T> corr(const hhg_ctx c, int l);
+template <>
+CorrView<double> corr<double>(const hhg_ctx c, int l)
+{
+    const Level &L = c->lv[l];
+    return CorrView<double>{L.n_corr_rows, L.c_off, L.c_self, L.c_nb, L.c_d64, L.c_base, L.c_nbdir,
+                            L.p_off, L.p_slot};
+}
+template <>
+CorrView<float> corr<float>(const hhg_ctx c, int l)
+{
+    const Level &L = c->lv[l];
+    return CorrView<float>{L.n_corr_rows, L.c_off, L.c_self, L.c_nb, L.c_d32, L.c_base, L.c_nbdir,
+                           L.p_off, L.p_slot};
+}
+
+template <typename T> T *&work_r(Level &L);
+template <> double *&work_r<double>(Level &L) { return L.r64; }
+template <> float *&work_r<float>(Level &L) { return L.r32; }
+template <typename T> T *&work_d(Level &L);
+template <> double *&work_d<double>(Level &L) { return L.d64; }
+template <> float *&work_d<float>(Level &L) { return L.d32; }
+template <typename T> T *&work_f(Level &L);
+template <> double *&work_f<double>(Level &L) { return L.f64; }
+template <> float *&work_f<float>(Level &L) { return L.f32; }
+template <typename T> T *&work_u(Level &L);
+template <> double *&work_u<double>(Level &L) { return L.u64; }
+template <> float *&work_u<float>(Level &L) { return L.u32; }
+template <typename T> T *&invd(Level &L);
+template <> double *&invd<double>(Level &L) { return L.invd64; }
+template <> float *&invd<float>(Level &L) { return L.invd32; }
+
+// ---------------------------------------------------------------- level set-up
+hhg_status build_level(hhg_ctx c, int l)
+{
+    const Topology &tp = c->topo;
+    Level &L = c->lv[l];
+    L.l = l;
+    L.n = 1 << l;
+    L.S = (int)tet_count(L.n);
+    L.Spad = ((int64_t)L.S + 63) / 64 * 64;
+    L.bpt = (L.S + BLOCK - 1) / BLOCK;
+    L.n_slots = (int64_t)tp.nt * L.Spad;
+    const int64_t N = L.n;
+    L.n_nodes = tp.nvu + (int64_t)tp.edges.size() * (N - 1) + (int64_t)tp.faces.size() * (N - 1) * (N - 2) / 2 +
+                (int64_t)tp.nt * (N - 1) * (N - 2) * (N - 3) / 6;
+    // unknowns: nodes not on a Dirichlet primitive
+    int64_t nu = 0;
+    for (int v = 0; v < tp.nv; ++v)
+        if (tp.vpos[v] >= 0 && !tp.v_bnd[v]) ++nu;
+    for (size_t e = 0; e < tp.edges.size(); ++e)
+        if (!tp.e_bnd[e]) nu += N - 1;
+    for (size_t f = 0; f < tp.faces.size(); ++f)
+        if (!tp.f_bnd[f]) nu += (N - 1) * (N - 2) / 2;
+    nu += (int64_t)tp.nt * (N - 1) * (N - 2) * (N - 3) / 6;
+    L.n_unknowns = nu;
+    L.h_poff.assign(L.n + 2, 0);
+    for (int k = 1; k <= L.n; ++k) {
+        const int64_t M = N - 1 - k;
+        L.h_poff[k + 1] = L.h_poff[k] + (M >= 2 ? (M - 1) * M / 2 : 0);
+    }
+
+    // per-tet tables
+    L.h_sten.assign((size_t)tp.nt * TET_STENCIL, 0.0);
+    L.h_rstw.assign((size_t)tp.nt * TET_STENCIL, 0.0);
+    L.h_emat.assign((size_t)tp.nt * TET_EMAT, 0.0);
+    L.h_dmask.assign(tp.nt, 0);
+    L.h_smask.assign(tp.nt, 0);
+    for (int t = 0; t < tp.nt; ++t) {
+        double E[NTYPE][4][4];
+        if (!type_matrices(tp, t, L.n, E)) return fail(c, HHG_EMESH, "tet %d is degenerate", t);
+        for (int ty = 0; ty < NTYPE; ++ty)
+            for (int a = 0; a < 4; ++a)
+                for (int b = 0; b < 4; ++b)
+                    L.h_emat[(size_t)t * TET_EMAT + ty * 16 + a * 4 + b] = E[ty][a][b] / 4.0;
+        for (int zp = 0; zp < 15; ++zp) {
+            if (popcount4(zp) == 4) continue;
+            if (tp.dirichlet(t, zp)) L.h_dmask[t] |= (uint16_t)(1u << zp);
+            else if (zp != 0) L.h_smask[t] |= (uint16_t)(1u << zp);
+            int ri, rj, rk;
+            representative(zp, ri, rj, rk);
+            double st[NDIR + 1] = {0};
+            int cnt[NDIR] = {0};
+            for (int ty = 0; ty < NTYPE; ++ty)
+                for (int a = 0; a < 4; ++a) {
+                    const int bi = ri - TYPE_OFF[ty][a][0], bj = rj - TYPE_OFF[ty][a][1],
+                              bk = rk - TYPE_OFF[ty][a][2];
+                    if (!element_valid(8, bi, bj, bk, ty)) continue;
+                    for (int b = 0; b < 4; ++b) {
+                        const int d = dir_index(TYPE_OFF[ty][b][0] - TYPE_OFF[ty][a][0],
+                                                TYPE_OFF[ty][b][1] - TYPE_OFF[ty][a][1],
+                                                TYPE_OFF[ty][b][2] - TYPE_OFF[ty][a][2]);
+                        st[d] += E[ty][a][b];
+                        if (d < NDIR) cnt[d]++;
+                    }
+                }
+            double *row = &L.h_sten[(size_t)t * TET_STENCIL + zp * KIND_STRIDE];
+            double *rw = &L.h_rstw[(size_t)t * TET_STENCIL + zp * KIND_STRIDE];
+            for (int d = 0; d < NDIR; ++d) row[d] = 0.5 * st[d];
+            row[NDIR] = st[NDIR];
+            // restriction weights: 1/2 per coarse edge split evenly over the
+            // tets holding that edge; the centre 1 split over the node's tets
+            rw[NDIR] = 1.0 / tp.valence(t, zp);
+            for (int d = 0; d < NDIR; ++d) {
+                if (!cnt[d]) continue;
+                const int zq = zero_pattern(8, ri + DIR[d][0], rj + DIR[d][1], rk + DIR[d][2]);
+                rw[d] = 0.5 / tp.valence(t, zp & zq);
+            }
+        }
+    }
+    // nodes on shared primitives: every non-Dirichlet vertex / edge / face of
+    // the macro mesh that is not inside one tet, with all tets holding it
+    L.h_sh_off.assign(1, 0);
+    L.h_sh_copy.clear();
+    auto add_node = [&](const std::vector<int> &verts, const std::vector<int> &wts) {
+        for (int t = 0; t < tp.nt; ++t) {
+            int w[4] = {0, 0, 0, 0};
+            int found = 0;
+            for (size_t a = 0; a < verts.size(); ++a)
+                for (int b = 0; b < 4; ++b)
+                    if (tp.tet[4 * t + b] == verts[a]) { w[b] = wts[a]; ++found; }
+            if (found != (int)verts.size()) continue;
+            const int zp = (w[0] == 0) | ((w[1] == 0) << 1) | ((w[2] == 0) << 2) | ((w[3] == 0) << 3);
+            L.h_sh_copy.push_back(pack_copy(t, zp, w[1], w[2], w[3]));
+        }
+        L.h_sh_off.push_back((int32_t)L.h_sh_copy.size());
+    };
+    for (int v = 0; v < tp.nv; ++v)
+        if (tp.vpos[v] >= 0 && !tp.v_bnd[v]) add_node({v}, {L.n});
+    for (size_t e = 0; e < tp.edges.size(); ++e)
+        if (!tp.e_bnd[e])
+            for (int s = 1; s < L.n; ++s) add_node({tp.edges[e][0], tp.edges[e][1]}, {L.n - s, s});
+    for (size_t f = 0; f < tp.faces.size(); ++f)
+        if (!tp.f_bnd[f])
+            for (int tt = 1; tt < L.n; ++tt)
+                for (int s = 1; s + tt < L.n; ++s)
+                    add_node({tp.faces[f][0], tp.faces[f][1], tp.faces[f][2]}, {L.n - s - tt, s, tt});
+    L.n_shared = (int)L.h_sh_off.size() - 1;
+
+    std::vector<float> s32(L.h_sten.begin(), L.h_sten.end()), e32(L.h_emat.begin(), L.h_emat.end()),
+        r32(L.h_rstw.begin(), L.h_rstw.end());
+    TRY(upload(c, &L.sten64, L.h_sten));
+    TRY(upload(c, &L.emat64, L.h_emat));
+    TRY(upload(c, &L.rstw64, L.h_rstw));
+    TRY(upload(c, &L.sten32, s32));
+    TRY(upload(c, &L.emat32, e32));
+    TRY(upload(c, &L.rstw32, r32));
+    TRY(upload(c, &L.dmask, L.h_dmask));
+    TRY(upload(c, &L.smask, L.h_smask));
+    TRY(upload(c, &L.sh_off, L.h_sh_off));
+    TRY(upload(c, &L.sh_copy, L.h_sh_copy));
+    // coefficient and work vectors
+    TRY(dalloc(c, &L.k64, L.n_slots));
+    TRY(dalloc(c, &L.k32, L.n_slots));
+    TRY(dalloc(c, &L.invd64, L.n_slots));
+    TRY(dalloc(c, &L.invd32, L.n_slots));
+    TRY(dalloc(c, &L.r64, L.n_slots));
+    TRY(dalloc(c, &L.d64, L.n_slots));
+    TRY(dalloc(c, &L.r32, L.n_slots));
+    TRY(dalloc(c, &L.d32, L.n_slots));
+    TRY(dalloc(c, &L.f32, L.n_slots));
+    TRY(dalloc(c, &L.u32, L.n_slots));
+    if (l < c->max_level) {
+        TRY(dalloc(c, &L.f64, L.n_slots));
+        TRY(dalloc(c, &L.u64, L.n_slots));
+    }
+    // Dirichlet slots of the work vectors must read 0 even before first use
+    HIPCHK(c, hipMemset(L.r64, 0, L.n_slots * 8));
+    HIPCHK(c, hipMemset(L.r32, 0, L.n_slots * 4));
+    HIPCHK(c, hipMemset(L.f32, 0, L.n_slots * 4));
+    HIPCHK(c, hipMemset(L.u32, 0, L.n_slots * 4));
+    HIPCHK(c, hipMemset(L.d64, 0, L.n_slots * 8));
+    HIPCHK(c, hipMemset(L.d32, 0, L.n_slots * 4));
+    if (L.f64) HIPCHK(c, hipMemset(L.f64, 0, L.n_slots * 8));
+    if (L.u64) HIPCHK(c, hipMemset(L.u64, 0, L.n_slots * 8));
+    return HHG_OK;
+}
+
+hhg_status ensure_canon_maps(hhg_ctx c, int l)
+{
+    Level &L = c->lv[l];
+    if (L.slot2canon) return HHG_OK;
+    if (L.n_nodes >= (int64_t)1 << 31)
+        return fail(c, HHG_EINVAL, "level %d has too many nodes for canonical maps", l);
+    std::vector<int32_t> s2c((size_t)L.n_slots, -1);
+    std::vector<int64_t> c2s((size_t)L.n_nodes, -1);
+    const Topology &tp = c->topo;
+    for (int t = 0; t < tp.nt; ++t)
+        for (int k = 0; k <= L.n; ++k)
+            for (int j = 0; j + k <= L.n; ++j)
+                for (int i = 0; i + j + k <= L.n; ++i) {
+                    const int64_t slot = (int64_t)t * L.Spad + slot_of(L.n, i, j, k);
+                    const int64_t ci = canon_index(tp, t, L.n, i, j, k, L.h_poff.data());
+                    if (ci < 0 || ci >= L.n_nodes)
+                        return fail(c, HHG_EMESH, "canonical numbering out of range at level %d", l);
+                    const int zp = zero_pattern(L.n, i, j, k);
+                    s2c[slot] = ((L.h_dmask[t] >> zp) & 1) ? (int32_t)(-ci - 1) : (int32_t)ci;
+                    if (c2s[ci] < 0) c2s[ci] = slot;
+                }
+    for (int64_t ci = 0; ci < L.n_nodes; ++ci)
+        if (c2s[ci] < 0) return fail(c, HHG_EMESH, "canonical node %lld has no slot", (long long)ci);
+    TRY(upload(c, &L.slot2canon, s2c));
+    TRY(upload(c, &L.canon2slot, c2s));
+    return HHG_OK;
+}
+
+// ---------------------------------------------------------------- operator drivers
+template <typename T>
+hhg_status apply_scaled_t(hhg_ctx c, int l, const T *u, T *y, hipStream_t st)
+{
+    LevelView<T> V = view<T>(c, l);
+    HIPCHK(c, launch_scaled<T>(V, MODE_APPLY, u, nullptr, y, nullptr, nullptr, st));
+    HIPCHK(c, launch_correction<T>(V, corr<T>(c, l), MODE_APPLY, u, y, nullptr, st));
+    return HHG_OK;
+}
+
+// r = f - A u; if norm, the Euclidean norm over the unknowns (synchronises)
+template <typename T>
+hhg_status residual_t(hhg_ctx c, int l, const T *f, const T *u, T *r, double *norm, hipStream_t st)
+{
+    LevelView<T> V = view<T>(c, l);
+    int np = 0;
+    HIPCHK(c, launch_scaled<T>(V, MODE_RESID, u, f, r, c->partial, &np, st));
+    CorrView<T> C = corr<T>(c, l);
+    HIPCHK(c, launch_correction<T>(V, C, MODE_RESID, u, r, c->partial + np, st));
+    if (C.n_rows) np += (C.n_rows + BLOCK - 1) / BLOCK;
+    if (norm) {
+        HIPCHK(c, launch_reduce(c->partial, np, 0, c->dscalar, st));
+        HIPCHK(c, hipMemcpyAsync(c->hscalar, c->dscalar, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        *norm = std::sqrt(std::max(0.0, c->hscalar[0]));
+    }
+    return HHG_OK;
+}
+
+template <typename T>
+hhg_status smooth_t(hhg_ctx c, int l, hhg_smoother sm, int sweeps, double omega, const T *f, T *u,
+                    hipStream_t st)
+{
+    Level &L = c->lv[l];
+    T *r = work_r<T>(L), *d = work_d<T>(L);
+    const T *id = invd<T>(L);
+    if (sm == HHG_JACOBI) {
+        for (int s = 0; s < sweeps; ++s) {
+            TRY(residual_t<T>(c, l, f, u, r, nullptr, st));
+            HIPCHK(c, launch_jacobi_update<T>(u, r, id, (T)omega, L.n_slots, st));
+        }
+        return HHG_OK;
+    }
+    // Chebyshev iteration on D^{-1} A over [0.1, 1] x lambda_max
+    const double a = 0.1 * L.lam, b = L.lam;
+    const double theta = 0.5 * (b + a), delta = 0.5 * (b - a), sigma = theta / delta;
+    double rho = 1.0 / sigma;
+    for (int s = 0; s < sweeps; ++s) {
+        TRY(residual_t<T>(c, l, f, u, r, nullptr, st));
+        if (s == 0) {
+            HIPCHK(c, launch_cheb_update<T>(u, d, r, id, T(0), (T)(1.0 / theta), L.n_slots, st));
+        } else {
+            const double rn = 1.0 / (2.0 * sigma - rho);
+            HIPCHK(c, launch_cheb_update<T>(u, d, r, id, (T)(rn * rho), (T)(2.0 * rn / delta),
+                                            L.n_slots, st));
+            rho = rn;
+        }
+    }
+    return HHG_OK;
+}
+
+template <typename T>
+hhg_status coarse_solve_t(hhg_ctx c, const T *f, T *u, hipStream_t st)
+{
+    Level &L = c->lv[c->coarse];
+    HIPCHK(c, launch_fill<T>(u, T(0), L.n_slots, st));
+    HIPCHK(c, launch_coarse_solve<T>(c->ainv, c->cu, c->cgather, c->ccoff, c->ccslot, f, u, st));
+    return HHG_OK;
+}
+
+template <typename T>
+hhg_status learned_smooth_t(hhg_ctx c, int l, int sweeps, const T *f, T *u, hipStream_t st);
+
+// V(pre,post) cycle; the learned smoother (if asked for) acts on the cycle's
+// top level only, coarser levels use Chebyshev
+template <typename T>
+hhg_status vcycle_t(hhg_ctx c, int l, const T *f, T *u, int pre, int post, hhg_smoother sm,
+                    hipStream_t st)
+{
+    if (l == c->coarse) return coarse_solve_t<T>(c, f, u, st);
+    Level &L = c->lv[l], &Lc = c->lv[l - 1];
+    const hhg_smoother below = sm == HHG_LEARNED ? HHG_CHEBYSHEV : sm;
+    if (sm == HHG_LEARNED) TRY(learned_smooth_t<T>(c, l, pre, f, u, st));
+    else TRY(smooth_t<T>(c, l, sm, pre, 2.0 / 3.0, f, u, st));
+    T *r = work_r<T>(L);
+    TRY(residual_t<T>(c, l, f, u, r, nullptr, st));
+    T *fc = work_f<T>(Lc), *uc = work_u<T>(Lc);
+    HIPCHK(c, launch_restrict<T>(view<T>(c, l - 1), view<T>(c, l), r, fc, st));
+    TRY(vcycle_t<T>(c, l - 1, fc, uc, pre, post, below, st));
+    HIPCHK(c, launch_prolong_add<T>(view<T>(c, l - 1), view<T>(c, l), uc, u, st));
+    if (sm == HHG_LEARNED) TRY(learned_smooth_t<T>(c, l, post, f, u, st));
+    else TRY(smooth_t<T>(c, l, sm, post, 2.0 / 3.0, f, u, st));
+    return HHG_OK;
+}
+
+// ---------------------------------------------------------------- coefficient set-up
+// modification (Sec. 4.1, read for 3D): per tet, per edge with a positive
+// element entry, compare k_e with the minimum edge average over the edge's
+// element patch; replace k_e where triggered.  Builds the correction lists.
+hhg_status build_modification(hhg_ctx c, int l)
+{
+    Level &L = c->lv[l];
+    const Topology &tp = c->topo;
+    L.n_corr_rows = 0;
+    L.n_corr = 0;
+    if (c->flags & HHG_FLAG_NO_MODIFICATION) return HHG_OK;
+    init_edge_use();
+    std::vector<double> kh;  // host copy of k at this level, fetched on demand
+    struct Corr {
+        int64_t self, nb;
+        double delta, base;
+        uint8_t nbdir;
+    };
+    std::map<int64_t, std::vector<Corr>> rows;  // row key -> corrections
+    // row key: interior slot -> global slot; shared node q -> -(q+1)
+    std::unordered_map<int64_t, int64_t> shared_of;
+    bool shared_built = false;
+    for (int t = 0; t < tp.nt; ++t) {
+        double E[NTYPE][4][4];
+        type_matrices(tp, t, L.n, E);
+        bool any_pos = false;
+        for (int ty = 0; ty < NTYPE; ++ty)
+            for (int a = 0; a < 4; ++a)
+                for (int b = 0; b < 4; ++b)
+                    if (a != b && E[ty][a][b] > 0.0) any_pos = true;
+        if (!any_pos) continue;
+        double lamT = 1e300;
+        for (int ty = 0; ty < NTYPE; ++ty) lamT = std::min(lamT, lambda_min_element(E[ty]));
+        if (kh.empty()) {
+            kh.resize((size_t)L.n_slots);
+            HIPCHK(c, hipMemcpy(kh.data(), L.k64, L.n_slots * sizeof(double), hipMemcpyDeviceToHost));
+        }
+        if (!shared_built) {
+            for (int q = 0; q < L.n_shared; ++q)
+                for (int p = L.h_sh_off[q]; p < L.h_sh_off[q + 1]; ++p) {
+                    int tt, kind, i, j, k;
+                    unpack_copy(L.h_sh_copy[p], tt, kind, i, j, k);
+                    shared_of[(int64_t)tt * L.Spad + slot_of(L.n, i, j, k)] = q;
+                }
+            shared_built = true;
+        }
+        const double *kt = kh.data() + (int64_t)t * L.Spad;
+        auto kat = [&](int i, int j, int k) { return kt[slot_of(L.n, i, j, k)]; };
+        const int n = L.n;
+        for (int k = 0; k <= n; ++k)
+            for (int j = 0; j + k <= n; ++j)
+                for (int i = 0; i + j + k <= n; ++i)
+                    for (int d = 0; d < 7; ++d) {
+                        const int i2 = i + DIR[d][0], j2 = j + DIR[d][1], k2 = k + DIR[d][2];
+                        if (!in_lattice(n, i2, j2, k2)) continue;
+                        double aplus = -1e300, ref = 0.0, kmin = 1e300;
+                        int nel = 0;
+                        for (const EdgeUse &eu : g_edge_use[d]) {
+                            const int bi = i - TYPE_OFF[eu.t][eu.a][0], bj = j - TYPE_OFF[eu.t][eu.a][1],
+                                      bk = k - TYPE_OFF[eu.t][eu.a][2];
+                            if (!element_valid(n, bi, bj, bk, eu.t)) continue;
+                            ++nel;
+                            const double e = E[eu.t][eu.a][eu.b];
+                            aplus = std::max(aplus, e);
+                            ref += e;
+                            double kv[4];
+                            for (int v = 0; v < 4; ++v)
+                                kv[v] = kat(bi + TYPE_OFF[eu.t][v][0], bj + TYPE_OFF[eu.t][v][1],
+                                            bk + TYPE_OFF[eu.t][v][2]);
+                            for (int a = 0; a < 4; ++a)
+                                for (int b = a + 1; b < 4; ++b) kmin = std::min(kmin, 0.5 * (kv[a] + kv[b]));
+                        }
+                        if (!nel || !(aplus > 0.0)) continue;
+                        const double ka = kat(i, j, k), kb = kat(i2, j2, k2);
+                        const double ke = 0.5 * (ka + kb);
+                        if (!((ke - kmin) * aplus > kmin * lamT)) continue;
+                        const double kmod = kmin * (1.0 + lamT / aplus);
+                        const double delta = (kmod - ke) * ref, base = ke * ref;
+                        const int64_t sa = (int64_t)t * L.Spad + slot_of(n, i, j, k);
+                        const int64_t sb = (int64_t)t * L.Spad + slot_of(n, i2, j2, k2);
+                        const bool da = (L.h_dmask[t] >> zero_pattern(n, i, j, k)) & 1;
+                        const bool db = (L.h_dmask[t] >> zero_pattern(n, i2, j2, k2)) & 1;
+                        auto key = [&](int64_t slot, int zp) -> int64_t {
+                            if (zp == 0) return slot;
+                            return -(shared_of.at(slot) + 1);
+                        };
+                        if (!da) rows[key(sa, zero_pattern(n, i, j, k))].push_back({sa, sb, delta, base, (uint8_t)db});
+                        if (!db) rows[key(sb, zero_pattern(n, i2, j2, k2))].push_back({sb, sa, delta, base, (uint8_t)da});
+                        L.n_corr++;
+                    }
+    }
+    if (rows.empty()) return HHG_OK;
+    std::vector<int32_t> coff(1, 0), poff(1, 0);
+    std::vector<int64_t> cself, cnb, pslot;
+    std::vector<double> cd, cbase;
+    std::vector<float> cd32;
+    std::vector<uint8_t> cnbd;
+    for (auto &kv : rows) {
+        for (const Corr &q : kv.second) {
+            cself.push_back(q.self); cnb.push_back(q.nb); cd.push_back(q.delta);
+            cd32.push_back((float)q.delta); cbase.push_back(q.base); cnbd.push_back(q.nbdir);
+        }
+        coff.push_back((int32_t)cself.size());
+        if (kv.first >= 0) {
+            pslot.push_back(kv.first);
+        } else {
+            const int q = (int)(-kv.first - 1);
+            for (int p = L.h_sh_off[q]; p < L.h_sh_off[q + 1]; ++p) {
+                int tt, kind, i, j, k;
+                unpack_copy(L.h_sh_copy[p], tt, kind, i, j, k);
+                pslot.push_back((int64_t)tt * L.Spad + slot_of(L.n, i, j, k));
+            }
+        }
+        poff.push_back((int32_t)pslot.size());
+    }
+    L.n_corr_rows = (int)rows.size();
+    TRY(upload(c, &L.c_off, coff));
+    TRY(upload(c, &L.p_off, poff));
+    TRY(upload(c, &L.c_self, cself));
+    TRY(upload(c, &L.c_nb, cnb));
+    TRY(upload(c, &L.p_slot, pslot));
+    TRY(upload(c, &L.c_d64, cd));
+    TRY(upload(c, &L.c_d32, cd32));
+    TRY(upload(c, &L.c_base, cbase));
+    TRY(upload(c, &L.c_nbdir, cnbd));
+    return HHG_OK;
+}
+
+// Jacobi diagonal (with corrections) and the Gershgorin bound of D^{-1}A
+hhg_status build_diag(hhg_ctx c, int l, hipStream_t st)
+{
+    Level &L = c->lv[l];
+    LevelView<double> V = view<double>(c, l);
+    const bool corrected = L.n_corr_rows > 0;
+    double *asum = nullptr;
+    if (corrected) TRY(dalloc(c, &asum, L.n_slots));
+    double *gabs = nullptr;
+    TRY(dalloc(c, &gabs, 2 * (int64_t)std::max(1, L.n_shared)));
+    int np = 0;
+    HIPCHK(c, launch_diag<double>(V, L.invd64, asum, c->partial, gabs, &np, st));
+    HIPCHK(c, launch_reduce(c->partial, np, 1, c->dscalar, st));
+    HIPCHK(c, hipMemcpyAsync(c->hscalar, c->dscalar, sizeof(double), hipMemcpyDeviceToHost, st));
+    std::vector<double> g((size_t)2 * L.n_shared);
+    if (L.n_shared)
+        HIPCHK(c, hipMemcpyAsync(g.data(), gabs, g.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    double lam = c->hscalar[0];
+    for (int q = 0; q < L.n_shared; ++q) lam = std::max(lam, 1.0 + g[2 * q] / g[2 * q + 1]);
+    if (corrected) {
+        // download D and |row| sums, apply the corrections per unique row, upload D
+        std::vector<double> D((size_t)L.n_slots), A((size_t)L.n_slots);
+        HIPCHK(c, hipMemcpy(D.data(), L.invd64, L.n_slots * 8, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(A.data(), asum, L.n_slots * 8, hipMemcpyDeviceToHost));
+        std::vector<int32_t> coff(L.n_corr_rows + 1), poff(L.n_corr_rows + 1);
+        HIPCHK(c, hipMemcpy(coff.data(), L.c_off, coff.size() * 4, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(poff.data(), L.p_off, poff.size() * 4, hipMemcpyDeviceToHost));
+        const int64_t ncorr = coff.back(), npos = poff.back();
+        std::vector<double> cd(ncorr), cb(ncorr);
+        std::vector<uint8_t> cn(ncorr);
+        std::vector<int64_t> ps(npos);
+        HIPCHK(c, hipMemcpy(cd.data(), L.c_d64, ncorr * 8, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(cb.data(), L.c_base, ncorr * 8, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(cn.data(), L.c_nbdir, ncorr, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(ps.data(), L.p_slot, npos * 8, hipMemcpyDeviceToHost));
+        std::vector<uint8_t> corrected_slot((size_t)L.n_slots, 0);
+        for (int q = 0; q < L.n_corr_rows; ++q) {
+            double dd = D[ps[poff[q]]], aa = A[ps[poff[q]]];
+            for (int64_t x = coff[q]; x < coff[q + 1]; ++x) {
+                dd -= cd[x];
+                if (!cn[x]) aa += std::fabs(cb[x] + cd[x]) - std::fabs(cb[x]);
+            }
+            for (int p = poff[q]; p < poff[q + 1]; ++p) {
+                D[ps[p]] = dd;
+                A[ps[p]] = aa;
+                corrected_slot[ps[p]] = 1;
+            }
+        }
+        HIPCHK(c, hipMemcpy(L.invd64, D.data(), L.n_slots * 8, hipMemcpyHostToDevice));
+        // exact maximum over all unknown rows
+        lam = 0.0;
+        const Topology &tp = c->topo;
+        for (int t = 0; t < tp.nt; ++t)
+            for (int k = 0; k <= L.n; ++k)
+                for (int j = 0; j + k <= L.n; ++j)
+                    for (int i = 0; i + j + k <= L.n; ++i) {
+                        const int zp = zero_pattern(L.n, i, j, k);
+                        if ((L.h_dmask[t] >> zp) & 1) continue;
+                        const int64_t s = (int64_t)t * L.Spad + slot_of(L.n, i, j, k);
+                        lam = std::max(lam, 1.0 + A[s] / D[s]);
+                    }
+    }
+    L.lam = lam;
+    HIPCHK(c, launch_invert_diag<double>(L.invd64, L.n_slots, st));
+    HIPCHK(c, launch_convert<double, float>(L.invd64, L.invd32, L.n_slots, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    dfree(c, asum);
+    dfree(c, gabs);
+    return HHG_OK;
+}
+
+// dense inverse of the coarse operator over its unknowns, column by column
+// from the FP64 apply kernel
+hhg_status build_coarse(hhg_ctx c, hipStream_t st)
+{
+    TRY(ensure_canon_maps(c, c->coarse));
+    Level &L = c->lv[c->coarse];
+    const Topology &tp = c->topo;
+    // unknowns of the coarse level with all their copies, canonical order
+    std::vector<std::vector<int64_t>> copies((size_t)L.n_nodes);
+    std::vector<uint8_t> dir((size_t)L.n_nodes, 0);
+    for (int t = 0; t < tp.nt; ++t)
+        for (int k = 0; k <= L.n; ++k)
+            for (int j = 0; j + k <= L.n; ++j)
+                for (int i = 0; i + j + k <= L.n; ++i) {
+                    const int64_t ci = canon_index(tp, t, L.n, i, j, k, L.h_poff.data());
+                    copies[ci].push_back((int64_t)t * L.Spad + slot_of(L.n, i, j, k));
+                    if ((L.h_dmask[t] >> zero_pattern(L.n, i, j, k)) & 1) dir[ci] = 1;
+                }
+    std::vector<int64_t> gather, cslot;
+    std::vector<int32_t> coff(1, 0);
+    for (int64_t ci = 0; ci < L.n_nodes; ++ci) {
+        if (dir[ci]) continue;
+        gather.push_back(copies[ci][0]);
+        for (int64_t s : copies[ci]) cslot.push_back(s);
+        coff.push_back((int32_t)cslot.size());
+    }
+    const int nu = (int)gather.size();
+    if (nu == 0) return fail(c, HHG_EINVAL, "coarse level %d has no unknowns", c->coarse);
+    if (nu > 4096) return fail(c, HHG_EINVAL, "coarse level %d has %d unknowns (max 4096)", c->coarse, nu);
+    std::vector<double> A((size_t)nu * nu);
+    std::vector<double> e((size_t)L.n_slots), y((size_t)L.n_slots);
+    double *de = L.r64, *dy = L.d64;  // scratch at set-up time
+    for (int col = 0; col < nu; ++col) {
+        std::fill(e.begin(), e.end(), 0.0);
+        for (int p = coff[col]; p < coff[col + 1]; ++p) e[cslot[p]] = 1.0;
+        HIPCHK(c, hipMemcpyAsync(de, e.data(), L.n_slots * 8, hipMemcpyHostToDevice, st));
+        TRY(apply_scaled_t<double>(c, c->coarse, de, dy, st));
+        HIPCHK(c, hipMemcpyAsync(y.data(), dy, L.n_slots * 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        for (int row = 0; row < nu; ++row) A[(size_t)row * nu + col] = y[gather[row]];
+    }
+    HIPCHK(c, hipMemsetAsync(de, 0, L.n_slots * 8, st));
+    HIPCHK(c, hipMemsetAsync(dy, 0, L.n_slots * 8, st));
+    if (!invert_dense(A, nu)) return fail(c, HHG_ECOEF, "coarse operator is singular");
+    if (c->ainv) {
+        for (void *p : {(void *)c->ainv, (void *)c->cgather, (void *)c->ccoff, (void *)c->ccslot})
+            dfree(c, p);
+    }
+    c->cu = nu;
+    TRY(upload(c, &c->ainv, A));
+    TRY(upload(c, &c->cgather, gather));
+    TRY(upload(c, &c->ccoff, coff));
+    TRY(upload(c, &c->ccslot, cslot));
+    HIPCHK(c, hipStreamSynchronize(st));
+    return HHG_OK;
+}
+
+int default_coarse(hhg_ctx c)
+{
+    int best = -1;
+    for (int l = 0; l <= c->max_level; ++l)
+        if (c->lv[l].n_unknowns >= 1 && c->lv[l].n_unknowns <= 1000) best = l;
+    if (best < 0)
+        for (int l = 0; l <= c->max_level; ++l)
+            if (c->lv[l].n_unknowns >= 1) { best = l; break; }
+    return best < 0 ? c->max_level : best;
+}
+
+template <typename T>
+hhg_status learned_smooth_t(hhg_ctx c, int l, int sweeps, const T *f, T *u, hipStream_t st)
+{
+    (void)l; (void)sweeps; (void)f; (void)u; (void)st;
+    return fail(c, HHG_ESTATE, "learned smoother not available");
+}
+
+}  // namespace
+
+namespace hhg {
+void learned_free(LearnedState &s) { (void)s; }
+}  // namespace hhg
+
+// ================================================================ C ABI
+extern "C" {
+
+hhg_status hhg_create_macro(const double *vert_xyz, int32_t n_vert, const int32_t *tet_vert,
+                            int32_t n_tet, int32_t max_level, uint32_t flags, void *hip_stream,
+                            hhg_ctx *out)
+{
+    if (out) *out = nullptr;
+    if (!vert_xyz || !tet_vert || !out || n_vert <= 0 || n_tet <= 0 || n_tet >= (1 << 16))
+        return fail(nullptr, HHG_EINVAL, "invalid mesh arguments");
+    if (max_level < 0 || max_level > 10) return fail(nullptr, HHG_EINVAL, "max_level must be in [0, 10]");
+    if (flags & ~HHG_FLAG_NO_MODIFICATION) return fail(nullptr, HHG_EINVAL, "unknown flag bits");
+    for (int i = 0; i < 4 * n_tet; ++i)
+        if (tet_vert[i] < 0 || tet_vert[i] >= n_vert) return fail(nullptr, HHG_EINVAL, "vertex id out of range");
+    hhg_ctx c = new hhg_ctx_s();
+    c->flags = flags;
+    c->stream = (hipStream_t)hip_stream;
+    c->max_level = max_level;
+    Topology &tp = c->topo;
+    tp.nv = n_vert;
+    tp.nt = n_tet;
+    tp.X.assign(vert_xyz, vert_xyz + 3 * n_vert);
+    tp.tet.assign(tet_vert, tet_vert + 4 * n_tet);
+    tp.vpos.assign(n_vert, -1);
+    for (int i = 0; i < 4 * n_tet; ++i) tp.vpos[tet_vert[i]] = 1;
+    for (int v = 0; v < n_vert; ++v)
+        if (tp.vpos[v] == 1) tp.vpos[v] = tp.nvu++;
+    std::vector<std::array<int, 2>> E;
+    std::vector<std::array<int, 3>> F;
+    for (int t = 0; t < n_tet; ++t) {
+        const int *v = tet_vert + 4 * t;
+        for (int a = 0; a < 4; ++a)
+            for (int b = a + 1; b < 4; ++b) {
+                if (v[a] == v[b]) { delete c; return fail(nullptr, HHG_EMESH, "tet %d repeats a vertex", t); }
+                E.push_back({std::min(v[a], v[b]), std::max(v[a], v[b])});
+            }
+        for (int skip = 0; skip < 4; ++skip) {
+            std::array<int, 3> f;
+            int q = 0;
+            for (int a = 0; a < 4; ++a)
+                if (a != skip) f[q++] = v[a];
+            std::sort(f.begin(), f.end());
+            F.push_back(f);
+        }
+    }
+    std::sort(E.begin(), E.end());
+    std::sort(F.begin(), F.end());
+    for (size_t i = 0; i < E.size(); ++i)
+        if (i == 0 || E[i] != E[i - 1]) { tp.edges.push_back(E[i]); tp.e_val.push_back(0); }
+        else {}
+    for (size_t i = 0; i < F.size(); ++i) {
+        if (i == 0 || F[i] != F[i - 1]) { tp.faces.push_back(F[i]); tp.f_val.push_back(0); }
+        tp.f_val.back()++;
+    }
+    for (size_t f = 0; f < tp.faces.size(); ++f)
+        if (tp.f_val[f] > 2) { delete c; return fail(nullptr, HHG_EMESH, "a face is shared by more than two tets"); }
+    tp.v_val.assign(n_vert, 0);
+    for (int t = 0; t < n_tet; ++t) {
+        const int *v = tet_vert + 4 * t;
+        for (int a = 0; a < 4; ++a) tp.v_val[v[a]]++;
+        for (int a = 0; a < 4; ++a)
+            for (int b = a + 1; b < 4; ++b) tp.e_val[tp.find_edge(v[a], v[b])]++;
+    }
+    tp.v_bnd.assign(n_vert, 0);
+    tp.e_bnd.assign(tp.edges.size(), 0);
+    tp.f_bnd.assign(tp.faces.size(), 0);
+    for (size_t f = 0; f < tp.faces.size(); ++f) {
+        if (tp.f_val[f] != 1) continue;
+        tp.f_bnd[f] = 1;
+        const auto &fv = tp.faces[f];
+        for (int a = 0; a < 3; ++a) {
+            tp.v_bnd[fv[a]] = 1;
+            for (int b = a + 1; b < 3; ++b) tp.e_bnd[tp.find_edge(fv[a], fv[b])] = 1;
+        }
+    }
+    // every tet must have positive volume
+    for (int t = 0; t < n_tet; ++t) {
+        double E0[NTYPE][4][4];
+        if (!type_matrices(tp, t, 1, E0)) { delete c; return fail(nullptr, HHG_EMESH, "tet %d is degenerate", t); }
+    }
+    c->lv.resize(max_level + 1);
+    hhg_status s = HHG_OK;
+    for (int l = 0; l <= max_level && s == HHG_OK; ++l) s = build_level(c, l);
+    if (s == HHG_OK) {
+        int64_t pc = 1024;
+        for (int l = 0; l <= max_level; ++l) {
+            const Level &L = c->lv[l];
+            const int64_t gv = ((int64_t)tp.nt * L.bpt + 7) / 8 * 8;
+            pc = std::max(pc, gv + (L.n_shared + BLOCK - 1) / BLOCK + (L.n_slots + BLOCK - 1) / BLOCK + 8);
+        }
+        c->partial_cap = pc;
+        s = dalloc(c, &c->partial, pc);
+        if (s == HHG_OK) s = dalloc(c, &c->dscalar, 16);
+        if (s == HHG_OK) s = dalloc(c, &c->dflag, 4);
+        if (s == HHG_OK && hipHostMalloc((void **)&c->hscalar, 16 * sizeof(double)) != hipSuccess)
+            s = fail(c, HHG_ENOMEM, "hipHostMalloc failed");
+    }
+    if (s != HHG_OK) {
+        g_create_error = c->err;
+        hhg_destroy(c);
+        return s;
+    }
+    c->coarse = default_coarse(c);
+    *out = c;
+    return HHG_OK;
+}
+
+hhg_status hhg_destroy(hhg_ctx c)
+{
+    if (!c) return HHG_OK;
+    (void)hipDeviceSynchronize();
+    for (void *p : c->allocs) (void)hipFree(p);
+    if (c->hscalar) (void)hipHostFree(c->hscalar);
+    learned_free(c->learned);
+    delete c;
+    return HHG_OK;
+}
+
+const char *hhg_last_error(hhg_ctx c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+static hhg_status check_level(hhg_ctx c, int32_t level)
+{
+    if (!c) return HHG_EINVAL;
+    if (level < 0 || level > c->max_level) return fail(c, HHG_EINVAL, "level %d out of range", level);
+    return HHG_OK;
+}
+
+hhg_status hhg_vector_size(hhg_ctx c, int32_t level, int64_t *n_slots, int64_t *n_unknowns,
+                           int64_t *n_nodes)
+{
+    TRY(check_level(c, level));
+    const Level &L = c->lv[level];
+    if (n_slots) *n_slots = L.n_slots;
+    if (n_unknowns) *n_unknowns = L.n_unknowns;
+    if (n_nodes) *n_nodes = L.n_nodes;
+    return HHG_OK;
+}
+
+hhg_status hhg_node_coords(hhg_ctx c, int32_t level, double *xyz, uint8_t *dirichlet)
+{
+    TRY(check_level(c, level));
+    if (!xyz) return fail(c, HHG_EINVAL, "xyz is NULL");
+    const Level &L = c->lv[level];
+    const Topology &tp = c->topo;
+    for (int t = 0; t < tp.nt; ++t)
+        for (int k = 0; k <= L.n; ++k)
+            for (int j = 0; j + k <= L.n; ++j)
+                for (int i = 0; i + j + k <= L.n; ++i) {
+                    const int64_t ci = canon_index(tp, t, L.n, i, j, k, L.h_poff.data());
+                    if (ci < 0 || ci >= L.n_nodes) return fail(c, HHG_EMESH, "canonical numbering out of range");
+                    lattice_point(tp, t, L.n, i, j, k, xyz + 3 * ci);
+                    if (dirichlet) dirichlet[ci] = (L.h_dmask[t] >> zero_pattern(L.n, i, j, k)) & 1;
+                }
+    return HHG_OK;
+}
+
+hhg_status hhg_to_canonical(hhg_ctx c, int32_t level, hhg_dtype dt, const void *v_slots, void *v_canon,
+                            void *stream)
+{
+    TRY(check_level(c, level));
+    if (!v_slots || !v_canon) return fail(c, HHG_EINVAL, "NULL vector");
+    TRY(ensure_canon_maps(c, level));
+    const Level &L = c->lv[level];
+    hipStream_t st = pick(c, stream);
+    if (dt == HHG_F64)
+        HIPCHK(c, launch_to_canonical<double>((const double *)v_slots, L.canon2slot, (double *)v_canon, L.n_nodes, st));
+    else if (dt == HHG_F32)
+        HIPCHK(c, launch_to_canonical<float>((const float *)v_slots, L.canon2slot, (float *)v_canon, L.n_nodes, st));
+    else return fail(c, HHG_EINVAL, "bad dtype");
+    return HHG_OK;
+}
+
+hhg_status hhg_from_canonical(hhg_ctx c, int32_t level, hhg_dtype dt, const void *v_canon,
+                              void *v_slots, void *stream)
+{
+    TRY(check_level(c, level));
+    if (!v_slots || !v_canon) return fail(c, HHG_EINVAL, "NULL vector");
+    TRY(ensure_canon_maps(c, level));
+    const Level &L = c->lv[level];
+    hipStream_t st = pick(c, stream);
+    if (dt == HHG_F64)
+        HIPCHK(c, launch_from_canonical<double>((const double *)v_canon, L.slot2canon, (double *)v_slots, L.n_slots, 0, L.S, L.Spad, st));
+    else if (dt == HHG_F32)
+        HIPCHK(c, launch_from_canonical<float>((const float *)v_canon, L.slot2canon, (float *)v_slots, L.n_slots, 0, L.S, L.Spad, st));
+    else return fail(c, HHG_EINVAL, "bad dtype");
+    return HHG_OK;
+}
+
+hhg_status hhg_set_coefficient(hhg_ctx c, const double *k, int on_device, void *stream)
+{
+    if (!c || !k) return fail(c, HHG_EINVAL, "NULL argument");
+    hipStream_t st = pick(c, stream);
+    const int Lmax = c->max_level;
+    Level &F = c->lv[Lmax];
+    TRY(ensure_canon_maps(c, Lmax));
+    double *dk = nullptr;
+    TRY(dalloc(c, &dk, F.n_nodes));
+    auto release = [&]() { dfree(c, dk); };
+    HIPCHK(c, hipMemcpyAsync(dk, k, F.n_nodes * 8, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipMemsetAsync(c->dflag, 0, 4, st));
+    HIPCHK(c, launch_positive_check(dk, F.n_nodes, c->dflag, st));
+    int bad = 0;
+    HIPCHK(c, hipMemcpyAsync(&bad, c->dflag, 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    if (bad) { release(); return fail(c, HHG_ECOEF, "coefficient must be positive and finite at every node"); }
+    // Dirichlet slots also need k (rows next to the boundary read it): fill
+    // every slot from its node, Dirichlet ones included; padding slots get 1
+    HIPCHK(c, launch_fill<double>(F.k64, 1.0, F.n_slots, st));
+    HIPCHK(c, launch_from_canonical<double>(dk, F.slot2canon, F.k64, F.n_slots, 1, F.S, F.Spad, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    release();
+    for (int l = Lmax - 1; l >= 0; --l) {
+        Level &Lc = c->lv[l], &Lf = c->lv[l + 1];
+        HIPCHK(c, launch_fill<double>(Lc.k64, 1.0, Lc.n_slots, st));
+        HIPCHK(c, launch_inject<double>(Lf.k64, Lf.n, Lc.k64, Lc.n, c->topo.nt, Lf.Spad, Lc.Spad, st));
+    }
+    for (int l = 0; l <= Lmax; ++l)
+        HIPCHK(c, launch_convert<double, float>(c->lv[l].k64, c->lv[l].k32, c->lv[l].n_slots, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    for (int l = 0; l <= Lmax; ++l) {
+        TRY(build_modification(c, l));
+        TRY(build_diag(c, l, st));
+    }
+    c->have_k = true;
+    TRY(build_coarse(c, st));
+    return HHG_OK;
+}
+
+hhg_status hhg_set_coarse_level(hhg_ctx c, int32_t level)
+{
+    TRY(check_level(c, level));
+    if (c->lv[level].n_unknowns < 1) return fail(c, HHG_EINVAL, "level %d has no unknowns", level);
+    c->coarse = level;
+    if (c->have_k) TRY(build_coarse(c, c->stream));
+    return HHG_OK;
+}
+
+hhg_status hhg_level_info(hhg_ctx c, int32_t level, double *lambda_max, int64_t *n_mod, int32_t *coarse)
+{
+    TRY(check_level(c, level));
+    if (lambda_max) *lambda_max = c->lv[level].lam;
+    if (n_mod) *n_mod = c->lv[level].n_corr;
+    if (coarse) *coarse = c->coarse;
+    return HHG_OK;
+}
+
+#define NEED_K(c)                                                                   \
+    do {                                                                            \
+        if (!(c)->have_k) return fail((c), HHG_ESTATE, "no coefficient set");       \
+    } while (0)
+
+hhg_status hhg_apply_scaled(hhg_ctx c, int32_t level, hhg_dtype dt, const void *u, void *y, void *stream)
+{
+    TRY(check_level(c, level));
+    NEED_K(c);
+    if (!u || !y || u == y) return fail(c, HHG_EINVAL, "u and y must be distinct non-NULL vectors");
+    hipStream_t st = pick(c, stream);
+    if (dt == HHG_F64) return apply_scaled_t<double>(c, level, (const double *)u, (double *)y, st);
+    if (dt == HHG_F32) return apply_scaled_t<float>(c, level, (const float *)u, (float *)y, st);
+    return fail(c, HHG_EINVAL, "bad dtype");
+}
+
+hhg_status hhg_apply_nodal(hhg_ctx c, int32_t level, hhg_dtype dt, const void *u, void *y, void *stream)
+{
+    TRY(check_level(c, level));
+    NEED_K(c);
+    if (!u || !y || u == y) return fail(c, HHG_EINVAL, "u and y must be distinct non-NULL vectors");
+    hipStream_t st = pick(c, stream);
+    if (dt == HHG_F64) HIPCHK(c, launch_nodal<double>(view<double>(c, level), (const double *)u, (double *)y, st));
+    else if (dt == HHG_F32) HIPCHK(c, launch_nodal<float>(view<float>(c, level), (const float *)u, (float *)y, st));
+    else return fail(c, HHG_EINVAL, "bad dtype");
+    return HHG_OK;
+}
+
+hhg_status hhg_residual(hhg_ctx c, int32_t level, hhg_dtype dt, const void *f, const void *u, void *r,
+                        double *norm2_out, void *stream)
+{
+    TRY(check_level(c, level));
+    NEED_K(c);
+    if (!f || !u || !r || r == u || r == f) return fail(c, HHG_EINVAL, "bad vectors");
+    hipStream_t st = pick(c, stream);
+    if (dt == HHG_F64) return residual_t<double>(c, level, (const double *)f, (const double *)u, (double *)r, norm2_out, st);
+    if (dt == HHG_F32) return residual_t<float>(c, level, (const float *)f, (const float *)u, (float *)r, norm2_out, st);
+    return fail(c, HHG_EINVAL, "bad dtype");
+}
+
+hhg_status hhg_smooth(hhg_ctx c, int32_t level, hhg_dtype dt, hhg_smoother sm, int32_t sweeps, double omega,
+                      const void *f, void *u, void *stream)
+{
+    TRY(check_level(c, level));
+    NEED_K(c);
+    if (!f || !u || f == u || sweeps < 0) return fail(c, HHG_EINVAL, "bad arguments");
+    hipStream_t st = pick(c, stream);
+    if (sm == HHG_LEARNED) {
+        if (dt == HHG_F64) return learned_smooth_t<double>(c, level, sweeps, (const double *)f, (double *)u, st);
+        if (dt == HHG_F32) return learned_smooth_t<float>(c, level, sweeps, (const float *)f, (float *)u, st);
+        return fail(c, HHG_EINVAL, "bad dtype");
+    }
+    if (sm != HHG_JACOBI && sm != HHG_CHEBYSHEV) return fail(c, HHG_EINVAL, "bad smoother");
+    if (dt == HHG_F64) return smooth_t<double>(c, level, sm, sweeps, omega, (const double *)f, (double *)u, st);
+    if (dt == HHG_F32) return smooth_t<float>(c, level, sm, sweeps, omega, (const float *)f, (float *)u, st);
+    return fail(c, HHG_EINVAL, "bad dtype");
+}
+
+hhg_status hhg_vcycle(hhg_ctx c, int32_t level, hhg_dtype dt, int32_t pre, int32_t post, hhg_smoother sm,
+                      const void *f, void *u, double *rel_res_out, void *stream)
+{
+    TRY(check_level(c, level));
+    NEED_K(c);
+    if (!f || !u || f == u || pre < 0 || post < 0) return fail(c, HHG_EINVAL, "bad arguments");
+    if (level < c->coarse) return fail(c, HHG_EINVAL, "level below the coarse level");
+    if (sm != HHG_JACOBI && sm != HHG_CHEBYSHEV && sm != HHG_LEARNED) return fail(c, HHG_EINVAL, "bad smoother");
+    hipStream_t st = pick(c, stream);
+    Level &L = c->lv[level];
+    if (dt == HHG_F64) {
+        TRY(vcycle_t<double>(c, level, (const double *)f, (double *)u, pre, post, sm, st));
+        if (rel_res_out) {
+            double nr, nf;
+            TRY(residual_t<double>(c, level, (const double *)f, (const double *)u, L.r64, &nr, st));
+            HIPCHK(c, launch_fill<double>(L.d64, 0.0, L.n_slots, st));
+            TRY(residual_t<double>(c, level, (const double *)f, L.d64, L.r64, &nf, st));
+            *rel_res_out = nf > 0 ? nr / nf : nr;
+        }
+        return HHG_OK;
+    }
+    if (dt == HHG_F32) {
+        TRY(vcycle_t<float>(c, level, (const float *)f, (float *)u, pre, post, sm, st));
+        if (rel_res_out) {
+            double nr, nf;
+            TRY(residual_t<float>(c, level, (const float *)f, (const float *)u, L.r32, &nr, st));
+            HIPCHK(c, launch_fill<float>(L.d32, 0.0f, L.n_slots, st));
+            TRY(residual_t<float>(c, level, (const float *)f, L.d32, L.r32, &nf, st));
+            *rel_res_out = nf > 0 ? nr / nf : nr;
+        }
+        return HHG_OK;
+    }
+    return fail(c, HHG_EINVAL, "bad dtype");
+}
+
+hhg_status hhg_solve(hhg_ctx c, int32_t level, hhg_solve_mode mode, int32_t pre, int32_t post, double tol,
+                     int32_t max_iter, const double *f, double *u, hhg_solve_stats *stats, void *stream)
+{
+    TRY(check_level(c, level));
+    NEED_K(c);
+    if (!f || !u || f == u || max_iter < 0 || pre < 0 || post < 0) return fail(c, HHG_EINVAL, "bad arguments");
+    if (level < c->coarse) return fail(c, HHG_EINVAL, "level below the coarse level");
+    if (mode == HHG_SOLVE_LEARNED && !c->learned.ready) return fail(c, HHG_ESTATE, "no learned weights set");
+    hipStream_t st = pick(c, stream);
+    Level &L = c->lv[level];
+    HIPCHK(c, hipStreamSynchronize(st));
+    const auto t0 = std::chrono::steady_clock::now();
+    double nf = 0.0, nr = 0.0;
+    // |f| over the unknowns: residual of the zero vector
+    HIPCHK(c, launch_fill<double>(L.d64, 0.0, L.n_slots, st));
+    TRY(residual_t<double>(c, level, f, L.d64, L.r64, &nf, st));
+    if (!(nf > 0.0)) nf = 1.0;
+    std::vector<double> hist;
+    int fallback = 0;
+    bool use_learned = mode == HHG_SOLVE_LEARNED;
+    for (int it = 0;; ++it) {
+        TRY(residual_t<double>(c, level, f, u, L.r64, &nr, st));
+        hist.push_back(nr / nf);
+        if (!std::isfinite(nr)) break;
+        if (hist.back() <= tol || it >= max_iter) break;
+        // fallback: the learned cycle must keep contracting at least as well as
+        // the plain cycle's measured rate (taken from the first plain cycles)
+        if (use_learned && it >= 2) {
+            const double q = hist[it] / hist[it - 1];
+            if (!std::isfinite(q) || q > c->learned.fallback_rate) { use_learned = false; fallback = 1; }
+        }
+        if (mode == HHG_SOLVE_F64) {
+            TRY(vcycle_t<double>(c, level, f, u, pre, post, HHG_CHEBYSHEV, st));
+        } else {
+            HIPCHK(c, launch_convert<double, float>(L.r64, L.f32, L.n_slots, st));
+            HIPCHK(c, launch_fill<float>(L.u32, 0.0f, L.n_slots, st));
+            TRY(vcycle_t<float>(c, level, L.f32, L.u32, pre, post, use_learned ? HHG_LEARNED : HHG_CHEBYSHEV, st));
+            HIPCHK(c, launch_add_f32_to_f64(u, L.u32, L.n_slots, st));
+        }
+    }
+    HIPCHK(c, hipStreamSynchronize(st));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (stats) {
+        const int n = (int)hist.size() - 1;
+        stats->iterations = n;
+        stats->fallback = fallback;
+        stats->rel_residual = hist.back();
+        stats->seconds = secs;
+        if (n > 5) stats->rho = std::pow(hist[n] / hist[5], 1.0 / (n - 5));
+        else if (n > 0) stats->rho = std::pow(hist[n] / hist[0], 1.0 / n);
+        else stats->rho = 0.0;
+    }
+    return fallback ? HHG_WFALLBACK : HHG_OK;
+}
+
+hhg_status hhg_learned_set_weights(hhg_ctx c, const float *w, int64_t n)
+{
+    (void)w; (void)n;
+    return fail(c, HHG_ESTATE, "learned smoother not available");
+}
+hhg_status hhg_learned_forward(hhg_ctx c, int32_t level, const float *r, float *c_out, void *stream)
+{
+    (void)level; (void)r; (void)c_out; (void)stream;
+    return fail(c, HHG_ESTATE, "learned smoother not available");
+}
+hhg_status hhg_learned_backward(hhg_ctx c, int32_t level, const float *r, const float *g, float *dw,
+                                void *stream)
+{
+    (void)level; (void)r; (void)g; (void)dw; (void)stream;
+    return fail(c, HHG_ESTATE, "learned smoother not available");
+}
+
+}  // extern "C"

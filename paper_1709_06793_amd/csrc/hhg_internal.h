@@ -1,0 +1,101 @@
+// hhg_internal.h -- device-side views of one refinement level and the kernel
+// launchers the host driver calls.  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hhg {
+
+constexpr int BLOCK = 256;
+constexpr int KIND_STRIDE = 16;                // entries per (tet, kind) stencil row
+constexpr int TET_STENCIL = 16 * KIND_STRIDE;  // 16 kinds (15 used) per tet
+constexpr int TET_EMAT = 6 * 16;               // six 4x4 element matrices per tet
+
+// Everything a kernel needs about one level, for one precision T.
+template <typename T>
+struct LevelView {
+    int n;          // intervals per macro edge (2^level)
+    int n_tet;
+    int S;          // slots of one closed tet lattice
+    int64_t Spad;   // slots per tet in memory (multiple of 64)
+    int bpt;        // 256-slot blocks per tet
+    const T *sten;          // [tet][16 kinds][16]: entries 0..13 = half reference entry per direction
+    const T *emat;          // [tet][6 types][4][4]: element matrices / 4 (nodal kernel)
+    const T *rstw;          // [tet][16 kinds][16]: restriction weights (0..13 dirs, 14 centre)
+    const uint16_t *dmask;  // [tet]: bit = kind is on the Dirichlet boundary
+    const uint16_t *smask;  // [tet]: bit = kind is shared with another tet (not Dirichlet)
+    const T *kap;           // nodal coefficient, slot layout
+    // unique nodes on inter-tet primitives: copies of node q are
+    // sh_copy[sh_off[q] .. sh_off[q+1]) (packed tet, kind, i, j, k)
+    int n_shared;
+    const int32_t *sh_off;
+    const uint64_t *sh_copy;
+};
+
+// sparse corrections of the modification (Sec. 4.1) at one level
+template <typename T>
+struct CorrView {
+    int n_rows;               // corrected unique rows
+    const int32_t *c_off;     // corrections of row q: [c_off[q], c_off[q+1])
+    const int64_t *c_self;    // slot of the row's node in the edge's tet
+    const int64_t *c_nb;      // slot of the other end of the edge
+    const T *c_delta;         // (k_mod - k_e) * reference entry of the edge in that tet
+    const double *c_base;     // unmodified entry (k_e * reference entry), FP64
+    const uint8_t *c_nbdir;   // 1 if the other end is a Dirichlet node
+    const int32_t *p_off;     // copies of row q: [p_off[q], p_off[q+1])
+    const int64_t *p_slot;
+};
+
+// kernel launchers (hhg_kernels.hip); every launcher returns hipGetLastError()
+enum ApplyMode { MODE_APPLY = 0, MODE_RESID = 1 };
+
+template <typename T>
+hipError_t launch_scaled(const LevelView<T> &L, int mode, const T *u, const T *f, T *y,
+                         double *partial, int *n_partial, hipStream_t st);
+template <typename T>
+hipError_t launch_nodal(const LevelView<T> &L, const T *u, T *y, hipStream_t st);
+template <typename T>
+hipError_t launch_correction(const LevelView<T> &L, const CorrView<T> &C, int mode, const T *u,
+                             T *y, double *partial, hipStream_t st);
+// D (diagonal, not inverted) into d; per-slot Gershgorin absolute row sums
+// into asum (nullable); block maxima of the volume rows' ratios into partial
+// (n_partial of them); (asum, D) per shared node into gabs
+template <typename T>
+hipError_t launch_diag(const LevelView<T> &L, T *d, double *asum, double *partial, double *gabs,
+                       int *n_partial, hipStream_t st);
+hipError_t launch_reduce(const double *partial, int n, int op_max, double *out, hipStream_t st);
+
+template <typename T>
+hipError_t launch_invert_diag(T *d, int64_t n, hipStream_t st);
+template <typename T>
+hipError_t launch_jacobi_update(T *u, const T *r, const T *invd, T omega, int64_t n, hipStream_t st);
+template <typename T>
+hipError_t launch_cheb_update(T *u, T *dvec, const T *r, const T *invd, T c_old, T c_r,
+                              int64_t n, hipStream_t st);
+template <typename T>
+hipError_t launch_restrict(const LevelView<T> &Lc, const LevelView<T> &Lf, const T *rf, T *rc,
+                           hipStream_t st);
+template <typename T>
+hipError_t launch_prolong_add(const LevelView<T> &Lc, const LevelView<T> &Lf, const T *uc, T *uf,
+                              hipStream_t st);
+template <typename T>
+hipError_t launch_coarse_solve(const double *ainv, int nu, const int64_t *gather,
+                               const int32_t *copy_off, const int64_t *copy_slot, const T *f, T *u,
+                               hipStream_t st);
+template <typename T>
+hipError_t launch_fill(T *x, T v, int64_t n, hipStream_t st);
+template <typename Ti, typename To>
+hipError_t launch_convert(const Ti *in, To *out, int64_t n, hipStream_t st);
+hipError_t launch_add_f32_to_f64(double *u, const float *c, int64_t n, hipStream_t st);
+template <typename T>
+hipError_t launch_inject(const T *kf, int nf, T *kc, int nc, int n_tet, int64_t Spad_f,
+                         int64_t Spad_c, hipStream_t st);
+template <typename T>
+hipError_t launch_from_canonical(const T *canon, const int32_t *slot2canon, T *slots, int64_t n,
+                                 int keep_dirichlet, int S, int64_t Spad, hipStream_t st);
+template <typename T>
+hipError_t launch_to_canonical(const T *slots, const int64_t *canon2slot, T *canon, int64_t n,
+                               hipStream_t st);
+hipError_t launch_positive_check(const double *k, int64_t n, int *bad, hipStream_t st);
+
+}  // namespace hhg

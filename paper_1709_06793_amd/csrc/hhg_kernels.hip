@@ -1,0 +1,799 @@
+// hhg_kernels.hip -- HIP kernels for gfx950 (MI355X): scaled-stencil and
+// nodal-integration operator application on tetrahedral-index lattices,
+// residual norms, smoother updates, grid transfer and the coarse solve.
+//
+// Work decomposition.  Slot vectors hold one closed tet lattice per macro tet.
+// The "volume" kernels give one thread to one lattice slot: interior slots
+// compute their row from the 14 lattice neighbours, Dirichlet boundary slots
+// are written 0, and slots on primitives shared with other tets are left to
+// the "shared" kernels, which give one thread to one unique shared node and
+// sum the tet-restricted rows of all its copies, writing the result to every
+// copy.  Volume grids are remapped so that each of the 8 XCDs of the chip
+// walks one contiguous eighth of the slot range (neighbouring planes then hit
+// in that XCD's L2).
+#include <hip/hip_runtime.h>
+
+#include "hhg_internal.h"
+#include "hhg_lattice.h"
+
+namespace hhg {
+
+// ---------------------------------------------------------------- helpers
+__device__ __forceinline__ int tc32(int m) { return (m + 1) * (m + 2) * (m + 3) / 6; }
+__device__ __forceinline__ int tr32(int m) { return (m + 1) * (m + 2) / 2; }
+
+// (i,j,k) of slot s of a tet lattice with n intervals (n <= 1024)
+__device__ __forceinline__ void decode_slot(int n, int s, int &i, int &j, int &k)
+{
+    const int q = tc32(n) - s;  // slots in planes >= k, counted from the top
+    int m = (int)(cbrtf(6.0f * (float)q)) - 2;
+    m = m < 0 ? 0 : m;
+    while (tc32(m) < q) ++m;
+    while (m > 0 && tc32(m - 1) >= q) --m;
+    k = n - m;
+    const int t = s - (tc32(n) - tc32(m));
+    const int p = tr32(m) - t;
+    int r = (int)(sqrtf(2.0f * (float)p)) - 1;
+    r = r < 0 ? 0 : r;
+    while (tr32(r) < p) ++r;
+    while (r > 0 && tr32(r - 1) >= p) --r;
+    j = m - r;
+    i = t - (j * (m + 1) - j * (j - 1) / 2);
+}
+
+// slots of the 14 neighbours of slot s = (i,j,k), m = n-k, in DIR order
+__device__ __forceinline__ void neighbour_slots(int s, int j, int m, int nb[NDIR])
+{
+    const int rl = m - j + 1;          // length of row j in plane k
+    const int up = s + tr32(m) - j;    // (i, j, k+1)
+    const int dn = s - tr32(m + 1) + j;  // (i, j, k-1)
+    nb[0] = s + 1;                     // ( 1, 0, 0)
+    nb[1] = s + rl;                    // ( 0, 1, 0)
+    nb[2] = up;                        // ( 0, 0, 1)
+    nb[3] = s - rl - 1 + 1;            // ( 1,-1, 0): row j-1 has length rl+1
+    nb[4] = dn + 1;                    // ( 1, 0,-1)
+    nb[5] = dn + rl + 1;               // ( 0, 1,-1): row j of plane k-1 has length rl+1
+    nb[6] = up - rl + 1;               // ( 1,-1, 1): row j-1 of plane k+1 has length rl
+    nb[7] = s - 1;                     // (-1, 0, 0)
+    nb[8] = s - rl - 1;                // ( 0,-1, 0)
+    nb[9] = dn;                        // ( 0, 0,-1)
+    nb[10] = s + rl - 1;               // (-1, 1, 0)
+    nb[11] = up - 1;                   // (-1, 0, 1)
+    nb[12] = up - rl;                  // ( 0,-1, 1)
+    nb[13] = dn + rl;                  // (-1, 1,-1)
+}
+
+__device__ __forceinline__ int xcd_remap(int b, int grid)
+{
+    const int per = grid >> 3;  // grid is a multiple of 8
+    return (b & 7) * per + (b >> 3);
+}
+
+__device__ __forceinline__ double warp_sum(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double warp_max(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
+    return v;
+}
+// block-wide sum (op_max = 0) or max (op_max = 1); result valid in thread 0
+__device__ __forceinline__ double block_reduce(double v, int op_max)
+{
+    __shared__ double red[BLOCK / 64];
+    v = op_max ? warp_max(v) : warp_sum(v);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    if (l == 0) red[w] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 1; q < BLOCK / 64; ++q) v = op_max ? fmax(v, red[q]) : v + red[q];
+    }
+    return v;
+}
+
+static inline int volume_grid(int n_tet, int bpt)
+{
+    const int nb = n_tet * bpt;
+    return ((nb + 7) / 8) * 8;
+}
+
+static inline int blocks_for(int64_t n) { return (int)((n + BLOCK - 1) / BLOCK); }
+
+// element vertex directions: ELEM_DIR[t][a][b] = direction index of vertex b
+// of element shape t seen from its vertex a (14 when a == b)
+struct ElemDirTable {
+    int v[NTYPE][4][4];
+    constexpr ElemDirTable() : v()
+    {
+        for (int t = 0; t < NTYPE; ++t)
+            for (int a = 0; a < 4; ++a)
+                for (int b = 0; b < 4; ++b)
+                    v[t][a][b] = dir_index(TYPE_OFF[t][b][0] - TYPE_OFF[t][a][0],
+                                           TYPE_OFF[t][b][1] - TYPE_OFF[t][a][1],
+                                           TYPE_OFF[t][b][2] - TYPE_OFF[t][a][2]);
+    }
+};
+constexpr ElemDirTable ELEM_DIR{};
+
+// ---------------------------------------------------------------- scaled operator
+// y_i = sum_d w_d (k_i + k_{i+d}) (u_{i+d} - u_i), w_d = shat_d / 2 (Sec. 6.1,
+// difference form of Sec. 6.3).  MODE_RESID writes r = f - A u and one partial
+// sum of r^2 per block.
+template <typename T, int MODE>
+__global__ __launch_bounds__(BLOCK) void k_scaled_volume(LevelView<T> L, const T *__restrict__ u,
+                                                          const T *__restrict__ f,
+                                                          T *__restrict__ y,
+                                                          double *__restrict__ partial)
+{
+    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    double sq = 0.0;
+    if (lb < L.n_tet * L.bpt) {
+        const int tet = lb / L.bpt;
+        const int s = (lb - tet * L.bpt) * BLOCK + threadIdx.x;
+        if (s < L.S) {
+            const int64_t base = (int64_t)tet * L.Spad;
+            int i, j, k;
+            decode_slot(L.n, s, i, j, k);
+            if (i == 0 || j == 0 || k == 0 || i + j + k == L.n) {
+                const int zp = zero_pattern(L.n, i, j, k);
+                if ((L.dmask[tet] >> zp) & 1) y[base + s] = T(0);
+            } else {
+                const T *__restrict__ ub = u + base;
+                const T *__restrict__ kb = L.kap + base;
+                const T *__restrict__ w = L.sten + (int64_t)tet * TET_STENCIL;  // kind 0
+                int nb[NDIR];
+                neighbour_slots(s, j, L.n - k, nb);
+                const T u0 = ub[s], k0 = kb[s];
+                T acc = T(0);
+#pragma unroll
+                for (int d = 0; d < NDIR; ++d) acc += w[d] * (k0 + kb[nb[d]]) * (ub[nb[d]] - u0);
+                if (MODE == MODE_APPLY) {
+                    y[base + s] = acc;
+                } else {
+                    const T r = f[base + s] - acc;
+                    y[base + s] = r;
+                    sq = (double)r * (double)r;
+                }
+            }
+        }
+    }
+    if (MODE == MODE_RESID) {
+        sq = block_reduce(sq, 0);
+        if (threadIdx.x == 0) partial[blockIdx.x] = sq;
+    }
+}
+
+// rows of nodes on primitives shared by several tets: sum of the tet-restricted
+// scaled stencils of all copies (Sec. 2.2: one stencil per primitive and tet)
+template <typename T, int MODE>
+__global__ __launch_bounds__(BLOCK) void k_scaled_shared(LevelView<T> L, const T *__restrict__ u,
+                                                          const T *__restrict__ f,
+                                                          T *__restrict__ y,
+                                                          double *__restrict__ partial)
+{
+    const int q = blockIdx.x * BLOCK + threadIdx.x;
+    double sq = 0.0;
+    if (q < L.n_shared) {
+        T acc = T(0);
+        int64_t self = 0;
+        for (int c = L.sh_off[q]; c < L.sh_off[q + 1]; ++c) {
+            int tet, kind, i, j, k;
+            unpack_copy(L.sh_copy[c], tet, kind, i, j, k);
+            const int64_t base = (int64_t)tet * L.Spad;
+            const int s = (int)slot_of(L.n, i, j, k);
+            self = base + s;
+            int nb[NDIR];
+            neighbour_slots(s, j, L.n - k, nb);
+            const T *w = L.sten + (int64_t)tet * TET_STENCIL + kind * KIND_STRIDE;
+            const T u0 = u[base + s], k0 = L.kap[base + s];
+            for (int d = 0; d < NDIR; ++d) {
+                const T wd = w[d];
+                if (wd != T(0)) acc += wd * (k0 + L.kap[base + nb[d]]) * (u[base + nb[d]] - u0);
+            }
+        }
+        T out = acc;
+        if (MODE == MODE_RESID) {
+            out = f[self] - acc;
+            sq = (double)out * (double)out;
+        }
+        for (int c = L.sh_off[q]; c < L.sh_off[q + 1]; ++c) {
+            int tet, kind, i, j, k;
+            unpack_copy(L.sh_copy[c], tet, kind, i, j, k);
+            y[(int64_t)tet * L.Spad + slot_of(L.n, i, j, k)] = out;
+        }
+    }
+    if (MODE == MODE_RESID) {
+        sq = block_reduce(sq, 0);
+        if (threadIdx.x == 0) partial[blockIdx.x] = sq;
+    }
+}
+
+template <typename T>
+hipError_t launch_scaled(const LevelView<T> &L, int mode, const T *u, const T *f, T *y,
+                         double *partial, int *n_partial, hipStream_t st)
+{
+    const int gv = volume_grid(L.n_tet, L.bpt);
+    const int gs = blocks_for(L.n_shared);
+    if (mode == MODE_APPLY) {
+        k_scaled_volume<T, MODE_APPLY><<<gv, BLOCK, 0, st>>>(L, u, f, y, partial);
+        if (gs) k_scaled_shared<T, MODE_APPLY><<<gs, BLOCK, 0, st>>>(L, u, f, y, partial);
+    } else {
+        k_scaled_volume<T, MODE_RESID><<<gv, BLOCK, 0, st>>>(L, u, f, y, partial);
+        if (gs) k_scaled_shared<T, MODE_RESID><<<gs, BLOCK, 0, st>>>(L, u, f, y, partial + gv);
+        if (n_partial) *n_partial = gv + gs;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- nodal integration
+// y_i = sum_{t containing i} kbar_t sum_b A_t[i,b] (u_b - u_i), kbar_t the mean
+// of k at t's vertices (eq. (standardfe)); the 24 elements around an interior
+// node are the six shapes at the four bases that make i one of their vertices.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_nodal_volume(LevelView<T> L, const T *__restrict__ u,
+                                                         T *__restrict__ y)
+{
+    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    if (lb >= L.n_tet * L.bpt) return;
+    const int tet = lb / L.bpt;
+    const int s = (lb - tet * L.bpt) * BLOCK + threadIdx.x;
+    if (s >= L.S) return;
+    const int64_t base = (int64_t)tet * L.Spad;
+    int i, j, k;
+    decode_slot(L.n, s, i, j, k);
+    if (i == 0 || j == 0 || k == 0 || i + j + k == L.n) {
+        const int zp = zero_pattern(L.n, i, j, k);
+        if ((L.dmask[tet] >> zp) & 1) y[base + s] = T(0);
+        return;
+    }
+    const T *__restrict__ ub = u + base;
+    const T *__restrict__ kb = L.kap + base;
+    const T *__restrict__ E = L.emat + (int64_t)tet * TET_EMAT;  // element matrices / 4
+    int nb[NDIR];
+    neighbour_slots(s, j, L.n - k, nb);
+    T du[NDIR + 1], kk[NDIR + 1];
+    const T u0 = ub[s];
+#pragma unroll
+    for (int d = 0; d < NDIR; ++d) {
+        du[d] = ub[nb[d]] - u0;
+        kk[d] = kb[nb[d]];
+    }
+    du[NDIR] = T(0);
+    kk[NDIR] = kb[s];
+    T acc = T(0);
+#pragma unroll
+    for (int t = 0; t < NTYPE; ++t)
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const int d0 = ELEM_DIR.v[t][a][0], d1 = ELEM_DIR.v[t][a][1];
+            const int d2 = ELEM_DIR.v[t][a][2], d3 = ELEM_DIR.v[t][a][3];
+            const T ks = (kk[d0] + kk[d1]) + (kk[d2] + kk[d3]);
+            const T *e = E + t * 16 + a * 4;
+            const T sv = e[0] * du[d0] + e[1] * du[d1] + e[2] * du[d2] + e[3] * du[d3];
+            acc += ks * sv;
+        }
+    y[base + s] = acc;
+}
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_nodal_shared(LevelView<T> L, const T *__restrict__ u,
+                                                         T *__restrict__ y)
+{
+    const int q = blockIdx.x * BLOCK + threadIdx.x;
+    if (q >= L.n_shared) return;
+    T acc = T(0);
+    for (int c = L.sh_off[q]; c < L.sh_off[q + 1]; ++c) {
+        int tet, kind, i, j, k;
+        unpack_copy(L.sh_copy[c], tet, kind, i, j, k);
+        const int64_t base = (int64_t)tet * L.Spad;
+        const T *E = L.emat + (int64_t)tet * TET_EMAT;
+        const T u0 = u[base + slot_of(L.n, i, j, k)];
+        for (int t = 0; t < NTYPE; ++t)
+            for (int a = 0; a < 4; ++a) {
+                // element of shape t whose vertex a is this node
+                const int bi = i - TYPE_OFF[t][a][0], bj = j - TYPE_OFF[t][a][1],
+                          bk = k - TYPE_OFF[t][a][2];
+                bool ok = true;
+                for (int v = 0; v < 4; ++v)
+                    ok = ok && in_lattice(L.n, bi + TYPE_OFF[t][v][0], bj + TYPE_OFF[t][v][1],
+                                          bk + TYPE_OFF[t][v][2]);
+                if (!ok) continue;
+                T ks = T(0), sv = T(0);
+                for (int v = 0; v < 4; ++v) {
+                    const int64_t sl = base + slot_of(L.n, bi + TYPE_OFF[t][v][0],
+                                                      bj + TYPE_OFF[t][v][1],
+                                                      bk + TYPE_OFF[t][v][2]);
+                    ks += L.kap[sl];
+                    sv += E[t * 16 + a * 4 + v] * (u[sl] - u0);
+                }
+                acc += ks * sv;
+            }
+    }
+    for (int c = L.sh_off[q]; c < L.sh_off[q + 1]; ++c) {
+        int tet, kind, i, j, k;
+        unpack_copy(L.sh_copy[c], tet, kind, i, j, k);
+        y[(int64_t)tet * L.Spad + slot_of(L.n, i, j, k)] = acc;
+    }
+}
+
+template <typename T>
+hipError_t launch_nodal(const LevelView<T> &L, const T *u, T *y, hipStream_t st)
+{
+    k_nodal_volume<T><<<volume_grid(L.n_tet, L.bpt), BLOCK, 0, st>>>(L, u, y);
+    if (L.n_shared) k_nodal_shared<T><<<blocks_for(L.n_shared), BLOCK, 0, st>>>(L, u, y);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- modification
+// Row q gets sum_c delta_c (u_nb - u_self) added (MODE_APPLY) or subtracted
+// from the residual (MODE_RESID, with the change of r^2 per block).
+template <typename T, int MODE>
+__global__ __launch_bounds__(BLOCK) void k_correction(CorrView<T> C, const T *__restrict__ u,
+                                                      T *__restrict__ y,
+                                                      double *__restrict__ partial)
+{
+    const int q = blockIdx.x * BLOCK + threadIdx.x;
+    double dsq = 0.0;
+    if (q < C.n_rows) {
+        T acc = T(0);
+        for (int c = C.c_off[q]; c < C.c_off[q + 1]; ++c)
+            acc += C.c_delta[c] * (u[C.c_nb[c]] - u[C.c_self[c]]);
+        const T old = y[C.p_slot[C.p_off[q]]];
+        const T nw = MODE == MODE_APPLY ? old + acc : old - acc;
+        for (int p = C.p_off[q]; p < C.p_off[q + 1]; ++p) y[C.p_slot[p]] = nw;
+        dsq = (double)nw * (double)nw - (double)old * (double)old;
+    }
+    if (MODE == MODE_RESID) {
+        dsq = block_reduce(dsq, 0);
+        if (threadIdx.x == 0) partial[blockIdx.x] = dsq;
+    }
+}
+
+template <typename T>
+hipError_t launch_correction(const LevelView<T> &L, const CorrView<T> &C, int mode, const T *u,
+                             T *y, double *partial, hipStream_t st)
+{
+    (void)L;
+    if (!C.n_rows) return hipSuccess;
+    if (mode == MODE_APPLY)
+        k_correction<T, MODE_APPLY><<<blocks_for(C.n_rows), BLOCK, 0, st>>>(C, u, y, partial);
+    else
+        k_correction<T, MODE_RESID><<<blocks_for(C.n_rows), BLOCK, 0, st>>>(C, u, y, partial);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- diagonal
+// D_i = -sum_d w_d (k_i + k_{i+d}); per row the Gershgorin ratio
+// 1 + sum over tets and directions of |entry| / D_i (entries to Dirichlet
+// nodes excluded); block maxima go to `partial`.
+__device__ __forceinline__ bool is_dirichlet(const uint16_t *dmask, int tet, int n, int i, int j, int k)
+{
+    return (dmask[tet] >> zero_pattern(n, i, j, k)) & 1;
+}
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_diag_volume(LevelView<T> L, T *__restrict__ dout,
+                                                        double *__restrict__ asum_out,
+                                                        double *__restrict__ partial)
+{
+    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    double g = 0.0;
+    if (lb < L.n_tet * L.bpt) {
+        const int tet = lb / L.bpt;
+        const int s = (lb - tet * L.bpt) * BLOCK + threadIdx.x;
+        if (s < L.S) {
+            const int64_t base = (int64_t)tet * L.Spad;
+            int i, j, k;
+            decode_slot(L.n, s, i, j, k);
+            if (i == 0 || j == 0 || k == 0 || i + j + k == L.n) {
+                if (is_dirichlet(L.dmask, tet, L.n, i, j, k)) dout[base + s] = T(0);
+            } else {
+                const T *w = L.sten + (int64_t)tet * TET_STENCIL;
+                int nb[NDIR];
+                neighbour_slots(s, j, L.n - k, nb);
+                const double k0 = (double)L.kap[base + s];
+                double dsum = 0.0, asum = 0.0;
+                for (int d = 0; d < NDIR; ++d) {
+                    const double e = (double)w[d] * (k0 + (double)L.kap[base + nb[d]]);
+                    dsum -= e;
+                    if (!is_dirichlet(L.dmask, tet, L.n, i + DIR[d][0], j + DIR[d][1], k + DIR[d][2]))
+                        asum += fabs(e);
+                }
+                dout[base + s] = (T)dsum;
+                if (asum_out) asum_out[base + s] = asum;
+                g = 1.0 + asum / dsum;
+            }
+        }
+    }
+    g = block_reduce(g, 1);
+    if (threadIdx.x == 0) partial[blockIdx.x] = g;
+}
+
+// shared rows: D and the Gershgorin absolute row sum (sum over copies and
+// directions) into every copy, and (asum, D) per shared node into gabs
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_diag_shared(LevelView<T> L, T *__restrict__ dout,
+                                                        double *__restrict__ asum_out,
+                                                        double *__restrict__ gabs)
+{
+    const int q = blockIdx.x * BLOCK + threadIdx.x;
+    if (q >= L.n_shared) return;
+    double dsum = 0.0, asum = 0.0;
+    for (int c = L.sh_off[q]; c < L.sh_off[q + 1]; ++c) {
+        int tet, kind, i, j, k;
+        unpack_copy(L.sh_copy[c], tet, kind, i, j, k);
+        const int64_t base = (int64_t)tet * L.Spad;
+        const int s = (int)slot_of(L.n, i, j, k);
+        int nb[NDIR];
+        neighbour_slots(s, j, L.n - k, nb);
+        const T *w = L.sten + (int64_t)tet * TET_STENCIL + kind * KIND_STRIDE;
+        const double k0 = (double)L.kap[base + s];
+        for (int d = 0; d < NDIR; ++d) {
+            if (w[d] == T(0)) continue;
+            const double e = (double)w[d] * (k0 + (double)L.kap[base + nb[d]]);
+            dsum -= e;
+            if (!is_dirichlet(L.dmask, tet, L.n, i + DIR[d][0], j + DIR[d][1], k + DIR[d][2]))
+                asum += fabs(e);
+        }
+    }
+    for (int c = L.sh_off[q]; c < L.sh_off[q + 1]; ++c) {
+        int tet, kind, i, j, k;
+        unpack_copy(L.sh_copy[c], tet, kind, i, j, k);
+        const int64_t sl = (int64_t)tet * L.Spad + slot_of(L.n, i, j, k);
+        dout[sl] = (T)dsum;
+        if (asum_out) asum_out[sl] = asum;
+    }
+    gabs[2 * q] = asum;
+    gabs[2 * q + 1] = dsum;
+}
+
+template <typename T>
+hipError_t launch_diag(const LevelView<T> &L, T *d, double *asum, double *partial, double *gabs,
+                       int *n_partial, hipStream_t st)
+{
+    const int gv = volume_grid(L.n_tet, L.bpt);
+    k_diag_volume<T><<<gv, BLOCK, 0, st>>>(L, d, asum, partial);
+    if (L.n_shared) k_diag_shared<T><<<blocks_for(L.n_shared), BLOCK, 0, st>>>(L, d, asum, gabs);
+    *n_partial = gv;
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- reductions
+__global__ __launch_bounds__(BLOCK) void k_reduce(const double *__restrict__ p, int n, int op_max,
+                                                  double *__restrict__ out)
+{
+    double v = op_max ? -1e300 : 0.0;
+    for (int q = threadIdx.x; q < n; q += BLOCK) v = op_max ? fmax(v, p[q]) : v + p[q];
+    v = block_reduce(v, op_max);
+    if (threadIdx.x == 0) *out = v;
+}
+
+hipError_t launch_reduce(const double *partial, int n, int op_max, double *out, hipStream_t st)
+{
+    k_reduce<<<1, BLOCK, 0, st>>>(partial, n, op_max, out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- vector updates
+template <typename T>
+__global__ void k_invert(T *d, int64_t n)
+{
+    const int64_t q = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (q < n) d[q] = d[q] != T(0) ? T(1) / d[q] : T(0);
+}
+template <typename T>
+hipError_t launch_invert_diag(T *d, int64_t n, hipStream_t st)
+{
+    k_invert<T><<<blocks_for(n), BLOCK, 0, st>>>(d, n);
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ void k_jacobi(T *__restrict__ u, const T *__restrict__ r, const T *__restrict__ invd,
+                         T omega, int64_t n)
+{
+    const int64_t q = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (q < n) u[q] += omega * invd[q] * r[q];
+}
+template <typename T>
+hipError_t launch_jacobi_update(T *u, const T *r, const T *invd, T omega, int64_t n, hipStream_t st)
+{
+    k_jacobi<T><<<blocks_for(n), BLOCK, 0, st>>>(u, r, invd, omega, n);
+    return hipGetLastError();
+}
+
+// Chebyshev step: d <- c_old d + c_r D^{-1} r ; u <- u + d
+template <typename T>
+__global__ void k_cheb(T *__restrict__ u, T *__restrict__ dv, const T *__restrict__ r,
+                       const T *__restrict__ invd, T c_old, T c_r, int64_t n)
+{
+    const int64_t q = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (q < n) {
+        const T d = (c_old != T(0) ? c_old * dv[q] : T(0)) + c_r * invd[q] * r[q];
+        dv[q] = d;
+        u[q] += d;
+    }
+}
+template <typename T>
+hipError_t launch_cheb_update(T *u, T *dvec, const T *r, const T *invd, T c_old, T c_r,
+                              int64_t n, hipStream_t st)
+{
+    k_cheb<T><<<blocks_for(n), BLOCK, 0, st>>>(u, dvec, r, invd, c_old, c_r, n);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- grid transfer
+// restriction = transpose of P1 interpolation: r_c(x) = r_f(2x) + 1/2 sum_d r_f(2x+d)
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_restrict_volume(LevelView<T> Lc, LevelView<T> Lf,
+                                                            const T *__restrict__ rf,
+                                                            T *__restrict__ rc)
+{
+    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    if (lb >= Lc.n_tet * Lc.bpt) return;
+    const int tet = lb / Lc.bpt;
+    const int s = (lb - tet * Lc.bpt) * BLOCK + threadIdx.x;
+    if (s >= Lc.S) return;
+    int i, j, k;
+    decode_slot(Lc.n, s, i, j, k);
+    const int64_t bc = (int64_t)tet * Lc.Spad;
+    if (i == 0 || j == 0 || k == 0 || i + j + k == Lc.n) {
+        if (is_dirichlet(Lc.dmask, tet, Lc.n, i, j, k)) rc[bc + s] = T(0);
+        return;
+    }
+    const T *__restrict__ fb = rf + (int64_t)tet * Lf.Spad;
+    const int sf = (int)slot_of(Lf.n, 2 * i, 2 * j, 2 * k);
+    int nb[NDIR];
+    neighbour_slots(sf, 2 * j, Lf.n - 2 * k, nb);
+    T acc = T(0);
+#pragma unroll
+    for (int d = 0; d < NDIR; ++d) acc += fb[nb[d]];
+    rc[bc + s] = fb[sf] + T(0.5) * acc;
+}
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_restrict_shared(LevelView<T> Lc, LevelView<T> Lf,
+                                                            const T *__restrict__ rf,
+                                                            T *__restrict__ rc)
+{
+    const int q = blockIdx.x * BLOCK + threadIdx.x;
+    if (q >= Lc.n_shared) return;
+    T acc = T(0);
+    for (int c = Lc.sh_off[q]; c < Lc.sh_off[q + 1]; ++c) {
+        int tet, kind, i, j, k;
+        unpack_copy(Lc.sh_copy[c], tet, kind, i, j, k);
+        const T *fb = rf + (int64_t)tet * Lf.Spad;
+        const T *w = Lc.rstw + (int64_t)tet * TET_STENCIL + kind * KIND_STRIDE;
+        const int sf = (int)slot_of(Lf.n, 2 * i, 2 * j, 2 * k);
+        int nb[NDIR];
+        neighbour_slots(sf, 2 * j, Lf.n - 2 * k, nb);
+        acc += w[NDIR] * fb[sf];
+        for (int d = 0; d < NDIR; ++d)
+            if (w[d] != T(0)) acc += w[d] * fb[nb[d]];
+    }
+    for (int c = Lc.sh_off[q]; c < Lc.sh_off[q + 1]; ++c) {
+        int tet, kind, i, j, k;
+        unpack_copy(Lc.sh_copy[c], tet, kind, i, j, k);
+        rc[(int64_t)tet * Lc.Spad + slot_of(Lc.n, i, j, k)] = acc;
+    }
+}
+
+template <typename T>
+hipError_t launch_restrict(const LevelView<T> &Lc, const LevelView<T> &Lf, const T *rf, T *rc,
+                           hipStream_t st)
+{
+    k_restrict_volume<T><<<volume_grid(Lc.n_tet, Lc.bpt), BLOCK, 0, st>>>(Lc, Lf, rf, rc);
+    if (Lc.n_shared) k_restrict_shared<T><<<blocks_for(Lc.n_shared), BLOCK, 0, st>>>(Lc, Lf, rf, rc);
+    return hipGetLastError();
+}
+
+// P1 interpolation and add: a fine node with all-even lattice coordinates is a
+// coarse node; any other fine node is the midpoint of the coarse edge whose
+// direction has the same parity pattern.
+__constant__ int PARITY_DIR[8][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {1, -1, 0},
+                                     {0, 0, 1}, {1, 0, -1}, {0, 1, -1}, {1, -1, 1}};
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_prolong_add(LevelView<T> Lc, LevelView<T> Lf,
+                                                        const T *__restrict__ uc,
+                                                        T *__restrict__ uf)
+{
+    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    if (lb >= Lf.n_tet * Lf.bpt) return;
+    const int tet = lb / Lf.bpt;
+    const int s = (lb - tet * Lf.bpt) * BLOCK + threadIdx.x;
+    if (s >= Lf.S) return;
+    int i, j, k;
+    decode_slot(Lf.n, s, i, j, k);
+    const T *__restrict__ cb = uc + (int64_t)tet * Lc.Spad;
+    const int p = (i & 1) | ((j & 1) << 1) | ((k & 1) << 2);
+    T v;
+    if (p == 0) {
+        v = cb[slot_of(Lc.n, i >> 1, j >> 1, k >> 1)];
+    } else {
+        const int di = PARITY_DIR[p][0], dj = PARITY_DIR[p][1], dk = PARITY_DIR[p][2];
+        const T a = cb[slot_of(Lc.n, (i - di) >> 1, (j - dj) >> 1, (k - dk) >> 1)];
+        const T b = cb[slot_of(Lc.n, (i + di) >> 1, (j + dj) >> 1, (k + dk) >> 1)];
+        v = T(0.5) * (a + b);
+    }
+    uf[(int64_t)tet * Lf.Spad + s] += v;
+}
+
+template <typename T>
+hipError_t launch_prolong_add(const LevelView<T> &Lc, const LevelView<T> &Lf, const T *uc, T *uf,
+                              hipStream_t st)
+{
+    k_prolong_add<T><<<volume_grid(Lf.n_tet, Lf.bpt), BLOCK, 0, st>>>(Lc, Lf, uc, uf);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- coarse solve
+// u[copies of row r] = sum_c Ainv[r][c] f[gather[c]] in FP64 (u zeroed before)
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_coarse(const double *__restrict__ ainv, int nu,
+                                                   const int64_t *__restrict__ gather,
+                                                   const int32_t *__restrict__ coff,
+                                                   const int64_t *__restrict__ cslot,
+                                                   const T *__restrict__ f, T *__restrict__ u)
+{
+    const int r = blockIdx.x * BLOCK + threadIdx.x;
+    if (r >= nu) return;
+    double acc = 0.0;
+    const double *row = ainv + (int64_t)r * nu;
+    for (int c = 0; c < nu; ++c) acc += row[c] * (double)f[gather[c]];
+    for (int p = coff[r]; p < coff[r + 1]; ++p) u[cslot[p]] = (T)acc;
+}
+
+template <typename T>
+hipError_t launch_coarse_solve(const double *ainv, int nu, const int64_t *gather,
+                               const int32_t *copy_off, const int64_t *copy_slot, const T *f, T *u,
+                               hipStream_t st)
+{
+    k_coarse<T><<<blocks_for(nu), BLOCK, 0, st>>>(ainv, nu, gather, copy_off, copy_slot, f, u);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- misc
+template <typename T>
+__global__ void k_fill(T *x, T v, int64_t n)
+{
+    const int64_t q = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (q < n) x[q] = v;
+}
+template <typename T>
+hipError_t launch_fill(T *x, T v, int64_t n, hipStream_t st)
+{
+    if (n > 0) k_fill<T><<<blocks_for(n), BLOCK, 0, st>>>(x, v, n);
+    return hipGetLastError();
+}
+
+template <typename Ti, typename To>
+__global__ void k_convert(const Ti *__restrict__ in, To *__restrict__ out, int64_t n)
+{
+    const int64_t q = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (q < n) out[q] = (To)in[q];
+}
+template <typename Ti, typename To>
+hipError_t launch_convert(const Ti *in, To *out, int64_t n, hipStream_t st)
+{
+    k_convert<Ti, To><<<blocks_for(n), BLOCK, 0, st>>>(in, out, n);
+    return hipGetLastError();
+}
+
+__global__ void k_add_f32(double *__restrict__ u, const float *__restrict__ c, int64_t n)
+{
+    const int64_t q = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (q < n) u[q] += (double)c[q];
+}
+hipError_t launch_add_f32_to_f64(double *u, const float *c, int64_t n, hipStream_t st)
+{
+    k_add_f32<<<blocks_for(n), BLOCK, 0, st>>>(u, c, n);
+    return hipGetLastError();
+}
+
+// coarse nodes are the fine nodes with doubled lattice coordinates
+template <typename T>
+__global__ void k_inject(const T *__restrict__ kf, int nf, T *__restrict__ kc, int nc, int n_tet,
+                         int64_t Spad_f, int64_t Spad_c)
+{
+    const int S = tc32(nc);
+    const int64_t q = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (q >= (int64_t)S * n_tet) return;
+    const int tet = (int)(q / S), s = (int)(q - (int64_t)tet * S);
+    int i, j, k;
+    decode_slot(nc, s, i, j, k);
+    kc[tet * Spad_c + s] = kf[tet * Spad_f + slot_of(nf, 2 * i, 2 * j, 2 * k)];
+}
+template <typename T>
+hipError_t launch_inject(const T *kf, int nf, T *kc, int nc, int n_tet, int64_t Spad_f,
+                         int64_t Spad_c, hipStream_t st)
+{
+    k_inject<T><<<blocks_for((int64_t)tet_count(nc) * n_tet), BLOCK, 0, st>>>(kf, nf, kc, nc, n_tet,
+                                                                             Spad_f, Spad_c);
+    return hipGetLastError();
+}
+
+// map[q] = canonical node of slot q, or -(node+1) on a Dirichlet slot (then 0
+// is written unless keep_dirichlet); padding slots are not touched
+template <typename T>
+__global__ void k_from_canon(const T *__restrict__ canon, const int32_t *__restrict__ map,
+                             T *__restrict__ slots, int64_t n, int keep_dirichlet, int S,
+                             int64_t Spad)
+{
+    const int64_t q = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (q >= n || q % Spad >= S) return;
+    const int32_t c = map[q];
+    slots[q] = c >= 0 ? canon[c] : (keep_dirichlet ? canon[-c - 1] : T(0));
+}
+template <typename T>
+hipError_t launch_from_canonical(const T *canon, const int32_t *slot2canon, T *slots, int64_t n,
+                                 int keep_dirichlet, int S, int64_t Spad, hipStream_t st)
+{
+    k_from_canon<T><<<blocks_for(n), BLOCK, 0, st>>>(canon, slot2canon, slots, n, keep_dirichlet, S,
+                                                     Spad);
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ void k_to_canon(const T *__restrict__ slots, const int64_t *__restrict__ map,
+                           T *__restrict__ canon, int64_t n)
+{
+    const int64_t q = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (q < n) canon[q] = slots[map[q]];
+}
+template <typename T>
+hipError_t launch_to_canonical(const T *slots, const int64_t *canon2slot, T *canon, int64_t n,
+                               hipStream_t st)
+{
+    k_to_canon<T><<<blocks_for(n), BLOCK, 0, st>>>(slots, canon2slot, canon, n);
+    return hipGetLastError();
+}
+
+__global__ void k_positive(const double *__restrict__ k, int64_t n, int *bad)
+{
+    const int64_t q = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (q < n && !(k[q] > 0.0 && k[q] < 1e300)) atomicOr(bad, 1);
+}
+hipError_t launch_positive_check(const double *k, int64_t n, int *bad, hipStream_t st)
+{
+    k_positive<<<blocks_for(n), BLOCK, 0, st>>>(k, n, bad);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- instantiations
+#define HHG_INST(T)                                                                               \
+    template hipError_t launch_scaled<T>(const LevelView<T> &, int, const T *, const T *, T *,     \
+                                         double *, int *, hipStream_t);                            \
+    template hipError_t launch_nodal<T>(const LevelView<T> &, const T *, T *, hipStream_t);        \
+    template hipError_t launch_correction<T>(const LevelView<T> &, const CorrView<T> &, int,       \
+                                             const T *, T *, double *, hipStream_t);               \
+    template hipError_t launch_diag<T>(const LevelView<T> &, T *, double *, double *, double *,    \
+                                       int *, hipStream_t);                                        \
+    template hipError_t launch_invert_diag<T>(T *, int64_t, hipStream_t);                          \
+    template hipError_t launch_jacobi_update<T>(T *, const T *, const T *, T, int64_t,             \
+                                                hipStream_t);                                      \
+    template hipError_t launch_cheb_update<T>(T *, T *, const T *, const T *, T, T, int64_t,       \
+                                              hipStream_t);                                        \
+    template hipError_t launch_restrict<T>(const LevelView<T> &, const LevelView<T> &, const T *,  \
+                                           T *, hipStream_t);                                      \
+    template hipError_t launch_prolong_add<T>(const LevelView<T> &, const LevelView<T> &,          \
+                                              const T *, T *, hipStream_t);                        \
+    template hipError_t launch_coarse_solve<T>(const double *, int, const int64_t *,               \
+                                               const int32_t *, const int64_t *, const T *, T *,   \
+                                               hipStream_t);                                       \
+    template hipError_t launch_fill<T>(T *, T, int64_t, hipStream_t);                              \
+    template hipError_t launch_inject<T>(const T *, int, T *, int, int, int64_t, int64_t,          \
+                                         hipStream_t);                                             \
+    template hipError_t launch_from_canonical<T>(const T *, const int32_t *, T *, int64_t, int,    \
+                                                 int, int64_t, hipStream_t);                       \
+    template hipError_t launch_to_canonical<T>(const T *, const int64_t *, T *, int64_t,           \
+                                               hipStream_t);
+
+HHG_INST(double)
+HHG_INST(float)
+template hipError_t launch_convert<double, float>(const double *, float *, int64_t, hipStream_t);
+template hipError_t launch_convert<float, double>(const float *, double *, int64_t, hipStream_t);
+
+}  // namespace hhg

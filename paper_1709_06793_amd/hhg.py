@@ -1,0 +1,232 @@
+"""Python binding of libhhg (include/hhg.h): argument marshalling only.
+
+Every computation runs in the HIP library; this module converts numpy /
+torch arguments to pointers and sizes, passes the current torch stream, and
+turns error codes into exceptions.  PyTorch provides device memory and streams.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhhg.so")
+
+F64, F32 = 0, 1
+JACOBI, CHEBYSHEV, LEARNED = 0, 1, 2
+SOLVE_F64, SOLVE_MIXED, SOLVE_LEARNED = 0, 1, 2
+FLAG_NO_MODIFICATION = 1
+LEARNED_NPARAM = 801
+WFALLBACK = 1
+
+# every symbol include/hhg.h declares
+EXPORTS = [
+    "hhg_create_macro", "hhg_destroy", "hhg_last_error", "hhg_vector_size", "hhg_node_coords",
+    "hhg_to_canonical", "hhg_from_canonical", "hhg_set_coefficient", "hhg_set_coarse_level",
+    "hhg_level_info", "hhg_apply_scaled", "hhg_apply_nodal", "hhg_residual", "hhg_smooth",
+    "hhg_vcycle", "hhg_solve", "hhg_learned_set_weights", "hhg_learned_forward",
+    "hhg_learned_backward",
+]
+
+
+class HHGError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"hhg error {code}: {msg}")
+        self.code = code
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("fallback", ctypes.c_int32),
+                ("rel_residual", ctypes.c_double), ("rho", ctypes.c_double),
+                ("seconds", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load():
+    """Load the in-tree libhhg.so; fails loudly when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_1709_06793_amd.build.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, D, U32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_uint32
+    sig = {
+        "hhg_create_macro": [P, I32, P, I32, I32, U32, P, ctypes.POINTER(P)],
+        "hhg_destroy": [P],
+        "hhg_vector_size": [P, I32, P, P, P],
+        "hhg_node_coords": [P, I32, P, P],
+        "hhg_to_canonical": [P, I32, I32, P, P, P],
+        "hhg_from_canonical": [P, I32, I32, P, P, P],
+        "hhg_set_coefficient": [P, P, ctypes.c_int, P],
+        "hhg_set_coarse_level": [P, I32],
+        "hhg_level_info": [P, I32, P, P, P],
+        "hhg_apply_scaled": [P, I32, I32, P, P, P],
+        "hhg_apply_nodal": [P, I32, I32, P, P, P],
+        "hhg_residual": [P, I32, I32, P, P, P, P, P],
+        "hhg_smooth": [P, I32, I32, I32, I32, D, P, P, P],
+        "hhg_vcycle": [P, I32, I32, I32, I32, I32, P, P, P, P],
+        "hhg_solve": [P, I32, I32, I32, I32, D, I32, P, P, P, P],
+        "hhg_learned_set_weights": [P, P, I64],
+        "hhg_learned_forward": [P, I32, P, P, P],
+        "hhg_learned_backward": [P, I32, P, P, P, P],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = I32
+    L.hhg_last_error.argtypes = [P]
+    L.hhg_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _ptr(x):
+    """Device/host pointer of a torch tensor or numpy array (None -> NULL)."""
+    if x is None:
+        return None
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data_as(ctypes.c_void_p)
+    return ctypes.c_void_p(x.data_ptr())
+
+
+def _dtype_code(t):
+    import torch
+    if t.dtype == torch.float64:
+        return F64
+    if t.dtype == torch.float32:
+        return F32
+    raise TypeError("vectors must be float64 or float32 torch tensors")
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Context:
+    """One macro mesh with its refinement hierarchy on the current GPU."""
+
+    def __init__(self, X, T, max_level, flags=0):
+        L = load()
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        T = np.ascontiguousarray(T, dtype=np.int32)
+        self._h = ctypes.c_void_p()
+        s = L.hhg_create_macro(_ptr(X), X.shape[0], _ptr(T), T.shape[0], int(max_level), int(flags),
+                               None, ctypes.byref(self._h))
+        if s < 0:
+            raise HHGError(s, L.hhg_last_error(None).decode())
+        self.max_level = int(max_level)
+        self.X, self.T = X, T
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            load().hhg_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, s):
+        if s < 0:
+            raise HHGError(s, load().hhg_last_error(self._h).decode())
+        return s
+
+    # ---- sizes and layout
+    def sizes(self, level):
+        a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        self._check(load().hhg_vector_size(self._h, level, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return dict(n_slots=a.value, n_unknowns=b.value, n_nodes=c.value)
+
+    def node_coords(self, level):
+        n = self.sizes(level)["n_nodes"]
+        xyz = np.empty((n, 3))
+        d = np.empty(n, dtype=np.uint8)
+        self._check(load().hhg_node_coords(self._h, level, _ptr(xyz), _ptr(d)))
+        return xyz, d.astype(bool)
+
+    def vector(self, level, dtype=None, fill=0.0):
+        import torch
+        dtype = dtype or torch.float64
+        return torch.full((self.sizes(level)["n_slots"],), fill, dtype=dtype, device="cuda")
+
+    def to_canonical(self, level, v):
+        import torch
+        out = torch.empty(self.sizes(level)["n_nodes"], dtype=v.dtype, device=v.device)
+        self._check(load().hhg_to_canonical(self._h, level, _dtype_code(v), _ptr(v), _ptr(out), _stream()))
+        return out
+
+    def from_canonical(self, level, v):
+        import torch
+        out = torch.zeros(self.sizes(level)["n_slots"], dtype=v.dtype, device=v.device)
+        self._check(load().hhg_from_canonical(self._h, level, _dtype_code(v), _ptr(v), _ptr(out), _stream()))
+        return out
+
+    # ---- coefficient and solver data
+    def set_coefficient(self, k):
+        """Finest-level nodal k, canonical order (numpy float64 or a torch tensor)."""
+        if isinstance(k, np.ndarray):
+            k = np.ascontiguousarray(k, dtype=np.float64)
+            self._check(load().hhg_set_coefficient(self._h, _ptr(k), 0, _stream()))
+        else:
+            self._check(load().hhg_set_coefficient(self._h, _ptr(k), 1 if k.is_cuda else 0, _stream()))
+
+    def set_coarse_level(self, level):
+        self._check(load().hhg_set_coarse_level(self._h, level))
+
+    def level_info(self, level):
+        lam, nm, cl = ctypes.c_double(), ctypes.c_int64(), ctypes.c_int32()
+        self._check(load().hhg_level_info(self._h, level, ctypes.byref(lam), ctypes.byref(nm), ctypes.byref(cl)))
+        return dict(lambda_max=lam.value, n_modified=nm.value, coarse_level=cl.value)
+
+    # ---- operators
+    def apply_scaled(self, level, u, y):
+        self._check(load().hhg_apply_scaled(self._h, level, _dtype_code(u), _ptr(u), _ptr(y), _stream()))
+        return y
+
+    def apply_nodal(self, level, u, y):
+        self._check(load().hhg_apply_nodal(self._h, level, _dtype_code(u), _ptr(u), _ptr(y), _stream()))
+        return y
+
+    def residual(self, level, f, u, r, norm=False):
+        nv = ctypes.c_double()
+        self._check(load().hhg_residual(self._h, level, _dtype_code(u), _ptr(f), _ptr(u), _ptr(r),
+                                        ctypes.byref(nv) if norm else None, _stream()))
+        return nv.value if norm else r
+
+    def smooth(self, level, f, u, sweeps, smoother=JACOBI, omega=2.0 / 3.0):
+        self._check(load().hhg_smooth(self._h, level, _dtype_code(u), smoother, sweeps, omega,
+                                      _ptr(f), _ptr(u), _stream()))
+        return u
+
+    def vcycle(self, level, f, u, pre=2, post=2, smoother=CHEBYSHEV, rel_res=False):
+        rr = ctypes.c_double()
+        self._check(load().hhg_vcycle(self._h, level, _dtype_code(u), pre, post, smoother, _ptr(f),
+                                      _ptr(u), ctypes.byref(rr) if rel_res else None, _stream()))
+        return rr.value if rel_res else u
+
+    def solve(self, level, f, u, mode=SOLVE_F64, tol=1e-8, max_iter=100, pre=2, post=2):
+        st = SolveStats()
+        s = self._check(load().hhg_solve(self._h, level, mode, pre, post, tol, max_iter, _ptr(f), _ptr(u),
+                                         ctypes.byref(st), _stream()))
+        return dict(iterations=st.iterations, fallback=st.fallback, rel_residual=st.rel_residual,
+                    rho=st.rho, seconds=st.seconds, status=s)
+
+    # ---- learned correction
+    def learned_set_weights(self, w):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        self._check(load().hhg_learned_set_weights(self._h, _ptr(w), w.size))
+
+    def learned_forward(self, level, r, c_out):
+        self._check(load().hhg_learned_forward(self._h, level, _ptr(r), _ptr(c_out), _stream()))
+        return c_out
+
+    def learned_backward(self, level, r, g):
+        dw = np.zeros(LEARNED_NPARAM, dtype=np.float32)
+        self._check(load().hhg_learned_backward(self._h, level, _ptr(r), _ptr(g), _ptr(dw), _stream()))
+        return dw

@@ -1,0 +1,46 @@
+"""CPU-side checks of the boundary: the HIP library builds/loads and exports
+every symbol the public header declares; the binding lists exactly those."""
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_1709_06793_amd import hhg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_symbols():
+    src = open(os.path.join(ROOT, "include", "hhg.h")).read()
+    return sorted(set(re.findall(r"^\S.*?\b(hhg_[a-z_0-9]+)\s*\(", src, flags=re.M)))
+
+
+def test_header_and_binding_agree():
+    assert _header_symbols() == sorted(hhg.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(hhg.LIB_PATH):
+        pytest.skip("libhhg.so not built")
+    out = subprocess.run(["nm", "-D", "--defined-only", hhg.LIB_PATH], capture_output=True, text=True).stdout
+    names = {l.split()[-1] for l in out.splitlines() if l.strip()}
+    missing = [s for s in _header_symbols() if s not in names]
+    assert not missing, missing
+    L = hhg.load()
+    for s in _header_symbols():
+        assert hasattr(L, s)
+
+
+def test_create_rejects_bad_arguments_without_gpu_work():
+    """Argument checks run before any device call."""
+    if not os.path.exists(hhg.LIB_PATH):
+        pytest.skip("libhhg.so not built")
+    import numpy as np
+    X = np.zeros((4, 3))
+    T = np.array([[0, 1, 2, 7]], dtype=np.int32)   # vertex id out of range
+    with pytest.raises(hhg.HHGError) as e:
+        hhg.Context(X, T, 2)
+    assert e.value.code == -1
+    with pytest.raises(hhg.HHGError):
+        hhg.Context(X, np.array([[0, 1, 2, 3]], dtype=np.int32), 11)   # level out of range
