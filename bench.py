@@ -1,0 +1,272 @@
+"""Benchmark of the stencil-scaling hot path on one MI355X.
+
+One step = one application of the scaled-stencil operator (FP64) to one
+synthetic field on the unit macro tetrahedron at level 8 (2,731,135
+unknowns, lognormal k with sigma = 1, correlation length 0.1, seed 1).
+`value` is that apply's throughput in GDoF/s (unknowns per second).  The same
+run also reports, as context, the FP32 apply, the nodal-integration kernel,
+the HBM-resident 48-tet level-8 working set, multigrid time to a 1e-8
+relative residual (FP64 and FP32-in-FP64), the roofline of the dominant
+kernel, and the CPU oracle timed on this host.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "scaled-stencil matvec GDoF/s + %HBM peak; V-cycle time to 1e-8 rel. residual"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_DOF = {"f64": 24, "f32": 12}   # read u and k, write y (perfect neighbour reuse)
+PROFILE = os.path.join(ROOT, "profiles", "traffic_scaled_volume_f64_unit_tet_l8.txt")
+CSRC = os.path.join(ROOT, "paper_1709_06793_amd", "csrc")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".h")):
+            h.update(open(os.path.join(CSRC, name), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    if not os.path.exists(PROFILE):
+        return None
+    kv = {}
+    for line in open(PROFILE):
+        if ":" in line and not line.startswith("#"):
+            a, b = line.split(":", 1)
+            kv[a.strip()] = b.strip()
+    if kv.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def time_op(fn, steps, warmup, torch):
+    """Average ms per call over `steps` calls on the current stream (HIP events)."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def lognormal_on_device(xyz, prm, torch):
+    x = torch.tensor(xyz, dtype=torch.float64, device="cuda")
+    om = torch.tensor(prm["omega"], dtype=torch.float64, device="cuda")
+    ph = torch.tensor(prm["phi"], dtype=torch.float64, device="cuda")
+    g = torch.zeros(x.shape[0], dtype=torch.float64, device="cuda")
+    for a in range(0, x.shape[0], 1 << 24):
+        g[a:a + (1 << 24)] = torch.cos(x[a:a + (1 << 24)] @ om.T + ph).sum(dim=1)
+    M = om.shape[0]
+    return torch.exp(prm["sigma"] * np.sqrt(2.0 / M) * g)
+
+
+def cpu_baseline(level=7, seconds=8.0):
+    """The oracle as it stands on this host: CSR assembly of the scaled operator
+    on the unit tet at `level` (one eighth of the GPU workload at level 7), then
+    SpMV repeated for about `seconds`.  scipy's CSR SpMV uses one thread."""
+    from hhg_inputs import unit_tet, lognormal_params, lognormal_k
+    from oracle import oracle as O
+    X, T = unit_tet()
+    t0 = time.perf_counter()
+    m = O.Mesh(X, T, level)
+    prm = lognormal_params(1, 1.0, 0.1)
+    k = lognormal_k(m.xyz, prm)
+    op = O.make_operator(m, k, "scaled")
+    t_asm = time.perf_counter() - t0
+    x = np.random.default_rng(0).uniform(-1, 1, op.A.shape[0])
+    n = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        op.A @ x
+        n += 1
+    dt = (time.perf_counter() - t0) / n
+    nu = op.A.shape[0]
+    return {"value": nu / dt / 1e9, "unit": "GDoF/s", "cores": 1, "kind": "oracle",
+            "sample": f"unit tet level {level} ({nu} unknowns, 1/8 of the GPU workload): oracle CSR SpMV "
+                      f"(scipy, 1 thread), {n} reps; CSR assembly from k took {t_asm:.1f} s "
+                      f"({nu / t_asm / 1e9:.2e} GDoF/s if assembly is counted)",
+            "host_threads_available": os.cpu_count()}
+
+
+
+def kuhn48_applies(hhg, torch, steps, solves=True):
+    """HBM-resident working set: 48 Kuhn tets, level 8 (133M unknowns): apply
+    throughputs and, if asked, multigrid time to solution."""
+    from hhg_inputs import kuhn_cube_2x2x2, lognormal_params
+    level = 8
+    log("bench: 48-tet cube level 8")
+    X, T = kuhn_cube_2x2x2()
+    ctx = hhg.Context(X, T, level)
+    xyz, dirichlet = ctx.node_coords(level)
+    prm2 = lognormal_params(2, 1.5, 0.05)
+    k = lognormal_on_device(xyz, prm2, torch)
+    ctx.set_coefficient(k)
+    del k
+    sz = ctx.sizes(level)
+    nu48 = sz["n_unknowns"]
+    f = torch.tensor(prm2["rng"].uniform(-1, 1, xyz.shape[0]), device="cuda")
+    f[torch.tensor(dirichlet, device="cuda")] = 0.0
+    del xyz
+    f64 = ctx.from_canonical(level, f)
+    del f
+    y = ctx.vector(level)
+    steps48 = max(10, steps // 10)
+    m1 = time_op(lambda: ctx.apply_scaled(level, f64, y), steps48, 3, torch)
+    f32 = f64.float()
+    y32 = ctx.vector(level, torch.float32)
+    m2 = time_op(lambda: ctx.apply_scaled(level, f32, y32), steps48, 3, torch)
+    m3 = time_op(lambda: ctx.apply_nodal(level, f64, y), steps48, 3, torch)
+    m4 = time_op(lambda: ctx.apply_nodal(level, f32, y32), steps48, 3, torch)
+    del y32
+    out = {
+        "unknowns": nu48,
+        "scaled_f64_gdofs": round(nu48 / m1 / 1e6, 2),
+        "scaled_f64_hbm_frac": round(BYTES_PER_DOF["f64"] * nu48 / m1 / 1e6 / HBM_PEAK_GBS, 4),
+        "scaled_f32_gdofs": round(nu48 / m2 / 1e6, 2),
+        "scaled_f32_hbm_frac": round(BYTES_PER_DOF["f32"] * nu48 / m2 / 1e6 / HBM_PEAK_GBS, 4),
+        "nodal_f64_gdofs": round(nu48 / m3 / 1e6, 2),
+        "nodal_f32_gdofs": round(nu48 / m4 / 1e6, 2),
+        "note": "48 Kuhn macro tets (2x2x2 cubes), lognormal sigma 1.5, l_c 0.05, seed 2; "
+                "3.3 GB FP64 working set, HBM-resident"}
+    if solves:
+        res = {}
+        for name, mode, tol in (("f64", hhg.SOLVE_F64, 1e-8), ("mixed", hhg.SOLVE_MIXED, 1e-8),
+                                ("f64_1e-10", hhg.SOLVE_F64, 1e-10), ("mixed_1e-10", hhg.SOLVE_MIXED, 1e-10)):
+            uu = ctx.vector(level)
+            torch.cuda.synchronize()
+            st = ctx.solve(level, f64, uu, mode=mode, tol=tol, max_iter=200)
+            res[name] = {k2: (float(f"{v:.4g}") if isinstance(v, float) else v) for k2, v in st.items()}
+            log(f"bench: solve {name}: {st}")
+            del uu
+        out["vcycle_solves"] = res
+    del ctx, f64, y, f32
+    torch.cuda.empty_cache()
+    return out
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--quick", action="store_true", help="value only: skip the context measurements")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--k48-apply-only", action="store_true",
+                    help="only time the 48-tet level-8 applies (tuning runs)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a 1 GiB device copy (for HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    from hhg_inputs import unit_tet, kuhn_cube, kuhn_cube_2x2x2, lognormal_params, smooth_k
+    from paper_1709_06793_amd import hhg
+
+    torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": a.numel() * 8, "copy_bytes_written": a.numel() * 8}))
+        return
+
+    if args.k48_apply_only:
+        print(json.dumps(kuhn48_applies(hhg, torch, args.steps, solves=False)))
+        return
+
+    # ---------------- main workload: unit tet, level 8, lognormal k
+    level = 8
+    X, T = unit_tet()
+    log("bench: building unit tet level 8 context")
+    ctx = hhg.Context(X, T, level)
+    xyz, dirichlet = ctx.node_coords(level)
+    prm = lognormal_params(1, 1.0, 0.1)
+    k = lognormal_on_device(xyz, prm, torch)
+    u = torch.tensor(prm["rng"].uniform(-1, 1, xyz.shape[0]), device="cuda")
+    u[torch.tensor(dirichlet, device="cuda")] = 0.0
+    ctx.set_coefficient(k)
+    sz = ctx.sizes(level)
+    nu = sz["n_unknowns"]
+    u64 = ctx.from_canonical(level, u)
+    y64 = ctx.vector(level)
+    log(f"bench: unknowns {nu}, timing {args.steps} applies")
+    ms = time_op(lambda: ctx.apply_scaled(level, u64, y64), args.steps, args.warmup, torch)
+    value = nu / (ms * 1e-3) / 1e9
+    achieved = BYTES_PER_DOF["f64"] * nu / (ms * 1e-3) / 1e9
+    traffic = measured_traffic()
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "GDoF/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "unit macro tet (0,0,0),(1,0,0),(0,1,0),(0,0,1), level 8 "
+                               f"({sz['n_slots']} slots, {nu} unknowns), lognormal k (32 Fourier modes, "
+                               "sigma 1, correlation length 0.1, seed 1), u ~ U[-1,1]: one FP64 "
+                               "scaled-stencil apply per step",
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
+                     "kernel": "k_scaled_volume<double,APPLY> (the only kernel of this apply)",
+                     "algorithmic_bytes_per_launch": BYTES_PER_DOF["f64"] * nu},
+    }
+    extra = {}
+    if not args.quick:
+        # FP32 apply and the nodal-integration kernel on the same workload
+        u32 = u64.float()
+        y32 = ctx.vector(level, torch.float32)
+        ms32 = time_op(lambda: ctx.apply_scaled(level, u32, y32), args.steps, args.warmup, torch)
+        msn = time_op(lambda: ctx.apply_nodal(level, u64, y64), args.steps, args.warmup, torch)
+        msn32 = time_op(lambda: ctx.apply_nodal(level, u32, y32), args.steps, args.warmup, torch)
+        r64 = ctx.vector(level)
+        msr = time_op(lambda: ctx.residual(level, y64, u64, r64), args.steps, args.warmup, torch)
+        extra["unit_tet_l8"] = {
+            "scaled_f64_gdofs": round(value, 2), "scaled_f32_gdofs": round(nu / ms32 / 1e6, 2),
+            "nodal_f64_gdofs": round(nu / msn / 1e6, 2), "nodal_f32_gdofs": round(nu / msn32 / 1e6, 2),
+            "scaled_over_nodal_f64": round(msn / ms, 3), "scaled_over_nodal_f32": round(msn32 / ms32, 3),
+            "residual_f64_gdofs": round(nu / msr / 1e6, 2),
+            "scaled_f32_hbm_frac": round(BYTES_PER_DOF["f32"] * nu / ms32 / 1e6 / HBM_PEAK_GBS, 4),
+            "note": "working set (69 MB FP64) fits the 256 MB Infinity Cache"}
+        del ctx, u64, y64, u32, y32, r64
+        torch.cuda.empty_cache()
+
+        extra["kuhn48_l8"] = kuhn48_applies(hhg, torch, args.steps, solves=True)
+    out["extra"] = extra
+    if not args.no_cpu:
+        log("bench: CPU oracle baseline")
+        out["cpu_baseline"] = cpu_baseline()
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

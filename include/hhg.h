@@ -25,8 +25,9 @@
  *     for each macro tet t (input order) a closed tetrahedral lattice of
  *     (n+1)(n+2)(n+3)/6 slots, n = 2^level, padded to a multiple of 64 slots,
  *     slot of lattice point (i,j,k) (i,j,k >= 0, i+j+k <= n) inside tet t:
- *       S(n) - S(n-k) + j (n-k+1) - j (j-1)/2 + i,  S(m) = (m+1)(m+2)(m+3)/6,
- *     where (i,j,k) are the barycentric weights of t's vertices 1,2,3 times n.
+ *       S(n) - S(n-k) + (i+j)(i+j+1)/2 + i,  S(m) = (m+1)(m+2)(m+3)/6,
+ *     where (i,j,k) are the barycentric weights of t's vertices 1,2,3 times n
+ *     (planes k in turn, inside a plane the anti-diagonals i+j in turn).
  *     A node on a macro face/edge/vertex appears in every tet holding it; input
  *     vectors must hold the same value in all copies ("consistent"), and all
  *     outputs are consistent.  Dirichlet slots (nodes on the domain boundary)

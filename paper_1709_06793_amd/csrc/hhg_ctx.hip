@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -222,6 +223,12 @@ struct Level {
     double *sten64 = nullptr, *emat64 = nullptr, *rstw64 = nullptr;
     float *sten32 = nullptr, *emat32 = nullptr, *rstw32 = nullptr;
     uint16_t *dmask = nullptr, *smask = nullptr;
+    // column-marching work items and boundary slot list (same for every tet)
+    std::vector<uint32_t> h_items;  // pairs (t0, k0 | k1 << 16)
+    std::vector<uint32_t> h_bnd;
+    uint2 *items = nullptr;
+    uint32_t *bnd = nullptr;
+    int n_items = 0, n_bnd = 0, kc = 0;
     // shared nodes
     int n_shared = 0;
     std::vector<int32_t> h_sh_off;
@@ -441,6 +448,8 @@ LevelView<double> view<double>(const hhg_ctx c, int l)
     v.sten = L.sten64; v.emat = L.emat64; v.rstw = L.rstw64;
     v.dmask = L.dmask; v.smask = L.smask; v.kap = L.k64;
     v.n_shared = L.n_shared; v.sh_off = L.sh_off; v.sh_copy = L.sh_copy;
+    v.items = L.items; v.n_items = L.n_items; v.vpt = (L.n_items + 3) / 4;
+    v.bnd = L.bnd; v.n_bnd = L.n_bnd; v.bpt2 = (L.n_bnd + BLOCK - 1) / BLOCK;
     return v;
 }
 template <>
@@ -452,6 +461,8 @@ LevelView<float> view<float>(const hhg_ctx c, int l)
     v.sten = L.sten32; v.emat = L.emat32; v.rstw = L.rstw32;
     v.dmask = L.dmask; v.smask = L.smask; v.kap = L.k32;
     v.n_shared = L.n_shared; v.sh_off = L.sh_off; v.sh_copy = L.sh_copy;
+    v.items = L.items; v.n_items = L.n_items; v.vpt = (L.n_items + 3) / 4;
+    v.bnd = L.bnd; v.n_bnd = L.n_bnd; v.bpt2 = (L.n_bnd + BLOCK - 1) / BLOCK;
     return v;
 }
 
@@ -594,6 +605,63 @@ hhg_status build_level(hhg_ctx c, int l)
                 for (int s = 1; s + tt < L.n; ++s)
                     add_node({tp.faces[f][0], tp.faces[f][1], tp.faces[f][2]}, {L.n - s - tt, s, tt});
     L.n_shared = (int)L.h_sh_off.size() - 1;
+
+    // column-marching work items: waves over 62 in-plane offsets (plus one
+    // halo lane each side) and chunks of kc planes; kc is the largest of
+    // 32/16/8/4 that still gives about 8192 waves over all tets
+    {
+        const int n = L.n;
+        const int64_t T0 = tri_count(n);
+        auto diag_of = [](int64_t t) {
+            int64_t d = (int64_t)((std::sqrt(8.0 * (double)t + 1.0) - 1.0) / 2.0);
+            while ((d + 1) * (d + 2) / 2 <= t) ++d;
+            while (d > 0 && d * (d + 1) / 2 > t) --d;
+            return d;
+        };
+        std::vector<int> kcs = {32, 16, 8, 4};
+        if (const char *e = std::getenv("HHG_MARCH_KC")) {  // tuning override
+            const int v = std::atoi(e);
+            if (v >= 1 && v <= 1024) kcs = {v};
+        }
+        for (int kc : kcs) {
+            L.h_items.clear();
+            // k chunks outer, in-plane segments inner: the waves of one block
+            // then cover neighbouring diagonals of the same planes and share
+            // their loads through the CU's L1
+            std::vector<std::pair<int64_t, int>> seg;  // (t0, last interior plane)
+            for (int64_t t0 = 0; t0 < T0; t0 += 62) {
+                int64_t smin = -1;
+                for (int64_t t = t0; t < std::min<int64_t>(t0 + 62, T0); ++t) {
+                    const int64_t d = diag_of(t), i = t - d * (d + 1) / 2;
+                    if (d >= 2 && d <= n - 2 && i >= 1 && i <= d - 1) { smin = d; break; }
+                }
+                if (smin >= 0) seg.push_back({t0, (int)(n - 1 - smin)});
+            }
+            for (int k0 = 1; k0 <= n - 3; k0 += kc)
+                for (const auto &sg : seg) {
+                    if (k0 > sg.second) continue;
+                    const int k1 = std::min(sg.second, k0 + kc - 1);
+                    L.h_items.push_back((uint32_t)sg.first);
+                    L.h_items.push_back((uint32_t)k0 | ((uint32_t)k1 << 16));
+                }
+            L.kc = kc;
+            if ((int64_t)tp.nt * (int64_t)(L.h_items.size() / 2) >= 8192) break;
+        }
+        L.n_items = (int)(L.h_items.size() / 2);
+        L.h_bnd.clear();
+        for (int k = 0; k <= n; ++k)
+            for (int sd = 0; sd + k <= n; ++sd)
+                for (int i = 0; i <= sd; ++i) {
+                    const int zp = zero_pattern(n, i, sd - i, k);
+                    if (zp) L.h_bnd.push_back((uint32_t)(slot_of(n, i, sd - i, k) << 4) | (uint32_t)zp);
+                }
+        L.n_bnd = (int)L.h_bnd.size();
+        std::vector<uint32_t> items_copy = L.h_items;
+        uint32_t *ip = nullptr;
+        TRY(upload(c, &ip, items_copy));
+        L.items = (uint2 *)ip;
+        TRY(upload(c, &L.bnd, L.h_bnd));
+    }
 
     std::vector<float> s32(L.h_sten.begin(), L.h_sten.end()), e32(L.h_emat.begin(), L.h_emat.end()),
         r32(L.h_rstw.begin(), L.h_rstw.end());
@@ -750,6 +818,8 @@ hhg_status vcycle_t(hhg_ctx c, int l, const T *f, T *u, int pre, int post, hhg_s
     TRY(residual_t<T>(c, l, f, u, r, nullptr, st));
     T *fc = work_f<T>(Lc), *uc = work_u<T>(Lc);
     HIPCHK(c, launch_restrict<T>(view<T>(c, l - 1), view<T>(c, l), r, fc, st));
+    // the coarse correction starts from zero (the coarse solve overwrites it)
+    if (l - 1 > c->coarse) HIPCHK(c, launch_fill<T>(uc, T(0), Lc.n_slots, st));
     TRY(vcycle_t<T>(c, l - 1, fc, uc, pre, post, below, st));
     HIPCHK(c, launch_prolong_add<T>(view<T>(c, l - 1), view<T>(c, l), uc, u, st));
     if (sm == HHG_LEARNED) TRY(learned_smooth_t<T>(c, l, post, f, u, st));

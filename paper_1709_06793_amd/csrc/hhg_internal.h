@@ -18,7 +18,15 @@ struct LevelView {
     int n_tet;
     int S;          // slots of one closed tet lattice
     int64_t Spad;   // slots per tet in memory (multiple of 64)
-    int bpt;        // 256-slot blocks per tet
+    int bpt;        // 256-slot blocks per tet (flat kernels)
+    // interior rows by column marching: wave work items (first in-plane
+    // offset, k0 | k1 << 16), 4 per block; boundary slots (slot << 4 | kind)
+    const uint2 *items;
+    int n_items;
+    int vpt;        // marching blocks per tet
+    const uint32_t *bnd;
+    int n_bnd;
+    int bpt2;       // boundary blocks per tet
     const T *sten;          // [tet][16 kinds][16]: entries 0..13 = half reference entry per direction
     const T *emat;          // [tet][6 types][4][4]: element matrices / 4 (nodal kernel)
     const T *rstw;          // [tet][16 kinds][16]: restriction weights (0..13 dirs, 14 centre)

@@ -13,6 +13,8 @@
 // in that XCD's L2).
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+
 #include "hhg_internal.h"
 #include "hhg_lattice.h"
 
@@ -31,36 +33,35 @@ __device__ __forceinline__ void decode_slot(int n, int s, int &i, int &j, int &k
     while (tc32(m) < q) ++m;
     while (m > 0 && tc32(m - 1) >= q) --m;
     k = n - m;
-    const int t = s - (tc32(n) - tc32(m));
-    const int p = tr32(m) - t;
-    int r = (int)(sqrtf(2.0f * (float)p)) - 1;
-    r = r < 0 ? 0 : r;
-    while (tr32(r) < p) ++r;
-    while (r > 0 && tr32(r - 1) >= p) --r;
-    j = m - r;
-    i = t - (j * (m + 1) - j * (j - 1) / 2);
+    const int t = s - (tc32(n) - tc32(m));  // offset inside the plane
+    int d = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+    while ((d + 1) * (d + 2) / 2 <= t) ++d;
+    while (d > 0 && d * (d + 1) / 2 > t) --d;
+    i = t - d * (d + 1) / 2;
+    j = d - i;
 }
 
-// slots of the 14 neighbours of slot s = (i,j,k), m = n-k, in DIR order
-__device__ __forceinline__ void neighbour_slots(int s, int j, int m, int nb[NDIR])
+// slots of the 14 neighbours of slot s = (i,j,k) in DIR order; sd = i + j,
+// m = n - k.  Plane k holds tr32(m) slots, plane k-1 tr32(m+1); the
+// anti-diagonal s+1 starts s+1 slots after the start of diagonal s.
+__device__ __forceinline__ void neighbour_slots(int s, int sd, int m, int nb[NDIR])
 {
-    const int rl = m - j + 1;          // length of row j in plane k
-    const int up = s + tr32(m) - j;    // (i, j, k+1)
-    const int dn = s - tr32(m + 1) + j;  // (i, j, k-1)
-    nb[0] = s + 1;                     // ( 1, 0, 0)
-    nb[1] = s + rl;                    // ( 0, 1, 0)
+    const int up = s + tr32(m);        // (i, j, k+1)
+    const int dn = s - tr32(m + 1);    // (i, j, k-1)
+    nb[0] = s + sd + 2;                // ( 1, 0, 0)
+    nb[1] = s + sd + 1;                // ( 0, 1, 0)
     nb[2] = up;                        // ( 0, 0, 1)
-    nb[3] = s - rl - 1 + 1;            // ( 1,-1, 0): row j-1 has length rl+1
-    nb[4] = dn + 1;                    // ( 1, 0,-1)
-    nb[5] = dn + rl + 1;               // ( 0, 1,-1): row j of plane k-1 has length rl+1
-    nb[6] = up - rl + 1;               // ( 1,-1, 1): row j-1 of plane k+1 has length rl
-    nb[7] = s - 1;                     // (-1, 0, 0)
-    nb[8] = s - rl - 1;                // ( 0,-1, 0)
+    nb[3] = s + 1;                     // ( 1,-1, 0)
+    nb[4] = dn + sd + 2;               // ( 1, 0,-1)
+    nb[5] = dn + sd + 1;               // ( 0, 1,-1)
+    nb[6] = up + 1;                    // ( 1,-1, 1)
+    nb[7] = s - sd - 1;                // (-1, 0, 0)
+    nb[8] = s - sd;                    // ( 0,-1, 0)
     nb[9] = dn;                        // ( 0, 0,-1)
-    nb[10] = s + rl - 1;               // (-1, 1, 0)
-    nb[11] = up - 1;                   // (-1, 0, 1)
-    nb[12] = up - rl;                  // ( 0,-1, 1)
-    nb[13] = dn + rl;                  // (-1, 1,-1)
+    nb[10] = s - 1;                    // (-1, 1, 0)
+    nb[11] = up - sd - 1;              // (-1, 0, 1)
+    nb[12] = up - sd;                  // ( 0,-1, 1)
+    nb[13] = dn - 1;                   // (-1, 1,-1)
 }
 
 __device__ __forceinline__ int xcd_remap(int b, int grid)
@@ -117,51 +118,240 @@ struct ElemDirTable {
 };
 constexpr ElemDirTable ELEM_DIR{};
 
-// ---------------------------------------------------------------- scaled operator
-// y_i = sum_d w_d (k_i + k_{i+d}) (u_{i+d} - u_i), w_d = shat_d / 2 (Sec. 6.1,
-// difference form of Sec. 6.3).  MODE_RESID writes r = f - A u and one partial
-// sum of r^2 per block.
-template <typename T, int MODE>
-__global__ __launch_bounds__(BLOCK) void k_scaled_volume(LevelView<T> L, const T *__restrict__ u,
-                                                          const T *__restrict__ f,
-                                                          T *__restrict__ y,
-                                                          double *__restrict__ partial)
+// ---------------------------------------------------------------- interior rows
+// Interior rows by column marching.  One wave takes 64 consecutive in-plane
+// offsets t (the same (i,j) columns in every plane; lanes 1..62 produce rows,
+// lanes 0 and 63 only feed their neighbours) and walks the planes k0..k1.  At
+// plane k a row needs, per array, the anti-diagonals s-1, s, s+1 of planes
+// k-1, k, k+1 at positions i-1..i+1.  Positions i+-1 come from the adjacent
+// lanes (interior nodes never sit at a diagonal's end), and the planes roll
+// through registers, so each step loads three coalesced values per array:
+// diagonals s-1, s, s+1 of plane k+1 at position i.
+//
+// OP 0: scaled stencil  y_i = sum_d w_d (k_i + k_{i+d}) (u_{i+d} - u_i)
+//       (Sec. 6.1 with the difference form of Sec. 6.3; w_d = shat_d / 2);
+// OP 1: nodal integration y_i = sum_{t contains i} kbar_t sum_b A_t[i,b](u_b - u_i)
+//       (eq. (standardfe): 24 elements, kbar_t the mean vertex value of k).
+// Extra blocks after the interior ones write 0 to Dirichlet boundary slots.
+
+// lane shifts by one position (DPP wave_shr:1 / wave_shl:1; a lane without a
+// source lane gets 0)
+__device__ __forceinline__ float dpp_prev(float v)  // value of lane-1
 {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x138, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float dpp_next(float v)  // value of lane+1
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xf, 0xf, true));
+}
+__device__ __forceinline__ double dpp_prev(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)b, 0x138, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x138, 0xf, 0xf, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double dpp_next(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)b, 0x130, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x130, 0xf, 0xf, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// buffer loads relative to one tet's slot array: the hardware range check
+// returns 0 for any index outside [0, n_records), so lanes whose neighbour
+// does not exist read 0 without a branch
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t tet_rsrc(const void *p, int64_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, int idx);
+template <>
+__device__ __forceinline__ double bload<double>(__amdgpu_buffer_rsrc_t r, int idx)
+{
+    const auto q = __builtin_amdgcn_raw_buffer_load_b64(r, idx * 8, 0, 0);
+    double v;
+    __builtin_memcpy(&v, &q, 8);
+    return v;
+}
+template <>
+__device__ __forceinline__ float bload<float>(__amdgpu_buffer_rsrc_t r, int idx)
+{
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, idx * 4, 0, 0));
+}
+
+template <typename T, int OP>
+__device__ __forceinline__ T row_value(const T uu[NDIR + 1], const T kk[NDIR + 1], const T *__restrict__ w)
+{
+    const T u0 = uu[NDIR], k0 = kk[NDIR];
+    T acc = T(0);
+    if (OP == 0) {
+#pragma unroll
+        for (int d = 0; d < NDIR; ++d) acc += w[d] * (k0 + kk[d]) * (uu[d] - u0);
+    } else {
+#pragma unroll
+        for (int t = 0; t < NTYPE; ++t)
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                const int d0 = ELEM_DIR.v[t][a][0], d1 = ELEM_DIR.v[t][a][1];
+                const int d2 = ELEM_DIR.v[t][a][2], d3 = ELEM_DIR.v[t][a][3];
+                const T ks = (kk[d0] + kk[d1]) + (kk[d2] + kk[d3]);
+                const T *e = w + t * 16 + a * 4;
+                const T sv = e[0] * (uu[d0] - u0) + e[1] * (uu[d1] - u0) + e[2] * (uu[d2] - u0) +
+                             e[3] * (uu[d3] - u0);
+                acc += ks * sv;
+            }
+    }
+    return acc;
+}
+
+// PF: planes loaded ahead of the one being computed; WPE: waves per SIMD the
+// register budget must allow
+template <typename T, int MODE, int OP, int PF, int WPE>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) void k_march(
+    LevelView<T> L, const T *__restrict__ u, const T *__restrict__ f, T *__restrict__ y,
+    double *__restrict__ partial)
+{
+    const int per_tet = L.vpt + L.bpt2;
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
     double sq = 0.0;
-    if (lb < L.n_tet * L.bpt) {
-        const int tet = lb / L.bpt;
-        const int s = (lb - tet * L.bpt) * BLOCK + threadIdx.x;
-        if (s < L.S) {
-            const int64_t base = (int64_t)tet * L.Spad;
-            int i, j, k;
-            decode_slot(L.n, s, i, j, k);
-            if (i == 0 || j == 0 || k == 0 || i + j + k == L.n) {
-                const int zp = zero_pattern(L.n, i, j, k);
-                if ((L.dmask[tet] >> zp) & 1) y[base + s] = T(0);
-            } else {
-                const T *__restrict__ ub = u + base;
-                const T *__restrict__ kb = L.kap + base;
-                const T *__restrict__ w = L.sten + (int64_t)tet * TET_STENCIL;  // kind 0
-                int nb[NDIR];
-                neighbour_slots(s, j, L.n - k, nb);
-                const T u0 = ub[s], k0 = kb[s];
-                T acc = T(0);
-#pragma unroll
-                for (int d = 0; d < NDIR; ++d) acc += w[d] * (k0 + kb[nb[d]]) * (ub[nb[d]] - u0);
-                if (MODE == MODE_APPLY) {
-                    y[base + s] = acc;
-                } else {
-                    const T r = f[base + s] - acc;
-                    y[base + s] = r;
-                    sq = (double)r * (double)r;
+    if (lb < L.n_tet * per_tet) {
+        const int tet = lb / per_tet;
+        const int b = lb - tet * per_tet;
+        const int64_t base = (int64_t)tet * L.Spad;
+        if (b < L.vpt) {
+            const int item = __builtin_amdgcn_readfirstlane(b * 4 + (threadIdx.x >> 6));
+            if (item < L.n_items) {
+                const uint2 it = L.items[item];
+                const int n = L.n, lane = threadIdx.x & 63;
+                const int k0 = (int)(it.y & 0xffffu), k1 = (int)(it.y >> 16);
+                const int t = (int)it.x - 1 + lane;
+                int sd = t >= 0 ? (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f) : -1;
+                if (t >= 0) {
+                    while ((sd + 1) * (sd + 2) / 2 <= t) ++sd;
+                    while (sd > 0 && sd * (sd + 1) / 2 > t) --sd;
                 }
+                const int i = t - sd * (sd + 1) / 2;
+                const bool row_lane = t >= 0 && lane >= 1 && lane <= 62 && i >= 1 && i <= sd - 1;
+                const int kend = n - 1 - sd;  // last interior plane of this column
+                const __amdgpu_buffer_rsrc_t ru = tet_rsrc(u + base, (int64_t)L.S * sizeof(T));
+                const __amdgpu_buffer_rsrc_t rk = tet_rsrc(L.kap + base, (int64_t)L.S * sizeof(T));
+                const T *__restrict__ w = OP == 0 ? L.sten + (int64_t)tet * TET_STENCIL
+                                                  : L.emat + (int64_t)tet * TET_EMAT;
+                const int Sn = tc32(n);
+                // in-plane offsets of diagonals s-1, s, s+1 at position i
+                const int om = t - sd, oc = t, op = t + sd + 1;
+                // plane k-1 (diagonals s, s+1), plane k (s-1, s, s+1), plane k+1 raw
+                int P = Sn - tc32(n - (k0 - 1));
+                T um_s = bload<T>(ru, P + oc), um_sp = bload<T>(ru, P + op);
+                T km_s = bload<T>(rk, P + oc), km_sp = bload<T>(rk, P + op);
+                P = Sn - tc32(n - k0);
+                T uc_sm = bload<T>(ru, P + om), uc_s = bload<T>(ru, P + oc), uc_sp = bload<T>(ru, P + op);
+                T kc_sm = bload<T>(rk, P + om), kc_s = bload<T>(rk, P + oc), kc_sp = bload<T>(rk, P + op);
+                P = Sn - tc32(n - (k0 + 1));
+                T up_sm = bload<T>(ru, P + om), up_s = bload<T>(ru, P + oc), up_sp = bload<T>(ru, P + op);
+                T kp_sm = bload<T>(rk, P + om), kp_s = bload<T>(rk, P + oc), kp_sp = bload<T>(rk, P + op);
+                // planes k0+2 .. k0+PF already in flight
+                T qu[PF][3], qk[PF][3];
+#pragma unroll
+                for (int q = 0; q < PF - 1; ++q) {
+                    const int Pq = Sn - tc32(n - (k0 + 2 + q));
+                    qu[q][0] = bload<T>(ru, Pq + om); qu[q][1] = bload<T>(ru, Pq + oc); qu[q][2] = bload<T>(ru, Pq + op);
+                    qk[q][0] = bload<T>(rk, Pq + om); qk[q][1] = bload<T>(rk, Pq + oc); qk[q][2] = bload<T>(rk, Pq + op);
+                }
+                T um_s_l = dpp_prev(um_s), um_sp_r = dpp_next(um_sp);
+                T km_s_l = dpp_prev(km_s), km_sp_r = dpp_next(km_sp);
+                T uc_sm_l = dpp_prev(uc_sm), uc_s_r = dpp_next(uc_s);
+                T kc_sm_l = dpp_prev(kc_sm), kc_s_r = dpp_next(kc_s);
+                for (int k = k0; k <= k1; ++k) {
+                    // load plane k+1+PF while plane k is computed (past the
+                    // chunk's end these loads are wasted but in range or 0)
+                    const int Pn = Sn - tc32(n - (k + 1 + PF));
+                    qu[PF - 1][0] = bload<T>(ru, Pn + om); qu[PF - 1][1] = bload<T>(ru, Pn + oc);
+                    qu[PF - 1][2] = bload<T>(ru, Pn + op);
+                    qk[PF - 1][0] = bload<T>(rk, Pn + om); qk[PF - 1][1] = bload<T>(rk, Pn + oc);
+                    qk[PF - 1][2] = bload<T>(rk, Pn + op);
+                    const T uc_s_l = dpp_prev(uc_s), uc_sp_r = dpp_next(uc_sp);
+                    const T kc_s_l = dpp_prev(kc_s), kc_sp_r = dpp_next(kc_sp);
+                    const T up_sm_l = dpp_prev(up_sm), up_s_r = dpp_next(up_s);
+                    const T kp_sm_l = dpp_prev(kp_sm), kp_s_r = dpp_next(kp_s);
+                    if (row_lane && k <= kend) {
+                        // neighbours in DIR order, centre last
+                        const T uu[NDIR + 1] = {uc_sp_r, uc_sp, up_s, uc_s_r, um_sp_r, um_sp, up_s_r,
+                                                uc_sm_l, uc_sm, um_s, uc_s_l, up_sm_l, up_sm, um_s_l, uc_s};
+                        const T kk[NDIR + 1] = {kc_sp_r, kc_sp, kp_s, kc_s_r, km_sp_r, km_sp, kp_s_r,
+                                                kc_sm_l, kc_sm, km_s, kc_s_l, kp_sm_l, kp_sm, km_s_l, kc_s};
+                        const T acc = row_value<T, OP>(uu, kk, w);
+                        const int64_t slot = base + (Sn - tc32(n - k)) + t;
+                        if (MODE == MODE_APPLY) {
+                            y[slot] = acc;
+                        } else {
+                            const T r = f[slot] - acc;
+                            y[slot] = r;
+                            sq += (double)r * (double)r;
+                        }
+                    }
+                    // roll planes: k -> k-1, k+1 -> k, k+2 -> k+1, ...
+                    um_s = uc_s; um_sp = uc_sp; um_s_l = uc_s_l; um_sp_r = uc_sp_r;
+                    km_s = kc_s; km_sp = kc_sp; km_s_l = kc_s_l; km_sp_r = kc_sp_r;
+                    uc_sm = up_sm; uc_s = up_s; uc_sp = up_sp; uc_sm_l = up_sm_l; uc_s_r = up_s_r;
+                    kc_sm = kp_sm; kc_s = kp_s; kc_sp = kp_sp; kc_sm_l = kp_sm_l; kc_s_r = kp_s_r;
+                    up_sm = qu[0][0]; up_s = qu[0][1]; up_sp = qu[0][2];
+                    kp_sm = qk[0][0]; kp_s = qk[0][1]; kp_sp = qk[0][2];
+#pragma unroll
+                    for (int q = 0; q < PF - 1; ++q)
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            qu[q][c] = qu[q + 1][c];
+                            qk[q][c] = qk[q + 1][c];
+                        }
+                }
+            }
+        } else {
+            const int e = (b - L.vpt) * BLOCK + threadIdx.x;
+            if (e < L.n_bnd) {
+                const uint32_t v = L.bnd[e];
+                if ((L.dmask[tet] >> (v & 15u)) & 1) y[base + (v >> 4)] = T(0);
             }
         }
     }
     if (MODE == MODE_RESID) {
         sq = block_reduce(sq, 0);
         if (threadIdx.x == 0) partial[blockIdx.x] = sq;
+    }
+}
+
+static inline int march_grid(int n_tet, int vpt, int bpt2)
+{
+    const int nb = n_tet * (vpt + bpt2);
+    return ((nb + 7) / 8) * 8;
+}
+
+// variant of the marching kernel (prefetch depth, occupancy); HHG_MARCH_VARIANT
+// overrides the default for tuning runs
+static int march_variant()
+{
+    static int v = -1;
+    if (v < 0) {
+        const char *e = getenv("HHG_MARCH_VARIANT");
+        v = e ? atoi(e) : 0;
+        if (v < 0 || v > 3) v = 0;
+    }
+    return v;
+}
+
+template <typename T, int MODE, int OP>
+static void launch_march(const LevelView<T> &L, const T *u, const T *f, T *y, double *partial,
+                         hipStream_t st)
+{
+    const int g = march_grid(L.n_tet, L.vpt, L.bpt2);
+    switch (march_variant()) {
+    case 1: k_march<T, MODE, OP, 1, 8><<<g, BLOCK, 0, st>>>(L, u, f, y, partial); break;
+    case 2: k_march<T, MODE, OP, 2, 4><<<g, BLOCK, 0, st>>>(L, u, f, y, partial); break;
+    case 3: k_march<T, MODE, OP, 3, 4><<<g, BLOCK, 0, st>>>(L, u, f, y, partial); break;
+    default: k_march<T, MODE, OP, 1, 4><<<g, BLOCK, 0, st>>>(L, u, f, y, partial); break;
     }
 }
 
@@ -185,7 +375,7 @@ __global__ __launch_bounds__(BLOCK) void k_scaled_shared(LevelView<T> L, const T
             const int s = (int)slot_of(L.n, i, j, k);
             self = base + s;
             int nb[NDIR];
-            neighbour_slots(s, j, L.n - k, nb);
+            neighbour_slots(s, i + j, L.n - k, nb);
             const T *w = L.sten + (int64_t)tet * TET_STENCIL + kind * KIND_STRIDE;
             const T u0 = u[base + s], k0 = L.kap[base + s];
             for (int d = 0; d < NDIR; ++d) {
@@ -214,69 +404,20 @@ template <typename T>
 hipError_t launch_scaled(const LevelView<T> &L, int mode, const T *u, const T *f, T *y,
                          double *partial, int *n_partial, hipStream_t st)
 {
-    const int gv = volume_grid(L.n_tet, L.bpt);
+    const int gv = march_grid(L.n_tet, L.vpt, L.bpt2);
     const int gs = blocks_for(L.n_shared);
     if (mode == MODE_APPLY) {
-        k_scaled_volume<T, MODE_APPLY><<<gv, BLOCK, 0, st>>>(L, u, f, y, partial);
+        launch_march<T, MODE_APPLY, 0>(L, u, f, y, partial, st);
         if (gs) k_scaled_shared<T, MODE_APPLY><<<gs, BLOCK, 0, st>>>(L, u, f, y, partial);
     } else {
-        k_scaled_volume<T, MODE_RESID><<<gv, BLOCK, 0, st>>>(L, u, f, y, partial);
+        launch_march<T, MODE_RESID, 0>(L, u, f, y, partial, st);
         if (gs) k_scaled_shared<T, MODE_RESID><<<gs, BLOCK, 0, st>>>(L, u, f, y, partial + gv);
         if (n_partial) *n_partial = gv + gs;
     }
     return hipGetLastError();
 }
 
-// ---------------------------------------------------------------- nodal integration
-// y_i = sum_{t containing i} kbar_t sum_b A_t[i,b] (u_b - u_i), kbar_t the mean
-// of k at t's vertices (eq. (standardfe)); the 24 elements around an interior
-// node are the six shapes at the four bases that make i one of their vertices.
-template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_nodal_volume(LevelView<T> L, const T *__restrict__ u,
-                                                         T *__restrict__ y)
-{
-    const int lb = xcd_remap(blockIdx.x, gridDim.x);
-    if (lb >= L.n_tet * L.bpt) return;
-    const int tet = lb / L.bpt;
-    const int s = (lb - tet * L.bpt) * BLOCK + threadIdx.x;
-    if (s >= L.S) return;
-    const int64_t base = (int64_t)tet * L.Spad;
-    int i, j, k;
-    decode_slot(L.n, s, i, j, k);
-    if (i == 0 || j == 0 || k == 0 || i + j + k == L.n) {
-        const int zp = zero_pattern(L.n, i, j, k);
-        if ((L.dmask[tet] >> zp) & 1) y[base + s] = T(0);
-        return;
-    }
-    const T *__restrict__ ub = u + base;
-    const T *__restrict__ kb = L.kap + base;
-    const T *__restrict__ E = L.emat + (int64_t)tet * TET_EMAT;  // element matrices / 4
-    int nb[NDIR];
-    neighbour_slots(s, j, L.n - k, nb);
-    T du[NDIR + 1], kk[NDIR + 1];
-    const T u0 = ub[s];
-#pragma unroll
-    for (int d = 0; d < NDIR; ++d) {
-        du[d] = ub[nb[d]] - u0;
-        kk[d] = kb[nb[d]];
-    }
-    du[NDIR] = T(0);
-    kk[NDIR] = kb[s];
-    T acc = T(0);
-#pragma unroll
-    for (int t = 0; t < NTYPE; ++t)
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            const int d0 = ELEM_DIR.v[t][a][0], d1 = ELEM_DIR.v[t][a][1];
-            const int d2 = ELEM_DIR.v[t][a][2], d3 = ELEM_DIR.v[t][a][3];
-            const T ks = (kk[d0] + kk[d1]) + (kk[d2] + kk[d3]);
-            const T *e = E + t * 16 + a * 4;
-            const T sv = e[0] * du[d0] + e[1] * du[d1] + e[2] * du[d2] + e[3] * du[d3];
-            acc += ks * sv;
-        }
-    y[base + s] = acc;
-}
-
+// ---------------------------------------------------------------- nodal integration (shared rows)
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_nodal_shared(LevelView<T> L, const T *__restrict__ u,
                                                          T *__restrict__ y)
@@ -321,7 +462,7 @@ __global__ __launch_bounds__(BLOCK) void k_nodal_shared(LevelView<T> L, const T 
 template <typename T>
 hipError_t launch_nodal(const LevelView<T> &L, const T *u, T *y, hipStream_t st)
 {
-    k_nodal_volume<T><<<volume_grid(L.n_tet, L.bpt), BLOCK, 0, st>>>(L, u, y);
+    launch_march<T, MODE_APPLY, 1>(L, u, nullptr, y, nullptr, st);
     if (L.n_shared) k_nodal_shared<T><<<blocks_for(L.n_shared), BLOCK, 0, st>>>(L, u, y);
     return hipGetLastError();
 }
@@ -392,7 +533,7 @@ __global__ __launch_bounds__(BLOCK) void k_diag_volume(LevelView<T> L, T *__rest
             } else {
                 const T *w = L.sten + (int64_t)tet * TET_STENCIL;
                 int nb[NDIR];
-                neighbour_slots(s, j, L.n - k, nb);
+                neighbour_slots(s, i + j, L.n - k, nb);
                 const double k0 = (double)L.kap[base + s];
                 double dsum = 0.0, asum = 0.0;
                 for (int d = 0; d < NDIR; ++d) {
@@ -427,7 +568,7 @@ __global__ __launch_bounds__(BLOCK) void k_diag_shared(LevelView<T> L, T *__rest
         const int64_t base = (int64_t)tet * L.Spad;
         const int s = (int)slot_of(L.n, i, j, k);
         int nb[NDIR];
-        neighbour_slots(s, j, L.n - k, nb);
+        neighbour_slots(s, i + j, L.n - k, nb);
         const T *w = L.sten + (int64_t)tet * TET_STENCIL + kind * KIND_STRIDE;
         const double k0 = (double)L.kap[base + s];
         for (int d = 0; d < NDIR; ++d) {
@@ -546,7 +687,7 @@ __global__ __launch_bounds__(BLOCK) void k_restrict_volume(LevelView<T> Lc, Leve
     const T *__restrict__ fb = rf + (int64_t)tet * Lf.Spad;
     const int sf = (int)slot_of(Lf.n, 2 * i, 2 * j, 2 * k);
     int nb[NDIR];
-    neighbour_slots(sf, 2 * j, Lf.n - 2 * k, nb);
+    neighbour_slots(sf, 2 * (i + j), Lf.n - 2 * k, nb);
     T acc = T(0);
 #pragma unroll
     for (int d = 0; d < NDIR; ++d) acc += fb[nb[d]];
@@ -568,7 +709,7 @@ __global__ __launch_bounds__(BLOCK) void k_restrict_shared(LevelView<T> Lc, Leve
         const T *w = Lc.rstw + (int64_t)tet * TET_STENCIL + kind * KIND_STRIDE;
         const int sf = (int)slot_of(Lf.n, 2 * i, 2 * j, 2 * k);
         int nb[NDIR];
-        neighbour_slots(sf, 2 * j, Lf.n - 2 * k, nb);
+        neighbour_slots(sf, 2 * (i + j), Lf.n - 2 * k, nb);
         acc += w[NDIR] * fb[sf];
         for (int d = 0; d < NDIR; ++d)
             if (w[d] != T(0)) acc += w[d] * fb[nb[d]];

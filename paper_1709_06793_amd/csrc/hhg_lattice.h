@@ -11,7 +11,9 @@
 // +-(e1-e2), +-(e1-e3), +-(e2-e3) and +-(e1-e2+e3) (the octahedron diagonal,
 // the "gray" edge of Fig. 5).
 //
-// Storage: points ordered by plane k, then row j, then i (rows contiguous).
+// Storage: points ordered by plane k, then anti-diagonal s = i + j, then i.
+// Along an anti-diagonal the +-(e1-e2) neighbours are adjacent slots, and all
+// 14 neighbours sit at offsets that depend only on s and the plane.
 #pragma once
 #include <stdint.h>
 
@@ -64,19 +66,16 @@ HHG_HD int64_t tet_count(int64_t m) { return (m + 1) * (m + 2) * (m + 3) / 6; }
 // number of lattice points with i+j <= m in one plane
 HHG_HD int64_t tri_count(int64_t m) { return (m + 1) * (m + 2) / 2; }
 
-// slot of (i,j,k) inside one tet lattice of size n
+// slot of (i,j,k) inside one tet lattice of size n: planes k in turn; inside a
+// plane the anti-diagonals s = i + j in turn (positions i = 0..s).  A plane
+// with m = n - k holds (m+1)(m+2)/2 points.
 HHG_HD int64_t slot_of(int n, int i, int j, int k)
 {
-    const int64_t m = n - k;
-    return tet_count(n) - tet_count(m) + (int64_t)j * (m + 1) - (int64_t)j * (j - 1) / 2 + i;
+    const int64_t s = i + j;
+    return tet_count(n) - tet_count(n - k) + s * (s + 1) / 2 + i;
 }
-// first slot of plane k and first slot of row j inside it
+// first slot of plane k
 HHG_HD int64_t plane_start(int n, int k) { return tet_count(n) - tet_count(n - k); }
-HHG_HD int64_t row_start(int n, int j, int k)
-{
-    const int64_t m = n - k;
-    return (int64_t)j * (m + 1) - (int64_t)j * (j - 1) / 2;
-}
 
 // zero pattern of the barycentric weights: bit a set iff weight a is zero.
 // 0 = tet interior, one bit = face opposite vertex a, two bits = edge,
