@@ -184,22 +184,45 @@ hhg_status hhg_solve(hhg_ctx ctx, int32_t level, hhg_solve_mode mode, int32_t pr
                      double tol, int32_t max_iter, const double *f, double *u,
                      hhg_solve_stats *stats, void *stream);
 
-/* Learned smoothing correction (not in the paper).  Per node i a network maps
- * the 15-point neighbourhood features [r_{i+d}/s_i] and [log k_{i+d} - log k_i]
- * (15 + 15, padded to 32) through 32 -> 16 -> 16 -> 1 (ReLU), BF16 weights,
- * FP32 accumulation, to c_i; the correction is delta_i = s_i c_i / D_i with
- * s_i = max |r| over the neighbourhood + 1e-30.  Weight vector layout (FP32):
- * W1[16][32], b1[16], W2[16][16], b2[16], w3[16], b3  (801 values). */
-#define HHG_LEARNED_NPARAM 801
+/* Learned smoothing correction (not in the paper).  Per interior node i of a
+ * macro tet, a network maps the 15-point neighbourhood features
+ * x_p = r_p / s_i and x_{15+p} = L_p - L_i (p = 0: the node, p = 1..14: the
+ * neighbours in the tet-local lattice directions (1,0,0), (0,1,0), (0,0,1),
+ * (1,-1,0), (1,0,-1), (0,1,-1), (1,-1,1) and their negatives, in that order;
+ * s_i = max_p |r_p| + 1e-30; L = log k rounded to FP32; x_30 = x_31 = 0)
+ * through h1 = bf16(relu(W1 bf16(x) + b1)), h2 = relu(W2 h1 + b2),
+ * c = w3 . h2 + b3 (BF16 parameters, FP32 accumulation on the matrix cores).
+ * Nodes on macro faces/edges/vertices and Dirichlet nodes get c = 0.
+ * A learned smoothing step is u <- u + D^{-1}(omega r + s c), omega = 2/3.
+ * Parameter layout (FP32, rounded to BF16 inside):
+ * W1[16][32], b1[16], W2[16][16], b2[16], w3[16], b3 (817 values).
+ * The learned calls take FP32 slot vectors. */
+#define HHG_LEARNED_NPARAM 817
 hhg_status hhg_learned_set_weights(hhg_ctx ctx, const float *w_host, int64_t n);
-/* c_out[slot] = network output c_i (FP32, consistent slot vector; 0 on
- * Dirichlet slots).  r: FP32 slot vector. */
+/* Largest per-cycle residual ratio a learned solve accepts before it falls
+ * back to Chebyshev smoothing for the rest of the solve (default 1). */
+hhg_status hhg_learned_set_fallback(hhg_ctx ctx, double max_rate);
+/* c_out[slot] = network output c_i (consistent FP32 slot vector). */
 hhg_status hhg_learned_forward(hhg_ctx ctx, int32_t level, const float *r, float *c_out,
                                void *stream);
-/* Gradient of sum_i g_i c_i with respect to the 801 parameters (FP32 host
- * array), g = dL/dc given as an FP32 slot vector; synchronises the stream. */
+/* Gradient of sum_i g_i c_i with respect to the 817 parameters into host
+ * memory dw_host (BF16 roundings of x and h1 taken as identities); g is an
+ * FP32 slot vector.  Synchronises the stream. */
 hhg_status hhg_learned_backward(hhg_ctx ctx, int32_t level, const float *r, const float *g,
                                 float *dw_host, void *stream);
+/* One training sample (r = A e): loss L = e1^T A e1 / e^T A e of the error
+ * e1 = e - D^{-1}(omega r + s c) after one learned step, and dL/dparameters
+ * into dw_host.  Synchronises the stream. */
+hhg_status hhg_learned_loss_grad(hhg_ctx ctx, int32_t level, const float *r, const float *e,
+                                 double *loss_out, float *dw_host, void *stream);
+/* r_out = (float)(f - A u), e_out = (float)(u_star - u): a training pair from
+ * FP64 slot vectors. */
+hhg_status hhg_training_pair(hhg_ctx ctx, int32_t level, const double *f, const double *u,
+                             const double *u_star, float *r_out, float *e_out, void *stream);
+/* Host-side Adam step (Kingma and Ba) on n parameters: w, m, v updated in
+ * place from gradient g at step t >= 1. */
+hhg_status hhg_adam_update(float *w, float *m, float *v, const float *g, int64_t n, int32_t t,
+                           double lr, double beta1, double beta2, double eps);
 
 #ifdef __cplusplus
 }

@@ -250,6 +250,11 @@ struct Level {
     double *c_d64 = nullptr, *c_base = nullptr;
     float *c_d32 = nullptr;
     uint8_t *c_nbdir = nullptr;
+    // learned correction: log k (FP32), ownership mask and FP32 scratch
+    float *logk32 = nullptr;
+    uint8_t *own = nullptr;
+    float *lt[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    double *ubak = nullptr;  // last accepted iterate of a learned solve
     // canonical maps (built on first use); slot2canon holds -(c+1) for a
     // Dirichlet slot of node c
     int32_t *slot2canon = nullptr;
@@ -686,6 +691,7 @@ hhg_status build_level(hhg_ctx c, int l)
     TRY(dalloc(c, &L.d32, L.n_slots));
     TRY(dalloc(c, &L.f32, L.n_slots));
     TRY(dalloc(c, &L.u32, L.n_slots));
+    TRY(dalloc(c, &L.logk32, L.n_slots));
     if (l < c->max_level) {
         TRY(dalloc(c, &L.f64, L.n_slots));
         TRY(dalloc(c, &L.u64, L.n_slots));
@@ -1095,20 +1101,78 @@ int default_coarse(hhg_ctx c)
     return best < 0 ? c->max_level : best;
 }
 
-template <typename T>
-hhg_status learned_smooth_t(hhg_ctx c, int l, int sweeps, const T *f, T *u, hipStream_t st)
+// FP32 scratch vectors of a level for the learned correction
+hhg_status learned_scratch(hhg_ctx c, int l)
 {
-    (void)l; (void)sweeps; (void)f; (void)u; (void)st;
-    return fail(c, HHG_ESTATE, "learned smoother not available");
+    Level &L = c->lv[l];
+    for (float *&p : L.lt)
+        if (!p) TRY(dalloc(c, &p, L.n_slots));
+    return HHG_OK;
+}
+
+// ownership mask: 1 on interior slots and on the first copy of every shared
+// non-Dirichlet node (dot products count each unknown once)
+hhg_status ensure_own(hhg_ctx c, int l)
+{
+    Level &L = c->lv[l];
+    if (L.own) return HHG_OK;
+    std::vector<uint8_t> own((size_t)L.n_slots, 0);
+    for (int t = 0; t < c->topo.nt; ++t)
+        for (int k = 1; k < L.n; ++k)
+            for (int sd = 2; sd + k < L.n; ++sd)
+                for (int i = 1; i < sd; ++i) own[(int64_t)t * L.Spad + slot_of(L.n, i, sd - i, k)] = 1;
+    for (int q = 0; q < L.n_shared; ++q) {
+        int tt, kind, i, j, k;
+        unpack_copy(L.h_sh_copy[L.h_sh_off[q]], tt, kind, i, j, k);
+        own[(int64_t)tt * L.Spad + slot_of(L.n, i, j, k)] = 1;
+    }
+    TRY(upload(c, &L.own, own));
+    return HHG_OK;
+}
+
+double dot_owned(hhg_ctx c, int l, const float *a, const float *b, hipStream_t st, hhg_status *err)
+{
+    Level &L = c->lv[l];
+    int nb = 0;
+    *err = HHG_OK;
+    if (launch_dot_owned(a, b, L.own, L.n_slots, c->partial, &nb, st) != hipSuccess ||
+        launch_reduce(c->partial, nb, 0, c->dscalar, st) != hipSuccess ||
+        hipMemcpyAsync(c->hscalar, c->dscalar, 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+        *err = fail(c, HHG_EHIP, "dot product failed");
+        return 0.0;
+    }
+    return c->hscalar[0];
+}
+
+// learned smoothing steps: r = f - A u; u += D^{-1}(omega r + s c(r, k))
+template <typename T>
+hhg_status learned_smooth_t(hhg_ctx c, int l, int sweeps, const T *f, T *u, hipStream_t st);
+
+template <>
+hhg_status learned_smooth_t<double>(hhg_ctx c, int, int, const double *, double *, hipStream_t)
+{
+    return fail(c, HHG_EINVAL, "the learned smoother runs in FP32");
+}
+
+template <>
+hhg_status learned_smooth_t<float>(hhg_ctx c, int l, int sweeps, const float *f, float *u, hipStream_t st)
+{
+    if (!c->learned.ready) return fail(c, HHG_ESTATE, "no learned weights set");
+    TRY(learned_scratch(c, l));
+    Level &L = c->lv[l];
+    for (int s = 0; s < sweeps; ++s) {
+        TRY(residual_t<float>(c, l, f, u, L.r32, nullptr, st));
+        HIPCHK(c, launch_learned_forward_full(view<float>(c, l), c->learned, L.r32, L.logk32, nullptr,
+                                              L.lt[0], nullptr, st));
+        HIPCHK(c, launch_learned_update(u, L.r32, L.lt[0], L.invd32, (float)c->learned.omega, L.n_slots, st));
+    }
+    return HHG_OK;
 }
 
 }  // namespace
 
-namespace hhg {
-void learned_free(LearnedState &s) { (void)s; }
-}  // namespace hhg
-
-// ================================================================ C ABI
+// ================================================================ C ABI// ================================================================ C ABI
 extern "C" {
 
 hhg_status hhg_create_macro(const double *vert_xyz, int32_t n_vert, const int32_t *tet_vert,
@@ -1221,7 +1285,6 @@ hhg_status hhg_destroy(hhg_ctx c)
     (void)hipDeviceSynchronize();
     for (void *p : c->allocs) (void)hipFree(p);
     if (c->hscalar) (void)hipHostFree(c->hscalar);
-    learned_free(c->learned);
     delete c;
     return HHG_OK;
 }
@@ -1324,8 +1387,10 @@ hhg_status hhg_set_coefficient(hhg_ctx c, const double *k, int on_device, void *
         HIPCHK(c, launch_fill<double>(Lc.k64, 1.0, Lc.n_slots, st));
         HIPCHK(c, launch_inject<double>(Lf.k64, Lf.n, Lc.k64, Lc.n, c->topo.nt, Lf.Spad, Lc.Spad, st));
     }
-    for (int l = 0; l <= Lmax; ++l)
+    for (int l = 0; l <= Lmax; ++l) {
         HIPCHK(c, launch_convert<double, float>(c->lv[l].k64, c->lv[l].k32, c->lv[l].n_slots, st));
+        HIPCHK(c, launch_logk(c->lv[l].k64, c->lv[l].logk32, c->lv[l].n_slots, st));
+    }
     HIPCHK(c, hipStreamSynchronize(st));
     for (int l = 0; l <= Lmax; ++l) {
         TRY(build_modification(c, l));
@@ -1467,20 +1532,30 @@ hhg_status hhg_solve(hhg_ctx c, int32_t level, hhg_solve_mode mode, int32_t pre,
     std::vector<double> hist;
     int fallback = 0;
     bool use_learned = mode == HHG_SOLVE_LEARNED;
+    if (use_learned && !L.ubak) TRY(dalloc(c, &L.ubak, L.n_slots));
     for (int it = 0;; ++it) {
         TRY(residual_t<double>(c, level, f, u, L.r64, &nr, st));
         hist.push_back(nr / nf);
+        // fallback: a learned cycle must contract at least by the accepted
+        // rate and keep the residual finite; otherwise its result is
+        // discarded and the solve continues with Chebyshev smoothing
+        if (use_learned && it >= 1) {
+            const double q = hist[it] / hist[it - 1];
+            if (!std::isfinite(nr) || !(q <= c->learned.fallback_rate)) {
+                use_learned = false;
+                fallback = 1;
+                HIPCHK(c, hipMemcpyAsync(u, L.ubak, L.n_slots * sizeof(double), hipMemcpyDeviceToDevice, st));
+                TRY(residual_t<double>(c, level, f, u, L.r64, &nr, st));
+                hist.back() = nr / nf;
+            }
+        }
         if (!std::isfinite(nr)) break;
         if (hist.back() <= tol || it >= max_iter) break;
-        // fallback: the learned cycle must keep contracting at least as well as
-        // the plain cycle's measured rate (taken from the first plain cycles)
-        if (use_learned && it >= 2) {
-            const double q = hist[it] / hist[it - 1];
-            if (!std::isfinite(q) || q > c->learned.fallback_rate) { use_learned = false; fallback = 1; }
-        }
         if (mode == HHG_SOLVE_F64) {
             TRY(vcycle_t<double>(c, level, f, u, pre, post, HHG_CHEBYSHEV, st));
         } else {
+            if (use_learned)
+                HIPCHK(c, hipMemcpyAsync(L.ubak, u, L.n_slots * sizeof(double), hipMemcpyDeviceToDevice, st));
             HIPCHK(c, launch_convert<double, float>(L.r64, L.f32, L.n_slots, st));
             HIPCHK(c, launch_fill<float>(L.u32, 0.0f, L.n_slots, st));
             TRY(vcycle_t<float>(c, level, L.f32, L.u32, pre, post, use_learned ? HHG_LEARNED : HHG_CHEBYSHEV, st));
@@ -1504,19 +1579,121 @@ hhg_status hhg_solve(hhg_ctx c, int32_t level, hhg_solve_mode mode, int32_t pre,
 
 hhg_status hhg_learned_set_weights(hhg_ctx c, const float *w, int64_t n)
 {
-    (void)w; (void)n;
-    return fail(c, HHG_ESTATE, "learned smoother not available");
+    if (!c || !w) return fail(c, HHG_EINVAL, "NULL argument");
+    if (n != LN_NPARAM) return fail(c, HHG_EINVAL, "expected %d parameters, got %lld", LN_NPARAM, (long long)n);
+    for (int64_t q = 0; q < n; ++q)
+        if (!std::isfinite(w[q])) return fail(c, HHG_EINVAL, "non-finite weight %lld", (long long)q);
+    LearnedState &S = c->learned;
+    if (!S.w32) {
+        TRY(dalloc(c, &S.w32, LN_NPARAM));
+        TRY(dalloc(c, &S.wbf, LN_NPARAM));
+        TRY(dalloc(c, &S.dgrad, LN_NPARAM));
+    }
+    HIPCHK(c, hipMemcpy(S.w32, w, LN_NPARAM * sizeof(float), hipMemcpyHostToDevice));
+    HIPCHK(c, launch_weights_bf16(S.w32, S.wbf, LN_NPARAM, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    S.ready = true;
+    return HHG_OK;
 }
+
+hhg_status hhg_learned_set_fallback(hhg_ctx c, double max_rate)
+{
+    if (!c || !(max_rate > 0.0)) return fail(c, HHG_EINVAL, "fallback rate must be positive");
+    c->learned.fallback_rate = max_rate;
+    return HHG_OK;
+}
+
 hhg_status hhg_learned_forward(hhg_ctx c, int32_t level, const float *r, float *c_out, void *stream)
 {
-    (void)level; (void)r; (void)c_out; (void)stream;
-    return fail(c, HHG_ESTATE, "learned smoother not available");
+    TRY(check_level(c, level));
+    NEED_K(c);
+    if (!c->learned.ready) return fail(c, HHG_ESTATE, "no learned weights set");
+    if (!r || !c_out || (const void *)r == (const void *)c_out) return fail(c, HHG_EINVAL, "bad vectors");
+    Level &L = c->lv[level];
+    HIPCHK(c, launch_learned_forward<float>(view<float>(c, level), c->learned, r, L.logk32, c_out,
+                                            pick(c, stream)));
+    return HHG_OK;
 }
+
+static hhg_status learned_grad_to_host(hhg_ctx c, int level, const float *r, const float *g, float *dw,
+                                       hipStream_t st)
+{
+    LearnedState &S = c->learned;
+    const int nb = learned_bwd_blocks(view<float>(c, level));
+    if (nb > S.gpart_blocks) {
+        if (S.gpart) dfree(c, S.gpart);
+        TRY(dalloc(c, &S.gpart, (int64_t)nb * LN_NPARAM));
+        S.gpart_blocks = nb;
+    }
+    HIPCHK(c, launch_learned_backward(view<float>(c, level), S, r, c->lv[level].logk32, g, st));
+    HIPCHK(c, hipMemcpyAsync(dw, S.dgrad, LN_NPARAM * sizeof(float), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    return HHG_OK;
+}
+
 hhg_status hhg_learned_backward(hhg_ctx c, int32_t level, const float *r, const float *g, float *dw,
                                 void *stream)
 {
-    (void)level; (void)r; (void)g; (void)dw; (void)stream;
-    return fail(c, HHG_ESTATE, "learned smoother not available");
+    TRY(check_level(c, level));
+    NEED_K(c);
+    if (!c->learned.ready) return fail(c, HHG_ESTATE, "no learned weights set");
+    if (!r || !g || !dw) return fail(c, HHG_EINVAL, "NULL argument");
+    return learned_grad_to_host(c, level, r, g, dw, pick(c, stream));
+}
+
+hhg_status hhg_learned_loss_grad(hhg_ctx c, int32_t level, const float *r, const float *e, double *loss,
+                                 float *dw, void *stream)
+{
+    TRY(check_level(c, level));
+    NEED_K(c);
+    if (!c->learned.ready) return fail(c, HHG_ESTATE, "no learned weights set");
+    if (!r || !e || !loss || !dw) return fail(c, HHG_EINVAL, "NULL argument");
+    hipStream_t st = pick(c, stream);
+    TRY(learned_scratch(c, level));
+    TRY(ensure_own(c, level));
+    Level &L = c->lv[level];
+    float *sc = L.lt[0], *sv = L.lt[1], *e1 = L.lt[2], *ae1 = L.lt[3], *ae = L.lt[4], *g = L.lt[5];
+    const float om = (float)c->learned.omega;
+    HIPCHK(c, launch_learned_forward_full(view<float>(c, level), c->learned, r, L.logk32, nullptr, sc, sv, st));
+    HIPCHK(c, launch_learned_err(e, r, sc, L.invd32, om, e1, L.n_slots, st));
+    TRY(apply_scaled_t<float>(c, level, e1, ae1, st));
+    TRY(apply_scaled_t<float>(c, level, e, ae, st));
+    hhg_status err;
+    const double e0 = dot_owned(c, level, e, ae, st, &err);
+    if (err) return err;
+    const double ee = dot_owned(c, level, e1, ae1, st, &err);
+    if (err) return err;
+    if (!(e0 > 0.0)) return fail(c, HHG_EINVAL, "training sample has zero energy");
+    *loss = ee / e0;
+    HIPCHK(c, launch_learned_lossgrad(ae1, sv, L.invd32, 1.0 / e0, g, L.n_slots, st));
+    return learned_grad_to_host(c, level, r, g, dw, st);
+}
+
+hhg_status hhg_training_pair(hhg_ctx c, int32_t level, const double *f, const double *u, const double *us,
+                             float *r_out, float *e_out, void *stream)
+{
+    TRY(check_level(c, level));
+    NEED_K(c);
+    if (!f || !u || !us || !r_out || !e_out) return fail(c, HHG_EINVAL, "NULL argument");
+    hipStream_t st = pick(c, stream);
+    Level &L = c->lv[level];
+    TRY(residual_t<double>(c, level, f, u, L.r64, nullptr, st));
+    HIPCHK(c, launch_pair(L.r64, us, u, r_out, e_out, L.n_slots, st));
+    return HHG_OK;
+}
+
+hhg_status hhg_adam_update(float *w, float *m, float *v, const float *g, int64_t n, int32_t t, double lr,
+                           double b1, double b2, double eps)
+{
+    if (!w || !m || !v || !g || n <= 0 || t < 1) return HHG_EINVAL;
+    const double c1 = 1.0 - std::pow(b1, t), c2 = 1.0 - std::pow(b2, t);
+    for (int64_t q = 0; q < n; ++q) {
+        m[q] = (float)(b1 * m[q] + (1.0 - b1) * g[q]);
+        v[q] = (float)(b2 * v[q] + (1.0 - b2) * (double)g[q] * g[q]);
+        const double mh = m[q] / c1, vh = v[q] / c2;
+        w[q] = (float)(w[q] - lr * mh / (std::sqrt(vh) + eps));
+    }
+    return HHG_OK;
 }
 
 }  // extern "C"

@@ -1,0 +1,409 @@
+// hhg_learned.hip -- kernels of the learned smoothing correction: features from
+// the 15-point neighbourhood, a 32 -> 16 -> 16 -> 1 ReLU network with BF16
+// weights on the matrix cores (v_mfma_f32_16x16x16_bf16, FP32 accumulation),
+// its parameter gradient, and the smoothing update that uses it.
+//
+// Features of an interior node i (positions p = 0: the node, p = 1..14: the
+// lattice neighbours in DIR order):  s = max_p |r_p| + 1e-30,
+// x_p = r_p / s, x_{15+p} = L_p - L_0 (L = log k rounded to FP32), x_30 = x_31 = 0.
+// Network:  h1 = bf16(relu(W1 bf16(x) + b1)),  h2 = relu(W2 h1 + b2),
+// c = w3 . h2 + b3.  Nodes on macro faces/edges/vertices and Dirichlet nodes
+// get c = 0.
+//
+// Matrix-core mapping: for 16 nodes at a time the wave forms the transposed
+// products C1^T = W1 X^T (two K=16 steps) and C2^T = W2 H1^T.  In the 16x16x16
+// layout lane l holds A[l%16][4(l/16)+q], B[4(l/16)+q][l%16] and
+// D[4(l/16)+q][l%16] (q = 0..3), so the output of layer 1 is already the B
+// operand of layer 2 and no data moves between the layers.
+#include <hip/hip_runtime.h>
+
+#include "hhg_internal.h"
+#include "hhg_lattice.h"
+#include "hhg_learned.h"
+
+namespace hhg {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int ltc32(int m) { return (m + 1) * (m + 2) * (m + 3) / 6; }
+
+__device__ __forceinline__ void ldecode(int n, int s, int &i, int &j, int &k)
+{
+    const int q = ltc32(n) - s;
+    int m = (int)(cbrtf(6.0f * (float)q)) - 2;
+    m = m < 0 ? 0 : m;
+    while (ltc32(m) < q) ++m;
+    while (m > 0 && ltc32(m - 1) >= q) --m;
+    k = n - m;
+    const int t = s - (ltc32(n) - ltc32(m));
+    int d = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+    while ((d + 1) * (d + 2) / 2 <= t) ++d;
+    while (d > 0 && d * (d + 1) / 2 > t) --d;
+    i = t - d * (d + 1) / 2;
+    j = d - i;
+}
+
+// slot offsets of the 14 neighbours (DIR order) of slot s = (i,j,k), sd = i+j, m = n-k
+__device__ __forceinline__ void lneighbours(int s, int sd, int m, int nb[NDIR])
+{
+    const int up = s + (m + 1) * (m + 2) / 2, dn = s - (m + 2) * (m + 3) / 2;
+    nb[0] = s + sd + 2; nb[1] = s + sd + 1; nb[2] = up; nb[3] = s + 1;
+    nb[4] = dn + sd + 2; nb[5] = dn + sd + 1; nb[6] = up + 1;
+    nb[7] = s - sd - 1; nb[8] = s - sd; nb[9] = dn; nb[10] = s - 1;
+    nb[11] = up - sd - 1; nb[12] = up - sd; nb[13] = dn - 1;
+}
+
+// round-to-nearest-even float -> bf16 bits
+__device__ __forceinline__ unsigned short to_bf16(float f)
+{
+    const unsigned int u = __float_as_uint(f);
+    const unsigned int r = u + 0x7FFFu + ((u >> 16) & 1u);
+    return (unsigned short)(r >> 16);
+}
+__device__ __forceinline__ float from_bf16(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
+
+// features of slot s (interior node assumed): 32 values and the scale
+__device__ __forceinline__ void node_features(const LevelView<float> &L, const float *__restrict__ r,
+                                              const float *__restrict__ logk, int64_t base, int s,
+                                              int sd, int k, float x[LN_IN], float &scale)
+{
+    int nb[NDIR];
+    lneighbours(s, sd, L.n - k, nb);
+    float rp[15], lp[15];
+    rp[0] = r[base + s];
+    lp[0] = logk[base + s];
+#pragma unroll
+    for (int d = 0; d < NDIR; ++d) {
+        rp[d + 1] = r[base + nb[d]];
+        lp[d + 1] = logk[base + nb[d]];
+    }
+    float m = 0.0f;
+#pragma unroll
+    for (int p = 0; p < 15; ++p) m = fmaxf(m, fabsf(rp[p]));
+    scale = m + 1e-30f;
+#pragma unroll
+    for (int p = 0; p < 15; ++p) {
+        x[p] = rp[p] / scale;
+        x[15 + p] = lp[p] - lp[0];
+    }
+    x[30] = 0.0f;
+    x[31] = 0.0f;
+}
+
+// ---------------------------------------------------------------- forward (MFMA)
+// c[slot] = network output, sc[slot] = s * c, s_out[slot] = s (each nullable)
+__global__ __launch_bounds__(BLOCK) void k_learned_fwd(LevelView<float> L, const float *__restrict__ r,
+                                                       const float *__restrict__ logk,
+                                                       const unsigned short *__restrict__ wbf,
+                                                       float *__restrict__ c_out, float *__restrict__ sc_out,
+                                                       float *__restrict__ s_out)
+{
+    __shared__ unsigned short xs[BLOCK][LN_IN + 4];  // bf16 features (row padded)
+    __shared__ float cs[BLOCK];
+    const int per_tet = L.bpt;
+    const int tet = blockIdx.x / per_tet;
+    const int s = (blockIdx.x - tet * per_tet) * BLOCK + threadIdx.x;
+    const int64_t base = (int64_t)tet * L.Spad;
+    bool interior = false;
+    float scale = 0.0f;
+    int i = 0, j = 0, k = 0;
+    if (tet < L.n_tet && s < L.S) {
+        ldecode(L.n, s, i, j, k);
+        interior = i > 0 && j > 0 && k > 0 && i + j + k < L.n;
+    }
+    {
+        float x[LN_IN];
+        if (interior) {
+            node_features(L, r, logk, base, s, i + j, k, x, scale);
+        } else {
+#pragma unroll
+            for (int f = 0; f < LN_IN; ++f) x[f] = 0.0f;
+        }
+#pragma unroll
+        for (int f = 0; f < LN_IN; ++f) xs[threadIdx.x][f] = to_bf16(x[f]);
+    }
+    __syncthreads();
+    // per-lane weight operands: W1 (two K halves), W2, biases, w3
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int row = lane & 15, kq = 4 * (lane >> 4);
+    bf16x4 a1lo, a1hi, a2;
+    for (int q = 0; q < 4; ++q) {
+        a1lo[q] = (short)wbf[row * 32 + kq + q];
+        a1hi[q] = (short)wbf[row * 32 + 16 + kq + q];
+        a2[q] = (short)wbf[528 + row * 16 + kq + q];
+    }
+    float b1v[4], b2v[4], w3v[4];
+    for (int q = 0; q < 4; ++q) {
+        b1v[q] = from_bf16(wbf[512 + kq + q]);
+        b2v[q] = from_bf16(wbf[784 + kq + q]);
+        w3v[q] = from_bf16(wbf[800 + kq + q]);
+    }
+    const float b3 = from_bf16(wbf[816]);
+    for (int g = 0; g < 4; ++g) {
+        const int node = wave * 64 + g * 16 + row;  // the node this lane feeds
+        bf16x4 xlo, xhi;
+        for (int q = 0; q < 4; ++q) {
+            xlo[q] = (short)xs[node][kq + q];
+            xhi[q] = (short)xs[node][16 + kq + q];
+        }
+        f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1lo, xlo, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1hi, xhi, acc, 0, 0, 0);
+        bf16x4 h1;
+        for (int q = 0; q < 4; ++q) h1[q] = (short)to_bf16(fmaxf(acc[q] + b1v[q], 0.0f));
+        f32x4 acc2 = {0.0f, 0.0f, 0.0f, 0.0f};
+        acc2 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2, h1, acc2, 0, 0, 0);
+        float part = 0.0f;
+        for (int q = 0; q < 4; ++q) part += w3v[q] * fmaxf(acc2[q] + b2v[q], 0.0f);
+        part += __shfl_xor(part, 16, 64);
+        part += __shfl_xor(part, 32, 64);
+        if (lane < 16) cs[wave * 64 + g * 16 + lane] = part + b3;
+    }
+    __syncthreads();
+    if (tet < L.n_tet && s < L.S) {
+        const float c = interior ? cs[threadIdx.x] : 0.0f;
+        if (c_out) c_out[base + s] = c;
+        if (sc_out) sc_out[base + s] = interior ? c * scale : 0.0f;
+        if (s_out) s_out[base + s] = interior ? scale : 0.0f;
+    }
+}
+
+template <>
+hipError_t launch_learned_forward<float>(const LevelView<float> &L, const LearnedState &S,
+                                         const float *r, const float *logk, float *c, hipStream_t st)
+{
+    k_learned_fwd<<<L.n_tet * L.bpt, BLOCK, 0, st>>>(L, r, logk, S.wbf, c, nullptr, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_learned_forward_full(const LevelView<float> &L, const LearnedState &S,
+                                       const float *r, const float *logk, float *c, float *sc,
+                                       float *s, hipStream_t st)
+{
+    k_learned_fwd<<<L.n_tet * L.bpt, BLOCK, 0, st>>>(L, r, logk, S.wbf, c, sc, s);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- backward (FP32)
+// Per block of LBW nodes: recompute the forward in FP32 (same bf16 roundings),
+// back-propagate g, and sum the per-node outer products over the block into
+// one partial gradient (817 floats) per block; a second kernel adds the
+// partials in block order.
+constexpr int LBW = 128;
+constexpr int LROW = 32 + 16 + 16 + 16 + 16 + 1;  // x, h1, dz1, dz2, h2, g per node
+
+__global__ __launch_bounds__(LBW) void k_learned_bwd(LevelView<float> L, const float *__restrict__ r,
+                                                     const float *__restrict__ logk,
+                                                     const unsigned short *__restrict__ wbf,
+                                                     const float *__restrict__ gvec,
+                                                     float *__restrict__ gpart)
+{
+    __shared__ float buf[LBW][LROW + 1];
+    const int per_tet = (L.S + LBW - 1) / LBW;
+    const int tet = blockIdx.x / per_tet;
+    const int s = (blockIdx.x - tet * per_tet) * LBW + threadIdx.x;
+    const int64_t base = (int64_t)tet * L.Spad;
+    float *me = buf[threadIdx.x];
+    bool interior = false;
+    int i = 0, j = 0, k = 0;
+    if (tet < L.n_tet && s < L.S) {
+        ldecode(L.n, s, i, j, k);
+        interior = i > 0 && j > 0 && k > 0 && i + j + k < L.n;
+    }
+    if (interior) {
+        float x[LN_IN], scale;
+        node_features(L, r, logk, base, s, i + j, k, x, scale);
+        for (int f = 0; f < LN_IN; ++f) x[f] = from_bf16(to_bf16(x[f]));
+        float h1[16], z1p[16], h2[16], z2p[16];
+        for (int h = 0; h < 16; ++h) {
+            float a = 0.0f;
+            for (int f = 0; f < LN_IN; ++f) a += from_bf16(wbf[h * 32 + f]) * x[f];
+            const float z = a + from_bf16(wbf[512 + h]);
+            z1p[h] = z > 0.0f ? 1.0f : 0.0f;
+            h1[h] = from_bf16(to_bf16(fmaxf(z, 0.0f)));
+        }
+        for (int h = 0; h < 16; ++h) {
+            float a = 0.0f;
+            for (int q = 0; q < 16; ++q) a += from_bf16(wbf[528 + h * 16 + q]) * h1[q];
+            const float z = a + from_bf16(wbf[784 + h]);
+            z2p[h] = z > 0.0f ? 1.0f : 0.0f;
+            h2[h] = fmaxf(z, 0.0f);
+        }
+        const float g = gvec[base + s];
+        float dz2[16], dz1[16];
+        for (int h = 0; h < 16; ++h) dz2[h] = g * from_bf16(wbf[800 + h]) * z2p[h];
+        for (int q = 0; q < 16; ++q) {
+            float a = 0.0f;
+            for (int h = 0; h < 16; ++h) a += from_bf16(wbf[528 + h * 16 + q]) * dz2[h];
+            dz1[q] = a * z1p[q];
+        }
+        for (int f = 0; f < 32; ++f) me[f] = x[f];
+        for (int h = 0; h < 16; ++h) {
+            me[32 + h] = h1[h];
+            me[48 + h] = dz1[h];
+            me[64 + h] = dz2[h];
+            me[80 + h] = h2[h];
+        }
+        me[96] = g;
+    } else {
+        for (int q = 0; q < LROW; ++q) me[q] = 0.0f;
+    }
+    __syncthreads();
+    // parameter p of the block partial: sum over the block's nodes
+    float *out = gpart + (int64_t)blockIdx.x * LN_NPARAM;
+    for (int p = threadIdx.x; p < LN_NPARAM; p += LBW) {
+        float a = 0.0f;
+        if (p < 512) {            // dW1[h][f] = dz1[h] x[f]
+            const int h = p >> 5, f = p & 31;
+            for (int q = 0; q < LBW; ++q) a += buf[q][48 + h] * buf[q][f];
+        } else if (p < 528) {     // db1
+            for (int q = 0; q < LBW; ++q) a += buf[q][48 + p - 512];
+        } else if (p < 784) {     // dW2[h][q'] = dz2[h] h1[q']
+            const int h = (p - 528) >> 4, q2 = (p - 528) & 15;
+            for (int q = 0; q < LBW; ++q) a += buf[q][64 + h] * buf[q][32 + q2];
+        } else if (p < 800) {     // db2
+            for (int q = 0; q < LBW; ++q) a += buf[q][64 + p - 784];
+        } else if (p < 816) {     // dw3 = g h2
+            for (int q = 0; q < LBW; ++q) a += buf[q][96] * buf[q][80 + p - 800];
+        } else {                  // db3
+            for (int q = 0; q < LBW; ++q) a += buf[q][96];
+        }
+        out[p] = a;
+    }
+}
+
+__global__ void k_learned_gred(const float *__restrict__ gpart, int nblk, float *__restrict__ g)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= LN_NPARAM) return;
+    double a = 0.0;
+    for (int b = 0; b < nblk; ++b) a += (double)gpart[(int64_t)b * LN_NPARAM + p];
+    g[p] = (float)a;
+}
+
+int learned_bwd_blocks(const LevelView<float> &L) { return L.n_tet * ((L.S + LBW - 1) / LBW); }
+
+hipError_t launch_learned_backward(const LevelView<float> &L, const LearnedState &S, const float *r,
+                                   const float *logk, const float *g, hipStream_t st)
+{
+    const int nb = learned_bwd_blocks(L);
+    k_learned_bwd<<<nb, LBW, 0, st>>>(L, r, logk, S.wbf, g, S.gpart);
+    k_learned_gred<<<(LN_NPARAM + 255) / 256, 256, 0, st>>>(S.gpart, nb, S.dgrad);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- smoothing update
+// u += D^{-1} (omega r + s c): damped Jacobi plus the learned correction
+// (sc = s c is 0 where the network is not applied)
+__global__ void k_learned_update(float *__restrict__ u, const float *__restrict__ r,
+                                 const float *__restrict__ sc, const float *__restrict__ invd,
+                                 float omega, int64_t n)
+{
+    const int64_t q = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (q < n) u[q] += invd[q] * (omega * r[q] + sc[q]);
+}
+hipError_t launch_learned_update(float *u, const float *r, const float *sc, const float *invd,
+                                 float omega, int64_t n, hipStream_t st)
+{
+    k_learned_update<<<(int)((n + BLOCK - 1) / BLOCK), BLOCK, 0, st>>>(u, r, sc, invd, omega, n);
+    return hipGetLastError();
+}
+
+// training: e1 = e - D^{-1}(omega r + s c)
+__global__ void k_learned_err(const float *__restrict__ e, const float *__restrict__ r,
+                              const float *__restrict__ sc, const float *__restrict__ invd,
+                              float omega, float *__restrict__ e1, int64_t n)
+{
+    const int64_t q = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (q < n) e1[q] = e[q] - invd[q] * (omega * r[q] + sc[q]);
+}
+hipError_t launch_learned_err(const float *e, const float *r, const float *sc, const float *invd,
+                              float omega, float *e1, int64_t n, hipStream_t st)
+{
+    k_learned_err<<<(int)((n + BLOCK - 1) / BLOCK), BLOCK, 0, st>>>(e, r, sc, invd, omega, e1, n);
+    return hipGetLastError();
+}
+
+// training: g = -2 (A e1) s D^{-1} / E0 on nodes with a network output
+__global__ void k_learned_lossgrad(const float *__restrict__ ae1, const float *__restrict__ s,
+                                   const float *__restrict__ invd, double inv_e0,
+                                   float *__restrict__ g, int64_t n)
+{
+    const int64_t q = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (q < n) g[q] = (float)(-2.0 * (double)ae1[q] * (double)s[q] * (double)invd[q] * inv_e0);
+}
+hipError_t launch_learned_lossgrad(const float *ae1, const float *s, const float *invd, double inv_e0,
+                                   float *g, int64_t n, hipStream_t st)
+{
+    k_learned_lossgrad<<<(int)((n + BLOCK - 1) / BLOCK), BLOCK, 0, st>>>(ae1, s, invd, inv_e0, g, n);
+    return hipGetLastError();
+}
+
+// weighted dot product sum_q w_q a_q b_q (w = 1 on one copy of every unknown)
+__global__ __launch_bounds__(BLOCK) void k_dot_owned(const float *__restrict__ a, const float *__restrict__ b,
+                                                     const uint8_t *__restrict__ own, int64_t n,
+                                                     double *__restrict__ partial)
+{
+    __shared__ double red[BLOCK / 64];
+    const int64_t q = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    double v = (q < n && own[q]) ? (double)a[q] * (double)b[q] : 0.0;
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < BLOCK / 64; ++w) v += red[w];
+        partial[blockIdx.x] = v;
+    }
+}
+hipError_t launch_dot_owned(const float *a, const float *b, const uint8_t *own, int64_t n,
+                            double *partial, int *nblk, hipStream_t st)
+{
+    *nblk = (int)((n + BLOCK - 1) / BLOCK);
+    k_dot_owned<<<*nblk, BLOCK, 0, st>>>(a, b, own, n, partial);
+    return hipGetLastError();
+}
+
+// log k rounded to FP32 (log in FP64)
+__global__ void k_logk(const double *__restrict__ k, float *__restrict__ lk, int64_t n)
+{
+    const int64_t q = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (q < n) lk[q] = (float)log(k[q]);
+}
+hipError_t launch_logk(const double *k, float *lk, int64_t n, hipStream_t st)
+{
+    k_logk<<<(int)((n + BLOCK - 1) / BLOCK), BLOCK, 0, st>>>(k, lk, n);
+    return hipGetLastError();
+}
+
+// FP32 master weights -> BF16 bits
+__global__ void k_to_bf16(const float *__restrict__ w, unsigned short *__restrict__ wb, int n)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) wb[q] = to_bf16(w[q]);
+}
+hipError_t launch_weights_bf16(const float *w, unsigned short *wb, int n, hipStream_t st)
+{
+    k_to_bf16<<<(n + 255) / 256, 256, 0, st>>>(w, wb, n);
+    return hipGetLastError();
+}
+
+// training pair: r = (float) r64, e = (float)(u* - u)
+__global__ void k_pair(const double *__restrict__ r64, const double *__restrict__ us,
+                       const double *__restrict__ u, float *__restrict__ r, float *__restrict__ e,
+                       int64_t n)
+{
+    const int64_t q = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (q < n) {
+        r[q] = (float)r64[q];
+        e[q] = (float)(us[q] - u[q]);
+    }
+}
+hipError_t launch_pair(const double *r64, const double *us, const double *u, float *r, float *e,
+                       int64_t n, hipStream_t st)
+{
+    k_pair<<<(int)((n + BLOCK - 1) / BLOCK), BLOCK, 0, st>>>(r64, us, u, r, e, n);
+    return hipGetLastError();
+}
+
+}  // namespace hhg

@@ -16,7 +16,7 @@ F64, F32 = 0, 1
 JACOBI, CHEBYSHEV, LEARNED = 0, 1, 2
 SOLVE_F64, SOLVE_MIXED, SOLVE_LEARNED = 0, 1, 2
 FLAG_NO_MODIFICATION = 1
-LEARNED_NPARAM = 801
+LEARNED_NPARAM = 817
 WFALLBACK = 1
 
 # every symbol include/hhg.h declares
@@ -24,8 +24,9 @@ EXPORTS = [
     "hhg_create_macro", "hhg_destroy", "hhg_last_error", "hhg_vector_size", "hhg_node_coords",
     "hhg_to_canonical", "hhg_from_canonical", "hhg_set_coefficient", "hhg_set_coarse_level",
     "hhg_level_info", "hhg_apply_scaled", "hhg_apply_nodal", "hhg_residual", "hhg_smooth",
-    "hhg_vcycle", "hhg_solve", "hhg_learned_set_weights", "hhg_learned_forward",
-    "hhg_learned_backward",
+    "hhg_vcycle", "hhg_solve", "hhg_learned_set_weights", "hhg_learned_set_fallback",
+    "hhg_learned_forward", "hhg_learned_backward", "hhg_learned_loss_grad", "hhg_training_pair",
+    "hhg_adam_update",
 ]
 
 
@@ -70,8 +71,12 @@ def load():
         "hhg_vcycle": [P, I32, I32, I32, I32, I32, P, P, P, P],
         "hhg_solve": [P, I32, I32, I32, I32, D, I32, P, P, P, P],
         "hhg_learned_set_weights": [P, P, I64],
+        "hhg_learned_set_fallback": [P, D],
         "hhg_learned_forward": [P, I32, P, P, P],
         "hhg_learned_backward": [P, I32, P, P, P, P],
+        "hhg_learned_loss_grad": [P, I32, P, P, P, P, P],
+        "hhg_training_pair": [P, I32, P, P, P, P, P, P],
+        "hhg_adam_update": [P, P, P, P, I64, I32, D, D, D, D],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -230,3 +235,24 @@ class Context:
         dw = np.zeros(LEARNED_NPARAM, dtype=np.float32)
         self._check(load().hhg_learned_backward(self._h, level, _ptr(r), _ptr(g), _ptr(dw), _stream()))
         return dw
+
+    def learned_set_fallback(self, max_rate):
+        self._check(load().hhg_learned_set_fallback(self._h, float(max_rate)))
+
+    def learned_loss_grad(self, level, r, e):
+        dw = np.zeros(LEARNED_NPARAM, dtype=np.float32)
+        loss = ctypes.c_double()
+        self._check(load().hhg_learned_loss_grad(self._h, level, _ptr(r), _ptr(e), ctypes.byref(loss),
+                                                 _ptr(dw), _stream()))
+        return loss.value, dw
+
+    def training_pair(self, level, f, u, u_star, r_out, e_out):
+        self._check(load().hhg_training_pair(self._h, level, _ptr(f), _ptr(u), _ptr(u_star), _ptr(r_out),
+                                             _ptr(e_out), _stream()))
+
+
+def adam_update(w, m, v, g, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    """Adam step in the library (host) on numpy float32 arrays, in place."""
+    s = load().hhg_adam_update(_ptr(w), _ptr(m), _ptr(v), _ptr(g), w.size, int(t), lr, beta1, beta2, eps)
+    if s < 0:
+        raise HHGError(s, "adam update failed")
