@@ -286,6 +286,10 @@ struct hhg_ctx_s {
     std::string err;
     // learned correction
     LearnedState learned;
+    // optional timing of the operator kernels of hhg_apply_scaled (event pairs)
+    bool timing = false;
+    std::vector<hipEvent_t> tev;
+    size_t tev_used = 0;
 };
 
 namespace {
@@ -741,7 +745,21 @@ template <typename T>
 hhg_status apply_scaled_t(hhg_ctx c, int l, const T *u, T *y, hipStream_t st)
 {
     LevelView<T> V = view<T>(c, l);
-    HIPCHK(c, launch_scaled<T>(V, MODE_APPLY, u, nullptr, y, nullptr, nullptr, st));
+    if (c->timing) {
+        if (c->tev_used + 2 > c->tev.size()) {
+            for (int q = 0; q < 2; ++q) {
+                hipEvent_t e;
+                HIPCHK(c, hipEventCreate(&e));
+                c->tev.push_back(e);
+            }
+        }
+        HIPCHK(c, hipEventRecord(c->tev[c->tev_used], st));
+        HIPCHK(c, launch_scaled<T>(V, MODE_APPLY, u, nullptr, y, nullptr, nullptr, st));
+        HIPCHK(c, hipEventRecord(c->tev[c->tev_used + 1], st));
+        c->tev_used += 2;
+    } else {
+        HIPCHK(c, launch_scaled<T>(V, MODE_APPLY, u, nullptr, y, nullptr, nullptr, st));
+    }
     HIPCHK(c, launch_correction<T>(V, corr<T>(c, l), MODE_APPLY, u, y, nullptr, st));
     return HHG_OK;
 }
@@ -1284,6 +1302,7 @@ hhg_status hhg_destroy(hhg_ctx c)
     if (!c) return HHG_OK;
     (void)hipDeviceSynchronize();
     for (void *p : c->allocs) (void)hipFree(p);
+    for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
     if (c->hscalar) (void)hipHostFree(c->hscalar);
     delete c;
     return HHG_OK;
@@ -1433,6 +1452,30 @@ hhg_status hhg_apply_scaled(hhg_ctx c, int32_t level, hhg_dtype dt, const void *
     if (dt == HHG_F64) return apply_scaled_t<double>(c, level, (const double *)u, (double *)y, st);
     if (dt == HHG_F32) return apply_scaled_t<float>(c, level, (const float *)u, (float *)y, st);
     return fail(c, HHG_EINVAL, "bad dtype");
+}
+
+hhg_status hhg_set_timing(hhg_ctx c, int32_t enable)
+{
+    if (!c) return HHG_EINVAL;
+    c->timing = enable != 0;
+    c->tev_used = 0;
+    return HHG_OK;
+}
+
+hhg_status hhg_read_timing(hhg_ctx c, double *ms_total, int64_t *launches)
+{
+    if (!c || !ms_total || !launches) return HHG_EINVAL;
+    double tot = 0.0;
+    for (size_t q = 0; q + 1 < c->tev_used; q += 2) {
+        HIPCHK(c, hipEventSynchronize(c->tev[q + 1]));
+        float ms = 0.0f;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->tev[q], c->tev[q + 1]));
+        tot += ms;
+    }
+    *ms_total = tot;
+    *launches = (int64_t)(c->tev_used / 2);
+    c->tev_used = 0;
+    return HHG_OK;
 }
 
 hhg_status hhg_apply_nodal(hhg_ctx c, int32_t level, hhg_dtype dt, const void *u, void *y, void *stream)

@@ -23,7 +23,7 @@ WFALLBACK = 1
 EXPORTS = [
     "hhg_create_macro", "hhg_destroy", "hhg_last_error", "hhg_vector_size", "hhg_node_coords",
     "hhg_to_canonical", "hhg_from_canonical", "hhg_set_coefficient", "hhg_set_coarse_level",
-    "hhg_level_info", "hhg_apply_scaled", "hhg_apply_nodal", "hhg_residual", "hhg_smooth",
+    "hhg_level_info", "hhg_apply_scaled", "hhg_set_timing", "hhg_read_timing", "hhg_apply_nodal", "hhg_residual", "hhg_smooth",
     "hhg_vcycle", "hhg_solve", "hhg_learned_set_weights", "hhg_learned_set_fallback",
     "hhg_learned_forward", "hhg_learned_backward", "hhg_learned_loss_grad", "hhg_training_pair",
     "hhg_adam_update",
@@ -65,6 +65,8 @@ def load():
         "hhg_set_coarse_level": [P, I32],
         "hhg_level_info": [P, I32, P, P, P],
         "hhg_apply_scaled": [P, I32, I32, P, P, P],
+        "hhg_set_timing": [P, I32],
+        "hhg_read_timing": [P, P, P],
         "hhg_apply_nodal": [P, I32, I32, P, P, P],
         "hhg_residual": [P, I32, I32, P, P, P, P, P],
         "hhg_smooth": [P, I32, I32, I32, I32, D, P, P, P],
@@ -193,6 +195,15 @@ class Context:
     def apply_scaled(self, level, u, y):
         self._check(load().hhg_apply_scaled(self._h, level, _dtype_code(u), _ptr(u), _ptr(y), _stream()))
         return y
+
+    def set_timing(self, enable):
+        self._check(load().hhg_set_timing(self._h, 1 if enable else 0))
+
+    def read_timing(self):
+        """(summed ms of the timed applies' stencil kernels, number of applies)"""
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        self._check(load().hhg_read_timing(self._h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
 
     def apply_nodal(self, level, u, y):
         self._check(load().hhg_apply_nodal(self._h, level, _dtype_code(u), _ptr(u), _ptr(y), _stream()))
