@@ -26,7 +26,7 @@ sys.path.insert(0, ROOT)
 METRIC = "scaled-stencil matvec GDoF/s + %HBM peak; V-cycle time to 1e-8 rel. residual"
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_DOF = {"f64": 24, "f32": 12}   # read u and k, write y (perfect neighbour reuse)
-PROFILE = os.path.join(ROOT, "profiles", "traffic_scaled_volume_f64_unit_tet_l8.txt")
+PROFILE = os.path.join(ROOT, "profiles", "traffic_k_march_scaled_f64_unit_tet_l8.txt")
 CSRC = os.path.join(ROOT, "paper_1709_06793_amd", "csrc")
 
 
