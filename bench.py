@@ -243,8 +243,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
-                     "kernel": "k_march<double, MODE_APPLY, scaled> (interior rows; the unit tet has no "
-                               "inter-tet rows)",
+                     "kernel": "k_march2<double, MODE_APPLY, scaled> (interior rows, two per lane; the unit "
+                               "tet has no inter-tet rows)",
                      "kernel_ms": round(k_ms, 5),
                      "algorithmic_bytes_per_launch": BYTES_PER_DOF["f64"] * nu,
                      "other_kernels": f"k_correction<double> ({n_mod} modified edges) once per apply"},

@@ -227,6 +227,9 @@ struct Level {
     std::vector<uint32_t> h_items;  // pairs (t0, k0 | k1 << 16)
     std::vector<uint32_t> h_bnd;
     uint2 *items = nullptr;
+    std::vector<uint32_t> h_items2;  // two-rows-per-lane kernel
+    uint2 *items2 = nullptr;
+    int n_items2 = 0, kc2 = 0;
     uint32_t *bnd = nullptr;
     int n_items = 0, n_bnd = 0, kc = 0;
     // shared nodes
@@ -458,6 +461,7 @@ LevelView<double> view<double>(const hhg_ctx c, int l)
     v.dmask = L.dmask; v.smask = L.smask; v.kap = L.k64;
     v.n_shared = L.n_shared; v.sh_off = L.sh_off; v.sh_copy = L.sh_copy;
     v.items = L.items; v.n_items = L.n_items; v.vpt = (L.n_items + 3) / 4;
+    v.items2 = L.items2; v.n_items2 = L.n_items2; v.vpt2 = (L.n_items2 + 3) / 4;
     v.bnd = L.bnd; v.n_bnd = L.n_bnd; v.bpt2 = (L.n_bnd + BLOCK - 1) / BLOCK;
     return v;
 }
@@ -471,6 +475,7 @@ LevelView<float> view<float>(const hhg_ctx c, int l)
     v.dmask = L.dmask; v.smask = L.smask; v.kap = L.k32;
     v.n_shared = L.n_shared; v.sh_off = L.sh_off; v.sh_copy = L.sh_copy;
     v.items = L.items; v.n_items = L.n_items; v.vpt = (L.n_items + 3) / 4;
+    v.items2 = L.items2; v.n_items2 = L.n_items2; v.vpt2 = (L.n_items2 + 3) / 4;
     v.bnd = L.bnd; v.n_bnd = L.n_bnd; v.bpt2 = (L.n_bnd + BLOCK - 1) / BLOCK;
     return v;
 }
@@ -576,6 +581,18 @@ hhg_status build_level(hhg_ctx c, int l)
             double *rw = &L.h_rstw[(size_t)t * TET_STENCIL + zp * KIND_STRIDE];
             for (int d = 0; d < NDIR; ++d) row[d] = 0.5 * st[d];
             row[NDIR] = st[NDIR];
+            if (zp == 0) {
+                // interior stencil: entries of opposite directions are equal
+                // (symmetric element matrices, translation invariance inside
+                // the tet); the interior kernel uses one weight per pair
+                double mx = 0.0;
+                for (int d = 0; d < NDIR; ++d) mx = std::max(mx, std::fabs(row[d]));
+                for (int d = 0; d < NDIR / 2; ++d) {
+                    if (std::fabs(row[d] - row[d + NDIR / 2]) > 1e-12 * mx)
+                        return fail(c, HHG_EMESH, "tet %d: interior stencil is not symmetric", t);
+                    row[d] = row[d + NDIR / 2] = 0.5 * (row[d] + row[d + NDIR / 2]);
+                }
+            }
             // restriction weights: 1/2 per coarse edge split evenly over the
             // tets holding that edge; the centre 1 split over the node's tets
             rw[NDIR] = 1.0 / tp.valence(t, zp);
@@ -627,35 +644,42 @@ hhg_status build_level(hhg_ctx c, int l)
             while (d > 0 && d * (d + 1) / 2 > t) --d;
             return d;
         };
-        std::vector<int> kcs = {32, 16, 8, 4};
-        if (const char *e = std::getenv("HHG_MARCH_KC")) {  // tuning override
-            const int v = std::atoi(e);
-            if (v >= 1 && v <= 1024) kcs = {v};
-        }
-        for (int kc : kcs) {
-            L.h_items.clear();
-            // k chunks outer, in-plane segments inner: the waves of one block
-            // then cover neighbouring diagonals of the same planes and share
-            // their loads through the CU's L1
-            std::vector<std::pair<int64_t, int>> seg;  // (t0, last interior plane)
-            for (int64_t t0 = 0; t0 < T0; t0 += 62) {
-                int64_t smin = -1;
-                for (int64_t t = t0; t < std::min<int64_t>(t0 + 62, T0); ++t) {
-                    const int64_t d = diag_of(t), i = t - d * (d + 1) / 2;
-                    if (d >= 2 && d <= n - 2 && i >= 1 && i <= d - 1) { smin = d; break; }
-                }
-                if (smin >= 0) seg.push_back({t0, (int)(n - 1 - smin)});
+        // items for waves of `width` rows: chunk length kc is the largest of
+        // 32/16/8/4 that still gives `target` waves over all tets
+        auto build_items = [&](int width, int64_t target, std::vector<uint32_t> &out, int &kc_out) {
+            std::vector<int> kcs = {32, 16, 8, 4};
+            if (const char *e = std::getenv("HHG_MARCH_KC")) {  // tuning override
+                const int v = std::atoi(e);
+                if (v >= 1 && v <= 1024) kcs = {v};
             }
-            for (int k0 = 1; k0 <= n - 3; k0 += kc)
-                for (const auto &sg : seg) {
-                    if (k0 > sg.second) continue;
-                    const int k1 = std::min(sg.second, k0 + kc - 1);
-                    L.h_items.push_back((uint32_t)sg.first);
-                    L.h_items.push_back((uint32_t)k0 | ((uint32_t)k1 << 16));
+            for (int kc : kcs) {
+                out.clear();
+                // k chunks outer, in-plane segments inner: the waves of one
+                // block then cover neighbouring diagonals of the same planes
+                // and share their loads through the CU's L1
+                std::vector<std::pair<int64_t, int>> seg;  // (t0, last interior plane)
+                for (int64_t t0 = 0; t0 < T0; t0 += width) {
+                    int64_t smin = -1;
+                    for (int64_t t = t0; t < std::min<int64_t>(t0 + width, T0); ++t) {
+                        const int64_t d = diag_of(t), i = t - d * (d + 1) / 2;
+                        if (d >= 2 && d <= n - 2 && i >= 1 && i <= d - 1) { smin = d; break; }
+                    }
+                    if (smin >= 0) seg.push_back({t0, (int)(n - 1 - smin)});
                 }
-            L.kc = kc;
-            if ((int64_t)tp.nt * (int64_t)(L.h_items.size() / 2) >= 8192) break;
-        }
+                for (int k0 = 1; k0 <= n - 3; k0 += kc)
+                    for (const auto &sg : seg) {
+                        if (k0 > sg.second) continue;
+                        const int k1 = std::min(sg.second, k0 + kc - 1);
+                        out.push_back((uint32_t)sg.first);
+                        out.push_back((uint32_t)k0 | ((uint32_t)k1 << 16));
+                    }
+                kc_out = kc;
+                if ((int64_t)tp.nt * (int64_t)(out.size() / 2) >= target) break;
+            }
+        };
+        build_items(62, 8192, L.h_items, L.kc);
+        build_items(126, 4096, L.h_items2, L.kc2);
+        L.n_items2 = (int)(L.h_items2.size() / 2);
         L.n_items = (int)(L.h_items.size() / 2);
         L.h_bnd.clear();
         for (int k = 0; k <= n; ++k)
@@ -669,6 +693,11 @@ hhg_status build_level(hhg_ctx c, int l)
         uint32_t *ip = nullptr;
         TRY(upload(c, &ip, items_copy));
         L.items = (uint2 *)ip;
+        std::vector<uint32_t> items2_copy = L.h_items2;
+        uint32_t *ip2 = nullptr;
+        if (items2_copy.empty()) items2_copy.assign(2, 0u);  // never read when n_items2 == 0
+        TRY(upload(c, &ip2, items2_copy));
+        L.items2 = (uint2 *)ip2;
         TRY(upload(c, &L.bnd, L.h_bnd));
     }
 
@@ -1277,7 +1306,10 @@ hhg_status hhg_create_macro(const double *vert_xyz, int32_t n_vert, const int32_
         int64_t pc = 1024;
         for (int l = 0; l <= max_level; ++l) {
             const Level &L = c->lv[l];
-            const int64_t gv = ((int64_t)tp.nt * L.bpt + 7) / 8 * 8;
+            const int64_t bp2 = (L.n_bnd + BLOCK - 1) / BLOCK;
+            const int64_t gm = std::max((int64_t)tp.nt * ((L.n_items + 3) / 4 + bp2),
+                                        (int64_t)tp.nt * ((L.n_items2 + 3) / 4 + bp2));
+            const int64_t gv = (std::max((int64_t)tp.nt * L.bpt, gm) + 7) / 8 * 8;
             pc = std::max(pc, gv + (L.n_shared + BLOCK - 1) / BLOCK + (L.n_slots + BLOCK - 1) / BLOCK + 8);
         }
         c->partial_cap = pc;

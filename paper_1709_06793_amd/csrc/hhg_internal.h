@@ -24,6 +24,10 @@ struct LevelView {
     const uint2 *items;
     int n_items;
     int vpt;        // marching blocks per tet
+    // the same for the two-rows-per-lane kernel (first row offset of 126)
+    const uint2 *items2;
+    int n_items2;
+    int vpt2;
     const uint32_t *bnd;
     int n_bnd;
     int bpt2;       // boundary blocks per tet

@@ -207,13 +207,108 @@ __device__ __forceinline__ T row_value(const T uu[NDIR + 1], const T kk[NDIR + 1
     return acc;
 }
 
-// PF: planes loaded ahead of the one being computed; WPE: waves per SIMD the
-// register budget must allow
-template <typename T, int MODE, int OP, int PF, int WPE>
+// buffer stores relative to one tet's slot array; the whole byte offset is
+// in the per-lane offset, which the range check covers: a store at an offset
+// at or beyond the range is dropped
+__device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, int voff)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v),
+                                          r, voff, 0, 0);
+}
+__device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r, int voff)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, 0, 0);
+}
+
+// one plane of a wave's columns: anti-diagonals s-1, s, s+1 at the lane's
+// position for u and k (and f), plus the lane-shifted copies the rows use
+template <typename T>
+struct MPlane {
+    T u[3], k[3], f;
+    T u_sm_l, u_s_l, u_s_r, u_sp_r;
+    T k_sm_l, k_s_l, k_s_r, k_sp_r;
+};
+
+// plane starting at slot P: in-plane offsets o[3] (slots).  Every load of a
+// slot outside the tet's range (planes past the top included) returns 0.
+template <typename T, int MODE>
+__device__ __forceinline__ void mplane_load(MPlane<T> &p, __amdgpu_buffer_rsrc_t ru,
+                                            __amdgpu_buffer_rsrc_t rk, __amdgpu_buffer_rsrc_t rf,
+                                            const int o[3], int P)
+{
+#pragma unroll
+    for (int c = 0; c < 3; ++c) p.u[c] = bload<T>(ru, P + o[c]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) p.k[c] = bload<T>(rk, P + o[c]);
+    if (MODE == MODE_RESID) p.f = bload<T>(rf, P + o[1]);
+}
+
+// shifted copies a plane needs as plane k+1 (and again as plane k) ...
+template <typename T>
+__device__ __forceinline__ void mplane_shift_up(MPlane<T> &p)
+{
+    p.u_sm_l = dpp_prev(p.u[0]);
+    p.u_s_r = dpp_next(p.u[1]);
+    p.k_sm_l = dpp_prev(p.k[0]);
+    p.k_s_r = dpp_next(p.k[1]);
+}
+// ... and those it needs as plane k (and again as plane k-1)
+template <typename T>
+__device__ __forceinline__ void mplane_shift_mid(MPlane<T> &p)
+{
+    p.u_s_l = dpp_prev(p.u[1]);
+    p.u_sp_r = dpp_next(p.u[2]);
+    p.k_s_l = dpp_prev(p.k[1]);
+    p.k_sp_r = dpp_next(p.k[2]);
+}
+
+// scaled row with the weights of opposite directions paired (interior
+// stencils have w_d = w_{d+7}):
+//   y = sum_{d<7} w_d [(k0 + k_d)(u_d - u0) + (k0 + k_{d+7})(u_{d+7} - u0)]
+template <typename T>
+__device__ __forceinline__ T scaled_row_paired(const T uu[NDIR + 1], const T kk[NDIR + 1], const T wr[NDIR / 2])
+{
+    const T u0 = uu[NDIR], k0 = kk[NDIR];
+    T acc = T(0);
+#pragma unroll
+    for (int d = 0; d < NDIR / 2; ++d) {
+        const T a = (k0 + kk[d + NDIR / 2]) * (uu[d + NDIR / 2] - u0);
+        acc += wr[d] * ((k0 + kk[d]) * (uu[d] - u0) + a);
+    }
+    return acc;
+}
+
+// an empty register-to-register asm: the value passes unchanged, but the
+// compiler can no longer prove it equal to its earlier self, so lane shifts
+// of it are recomputed where used instead of being held in registers
+template <typename T>
+__device__ __forceinline__ void renew(T &v)
+{
+    asm("" : "+v"(v));
+}
+template <typename T>
+__device__ __forceinline__ void mplane_renew(MPlane<T> &p)
+{
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        renew(p.u[c]);
+        renew(p.k[c]);
+    }
+}
+
+// PF: planes in flight ahead of the ones in use; WPE: waves per SIMD the
+// register budget must allow; SH 0 holds a plane's lane-shifted copies for
+// the two steps that use them, SH 1 recomputes them at each use (fewer
+// registers, more lane moves).  NS = PF + 3 register sets rotate through the
+// roles plane k-1, k, k+1 and the planes in flight; the march is unrolled by
+// NS so the rotation is a renaming, not a copy, and a set is reloaded only
+// after its last use (each wait is then for the oldest plane in flight).
+template <typename T, int MODE, int OP, int PF, int WPE, int SH>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) void k_march(
     LevelView<T> L, const T *__restrict__ u, const T *__restrict__ f, T *__restrict__ y,
     double *__restrict__ partial)
 {
+    constexpr int NS = PF + 3;
     const int per_tet = L.vpt + L.bpt2;
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
     double sq = 0.0;
@@ -226,7 +321,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
             if (item < L.n_items) {
                 const uint2 it = L.items[item];
                 const int n = L.n, lane = threadIdx.x & 63;
-                const int k0 = (int)(it.y & 0xffffu), k1 = (int)(it.y >> 16);
+                const int k0 = __builtin_amdgcn_readfirstlane((int)(it.y & 0xffffu));
+                const int k1 = __builtin_amdgcn_readfirstlane((int)(it.y >> 16));
                 const int t = (int)it.x - 1 + lane;
                 int sd = t >= 0 ? (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f) : -1;
                 if (t >= 0) {
@@ -236,81 +332,263 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
                 const int i = t - sd * (sd + 1) / 2;
                 const bool row_lane = t >= 0 && lane >= 1 && lane <= 62 && i >= 1 && i <= sd - 1;
                 const int kend = n - 1 - sd;  // last interior plane of this column
-                const __amdgpu_buffer_rsrc_t ru = tet_rsrc(u + base, (int64_t)L.S * sizeof(T));
-                const __amdgpu_buffer_rsrc_t rk = tet_rsrc(L.kap + base, (int64_t)L.S * sizeof(T));
+                constexpr int B = (int)sizeof(T);
+                const __amdgpu_buffer_rsrc_t ru = tet_rsrc(u + base, (int64_t)L.S * B);
+                const __amdgpu_buffer_rsrc_t rk = tet_rsrc(L.kap + base, (int64_t)L.S * B);
+                const __amdgpu_buffer_rsrc_t rf = tet_rsrc(MODE == MODE_RESID ? f + base : u + base,
+                                                           (int64_t)L.S * B);
+                const __amdgpu_buffer_rsrc_t ry = tet_rsrc(y + base, (int64_t)L.S * B);
+                // in-plane offsets of diagonals s-1, s, s+1 at position i (a
+                // lane left of the tet's first column reads offset 0: in range
+                // and unused)
+                const int vo[3] = {t >= 0 ? t - sd : 0, t >= 0 ? t : 0, t >= 0 ? t + sd + 1 : 0};
+                const int Sn = tc32(n);
+                // first slot of plane p; for planes past the top (p <= n + 2NS)
+                // this is >= Sn, so their slots lie beyond the tet's range
+                auto plane = [&](int p) { return Sn - tc32(n - p); };
+                T wr[NDIR / 2];
                 const T *__restrict__ w = OP == 0 ? L.sten + (int64_t)tet * TET_STENCIL
                                                   : L.emat + (int64_t)tet * TET_EMAT;
-                const int Sn = tc32(n);
-                // in-plane offsets of diagonals s-1, s, s+1 at position i
-                const int om = t - sd, oc = t, op = t + sd + 1;
-                // plane k-1 (diagonals s, s+1), plane k (s-1, s, s+1), plane k+1 raw
-                int P = Sn - tc32(n - (k0 - 1));
-                T um_s = bload<T>(ru, P + oc), um_sp = bload<T>(ru, P + op);
-                T km_s = bload<T>(rk, P + oc), km_sp = bload<T>(rk, P + op);
-                P = Sn - tc32(n - k0);
-                T uc_sm = bload<T>(ru, P + om), uc_s = bload<T>(ru, P + oc), uc_sp = bload<T>(ru, P + op);
-                T kc_sm = bload<T>(rk, P + om), kc_s = bload<T>(rk, P + oc), kc_sp = bload<T>(rk, P + op);
-                P = Sn - tc32(n - (k0 + 1));
-                T up_sm = bload<T>(ru, P + om), up_s = bload<T>(ru, P + oc), up_sp = bload<T>(ru, P + op);
-                T kp_sm = bload<T>(rk, P + om), kp_s = bload<T>(rk, P + oc), kp_sp = bload<T>(rk, P + op);
-                // planes k0+2 .. k0+PF already in flight
-                T qu[PF][3], qk[PF][3];
+                if (OP == 0) {
 #pragma unroll
-                for (int q = 0; q < PF - 1; ++q) {
-                    const int Pq = Sn - tc32(n - (k0 + 2 + q));
-                    qu[q][0] = bload<T>(ru, Pq + om); qu[q][1] = bload<T>(ru, Pq + oc); qu[q][2] = bload<T>(ru, Pq + op);
-                    qk[q][0] = bload<T>(rk, Pq + om); qk[q][1] = bload<T>(rk, Pq + oc); qk[q][2] = bload<T>(rk, Pq + op);
+                    for (int d = 0; d < NDIR / 2; ++d) wr[d] = w[d];
                 }
-                T um_s_l = dpp_prev(um_s), um_sp_r = dpp_next(um_sp);
-                T km_s_l = dpp_prev(km_s), km_sp_r = dpp_next(km_sp);
-                T uc_sm_l = dpp_prev(uc_sm), uc_s_r = dpp_next(uc_s);
-                T kc_sm_l = dpp_prev(kc_sm), kc_s_r = dpp_next(kc_s);
-                for (int k = k0; k <= k1; ++k) {
-                    // load plane k+1+PF while plane k is computed (past the
-                    // chunk's end these loads are wasted but in range or 0)
-                    const int Pn = Sn - tc32(n - (k + 1 + PF));
-                    qu[PF - 1][0] = bload<T>(ru, Pn + om); qu[PF - 1][1] = bload<T>(ru, Pn + oc);
-                    qu[PF - 1][2] = bload<T>(ru, Pn + op);
-                    qk[PF - 1][0] = bload<T>(rk, Pn + om); qk[PF - 1][1] = bload<T>(rk, Pn + oc);
-                    qk[PF - 1][2] = bload<T>(rk, Pn + op);
-                    const T uc_s_l = dpp_prev(uc_s), uc_sp_r = dpp_next(uc_sp);
-                    const T kc_s_l = dpp_prev(kc_s), kc_sp_r = dpp_next(kc_sp);
-                    const T up_sm_l = dpp_prev(up_sm), up_s_r = dpp_next(up_s);
-                    const T kp_sm_l = dpp_prev(kp_sm), kp_s_r = dpp_next(kp_s);
-                    if (row_lane && k <= kend) {
+                MPlane<T> R[NS];
+#pragma unroll
+                for (int q = 0; q < NS; ++q) {
+                    mplane_load<T, MODE>(R[q], ru, rk, rf, vo, plane(k0 - 1 + q));
+                    // keep the sets in issue order (waits go by issue order)
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                mplane_shift_mid(R[0]);
+                mplane_shift_up(R[1]);
+                // the unrolled body has no branch: every lane computes, and a
+                // lane without a row at this plane (or a step past the chunk)
+                // stores to a byte offset beyond the tet's range, which the
+                // buffer range check drops.  The wait for a plane's loads is
+                // then the same at every step.
+                const int lastk = row_lane ? min(kend, k1) : -1;
+                constexpr int DROP = 0x7ffffff0;
+                for (int kb = k0; kb <= k1; kb += NS) {
+#pragma unroll
+                    for (int q = 0; q < NS; ++q) {
+                        const int k = kb + q;
+                        MPlane<T> &M = R[q % NS], &C = R[(q + 1) % NS], &P = R[(q + 2) % NS];
+                        if (SH) {
+                            mplane_renew(M);
+                            mplane_renew(C);
+                            mplane_renew(P);
+                            mplane_shift_mid(M);
+                            mplane_shift_up(C);
+                        }
+                        mplane_shift_mid(C);
+                        mplane_shift_up(P);
                         // neighbours in DIR order, centre last
-                        const T uu[NDIR + 1] = {uc_sp_r, uc_sp, up_s, uc_s_r, um_sp_r, um_sp, up_s_r,
-                                                uc_sm_l, uc_sm, um_s, uc_s_l, up_sm_l, up_sm, um_s_l, uc_s};
-                        const T kk[NDIR + 1] = {kc_sp_r, kc_sp, kp_s, kc_s_r, km_sp_r, km_sp, kp_s_r,
-                                                kc_sm_l, kc_sm, km_s, kc_s_l, kp_sm_l, kp_sm, km_s_l, kc_s};
-                        const T acc = row_value<T, OP>(uu, kk, w);
-                        const int64_t slot = base + (Sn - tc32(n - k)) + t;
+                        const T uu[NDIR + 1] = {C.u_sp_r, C.u[2], P.u[1], C.u_s_r, M.u_sp_r, M.u[2],
+                                                P.u_s_r, C.u_sm_l, C.u[0], M.u[1], C.u_s_l, P.u_sm_l,
+                                                P.u[0], M.u_s_l, C.u[1]};
+                        const T kk[NDIR + 1] = {C.k_sp_r, C.k[2], P.k[1], C.k_s_r, M.k_sp_r, M.k[2],
+                                                P.k_s_r, C.k_sm_l, C.k[0], M.k[1], C.k_s_l, P.k_sm_l,
+                                                P.k[0], M.k_s_l, C.k[1]};
+                        const T acc = OP == 0 ? scaled_row_paired<T>(uu, kk, wr) : row_value<T, OP>(uu, kk, w);
+                        const bool live = k <= lastk;
+                        const int so = live ? (plane(k) + vo[1]) * B : DROP;
                         if (MODE == MODE_APPLY) {
-                            y[slot] = acc;
+                            bstore(acc, ry, so);
                         } else {
-                            const T r = f[slot] - acc;
-                            y[slot] = r;
-                            sq += (double)r * (double)r;
+                            const T r = C.f - acc;
+                            bstore(r, ry, so);
+                            sq += live ? (double)r * (double)r : 0.0;
                         }
+                        // plane k-1 is done with: its set takes plane k-1+NS
+                        mplane_load<T, MODE>(M, ru, rk, rf, vo, plane(k - 1 + NS));
+                        __builtin_amdgcn_sched_barrier(0);
                     }
-                    // roll planes: k -> k-1, k+1 -> k, k+2 -> k+1, ...
-                    um_s = uc_s; um_sp = uc_sp; um_s_l = uc_s_l; um_sp_r = uc_sp_r;
-                    km_s = kc_s; km_sp = kc_sp; km_s_l = kc_s_l; km_sp_r = kc_sp_r;
-                    uc_sm = up_sm; uc_s = up_s; uc_sp = up_sp; uc_sm_l = up_sm_l; uc_s_r = up_s_r;
-                    kc_sm = kp_sm; kc_s = kp_s; kc_sp = kp_sp; kc_sm_l = kp_sm_l; kc_s_r = kp_s_r;
-                    up_sm = qu[0][0]; up_s = qu[0][1]; up_sp = qu[0][2];
-                    kp_sm = qk[0][0]; kp_s = qk[0][1]; kp_sp = qk[0][2];
-#pragma unroll
-                    for (int q = 0; q < PF - 1; ++q)
-#pragma unroll
-                        for (int c = 0; c < 3; ++c) {
-                            qu[q][c] = qu[q + 1][c];
-                            qk[q][c] = qk[q + 1][c];
-                        }
                 }
             }
         } else {
             const int e = (b - L.vpt) * BLOCK + threadIdx.x;
+            if (e < L.n_bnd) {
+                const uint32_t v = L.bnd[e];
+                if ((L.dmask[tet] >> (v & 15u)) & 1) y[base + (v >> 4)] = T(0);
+            }
+        }
+    }
+    if (MODE == MODE_RESID) {
+        sq = block_reduce(sq, 0);
+        if (threadIdx.x == 0) partial[blockIdx.x] = sq;
+    }
+}
+
+// ---------------------------------------------------------------- two rows per lane
+// The same column march with each lane holding two consecutive in-plane
+// offsets (x = t0 - 1 + 2 lane, y = x + 1), so one 16-byte (FP64) or 8-byte
+// (FP32) load per anti-diagonal serves two rows and a wave produces 126 rows
+// per plane (x of lane 0 and y of lane 63 only feed their neighbours).  Left
+// neighbours of y and right neighbours of x are in the lane itself; the
+// others come from the adjacent lanes.  Loads of diagonal s-1 start at y's
+// offset and those of s+1 at x's: when a lane straddles two diagonals (x the
+// last node of diagonal s, y the first of s+1) the pair then still holds the
+// value each element's row neighbours use (x's s-1 and y's s+1 values are
+// used by no row in that case).
+template <typename T>
+struct P2 {
+    T x, y;
+};
+template <typename T>
+__device__ __forceinline__ P2<T> bload2(__amdgpu_buffer_rsrc_t r, int idx);
+template <>
+__device__ __forceinline__ P2<double> bload2<double>(__amdgpu_buffer_rsrc_t r, int idx)
+{
+    const auto q = __builtin_amdgcn_raw_buffer_load_b128(r, idx * 8, 0, 0);
+    P2<double> v;
+    __builtin_memcpy(&v, &q, 16);
+    return v;
+}
+template <>
+__device__ __forceinline__ P2<float> bload2<float>(__amdgpu_buffer_rsrc_t r, int idx)
+{
+    const auto q = __builtin_amdgcn_raw_buffer_load_b64(r, idx * 4, 0, 0);
+    P2<float> v;
+    __builtin_memcpy(&v, &q, 8);
+    return v;
+}
+
+template <typename T>
+struct MPlane2 {
+    P2<T> u[3], k[3], f;
+};
+
+template <typename T, int MODE>
+__device__ __forceinline__ void mplane2_load(MPlane2<T> &p, __amdgpu_buffer_rsrc_t ru, __amdgpu_buffer_rsrc_t rk,
+                                             __amdgpu_buffer_rsrc_t rf, const int o[3], int P)
+{
+#pragma unroll
+    for (int c = 0; c < 3; ++c) p.u[c] = bload2<T>(ru, P + o[c]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) p.k[c] = bload2<T>(rk, P + o[c]);
+    if (MODE == MODE_RESID) p.f = bload2<T>(rf, P + o[1]);
+}
+
+// the 15 values of x's and y's rows for one array: planes M (k-1), C (k), P (k+1)
+template <typename T>
+__device__ __forceinline__ void gather2(const P2<T> *M, const P2<T> *C, const P2<T> *P, T vx[NDIR + 1],
+                                        T vy[NDIR + 1])
+{
+    // lane shifts: left of x = y of lane-1, right of y = x of lane+1
+    const T C_sm_lx = dpp_prev(C[0].y), C_s_lx = dpp_prev(C[1].y);
+    const T C_s_ry = dpp_next(C[1].x), C_sp_ry = dpp_next(C[2].x);
+    const T P_sm_lx = dpp_prev(P[0].y), P_s_ry = dpp_next(P[1].x);
+    const T M_sp_ry = dpp_next(M[2].x), M_s_lx = dpp_prev(M[1].y);
+    // DIR order: (1,0,0) (0,1,0) (0,0,1) (1,-1,0) (1,0,-1) (0,1,-1) (1,-1,1), negatives, centre
+    vx[0] = C[2].y;  vy[0] = C_sp_ry;   // s+1, i+1
+    vx[1] = C[2].x;  vy[1] = C[2].y;    // s+1, i
+    vx[2] = P[1].x;  vy[2] = P[1].y;    // plane k+1: s, i
+    vx[3] = C[1].y;  vy[3] = C_s_ry;    // s, i+1
+    vx[4] = M[2].y;  vy[4] = M_sp_ry;   // plane k-1: s+1, i+1
+    vx[5] = M[2].x;  vy[5] = M[2].y;    // plane k-1: s+1, i
+    vx[6] = P[1].y;  vy[6] = P_s_ry;    // plane k+1: s, i+1
+    vx[7] = C_sm_lx; vy[7] = C[0].x;    // s-1, i-1
+    vx[8] = C[0].x;  vy[8] = C[0].y;    // s-1, i
+    vx[9] = M[1].x;  vy[9] = M[1].y;    // plane k-1: s, i
+    vx[10] = C_s_lx; vy[10] = C[1].x;   // s, i-1
+    vx[11] = P_sm_lx; vy[11] = P[0].x;  // plane k+1: s-1, i-1
+    vx[12] = P[0].x; vy[12] = P[0].y;   // plane k+1: s-1, i
+    vx[13] = M_s_lx; vy[13] = M[1].x;   // plane k-1: s, i-1
+    vx[14] = C[1].x; vy[14] = C[1].y;   // centre
+}
+
+__device__ __forceinline__ void bstore_drop(double v, __amdgpu_buffer_rsrc_t r, int voff) { bstore(v, r, voff); }
+__device__ __forceinline__ void bstore_drop(float v, __amdgpu_buffer_rsrc_t r, int voff) { bstore(v, r, voff); }
+
+template <typename T, int MODE, int OP, int PF, int WPE>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) void k_march2(
+    LevelView<T> L, const T *__restrict__ u, const T *__restrict__ f, T *__restrict__ y,
+    double *__restrict__ partial)
+{
+    constexpr int NS = PF + 3;
+    const int per_tet = L.vpt2 + L.bpt2;
+    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    double sq = 0.0;
+    if (lb < L.n_tet * per_tet) {
+        const int tet = lb / per_tet;
+        const int b = lb - tet * per_tet;
+        const int64_t base = (int64_t)tet * L.Spad;
+        if (b < L.vpt2) {
+            const int item = __builtin_amdgcn_readfirstlane(b * 4 + (threadIdx.x >> 6));
+            if (item < L.n_items2) {
+                const uint2 it = L.items2[item];
+                const int n = L.n, lane = threadIdx.x & 63;
+                const int k0 = __builtin_amdgcn_readfirstlane((int)(it.y & 0xffffu));
+                const int k1 = __builtin_amdgcn_readfirstlane((int)(it.y >> 16));
+                const int tx = (int)it.x - 1 + 2 * lane, ty = tx + 1;
+                auto diag = [](int t) {
+                    int d = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+                    while ((d + 1) * (d + 2) / 2 <= t) ++d;
+                    while (d > 0 && d * (d + 1) / 2 > t) --d;
+                    return d;
+                };
+                const int sdx = tx >= 0 ? diag(tx) : -1, sdy = diag(ty);
+                const int ix = tx - sdx * (sdx + 1) / 2, iy = ty - sdy * (sdy + 1) / 2;
+                const bool row_x = tx >= 0 && lane >= 1 && ix >= 1 && ix <= sdx - 1;
+                const bool row_y = lane <= 62 && iy >= 1 && iy <= sdy - 1;
+                const int lastx = row_x ? min(n - 1 - sdx, k1) : -1;
+                const int lasty = row_y ? min(n - 1 - sdy, k1) : -1;
+                constexpr int B = (int)sizeof(T);
+                const __amdgpu_buffer_rsrc_t ru = tet_rsrc(u + base, (int64_t)L.S * B);
+                const __amdgpu_buffer_rsrc_t rk = tet_rsrc(L.kap + base, (int64_t)L.S * B);
+                const __amdgpu_buffer_rsrc_t rf = tet_rsrc(MODE == MODE_RESID ? f + base : u + base,
+                                                           (int64_t)L.S * B);
+                const __amdgpu_buffer_rsrc_t ry = tet_rsrc(y + base, (int64_t)L.S * B);
+                // pair start offsets of diagonals s-1 (from y), s, s+1 (from x); a
+                // negative start (left of the tet's first column) reads offset 0
+                const int osm = ty - sdy - 1, oc = tx, osp = tx + sdx + 1;
+                const int vo[3] = {osm >= 0 ? osm : 0, oc >= 0 ? oc : 0, osp >= 0 ? osp : 0};
+                const int Sn = tc32(n);
+                auto plane = [&](int p) { return Sn - tc32(n - p); };
+                T wr[NDIR / 2];
+                const T *__restrict__ w = OP == 0 ? L.sten + (int64_t)tet * TET_STENCIL
+                                                  : L.emat + (int64_t)tet * TET_EMAT;
+                if (OP == 0) {
+#pragma unroll
+                    for (int d = 0; d < NDIR / 2; ++d) wr[d] = w[d];
+                }
+                MPlane2<T> R[NS];
+#pragma unroll
+                for (int q = 0; q < NS; ++q) {
+                    mplane2_load<T, MODE>(R[q], ru, rk, rf, vo, plane(k0 - 1 + q));
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                constexpr int DROP = 0x7ffffff0;
+                for (int kb = k0; kb <= k1; kb += NS) {
+#pragma unroll
+                    for (int q = 0; q < NS; ++q) {
+                        const int k = kb + q;
+                        MPlane2<T> &M = R[q % NS], &C = R[(q + 1) % NS], &P = R[(q + 2) % NS];
+                        T ux[NDIR + 1], uy[NDIR + 1], kx[NDIR + 1], ky[NDIR + 1];
+                        gather2<T>(M.u, C.u, P.u, ux, uy);
+                        gather2<T>(M.k, C.k, P.k, kx, ky);
+                        const T ax = OP == 0 ? scaled_row_paired<T>(ux, kx, wr) : row_value<T, OP>(ux, kx, w);
+                        const T ay = OP == 0 ? scaled_row_paired<T>(uy, ky, wr) : row_value<T, OP>(uy, ky, w);
+                        const int Pk = plane(k);
+                        const bool lx = k <= lastx, ly = k <= lasty;
+                        const int sx = lx ? (Pk + tx) * B : DROP, sy = ly ? (Pk + ty) * B : DROP;
+                        if (MODE == MODE_APPLY) {
+                            bstore(ax, ry, sx);
+                            bstore(ay, ry, sy);
+                        } else {
+                            const T rx = C.f.x - ax, rv = C.f.y - ay;
+                            bstore(rx, ry, sx);
+                            bstore(rv, ry, sy);
+                            sq += (lx ? (double)rx * (double)rx : 0.0) + (ly ? (double)rv * (double)rv : 0.0);
+                        }
+                        mplane2_load<T, MODE>(M, ru, rk, rf, vo, plane(k - 1 + NS));
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                }
+            }
+        } else {
+            const int e = (b - L.vpt2) * BLOCK + threadIdx.x;
             if (e < L.n_bnd) {
                 const uint32_t v = L.bnd[e];
                 if ((L.dmask[tet] >> (v & 15u)) & 1) y[base + (v >> 4)] = T(0);
@@ -329,29 +607,57 @@ static inline int march_grid(int n_tet, int vpt, int bpt2)
     return ((nb + 7) / 8) * 8;
 }
 
-// variant of the marching kernel (prefetch depth, occupancy); HHG_MARCH_VARIANT
-// overrides the default for tuning runs
+// variant of the marching kernel (rows per lane, prefetch depth, occupancy);
+// HHG_MARCH_VARIANT overrides the default for tuning runs
 static int march_variant()
 {
     static int v = -1;
     if (v < 0) {
         const char *e = getenv("HHG_MARCH_VARIANT");
         v = e ? atoi(e) : 0;
-        if (v < 0 || v > 3) v = 0;
+        if (v < 0 || v > 7) v = 0;
     }
     return v;
 }
+
+// variants 0 (default) and 6 run scaled rows two per lane; 1-5 and 7 one per lane
+static inline bool two_rows(int v) { return v == 0 || v == 6; }
+
+// blocks of the interior launch (one partial sum each in residual mode)
+template <typename T>
+static int march_blocks(const LevelView<T> &L)
+{
+    return two_rows(march_variant()) ? march_grid(L.n_tet, L.vpt2, L.bpt2) : march_grid(L.n_tet, L.vpt, L.bpt2);
+}
+// the nodal rows keep the one-row-per-lane kernel (their element sums need
+// too many registers for two rows per lane)
 
 template <typename T, int MODE, int OP>
 static void launch_march(const LevelView<T> &L, const T *u, const T *f, T *y, double *partial,
                          hipStream_t st)
 {
+    if constexpr (OP == 0) {
+        const int v = march_variant();
+        if (two_rows(v)) {
+            const int g2 = march_grid(L.n_tet, L.vpt2, L.bpt2);
+            if (v == 6) k_march2<T, MODE, OP, 0, 3><<<g2, BLOCK, 0, st>>>(L, u, f, y, partial);
+            else k_march2<T, MODE, OP, 1, 2><<<g2, BLOCK, 0, st>>>(L, u, f, y, partial);
+            return;
+        }
+    }
     const int g = march_grid(L.n_tet, L.vpt, L.bpt2);
+    // FP64 residual and nodal rows hold more values: a lower occupancy
+    // target keeps them out of scratch
+    constexpr bool big = sizeof(T) == 8 && (MODE == MODE_RESID || OP == 1);
+    constexpr int W4 = big ? 3 : 4;
+    constexpr bool f64 = sizeof(T) == 8;
     switch (march_variant()) {
-    case 1: k_march<T, MODE, OP, 1, 8><<<g, BLOCK, 0, st>>>(L, u, f, y, partial); break;
-    case 2: k_march<T, MODE, OP, 2, 4><<<g, BLOCK, 0, st>>>(L, u, f, y, partial); break;
-    case 3: k_march<T, MODE, OP, 3, 4><<<g, BLOCK, 0, st>>>(L, u, f, y, partial); break;
-    default: k_march<T, MODE, OP, 1, 4><<<g, BLOCK, 0, st>>>(L, u, f, y, partial); break;
+    case 1: k_march<T, MODE, OP, 1, big ? 3 : (f64 ? 5 : 8), 1><<<g, BLOCK, 0, st>>>(L, u, f, y, partial); break;
+    case 2: k_march<T, MODE, OP, 2, W4, 0><<<g, BLOCK, 0, st>>>(L, u, f, y, partial); break;
+    case 3: k_march<T, MODE, OP, 2, big ? 3 : (f64 ? 4 : 6), 1><<<g, BLOCK, 0, st>>>(L, u, f, y, partial); break;
+    case 4: k_march<T, MODE, OP, 0, 8, 1><<<g, BLOCK, 0, st>>>(L, u, f, y, partial); break;
+    case 5: k_march<T, MODE, OP, 0, big ? 5 : 6, 0><<<g, BLOCK, 0, st>>>(L, u, f, y, partial); break;
+    default: k_march<T, MODE, OP, 1, W4, 0><<<g, BLOCK, 0, st>>>(L, u, f, y, partial); break;
     }
 }
 
@@ -404,7 +710,7 @@ template <typename T>
 hipError_t launch_scaled(const LevelView<T> &L, int mode, const T *u, const T *f, T *y,
                          double *partial, int *n_partial, hipStream_t st)
 {
-    const int gv = march_grid(L.n_tet, L.vpt, L.bpt2);
+    const int gv = march_blocks(L);
     const int gs = blocks_for(L.n_shared);
     if (mode == MODE_APPLY) {
         launch_march<T, MODE_APPLY, 0>(L, u, f, y, partial, st);
