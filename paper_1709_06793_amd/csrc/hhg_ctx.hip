@@ -238,6 +238,11 @@ struct Level {
     std::vector<uint64_t> h_sh_copy;
     int32_t *sh_off = nullptr;
     uint64_t *sh_copy = nullptr;
+    int sh_w = 0;
+    int64_t *sh_nb = nullptr, *sh_self = nullptr, *sh_cslot = nullptr;
+    int8_t *sh_map = nullptr;  // [copy][16]: entry of direction d, -1 if none
+    double *sh_cs64 = nullptr, *sh_cn64 = nullptr;
+    float *sh_cs32 = nullptr, *sh_cn32 = nullptr;
     // coefficient dependent
     double *k64 = nullptr, *invd64 = nullptr;
     float *k32 = nullptr, *invd32 = nullptr;
@@ -461,6 +466,8 @@ LevelView<double> view<double>(const hhg_ctx c, int l)
     v.dmask = L.dmask; v.smask = L.smask; v.kap = L.k64;
     v.n_shared = L.n_shared; v.sh_off = L.sh_off; v.sh_copy = L.sh_copy;
     v.items = L.items; v.n_items = L.n_items; v.vpt = (L.n_items + 3) / 4;
+    v.sh_w = L.sh_w; v.sh_nb = L.sh_nb; v.sh_self = L.sh_self; v.sh_cslot = L.sh_cslot;
+    v.sh_cs = L.sh_cs64; v.sh_cn = L.sh_cn64;
     v.items2 = L.items2; v.n_items2 = L.n_items2; v.vpt2 = (L.n_items2 + 3) / 4;
     v.bnd = L.bnd; v.n_bnd = L.n_bnd; v.bpt2 = (L.n_bnd + BLOCK - 1) / BLOCK;
     return v;
@@ -475,6 +482,8 @@ LevelView<float> view<float>(const hhg_ctx c, int l)
     v.dmask = L.dmask; v.smask = L.smask; v.kap = L.k32;
     v.n_shared = L.n_shared; v.sh_off = L.sh_off; v.sh_copy = L.sh_copy;
     v.items = L.items; v.n_items = L.n_items; v.vpt = (L.n_items + 3) / 4;
+    v.sh_w = L.sh_w; v.sh_nb = L.sh_nb; v.sh_self = L.sh_self; v.sh_cslot = L.sh_cslot;
+    v.sh_cs = L.sh_cs32; v.sh_cn = L.sh_cn32;
     v.items2 = L.items2; v.n_items2 = L.n_items2; v.vpt2 = (L.n_items2 + 3) / 4;
     v.bnd = L.bnd; v.n_bnd = L.n_bnd; v.bpt2 = (L.n_bnd + BLOCK - 1) / BLOCK;
     return v;
@@ -631,6 +640,150 @@ hhg_status build_level(hhg_ctx c, int l)
                 for (int s = 1; s + tt < L.n; ++s)
                     add_node({tp.faces[f][0], tp.faces[f][1], tp.faces[f][2]}, {L.n - s - tt, s, tt});
     L.n_shared = (int)L.h_sh_off.size() - 1;
+
+    // order for memory locality: each node's first copy is one in whose tet
+    // its primitive runs along the slot order (a k = 0 face, then the face
+    // opposite vertex 0), and nodes go by the slot of that copy
+    if (L.n_shared > 1) {
+        auto rank = [](int kind) { return (kind & 8) ? 0 : (kind & 1) ? 1 : 2; };
+        std::vector<int64_t> key(L.n_shared);
+        std::vector<uint64_t> first(L.n_shared);
+        for (int q = 0; q < L.n_shared; ++q) {
+            int best = L.h_sh_off[q], br = 3;
+            for (int p = L.h_sh_off[q]; p < L.h_sh_off[q + 1]; ++p) {
+                int t, kind, i, j, k;
+                unpack_copy(L.h_sh_copy[p], t, kind, i, j, k);
+                if (rank(kind) < br) { br = rank(kind); best = p; }
+            }
+            std::swap(L.h_sh_copy[L.h_sh_off[q]], L.h_sh_copy[best]);
+            int t, kind, i, j, k;
+            unpack_copy(L.h_sh_copy[L.h_sh_off[q]], t, kind, i, j, k);
+            key[q] = (int64_t)t * L.Spad + slot_of(L.n, i, j, k);
+        }
+        std::vector<int> order(L.n_shared);
+        for (int q = 0; q < L.n_shared; ++q) order[q] = q;
+        std::sort(order.begin(), order.end(), [&](int a, int b) { return key[a] < key[b]; });
+        std::vector<int32_t> off2(1, 0);
+        std::vector<uint64_t> copy2;
+        copy2.reserve(L.h_sh_copy.size());
+        for (int q : order) {
+            for (int p = L.h_sh_off[q]; p < L.h_sh_off[q + 1]; ++p) copy2.push_back(L.h_sh_copy[p]);
+            off2.push_back((int32_t)copy2.size());
+        }
+        L.h_sh_off.swap(off2);
+        L.h_sh_copy.swap(copy2);
+    }
+
+    // merged neighbour lists of the shared rows.  An entry is kept for a
+    // (copy, direction) when the neighbour lies in the copy's tet and either
+    // the tet-restricted scaled weight or some element coupling in that
+    // direction is not negligible (below 1e-14 of the tet's largest entry);
+    // copies of one neighbour node in different tets (found by its macro
+    // vertices and barycentric weights) share an entry.
+    if (L.n_shared > 0) {
+        std::vector<uint8_t> need((size_t)tp.nt * 16 * NDIR, 0);
+        for (int t = 0; t < tp.nt; ++t) {
+            double ms = 0.0, me = 0.0;
+            for (int q = 0; q < TET_STENCIL; ++q) ms = std::max(ms, std::fabs(L.h_sten[(size_t)t * TET_STENCIL + q]));
+            for (int q = 0; q < TET_EMAT; ++q) me = std::max(me, std::fabs(L.h_emat[(size_t)t * TET_EMAT + q]));
+            for (int zp = 0; zp < 15; ++zp) {
+                if (popcount4(zp) == 4) continue;
+                uint8_t *nd = &need[((size_t)t * 16 + zp) * NDIR];
+                const double *row = &L.h_sten[(size_t)t * TET_STENCIL + zp * KIND_STRIDE];
+                for (int d = 0; d < NDIR; ++d) nd[d] = std::fabs(row[d]) > 1e-14 * ms;
+                int ri, rj, rk;
+                representative(zp, ri, rj, rk);
+                for (int ty = 0; ty < NTYPE; ++ty)
+                    for (int a = 0; a < 4; ++a) {
+                        if (!element_valid(8, ri - TYPE_OFF[ty][a][0], rj - TYPE_OFF[ty][a][1],
+                                           rk - TYPE_OFF[ty][a][2], ty))
+                            continue;
+                        for (int b = 0; b < 4; ++b) {
+                            if (b == a) continue;
+                            const int d = dir_index(TYPE_OFF[ty][b][0] - TYPE_OFF[ty][a][0],
+                                                    TYPE_OFF[ty][b][1] - TYPE_OFF[ty][a][1],
+                                                    TYPE_OFF[ty][b][2] - TYPE_OFF[ty][a][2]);
+                            if (std::fabs(L.h_emat[(size_t)t * TET_EMAT + ty * 16 + a * 4 + b]) > 1e-14 * me)
+                                nd[d] = 1;
+                        }
+                    }
+            }
+        }
+        const int64_t ncopy = (int64_t)L.h_sh_copy.size();
+        std::vector<int8_t> hmap((size_t)ncopy * 16, -1);
+        std::vector<int64_t> hcslot(ncopy), hself(L.n_shared);
+        std::vector<int32_t> ecount(L.n_shared);
+        std::vector<int64_t> enb;  // entries of all nodes, node after node
+        enb.reserve((size_t)L.n_shared * 8);
+        struct Key { int v[4], w[4]; };
+        auto key_of = [&](int t, int i, int j, int k, Key &K) {
+            const int wt[4] = {L.n - i - j - k, i, j, k};
+            int c2 = 0;
+            std::pair<int, int> pr[4];
+            for (int a = 0; a < 4; ++a)
+                if (wt[a] > 0) pr[c2++] = {tp.tet[4 * t + a], wt[a]};
+            std::sort(pr, pr + c2);
+            for (int a = 0; a < 4; ++a) {
+                K.v[a] = a < c2 ? pr[a].first : -1;
+                K.w[a] = a < c2 ? pr[a].second : 0;
+            }
+        };
+        auto same = [](const Key &A, const Key &B) {
+            for (int a = 0; a < 4; ++a)
+                if (A.v[a] != B.v[a] || A.w[a] != B.w[a]) return false;
+            return true;
+        };
+        int width = 0;
+        std::vector<Key> keys;
+        std::vector<int64_t> slots;
+        for (int q = 0; q < L.n_shared; ++q) {
+            keys.clear();
+            slots.clear();
+            for (int p = L.h_sh_off[q]; p < L.h_sh_off[q + 1]; ++p) {
+                int t, kind, i, j, k;
+                unpack_copy(L.h_sh_copy[p], t, kind, i, j, k);
+                hcslot[p] = (int64_t)t * L.Spad + slot_of(L.n, i, j, k);
+                if (p == L.h_sh_off[q]) hself[q] = hcslot[p];
+                const uint8_t *nd = &need[((size_t)t * 16 + kind) * NDIR];
+                for (int d = 0; d < NDIR; ++d) {
+                    const int i2 = i + DIR[d][0], j2 = j + DIR[d][1], k2 = k + DIR[d][2];
+                    if (!nd[d] || !in_lattice(L.n, i2, j2, k2)) continue;
+                    Key K;
+                    key_of(t, i2, j2, k2, K);
+                    int m = -1;
+                    for (size_t e = 0; e < keys.size(); ++e)
+                        if (same(keys[e], K)) { m = (int)e; break; }
+                    if (m < 0) {
+                        m = (int)keys.size();
+                        keys.push_back(K);
+                        slots.push_back((int64_t)t * L.Spad + slot_of(L.n, i2, j2, k2));
+                    }
+                    if (m > 127) return fail(c, HHG_EMESH, "shared node with more than 128 neighbours");
+                    hmap[(size_t)p * 16 + d] = (int8_t)m;
+                }
+            }
+            ecount[q] = (int32_t)keys.size();
+            width = std::max(width, (int)keys.size());
+            enb.insert(enb.end(), slots.begin(), slots.end());
+        }
+        L.sh_w = width;
+        std::vector<int64_t> ell((size_t)width * L.n_shared);
+        int64_t pos = 0;
+        for (int q = 0; q < L.n_shared; ++q) {
+            for (int m = 0; m < width; ++m)
+                ell[(size_t)m * L.n_shared + q] = m < ecount[q] ? enb[pos + m] : hself[q];
+            pos += ecount[q];
+        }
+        TRY(upload(c, &L.sh_nb, ell));
+        TRY(upload(c, &L.sh_self, hself));
+        TRY(upload(c, &L.sh_cslot, hcslot));
+        TRY(upload(c, &L.sh_map, hmap));
+        const int64_t ne = std::max<int64_t>(1, (int64_t)width * L.n_shared);
+        TRY(dalloc(c, &L.sh_cs64, ne));
+        TRY(dalloc(c, &L.sh_cn64, ne));
+        TRY(dalloc(c, &L.sh_cs32, ne));
+        TRY(dalloc(c, &L.sh_cn32, ne));
+    }
 
     // column-marching work items: waves over 62 in-plane offsets (plus one
     // halo lane each side) and chunks of kc planes; kc is the largest of
@@ -1439,8 +1592,15 @@ hhg_status hhg_set_coefficient(hhg_ctx c, const double *k, int on_device, void *
         HIPCHK(c, launch_inject<double>(Lf.k64, Lf.n, Lc.k64, Lc.n, c->topo.nt, Lf.Spad, Lc.Spad, st));
     }
     for (int l = 0; l <= Lmax; ++l) {
-        HIPCHK(c, launch_convert<double, float>(c->lv[l].k64, c->lv[l].k32, c->lv[l].n_slots, st));
-        HIPCHK(c, launch_logk(c->lv[l].k64, c->lv[l].logk32, c->lv[l].n_slots, st));
+        Level &L = c->lv[l];
+        HIPCHK(c, launch_convert<double, float>(L.k64, L.k32, L.n_slots, st));
+        HIPCHK(c, launch_logk(L.k64, L.logk32, L.n_slots, st));
+        if (L.n_shared > 0) {
+            const int64_t ne = (int64_t)L.sh_w * L.n_shared;
+            HIPCHK(c, launch_shared_coef(view<double>(c, l), L.sh_map, L.sh_cs64, L.sh_cn64, st));
+            HIPCHK(c, launch_convert<double, float>(L.sh_cs64, L.sh_cs32, ne, st));
+            HIPCHK(c, launch_convert<double, float>(L.sh_cn64, L.sh_cn32, ne, st));
+        }
     }
     HIPCHK(c, hipStreamSynchronize(st));
     for (int l = 0; l <= Lmax; ++l) {

@@ -42,6 +42,15 @@ struct LevelView {
     int n_shared;
     const int32_t *sh_off;
     const uint64_t *sh_copy;
+    // rows of the shared nodes as merged neighbour lists (ELL, entry m of
+    // node q at m * n_shared + q; padding entries: coefficient 0, neighbour
+    // = the node itself): row_q = sum_m c_m (u[sh_nb] - u[sh_self])
+    int sh_w;
+    const int64_t *sh_nb;     // global slot (tet * Spad + slot) of the neighbour
+    const int64_t *sh_self;   // global slot of the node's first copy
+    const int64_t *sh_cslot;  // global slot of every copy (sh_off order)
+    const T *sh_cs;           // scaled-operator coefficients
+    const T *sh_cn;           // nodal-operator coefficients
 };
 
 // sparse corrections of the modification (Sec. 4.1) at one level
@@ -98,6 +107,9 @@ template <typename T>
 hipError_t launch_fill(T *x, T v, int64_t n, hipStream_t st);
 template <typename Ti, typename To>
 hipError_t launch_convert(const Ti *in, To *out, int64_t n, hipStream_t st);
+// merged coefficients of the shared rows for the current k (scaled and nodal)
+hipError_t launch_shared_coef(const LevelView<double> &L, const int8_t *map, double *cs, double *cn,
+                              hipStream_t st);
 hipError_t launch_add_f32_to_f64(double *u, const float *c, int64_t n, hipStream_t st);
 template <typename T>
 hipError_t launch_inject(const T *kf, int nf, T *kc, int nc, int n_tet, int64_t Spad_f,

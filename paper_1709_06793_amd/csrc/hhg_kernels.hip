@@ -661,49 +661,94 @@ static void launch_march(const LevelView<T> &L, const T *u, const T *f, T *y, do
     }
 }
 
-// rows of nodes on primitives shared by several tets: sum of the tet-restricted
-// scaled stencils of all copies (Sec. 2.2: one stencil per primitive and tet)
+// rows of nodes on primitives shared by several tets (Sec. 2.2: the row is
+// the sum of the tet-restricted stencils of all copies).  The merged
+// coefficients are built once per coefficient field (k_shared_coef); a row
+// is then sum_m c_m (u_m - u_q), written to every copy of the node.
 template <typename T, int MODE>
-__global__ __launch_bounds__(BLOCK) void k_scaled_shared(LevelView<T> L, const T *__restrict__ u,
-                                                          const T *__restrict__ f,
-                                                          T *__restrict__ y,
-                                                          double *__restrict__ partial)
+__global__ __launch_bounds__(BLOCK) void k_shared_rows(LevelView<T> L, const T *__restrict__ coef,
+                                                        const T *__restrict__ u, const T *__restrict__ f,
+                                                        T *__restrict__ y, double *__restrict__ partial)
 {
     const int q = blockIdx.x * BLOCK + threadIdx.x;
+    const int ns = L.n_shared;
     double sq = 0.0;
-    if (q < L.n_shared) {
+    if (q < ns) {
+        const int64_t self = L.sh_self[q];
+        const T u0 = u[self];
         T acc = T(0);
-        int64_t self = 0;
-        for (int c = L.sh_off[q]; c < L.sh_off[q + 1]; ++c) {
-            int tet, kind, i, j, k;
-            unpack_copy(L.sh_copy[c], tet, kind, i, j, k);
-            const int64_t base = (int64_t)tet * L.Spad;
-            const int s = (int)slot_of(L.n, i, j, k);
-            self = base + s;
-            int nb[NDIR];
-            neighbour_slots(s, i + j, L.n - k, nb);
-            const T *w = L.sten + (int64_t)tet * TET_STENCIL + kind * KIND_STRIDE;
-            const T u0 = u[base + s], k0 = L.kap[base + s];
-            for (int d = 0; d < NDIR; ++d) {
-                const T wd = w[d];
-                if (wd != T(0)) acc += wd * (k0 + L.kap[base + nb[d]]) * (u[base + nb[d]] - u0);
-            }
+        for (int m = 0; m < L.sh_w; ++m) {
+            const int64_t e = (int64_t)m * ns + q;
+            acc += coef[e] * (u[L.sh_nb[e]] - u0);
         }
         T out = acc;
         if (MODE == MODE_RESID) {
             out = f[self] - acc;
             sq = (double)out * (double)out;
         }
-        for (int c = L.sh_off[q]; c < L.sh_off[q + 1]; ++c) {
-            int tet, kind, i, j, k;
-            unpack_copy(L.sh_copy[c], tet, kind, i, j, k);
-            y[(int64_t)tet * L.Spad + slot_of(L.n, i, j, k)] = out;
-        }
+        for (int c = L.sh_off[q]; c < L.sh_off[q + 1]; ++c) y[L.sh_cslot[c]] = out;
     }
     if (MODE == MODE_RESID) {
         sq = block_reduce(sq, 0);
         if (threadIdx.x == 0) partial[blockIdx.x] = sq;
     }
+}
+
+// merged coefficients of the shared rows (FP64, once per coefficient field):
+// scaled  c_m = sum over copies and directions d onto m of w_d (k_q + k_m);
+// nodal   c_m = sum over copies, elements t holding the node and m of
+//         (sum of k at t's vertices) (A_t / 4)[node, m]
+__global__ __launch_bounds__(BLOCK) void k_shared_coef(LevelView<double> L, const int8_t *__restrict__ map,
+                                                       double *__restrict__ cs, double *__restrict__ cn)
+{
+    const int q = blockIdx.x * BLOCK + threadIdx.x;
+    const int ns = L.n_shared;
+    if (q >= ns) return;
+    for (int m = 0; m < L.sh_w; ++m) {
+        cs[(int64_t)m * ns + q] = 0.0;
+        cn[(int64_t)m * ns + q] = 0.0;
+    }
+    for (int c = L.sh_off[q]; c < L.sh_off[q + 1]; ++c) {
+        int tet, kind, i, j, k;
+        unpack_copy(L.sh_copy[c], tet, kind, i, j, k);
+        const int64_t base = (int64_t)tet * L.Spad;
+        const int s = (int)slot_of(L.n, i, j, k);
+        const int8_t *mp = map + (int64_t)c * 16;
+        const double kq = L.kap[base + s];
+        int nb[NDIR];
+        neighbour_slots(s, i + j, L.n - k, nb);
+        const double *w = L.sten + (int64_t)tet * TET_STENCIL + kind * KIND_STRIDE;
+        for (int d = 0; d < NDIR; ++d) {
+            const int m = mp[d];
+            if (m >= 0) cs[(int64_t)m * ns + q] += w[d] * (kq + L.kap[base + nb[d]]);
+        }
+        const double *E = L.emat + (int64_t)tet * TET_EMAT;
+        for (int t = 0; t < NTYPE; ++t)
+            for (int a = 0; a < 4; ++a) {
+                // element of shape t whose vertex a is this node
+                const int bi = i - TYPE_OFF[t][a][0], bj = j - TYPE_OFF[t][a][1], bk = k - TYPE_OFF[t][a][2];
+                bool ok = true;
+                for (int v = 0; v < 4; ++v)
+                    ok = ok && in_lattice(L.n, bi + TYPE_OFF[t][v][0], bj + TYPE_OFF[t][v][1], bk + TYPE_OFF[t][v][2]);
+                if (!ok) continue;
+                double ks = 0.0;
+                for (int v = 0; v < 4; ++v)
+                    ks += L.kap[base + slot_of(L.n, bi + TYPE_OFF[t][v][0], bj + TYPE_OFF[t][v][1],
+                                               bk + TYPE_OFF[t][v][2])];
+                for (int v = 0; v < 4; ++v) {
+                    if (v == a) continue;
+                    const int m = mp[ELEM_DIR.v[t][a][v]];
+                    if (m >= 0) cn[(int64_t)m * ns + q] += ks * E[t * 16 + a * 4 + v];
+                }
+            }
+    }
+}
+
+hipError_t launch_shared_coef(const LevelView<double> &L, const int8_t *map, double *cs, double *cn,
+                              hipStream_t st)
+{
+    if (L.n_shared) k_shared_coef<<<blocks_for(L.n_shared), BLOCK, 0, st>>>(L, map, cs, cn);
+    return hipGetLastError();
 }
 
 template <typename T>
@@ -714,62 +759,20 @@ hipError_t launch_scaled(const LevelView<T> &L, int mode, const T *u, const T *f
     const int gs = blocks_for(L.n_shared);
     if (mode == MODE_APPLY) {
         launch_march<T, MODE_APPLY, 0>(L, u, f, y, partial, st);
-        if (gs) k_scaled_shared<T, MODE_APPLY><<<gs, BLOCK, 0, st>>>(L, u, f, y, partial);
+        if (gs) k_shared_rows<T, MODE_APPLY><<<gs, BLOCK, 0, st>>>(L, L.sh_cs, u, f, y, partial);
     } else {
         launch_march<T, MODE_RESID, 0>(L, u, f, y, partial, st);
-        if (gs) k_scaled_shared<T, MODE_RESID><<<gs, BLOCK, 0, st>>>(L, u, f, y, partial + gv);
+        if (gs) k_shared_rows<T, MODE_RESID><<<gs, BLOCK, 0, st>>>(L, L.sh_cs, u, f, y, partial + gv);
         if (n_partial) *n_partial = gv + gs;
     }
     return hipGetLastError();
-}
-
-// ---------------------------------------------------------------- nodal integration (shared rows)
-template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_nodal_shared(LevelView<T> L, const T *__restrict__ u,
-                                                         T *__restrict__ y)
-{
-    const int q = blockIdx.x * BLOCK + threadIdx.x;
-    if (q >= L.n_shared) return;
-    T acc = T(0);
-    for (int c = L.sh_off[q]; c < L.sh_off[q + 1]; ++c) {
-        int tet, kind, i, j, k;
-        unpack_copy(L.sh_copy[c], tet, kind, i, j, k);
-        const int64_t base = (int64_t)tet * L.Spad;
-        const T *E = L.emat + (int64_t)tet * TET_EMAT;
-        const T u0 = u[base + slot_of(L.n, i, j, k)];
-        for (int t = 0; t < NTYPE; ++t)
-            for (int a = 0; a < 4; ++a) {
-                // element of shape t whose vertex a is this node
-                const int bi = i - TYPE_OFF[t][a][0], bj = j - TYPE_OFF[t][a][1],
-                          bk = k - TYPE_OFF[t][a][2];
-                bool ok = true;
-                for (int v = 0; v < 4; ++v)
-                    ok = ok && in_lattice(L.n, bi + TYPE_OFF[t][v][0], bj + TYPE_OFF[t][v][1],
-                                          bk + TYPE_OFF[t][v][2]);
-                if (!ok) continue;
-                T ks = T(0), sv = T(0);
-                for (int v = 0; v < 4; ++v) {
-                    const int64_t sl = base + slot_of(L.n, bi + TYPE_OFF[t][v][0],
-                                                      bj + TYPE_OFF[t][v][1],
-                                                      bk + TYPE_OFF[t][v][2]);
-                    ks += L.kap[sl];
-                    sv += E[t * 16 + a * 4 + v] * (u[sl] - u0);
-                }
-                acc += ks * sv;
-            }
-    }
-    for (int c = L.sh_off[q]; c < L.sh_off[q + 1]; ++c) {
-        int tet, kind, i, j, k;
-        unpack_copy(L.sh_copy[c], tet, kind, i, j, k);
-        y[(int64_t)tet * L.Spad + slot_of(L.n, i, j, k)] = acc;
-    }
 }
 
 template <typename T>
 hipError_t launch_nodal(const LevelView<T> &L, const T *u, T *y, hipStream_t st)
 {
     launch_march<T, MODE_APPLY, 1>(L, u, nullptr, y, nullptr, st);
-    if (L.n_shared) k_nodal_shared<T><<<blocks_for(L.n_shared), BLOCK, 0, st>>>(L, u, y);
+    if (L.n_shared) k_shared_rows<T, MODE_APPLY><<<blocks_for(L.n_shared), BLOCK, 0, st>>>(L, L.sh_cn, u, nullptr, y, nullptr);
     return hipGetLastError();
 }
 
