@@ -195,8 +195,9 @@ hhg_status hhg_solve(hhg_ctx ctx, int32_t level, hhg_solve_mode mode, int32_t pr
 
 /* Learned smoothing correction (not in the paper).  Per interior node i of a
  * macro tet, a network maps the 15-point neighbourhood features
- * x_p = r_p / s_i and x_{15+p} = L_p - L_i (p = 0: the node, p = 1..14: the
- * neighbours in the tet-local lattice directions (1,0,0), (0,1,0), (0,0,1),
+ * x_p = r_p * (1/s_i) (reciprocal rounded to FP32) and x_{15+p} = L_p - L_i
+ * (p = 0: the node, p = 1..14: the neighbours in the tet-local lattice
+ * directions (1,0,0), (0,1,0), (0,0,1),
  * (1,-1,0), (1,0,-1), (0,1,-1), (1,-1,1) and their negatives, in that order;
  * s_i = max_p |r_p| + 1e-30; L = log k rounded to FP32; x_30 = x_31 = 0)
  * through h1 = bf16(relu(W1 bf16(x) + b1)), h2 = relu(W2 h1 + b2),

@@ -9,7 +9,7 @@ p = 1..14 the neighbours along the tet-local lattice directions
 (1,0,0),(0,1,0),(0,0,1),(1,-1,0),(1,0,-1),(0,1,-1),(1,-1,1) and their
 negatives, in that order:
     s_i  = max_p |r_p| + 1e-30                                   (float32)
-    x_p  = r_p / s_i,  x_{15+p} = L_p - L_0,  x_30 = x_31 = 0    (float32)
+    x_p  = r_p * fl32(1 / s_i),  x_{15+p} = L_p - L_0,  x_30 = x_31 = 0    (float32)
            with L = float32(log k) (log taken in float64)
     h1   = bf16(relu(float32(W1 bf16(x)) + b1))
     h2   = relu(float32(W2 h1) + b2)
@@ -109,7 +109,8 @@ def features(r32, logk32, pos):
     rp = r32[pos].astype(np.float32)
     s = (np.abs(rp).max(axis=1) + np.float32(1e-30)).astype(np.float32)
     x = np.zeros((pos.shape[0], 32), dtype=np.float32)
-    x[:, :15] = rp / s[:, None]
+    inv = (np.float32(1.0) / s).astype(np.float32)  # one FP32 reciprocal per node
+    x[:, :15] = rp * inv[:, None]
     lk = logk32[pos]
     x[:, 15:30] = lk - lk[:, :1]
     return x, s

@@ -17,13 +17,11 @@
 
 #include "hhg_internal.h"
 #include "hhg_lattice.h"
+#include "hhg_march.h"
 
 namespace hhg {
 
 // ---------------------------------------------------------------- helpers
-__device__ __forceinline__ int tc32(int m) { return (m + 1) * (m + 2) * (m + 3) / 6; }
-__device__ __forceinline__ int tr32(int m) { return (m + 1) * (m + 2) / 2; }
-
 // (i,j,k) of slot s of a tet lattice with n intervals (n <= 1024)
 __device__ __forceinline__ void decode_slot(int n, int s, int &i, int &j, int &k)
 {
@@ -62,12 +60,6 @@ __device__ __forceinline__ void neighbour_slots(int s, int sd, int m, int nb[NDI
     nb[11] = up - sd - 1;              // (-1, 0, 1)
     nb[12] = up - sd;                  // ( 0,-1, 1)
     nb[13] = dn - 1;                   // (-1, 1,-1)
-}
-
-__device__ __forceinline__ int xcd_remap(int b, int grid)
-{
-    const int per = grid >> 3;  // grid is a multiple of 8
-    return (b & 7) * per + (b >> 3);
 }
 
 __device__ __forceinline__ double warp_sum(double v)
@@ -134,54 +126,6 @@ constexpr ElemDirTable ELEM_DIR{};
 //       (eq. (standardfe): 24 elements, kbar_t the mean vertex value of k).
 // Extra blocks after the interior ones write 0 to Dirichlet boundary slots.
 
-// lane shifts by one position (DPP wave_shr:1 / wave_shl:1; a lane without a
-// source lane gets 0)
-__device__ __forceinline__ float dpp_prev(float v)  // value of lane-1
-{
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x138, 0xf, 0xf, true));
-}
-__device__ __forceinline__ float dpp_next(float v)  // value of lane+1
-{
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xf, 0xf, true));
-}
-__device__ __forceinline__ double dpp_prev(double v)
-{
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_mov_dpp((int)b, 0x138, 0xf, 0xf, true);
-    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x138, 0xf, 0xf, true);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-__device__ __forceinline__ double dpp_next(double v)
-{
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_mov_dpp((int)b, 0x130, 0xf, 0xf, true);
-    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x130, 0xf, 0xf, true);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-// buffer loads relative to one tet's slot array: the hardware range check
-// returns 0 for any index outside [0, n_records), so lanes whose neighbour
-// does not exist read 0 without a branch
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t tet_rsrc(const void *p, int64_t bytes)
-{
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
-}
-template <typename T>
-__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, int idx);
-template <>
-__device__ __forceinline__ double bload<double>(__amdgpu_buffer_rsrc_t r, int idx)
-{
-    const auto q = __builtin_amdgcn_raw_buffer_load_b64(r, idx * 8, 0, 0);
-    double v;
-    __builtin_memcpy(&v, &q, 8);
-    return v;
-}
-template <>
-__device__ __forceinline__ float bload<float>(__amdgpu_buffer_rsrc_t r, int idx)
-{
-    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, idx * 4, 0, 0));
-}
-
 template <typename T, int OP>
 __device__ __forceinline__ T row_value(const T uu[NDIR + 1], const T kk[NDIR + 1], const T *__restrict__ w)
 {
@@ -205,61 +149,6 @@ __device__ __forceinline__ T row_value(const T uu[NDIR + 1], const T kk[NDIR + 1
             }
     }
     return acc;
-}
-
-// buffer stores relative to one tet's slot array; the whole byte offset is
-// in the per-lane offset, which the range check covers: a store at an offset
-// at or beyond the range is dropped
-__device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, int voff)
-{
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v),
-                                          r, voff, 0, 0);
-}
-__device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r, int voff)
-{
-    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, 0, 0);
-}
-
-// one plane of a wave's columns: anti-diagonals s-1, s, s+1 at the lane's
-// position for u and k (and f), plus the lane-shifted copies the rows use
-template <typename T>
-struct MPlane {
-    T u[3], k[3], f;
-    T u_sm_l, u_s_l, u_s_r, u_sp_r;
-    T k_sm_l, k_s_l, k_s_r, k_sp_r;
-};
-
-// plane starting at slot P: in-plane offsets o[3] (slots).  Every load of a
-// slot outside the tet's range (planes past the top included) returns 0.
-template <typename T, int MODE>
-__device__ __forceinline__ void mplane_load(MPlane<T> &p, __amdgpu_buffer_rsrc_t ru,
-                                            __amdgpu_buffer_rsrc_t rk, __amdgpu_buffer_rsrc_t rf,
-                                            const int o[3], int P)
-{
-#pragma unroll
-    for (int c = 0; c < 3; ++c) p.u[c] = bload<T>(ru, P + o[c]);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) p.k[c] = bload<T>(rk, P + o[c]);
-    if (MODE == MODE_RESID) p.f = bload<T>(rf, P + o[1]);
-}
-
-// shifted copies a plane needs as plane k+1 (and again as plane k) ...
-template <typename T>
-__device__ __forceinline__ void mplane_shift_up(MPlane<T> &p)
-{
-    p.u_sm_l = dpp_prev(p.u[0]);
-    p.u_s_r = dpp_next(p.u[1]);
-    p.k_sm_l = dpp_prev(p.k[0]);
-    p.k_s_r = dpp_next(p.k[1]);
-}
-// ... and those it needs as plane k (and again as plane k-1)
-template <typename T>
-__device__ __forceinline__ void mplane_shift_mid(MPlane<T> &p)
-{
-    p.u_s_l = dpp_prev(p.u[1]);
-    p.u_sp_r = dpp_next(p.u[2]);
-    p.k_s_l = dpp_prev(p.k[1]);
-    p.k_sp_r = dpp_next(p.k[2]);
 }
 
 // scaled row with the weights of opposite directions paired (interior
@@ -419,6 +308,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
         if (threadIdx.x == 0) partial[blockIdx.x] = sq;
     }
 }
+
 
 // ---------------------------------------------------------------- two rows per lane
 // The same column march with each lane holding two consecutive in-plane
@@ -1080,20 +970,25 @@ hipError_t launch_prolong_add(const LevelView<T> &Lc, const LevelView<T> &Lf, co
 }
 
 // ---------------------------------------------------------------- coarse solve
-// u[copies of row r] = sum_c Ainv[r][c] f[gather[c]] in FP64 (u zeroed before)
+// u[copies of row r] = sum_c Ainv[r][c] f[gather[c]] in FP64 (u zeroed
+// before): one wave per row, lanes stride over the columns (coalesced row
+// reads), wave-wide sum
 template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_coarse(const double *__restrict__ ainv, int nu,
-                                                   const int64_t *__restrict__ gather,
-                                                   const int32_t *__restrict__ coff,
-                                                   const int64_t *__restrict__ cslot,
-                                                   const T *__restrict__ f, T *__restrict__ u)
+__global__ __launch_bounds__(64) void k_coarse(const double *__restrict__ ainv, int nu,
+                                               const int64_t *__restrict__ gather,
+                                               const int32_t *__restrict__ coff,
+                                               const int64_t *__restrict__ cslot,
+                                               const T *__restrict__ f, T *__restrict__ u)
 {
-    const int r = blockIdx.x * BLOCK + threadIdx.x;
-    if (r >= nu) return;
-    double acc = 0.0;
+    const int r = blockIdx.x;
+    const int lane = threadIdx.x;
     const double *row = ainv + (int64_t)r * nu;
-    for (int c = 0; c < nu; ++c) acc += row[c] * (double)f[gather[c]];
-    for (int p = coff[r]; p < coff[r + 1]; ++p) u[cslot[p]] = (T)acc;
+    double acc = 0.0;
+    for (int c = lane; c < nu; c += 64) acc += row[c] * (double)f[gather[c]];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (lane == 0)
+        for (int p = coff[r]; p < coff[r + 1]; ++p) u[cslot[p]] = (T)acc;
 }
 
 template <typename T>
@@ -1101,7 +996,7 @@ hipError_t launch_coarse_solve(const double *ainv, int nu, const int64_t *gather
                                const int32_t *copy_off, const int64_t *copy_slot, const T *f, T *u,
                                hipStream_t st)
 {
-    k_coarse<T><<<blocks_for(nu), BLOCK, 0, st>>>(ainv, nu, gather, copy_off, copy_slot, f, u);
+    if (nu > 0) k_coarse<T><<<nu, 64, 0, st>>>(ainv, nu, gather, copy_off, copy_slot, f, u);
     return hipGetLastError();
 }
 

@@ -5,7 +5,8 @@
 //
 // Features of an interior node i (positions p = 0: the node, p = 1..14: the
 // lattice neighbours in DIR order):  s = max_p |r_p| + 1e-30,
-// x_p = r_p / s, x_{15+p} = L_p - L_0 (L = log k rounded to FP32), x_30 = x_31 = 0.
+// x_p = r_p * (1/s) (the reciprocal rounded to FP32), x_{15+p} = L_p - L_0
+// (L = log k rounded to FP32), x_30 = x_31 = 0.
 // Network:  h1 = bf16(relu(W1 bf16(x) + b1)),  h2 = relu(W2 h1 + b2),
 // c = w3 . h2 + b3.  Nodes on macro faces/edges/vertices and Dirichlet nodes
 // get c = 0.
@@ -20,6 +21,7 @@
 #include "hhg_internal.h"
 #include "hhg_lattice.h"
 #include "hhg_learned.h"
+#include "hhg_march.h"
 
 namespace hhg {
 
@@ -62,6 +64,18 @@ __device__ __forceinline__ unsigned short to_bf16(float f)
     return (unsigned short)(r >> 16);
 }
 __device__ __forceinline__ float from_bf16(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
+// two floats to packed bf16 bits (low = a) with the hardware conversion
+// (round to nearest, ties to even: the same bits as to_bf16 for finite values)
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ unsigned int pack_bf16(float a, float b)
+{
+    const f32x2 v = {a, b};
+    const bf16x2v h = __builtin_convertvector(v, bf16x2v);
+    unsigned int u;
+    __builtin_memcpy(&u, &h, 4);
+    return u;
+}
 
 // features of slot s (interior node assumed): 32 values and the scale
 __device__ __forceinline__ void node_features(const LevelView<float> &L, const float *__restrict__ r,
@@ -82,9 +96,10 @@ __device__ __forceinline__ void node_features(const LevelView<float> &L, const f
 #pragma unroll
     for (int p = 0; p < 15; ++p) m = fmaxf(m, fabsf(rp[p]));
     scale = m + 1e-30f;
+    const float inv = 1.0f / scale;
 #pragma unroll
     for (int p = 0; p < 15; ++p) {
-        x[p] = rp[p] / scale;
+        x[p] = rp[p] * inv;
         x[15 + p] = lp[p] - lp[0];
     }
     x[30] = 0.0f;
@@ -92,40 +107,70 @@ __device__ __forceinline__ void node_features(const LevelView<float> &L, const f
 }
 
 // ---------------------------------------------------------------- forward (MFMA)
-// c[slot] = network output, sc[slot] = s * c, s_out[slot] = s (each nullable)
-__global__ __launch_bounds__(BLOCK) void k_learned_fwd(LevelView<float> L, const float *__restrict__ r,
-                                                       const float *__restrict__ logk,
-                                                       const unsigned short *__restrict__ wbf,
-                                                       float *__restrict__ c_out, float *__restrict__ sc_out,
-                                                       float *__restrict__ s_out)
+// c[slot] = network output, sc[slot] = s * c, s_out[slot] = s (each nullable).
+// Column marching, the traversal of the operator's interior kernel: a wave takes 64 consecutive in-plane offsets (lanes 1..62
+// hold nodes) and walks a chunk of planes with the planes of r and log k in
+// rotating registers (three coalesced loads per array and plane, neighbours
+// at i+-1 from the adjacent lanes).  Per plane each lane forms its node's
+// features, the wave stages them in LDS as BF16 and evaluates the network
+// for its 64 lanes in four groups of 16 on the matrix cores.  Extra blocks
+// write 0 to every slot on the tet's boundary.
+__global__ __launch_bounds__(BLOCK) void k_learned_fwd_march(LevelView<float> L, const float *__restrict__ r,
+                                                             const float *__restrict__ logk,
+                                                             const unsigned short *__restrict__ wbf,
+                                                             float *__restrict__ c_out,
+                                                             float *__restrict__ sc_out,
+                                                             float *__restrict__ s_out)
 {
-    __shared__ unsigned short xs[BLOCK][LN_IN + 4];  // bf16 features (row padded)
+    constexpr int NS = 4;
+    // bf16 features of a lane's node: 16 words, rows 18 words apart (the
+    // operand reads of 16 rows then fall in distinct banks)
+    constexpr int XW = 18;
+    __shared__ unsigned int xs[BLOCK * XW];
     __shared__ float cs[BLOCK];
-    const int per_tet = L.bpt;
-    const int tet = blockIdx.x / per_tet;
-    const int s = (blockIdx.x - tet * per_tet) * BLOCK + threadIdx.x;
+    const int per_tet = L.vpt + L.bpt2;
+    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    if (lb >= L.n_tet * per_tet) return;
+    const int tet = lb / per_tet;
+    const int b = lb - tet * per_tet;
     const int64_t base = (int64_t)tet * L.Spad;
-    bool interior = false;
-    float scale = 0.0f;
-    int i = 0, j = 0, k = 0;
-    if (tet < L.n_tet && s < L.S) {
-        ldecode(L.n, s, i, j, k);
-        interior = i > 0 && j > 0 && k > 0 && i + j + k < L.n;
-    }
-    {
-        float x[LN_IN];
-        if (interior) {
-            node_features(L, r, logk, base, s, i + j, k, x, scale);
-        } else {
-#pragma unroll
-            for (int f = 0; f < LN_IN; ++f) x[f] = 0.0f;
+    if (b >= L.vpt) {
+        const int e = (b - L.vpt) * BLOCK + threadIdx.x;
+        if (e < L.n_bnd) {
+            const int64_t sl = base + (L.bnd[e] >> 4);
+            if (c_out) c_out[sl] = 0.0f;
+            if (sc_out) sc_out[sl] = 0.0f;
+            if (s_out) s_out[sl] = 0.0f;
         }
-#pragma unroll
-        for (int f = 0; f < LN_IN; ++f) xs[threadIdx.x][f] = to_bf16(x[f]);
+        return;
     }
-    __syncthreads();
-    // per-lane weight operands: W1 (two K halves), W2, biases, w3
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int item = __builtin_amdgcn_readfirstlane(b * 4 + wave);
+    if (item >= L.n_items) return;
+    const uint2 it = L.items[item];
+    const int n = L.n;
+    const int k0 = __builtin_amdgcn_readfirstlane((int)(it.y & 0xffffu));
+    const int k1 = __builtin_amdgcn_readfirstlane((int)(it.y >> 16));
+    const int t = (int)it.x - 1 + lane;
+    int sd = t >= 0 ? (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f) : -1;
+    if (t >= 0) {
+        while ((sd + 1) * (sd + 2) / 2 <= t) ++sd;
+        while (sd > 0 && sd * (sd + 1) / 2 > t) --sd;
+    }
+    const int i = t - sd * (sd + 1) / 2;
+    const bool row_lane = t >= 0 && lane >= 1 && lane <= 62 && i >= 1 && i <= sd - 1;
+    const int lastk = row_lane ? min(n - 1 - sd, k1) : -1;
+    const int64_t bytes = (int64_t)L.S * 4;
+    const __amdgpu_buffer_rsrc_t rr = tet_rsrc(r + base, bytes);
+    const __amdgpu_buffer_rsrc_t rl = tet_rsrc(logk + base, bytes);
+    // a missing output gets an empty range: every store to it is dropped
+    const __amdgpu_buffer_rsrc_t rc = tet_rsrc(c_out ? c_out + base : r + base, c_out ? bytes : 0);
+    const __amdgpu_buffer_rsrc_t rsc = tet_rsrc(sc_out ? sc_out + base : r + base, sc_out ? bytes : 0);
+    const __amdgpu_buffer_rsrc_t rs = tet_rsrc(s_out ? s_out + base : r + base, s_out ? bytes : 0);
+    const int vo[3] = {t >= 0 ? t - sd : 0, t >= 0 ? t : 0, t >= 0 ? t + sd + 1 : 0};
+    const int Sn = tc32(n);
+    auto plane = [&](int p) { return Sn - tc32(n - p); };
+    // per-lane weight operands (A of the three products, biases, w3)
     const int row = lane & 15, kq = 4 * (lane >> 4);
     bf16x4 a1lo, a1hi, a2;
     for (int q = 0; q < 4; ++q) {
@@ -140,40 +185,92 @@ __global__ __launch_bounds__(BLOCK) void k_learned_fwd(LevelView<float> L, const
         w3v[q] = from_bf16(wbf[800 + kq + q]);
     }
     const float b3 = from_bf16(wbf[816]);
-    for (int g = 0; g < 4; ++g) {
-        const int node = wave * 64 + g * 16 + row;  // the node this lane feeds
-        bf16x4 xlo, xhi;
-        for (int q = 0; q < 4; ++q) {
-            xlo[q] = (short)xs[node][kq + q];
-            xhi[q] = (short)xs[node][16 + kq + q];
+    MPlane<float> R[NS];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        mplane_load<float, MODE_APPLY>(R[q], rr, rl, rr, vo, plane(k0 - 1 + q));
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    mplane_shift_mid(R[0]);
+    mplane_shift_up(R[1]);
+    constexpr int DROP = 0x7ffffff0;
+    for (int kb = k0; kb <= k1; kb += NS) {
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+            const int k = kb + q;
+            MPlane<float> &M = R[q % NS], &C = R[(q + 1) % NS], &P = R[(q + 2) % NS];
+            mplane_shift_mid(C);
+            mplane_shift_up(P);
+            // node first, then the neighbours in DIR order
+            const float rp[15] = {C.u[1], C.u_sp_r, C.u[2], P.u[1], C.u_s_r, M.u_sp_r, M.u[2], P.u_s_r,
+                                  C.u_sm_l, C.u[0], M.u[1], C.u_s_l, P.u_sm_l, P.u[0], M.u_s_l};
+            const float lp[15] = {C.k[1], C.k_sp_r, C.k[2], P.k[1], C.k_s_r, M.k_sp_r, M.k[2], P.k_s_r,
+                                  C.k_sm_l, C.k[0], M.k[1], C.k_s_l, P.k_sm_l, P.k[0], M.k_s_l};
+            float mx = 0.0f;
+#pragma unroll
+            for (int p2 = 0; p2 < 15; ++p2) mx = fmaxf(mx, fabsf(rp[p2]));
+            const float scale = mx + 1e-30f;
+            const float inv = 1.0f / scale;
+            float x[32];
+#pragma unroll
+            for (int p2 = 0; p2 < 15; ++p2) {
+                x[p2] = rp[p2] * inv;
+                x[15 + p2] = lp[p2] - lp[0];
+            }
+            x[30] = 0.0f;
+            x[31] = 0.0f;
+            uint2 *mine = reinterpret_cast<uint2 *>(xs + threadIdx.x * XW);
+#pragma unroll
+            for (int w2 = 0; w2 < 8; ++w2)
+                mine[w2] = make_uint2(pack_bf16(x[4 * w2], x[4 * w2 + 1]), pack_bf16(x[4 * w2 + 2], x[4 * w2 + 3]));
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const int node = wave * 64 + g * 16 + row;
+                const uint2 *src = reinterpret_cast<const uint2 *>(xs + node * XW);
+                const uint2 lo = src[lane >> 4], hi = src[4 + (lane >> 4)];
+                bf16x4 xlo, xhi;
+                __builtin_memcpy(&xlo, &lo, 8);
+                __builtin_memcpy(&xhi, &hi, 8);
+                f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1lo, xlo, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1hi, xhi, acc, 0, 0, 0);
+                const uint2 hp = make_uint2(pack_bf16(fmaxf(acc[0] + b1v[0], 0.0f), fmaxf(acc[1] + b1v[1], 0.0f)),
+                                            pack_bf16(fmaxf(acc[2] + b1v[2], 0.0f), fmaxf(acc[3] + b1v[3], 0.0f)));
+                bf16x4 h1;
+                __builtin_memcpy(&h1, &hp, 8);
+                f32x4 acc2 = {0.0f, 0.0f, 0.0f, 0.0f};
+                acc2 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2, h1, acc2, 0, 0, 0);
+                float part = 0.0f;
+                for (int q2 = 0; q2 < 4; ++q2) part += w3v[q2] * fmaxf(acc2[q2] + b2v[q2], 0.0f);
+                part += __shfl_xor(part, 16, 64);
+                part += __shfl_xor(part, 32, 64);
+                if (lane < 16) cs[wave * 64 + g * 16 + lane] = part + b3;
+            }
+            __builtin_amdgcn_wave_barrier();
+            const float c = cs[threadIdx.x];
+            const bool live = k <= lastk;
+            const int so = live ? (plane(k) + vo[1]) * 4 : DROP;
+            bstore(c, rc, so);
+            bstore(c * scale, rsc, so);
+            bstore(scale, rs, so);
+            mplane_load<float, MODE_APPLY>(M, rr, rl, rr, vo, plane(k - 1 + NS));
+            __builtin_amdgcn_sched_barrier(0);
         }
-        f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1lo, xlo, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1hi, xhi, acc, 0, 0, 0);
-        bf16x4 h1;
-        for (int q = 0; q < 4; ++q) h1[q] = (short)to_bf16(fmaxf(acc[q] + b1v[q], 0.0f));
-        f32x4 acc2 = {0.0f, 0.0f, 0.0f, 0.0f};
-        acc2 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2, h1, acc2, 0, 0, 0);
-        float part = 0.0f;
-        for (int q = 0; q < 4; ++q) part += w3v[q] * fmaxf(acc2[q] + b2v[q], 0.0f);
-        part += __shfl_xor(part, 16, 64);
-        part += __shfl_xor(part, 32, 64);
-        if (lane < 16) cs[wave * 64 + g * 16 + lane] = part + b3;
     }
-    __syncthreads();
-    if (tet < L.n_tet && s < L.S) {
-        const float c = interior ? cs[threadIdx.x] : 0.0f;
-        if (c_out) c_out[base + s] = c;
-        if (sc_out) sc_out[base + s] = interior ? c * scale : 0.0f;
-        if (s_out) s_out[base + s] = interior ? scale : 0.0f;
-    }
+}
+
+static int fwd_grid(const LevelView<float> &L)
+{
+    const int nb = L.n_tet * (L.vpt + L.bpt2);
+    return ((nb + 7) / 8) * 8;
 }
 
 template <>
 hipError_t launch_learned_forward<float>(const LevelView<float> &L, const LearnedState &S,
                                          const float *r, const float *logk, float *c, hipStream_t st)
 {
-    k_learned_fwd<<<L.n_tet * L.bpt, BLOCK, 0, st>>>(L, r, logk, S.wbf, c, nullptr, nullptr);
+    k_learned_fwd_march<<<fwd_grid(L), BLOCK, 0, st>>>(L, r, logk, S.wbf, c, nullptr, nullptr);
     return hipGetLastError();
 }
 
@@ -181,7 +278,7 @@ hipError_t launch_learned_forward_full(const LevelView<float> &L, const LearnedS
                                        const float *r, const float *logk, float *c, float *sc,
                                        float *s, hipStream_t st)
 {
-    k_learned_fwd<<<L.n_tet * L.bpt, BLOCK, 0, st>>>(L, r, logk, S.wbf, c, sc, s);
+    k_learned_fwd_march<<<fwd_grid(L), BLOCK, 0, st>>>(L, r, logk, S.wbf, c, sc, s);
     return hipGetLastError();
 }
 

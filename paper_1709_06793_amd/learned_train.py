@@ -135,3 +135,128 @@ def evaluate(ctx, f, level, w, torch, tol=1e-8, max_iter=200):
         u = ctx.vector(level)
         res[name] = ctx.solve(level, f, u, mode=hhg.SOLVE_LEARNED, tol=tol, max_iter=max_iter)
     return res
+
+
+# ---------------------------------------------------------------- full training / evaluation runs
+WEIGHTS_PATH = __import__("os").path.join(__import__("os").path.dirname(__file__), "learned_weights.json")
+
+
+def save_weights(w, path, meta):
+    import json
+    with open(path, "w") as fh:
+        json.dump({"nparam": int(w.size), "weights": [float(x) for x in w], "meta": meta}, fh)
+
+
+def load_weights(path=WEIGHTS_PATH):
+    """Trained parameters shipped with the package (float32, 817 values)."""
+    import json
+    with open(path) as fh:
+        d = json.load(fh)
+    w = np.asarray(d["weights"], dtype=np.float32)
+    if w.size != hhg.LEARNED_NPARAM:
+        raise ValueError(f"{path}: {w.size} parameters, expected {hhg.LEARNED_NPARAM}")
+    return w, d.get("meta", {})
+
+
+def evaluate_fields(level, seeds, w, torch, mesh_fn, tol=1e-8, log=None):
+    """Learned vs Chebyshev vs network-off solves on one context per mesh,
+    re-used across fields (set_coefficient per field)."""
+    from hhg_inputs import lognormal_params, lognormal_k
+    X, T = mesh_fn()
+    ctx = hhg.Context(X, T, level)
+    xyz, dirichlet = ctx.node_coords(level)
+    out = []
+    for q, seed in enumerate(seeds):
+        prm = lognormal_params(seed)
+        ctx.set_coefficient(lognormal_k(xyz, prm))
+        f = prm["rng"].uniform(-1, 1, xyz.shape[0])
+        f[dirichlet] = 0.0
+        fd = ctx.from_canonical(level, torch.tensor(f, device="cuda"))
+        res = evaluate(ctx, fd, level, w, torch, tol=tol)
+        u = ctx.vector(level)
+        res["f64"] = ctx.solve(level, fd, u, mode=hhg.SOLVE_F64, tol=tol, max_iter=200)
+        res["seed"] = seed
+        res["sigma"] = float(prm["sigma"])
+        res["corr_len"] = float(prm["corr_len"])
+        out.append(res)
+        if log:
+            log(f"eval field {seed}: iterations learned {res['learned']['iterations']} chebyshev "
+                f"{res['chebyshev']['iterations']} off {res['network_off']['iterations']}; seconds learned "
+                f"{res['learned']['seconds']:.3f} chebyshev {res['chebyshev']['seconds']:.3f} "
+                f"f64 {res['f64']['seconds']:.3f}; fallback {res['learned']['fallback']}")
+    return out
+
+
+def summarize(results):
+    def col(name, key):
+        return np.array([r[name][key] for r in results], dtype=float)
+    s = {"fields": len(results)}
+    for name in ("learned", "chebyshev", "network_off", "f64"):
+        s[name] = {"mean_iterations": float(col(name, "iterations").mean()),
+                   "mean_seconds": float(col(name, "seconds").mean()),
+                   "median_rho": float(np.median(col(name, "rho"))),
+                   "max_rel_residual": float(col(name, "rel_residual").max()),
+                   "fallbacks": int(col(name, "fallback").sum())}
+    s["learned_fewer_iterations_than_chebyshev"] = int((col("learned", "iterations") < col("chebyshev", "iterations")).sum())
+    s["learned_faster_than_chebyshev"] = int((col("learned", "seconds") < col("chebyshev", "seconds")).sum())
+    s["learned_faster_than_f64"] = int((col("learned", "seconds") < col("f64", "seconds")).sum())
+    return s
+
+
+def main(argv=None):
+    """python -m paper_1709_06793_amd.learned_train {train,eval} ...
+
+    train: fields 100..355 (256) on the 6-tet Kuhn cube at level 6, Adam on
+    the one-step energy loss, weights written to learned_weights.json.
+    eval: held-out fields 1000..1031 at level 8, learned vs Chebyshev vs
+    network-off (all FP32-in-FP64) and plain FP64 solves to 1e-8."""
+    import argparse
+    import json
+    import sys
+    import torch
+    from hhg_inputs import kuhn_cube
+    ap = argparse.ArgumentParser()
+    ap.add_argument("what", choices=["train", "eval"])
+    ap.add_argument("--level", type=int, default=None)
+    ap.add_argument("--first-seed", type=int, default=None)
+    ap.add_argument("--fields", type=int, default=None)
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--lr", type=float, default=3e-3)
+    ap.add_argument("--out", default=WEIGHTS_PATH)
+    ap.add_argument("--weights", default=WEIGHTS_PATH)
+    ap.add_argument("--json", default=None, help="write the evaluation records here")
+    a = ap.parse_args(argv)
+
+    def log(msg):
+        print(msg, flush=True)
+
+    torch.cuda.set_device(0)
+    if a.what == "train":
+        level = a.level or 6
+        s0 = 100 if a.first_seed is None else a.first_seed
+        nf = a.fields or 256
+        t0 = time.time()
+        data = generate_samples(level, list(range(s0, s0 + nf)), kuhn_cube, torch, log=log)
+        log(f"samples ready: {nf} fields, {sum(len(p) for _, p, _ in data)} pairs ({time.time() - t0:.1f} s)")
+        w, hist = train(data, level, epochs=a.epochs, lr=a.lr, log=log)
+        meta = {"level": level, "fields": [s0, s0 + nf - 1], "epochs": a.epochs, "lr": a.lr,
+                "loss_history": [float(h) for h in hist], "mesh": "6-tet Kuhn unit cube",
+                "pairs_per_field": "5 V(2,2)-cycle pairs + 3 random-error pairs"}
+        save_weights(w, a.out, meta)
+        log(json.dumps({"trained": a.out, "final_loss": hist[-1], "seconds": time.time() - t0}))
+        return 0
+    level = a.level or 8
+    s0 = 1000 if a.first_seed is None else a.first_seed
+    nf = a.fields or 32
+    w, meta = load_weights(a.weights)
+    res = evaluate_fields(level, list(range(s0, s0 + nf)), w, torch, kuhn_cube, log=log)
+    summ = summarize(res)
+    if a.json:
+        with open(a.json, "w") as fh:
+            json.dump({"summary": summ, "fields": res, "weights_meta": meta}, fh, indent=1)
+    log(json.dumps(summ))
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())
