@@ -169,6 +169,49 @@ def kuhn48_applies(hhg, torch, steps, solves=True):
     torch.cuda.empty_cache()
     return out
 
+def learned_solves(hhg, torch):
+    """Time to a 1e-8 relative residual on a held-out learned-smoother field
+    (6-tet Kuhn cube, level 8, 16.6M unknowns, field seed 1000): the learned
+    smoother (FP32 cycles, trained weights shipped with the package), plain
+    Chebyshev FP32-in-FP64 and plain FP64 multigrid; best of two runs each."""
+    from hhg_inputs import kuhn_cube, lognormal_params, lognormal_k
+    from paper_1709_06793_amd import learned_train as LT
+    level = 8
+    log("bench: learned smoother, 6-tet cube level 8, field 1000")
+    X, T = kuhn_cube()
+    ctx = hhg.Context(X, T, level)
+    xyz, dirichlet = ctx.node_coords(level)
+    prm = lognormal_params(1000)
+    ctx.set_coefficient(lognormal_k(xyz, prm))
+    f = prm["rng"].uniform(-1, 1, xyz.shape[0])
+    f[dirichlet] = 0.0
+    fd = ctx.from_canonical(level, torch.tensor(f, device="cuda"))
+    w, meta = LT.load_weights()
+    ctx.learned_set_weights(w)
+    ctx.learned_set_fallback(1.0)
+    out = {"unknowns": ctx.sizes(level)["n_unknowns"], "field_seed": 1000,
+           "sigma": round(prm["sigma"], 4), "corr_len": round(prm["corr_len"], 4), "tol": 1e-8}
+    for name, mode in (("learned", hhg.SOLVE_LEARNED), ("chebyshev_mixed", hhg.SOLVE_MIXED),
+                       ("chebyshev_f64", hhg.SOLVE_F64)):
+        best = None
+        for _ in range(2):
+            u = ctx.vector(level)
+            torch.cuda.synchronize()
+            st = ctx.solve(level, fd, u, mode=mode, tol=1e-8, max_iter=200)
+            if best is None or st["seconds"] < best["seconds"]:
+                best = st
+        out[name] = {k2: (float(f"{v:.4g}") if isinstance(v, float) else v) for k2, v in best.items()}
+        log(f"bench: {name}: {best}")
+    ev = meta.get("evaluation", {}).get("summary")
+    if ev:
+        out["held_out_32_fields"] = {k2: {"mean_iterations": v["mean_iterations"],
+                                          "mean_seconds": round(v["mean_seconds"], 5)}
+                                     for k2, v in ev.items() if isinstance(v, dict)}
+    del ctx
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -270,6 +313,7 @@ def main():
         torch.cuda.empty_cache()
 
         extra["kuhn48_l8"] = kuhn48_applies(hhg, torch, args.steps, solves=True)
+        extra["learned_l8"] = learned_solves(hhg, torch)
     out["extra"] = extra
     if not args.no_cpu:
         log("bench: CPU oracle baseline")
