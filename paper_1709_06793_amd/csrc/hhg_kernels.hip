@@ -505,13 +505,13 @@ static int march_variant()
     if (v < 0) {
         const char *e = getenv("HHG_MARCH_VARIANT");
         v = e ? atoi(e) : 0;
-        if (v < 0 || v > 7) v = 0;
+        if (v < 0 || v > 8) v = 0;
     }
     return v;
 }
 
 // variants 0 (default) and 6 run scaled rows two per lane; 1-5 and 7 one per lane
-static inline bool two_rows(int v) { return v == 0 || v == 6; }
+static inline bool two_rows(int v) { return v == 0 || v == 6 || v == 8; }
 
 // blocks of the interior launch (one partial sum each in residual mode)
 template <typename T>
@@ -531,6 +531,7 @@ static void launch_march(const LevelView<T> &L, const T *u, const T *f, T *y, do
         if (two_rows(v)) {
             const int g2 = march_grid(L.n_tet, L.vpt2, L.bpt2);
             if (v == 6) k_march2<T, MODE, OP, 0, 3><<<g2, BLOCK, 0, st>>>(L, u, f, y, partial);
+            else if (v == 8) k_march2<T, MODE, OP, 2, 2><<<g2, BLOCK, 0, st>>>(L, u, f, y, partial);
             else k_march2<T, MODE, OP, 1, 2><<<g2, BLOCK, 0, st>>>(L, u, f, y, partial);
             return;
         }
@@ -602,7 +603,7 @@ __global__ __launch_bounds__(BLOCK) void k_shared_coef(LevelView<double> L, cons
         int tet, kind, i, j, k;
         unpack_copy(L.sh_copy[c], tet, kind, i, j, k);
         const int64_t base = (int64_t)tet * L.Spad;
-        const int s = (int)slot_of(L.n, i, j, k);
+        const int s = slot32(L.n, i, j, k);
         const int8_t *mp = map + (int64_t)c * 16;
         const double kq = L.kap[base + s];
         int nb[NDIR];
@@ -623,7 +624,7 @@ __global__ __launch_bounds__(BLOCK) void k_shared_coef(LevelView<double> L, cons
                 if (!ok) continue;
                 double ks = 0.0;
                 for (int v = 0; v < 4; ++v)
-                    ks += L.kap[base + slot_of(L.n, bi + TYPE_OFF[t][v][0], bj + TYPE_OFF[t][v][1],
+                    ks += L.kap[base + slot32(L.n, bi + TYPE_OFF[t][v][0], bj + TYPE_OFF[t][v][1],
                                                bk + TYPE_OFF[t][v][2])];
                 for (int v = 0; v < 4; ++v) {
                     if (v == a) continue;
@@ -765,7 +766,7 @@ __global__ __launch_bounds__(BLOCK) void k_diag_shared(LevelView<T> L, T *__rest
         int tet, kind, i, j, k;
         unpack_copy(L.sh_copy[c], tet, kind, i, j, k);
         const int64_t base = (int64_t)tet * L.Spad;
-        const int s = (int)slot_of(L.n, i, j, k);
+        const int s = slot32(L.n, i, j, k);
         int nb[NDIR];
         neighbour_slots(s, i + j, L.n - k, nb);
         const T *w = L.sten + (int64_t)tet * TET_STENCIL + kind * KIND_STRIDE;
@@ -781,7 +782,7 @@ __global__ __launch_bounds__(BLOCK) void k_diag_shared(LevelView<T> L, T *__rest
     for (int c = L.sh_off[q]; c < L.sh_off[q + 1]; ++c) {
         int tet, kind, i, j, k;
         unpack_copy(L.sh_copy[c], tet, kind, i, j, k);
-        const int64_t sl = (int64_t)tet * L.Spad + slot_of(L.n, i, j, k);
+        const int64_t sl = (int64_t)tet * L.Spad + slot32(L.n, i, j, k);
         dout[sl] = (T)dsum;
         if (asum_out) asum_out[sl] = asum;
     }
@@ -866,25 +867,38 @@ hipError_t launch_cheb_update(T *u, T *dvec, const T *r, const T *invd, T c_old,
 
 // ---------------------------------------------------------------- grid transfer
 // restriction = transpose of P1 interpolation: r_c(x) = r_f(2x) + 1/2 sum_d r_f(2x+d)
+// grids over (in-plane chunk, plane k, tet): a thread finds its lattice point
+// from its in-plane offset alone (threads past the plane's end return)
+__device__ __forceinline__ bool plane_point(int n, int &i, int &j, int &k, int &s)
+{
+    k = blockIdx.y;
+    const int t = blockIdx.x * BLOCK + threadIdx.x;
+    if (t >= tr32(n - k)) return false;
+    int d = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+    while ((d + 1) * (d + 2) / 2 <= t) ++d;
+    while (d > 0 && d * (d + 1) / 2 > t) --d;
+    i = t - d * (d + 1) / 2;
+    j = d - i;
+    s = tc32(n) - tc32(n - k) + t;
+    return true;
+}
+static inline dim3 plane_grid(int n, int n_tet) { return dim3((unsigned)((tri_count(n) + BLOCK - 1) / BLOCK), (unsigned)(n + 1), (unsigned)n_tet); }
+
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_restrict_volume(LevelView<T> Lc, LevelView<T> Lf,
                                                             const T *__restrict__ rf,
                                                             T *__restrict__ rc)
 {
-    const int lb = xcd_remap(blockIdx.x, gridDim.x);
-    if (lb >= Lc.n_tet * Lc.bpt) return;
-    const int tet = lb / Lc.bpt;
-    const int s = (lb - tet * Lc.bpt) * BLOCK + threadIdx.x;
-    if (s >= Lc.S) return;
-    int i, j, k;
-    decode_slot(Lc.n, s, i, j, k);
+    int i, j, k, s;
+    if (!plane_point(Lc.n, i, j, k, s)) return;
+    const int tet = blockIdx.z;
     const int64_t bc = (int64_t)tet * Lc.Spad;
     if (i == 0 || j == 0 || k == 0 || i + j + k == Lc.n) {
         if (is_dirichlet(Lc.dmask, tet, Lc.n, i, j, k)) rc[bc + s] = T(0);
         return;
     }
     const T *__restrict__ fb = rf + (int64_t)tet * Lf.Spad;
-    const int sf = (int)slot_of(Lf.n, 2 * i, 2 * j, 2 * k);
+    const int sf = slot32(Lf.n, 2 * i, 2 * j, 2 * k);
     int nb[NDIR];
     neighbour_slots(sf, 2 * (i + j), Lf.n - 2 * k, nb);
     T acc = T(0);
@@ -906,7 +920,7 @@ __global__ __launch_bounds__(BLOCK) void k_restrict_shared(LevelView<T> Lc, Leve
         unpack_copy(Lc.sh_copy[c], tet, kind, i, j, k);
         const T *fb = rf + (int64_t)tet * Lf.Spad;
         const T *w = Lc.rstw + (int64_t)tet * TET_STENCIL + kind * KIND_STRIDE;
-        const int sf = (int)slot_of(Lf.n, 2 * i, 2 * j, 2 * k);
+        const int sf = slot32(Lf.n, 2 * i, 2 * j, 2 * k);
         int nb[NDIR];
         neighbour_slots(sf, 2 * (i + j), Lf.n - 2 * k, nb);
         acc += w[NDIR] * fb[sf];
@@ -916,7 +930,7 @@ __global__ __launch_bounds__(BLOCK) void k_restrict_shared(LevelView<T> Lc, Leve
     for (int c = Lc.sh_off[q]; c < Lc.sh_off[q + 1]; ++c) {
         int tet, kind, i, j, k;
         unpack_copy(Lc.sh_copy[c], tet, kind, i, j, k);
-        rc[(int64_t)tet * Lc.Spad + slot_of(Lc.n, i, j, k)] = acc;
+        rc[(int64_t)tet * Lc.Spad + slot32(Lc.n, i, j, k)] = acc;
     }
 }
 
@@ -924,7 +938,7 @@ template <typename T>
 hipError_t launch_restrict(const LevelView<T> &Lc, const LevelView<T> &Lf, const T *rf, T *rc,
                            hipStream_t st)
 {
-    k_restrict_volume<T><<<volume_grid(Lc.n_tet, Lc.bpt), BLOCK, 0, st>>>(Lc, Lf, rf, rc);
+    k_restrict_volume<T><<<plane_grid(Lc.n, Lc.n_tet), BLOCK, 0, st>>>(Lc, Lf, rf, rc);
     if (Lc.n_shared) k_restrict_shared<T><<<blocks_for(Lc.n_shared), BLOCK, 0, st>>>(Lc, Lf, rf, rc);
     return hipGetLastError();
 }
@@ -940,22 +954,18 @@ __global__ __launch_bounds__(BLOCK) void k_prolong_add(LevelView<T> Lc, LevelVie
                                                         const T *__restrict__ uc,
                                                         T *__restrict__ uf)
 {
-    const int lb = xcd_remap(blockIdx.x, gridDim.x);
-    if (lb >= Lf.n_tet * Lf.bpt) return;
-    const int tet = lb / Lf.bpt;
-    const int s = (lb - tet * Lf.bpt) * BLOCK + threadIdx.x;
-    if (s >= Lf.S) return;
-    int i, j, k;
-    decode_slot(Lf.n, s, i, j, k);
+    int i, j, k, s;
+    if (!plane_point(Lf.n, i, j, k, s)) return;
+    const int tet = blockIdx.z;
     const T *__restrict__ cb = uc + (int64_t)tet * Lc.Spad;
     const int p = (i & 1) | ((j & 1) << 1) | ((k & 1) << 2);
     T v;
     if (p == 0) {
-        v = cb[slot_of(Lc.n, i >> 1, j >> 1, k >> 1)];
+        v = cb[slot32(Lc.n, i >> 1, j >> 1, k >> 1)];
     } else {
         const int di = PARITY_DIR[p][0], dj = PARITY_DIR[p][1], dk = PARITY_DIR[p][2];
-        const T a = cb[slot_of(Lc.n, (i - di) >> 1, (j - dj) >> 1, (k - dk) >> 1)];
-        const T b = cb[slot_of(Lc.n, (i + di) >> 1, (j + dj) >> 1, (k + dk) >> 1)];
+        const T a = cb[slot32(Lc.n, (i - di) >> 1, (j - dj) >> 1, (k - dk) >> 1)];
+        const T b = cb[slot32(Lc.n, (i + di) >> 1, (j + dj) >> 1, (k + dk) >> 1)];
         v = T(0.5) * (a + b);
     }
     uf[(int64_t)tet * Lf.Spad + s] += v;
@@ -965,7 +975,7 @@ template <typename T>
 hipError_t launch_prolong_add(const LevelView<T> &Lc, const LevelView<T> &Lf, const T *uc, T *uf,
                               hipStream_t st)
 {
-    k_prolong_add<T><<<volume_grid(Lf.n_tet, Lf.bpt), BLOCK, 0, st>>>(Lc, Lf, uc, uf);
+    k_prolong_add<T><<<plane_grid(Lf.n, Lf.n_tet), BLOCK, 0, st>>>(Lc, Lf, uc, uf);
     return hipGetLastError();
 }
 
@@ -1049,7 +1059,7 @@ __global__ void k_inject(const T *__restrict__ kf, int nf, T *__restrict__ kc, i
     const int tet = (int)(q / S), s = (int)(q - (int64_t)tet * S);
     int i, j, k;
     decode_slot(nc, s, i, j, k);
-    kc[tet * Spad_c + s] = kf[tet * Spad_f + slot_of(nf, 2 * i, 2 * j, 2 * k)];
+    kc[tet * Spad_c + s] = kf[tet * Spad_f + slot32(nf, 2 * i, 2 * j, 2 * k)];
 }
 template <typename T>
 hipError_t launch_inject(const T *kf, int nf, T *kc, int nc, int n_tet, int64_t Spad_f,

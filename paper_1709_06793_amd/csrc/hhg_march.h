@@ -13,6 +13,12 @@ namespace hhg {
 
 __device__ __forceinline__ int tc32(int m) { return (m + 1) * (m + 2) * (m + 3) / 6; }
 __device__ __forceinline__ int tr32(int m) { return (m + 1) * (m + 2) / 2; }
+// slot of (i,j,k) in one tet lattice in 32-bit arithmetic (n <= 1024)
+__device__ __forceinline__ int slot32(int n, int i, int j, int k)
+{
+    const int s = i + j;
+    return tc32(n) - tc32(n - k) + s * (s + 1) / 2 + i;
+}
 
 __device__ __forceinline__ int xcd_remap(int b, int grid)
 {
