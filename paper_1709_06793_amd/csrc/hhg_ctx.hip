@@ -227,9 +227,9 @@ struct Level {
     std::vector<uint32_t> h_items;  // pairs (t0, k0 | k1 << 16)
     std::vector<uint32_t> h_bnd;
     uint2 *items = nullptr;
-    std::vector<uint32_t> h_items2;  // two-rows-per-lane kernel
-    uint2 *items2 = nullptr;
-    int n_items2 = 0, kc2 = 0;
+    std::vector<uint32_t> h_items2, h_items2f;  // two-rows-per-lane kernel (FP64, FP32)
+    uint2 *items2 = nullptr, *items2f = nullptr;
+    int n_items2 = 0, kc2 = 0, n_items2f = 0, kc2f = 0;
     uint32_t *bnd = nullptr;
     int n_items = 0, n_bnd = 0, kc = 0;
     // shared nodes
@@ -484,7 +484,7 @@ LevelView<float> view<float>(const hhg_ctx c, int l)
     v.items = L.items; v.n_items = L.n_items; v.vpt = (L.n_items + 3) / 4;
     v.sh_w = L.sh_w; v.sh_nb = L.sh_nb; v.sh_self = L.sh_self; v.sh_cslot = L.sh_cslot;
     v.sh_cs = L.sh_cs32; v.sh_cn = L.sh_cn32;
-    v.items2 = L.items2; v.n_items2 = L.n_items2; v.vpt2 = (L.n_items2 + 3) / 4;
+    v.items2 = L.items2f; v.n_items2 = L.n_items2f; v.vpt2 = (L.n_items2f + 3) / 4;
     v.bnd = L.bnd; v.n_bnd = L.n_bnd; v.bpt2 = (L.n_bnd + BLOCK - 1) / BLOCK;
     return v;
 }
@@ -831,8 +831,11 @@ hhg_status build_level(hhg_ctx c, int l)
             }
         };
         build_items(62, 8192, L.h_items, L.kc);
-        build_items(126, 4096, L.h_items2, L.kc2);
+        // two-rows-per-lane items: FP64 prefers more, shorter waves than FP32
+        build_items(126, 8192, L.h_items2, L.kc2);
         L.n_items2 = (int)(L.h_items2.size() / 2);
+        build_items(126, 4096, L.h_items2f, L.kc2f);
+        L.n_items2f = (int)(L.h_items2f.size() / 2);
         L.n_items = (int)(L.h_items.size() / 2);
         L.h_bnd.clear();
         for (int k = 0; k <= n; ++k)
@@ -846,11 +849,13 @@ hhg_status build_level(hhg_ctx c, int l)
         uint32_t *ip = nullptr;
         TRY(upload(c, &ip, items_copy));
         L.items = (uint2 *)ip;
-        std::vector<uint32_t> items2_copy = L.h_items2;
-        uint32_t *ip2 = nullptr;
-        if (items2_copy.empty()) items2_copy.assign(2, 0u);  // never read when n_items2 == 0
-        TRY(upload(c, &ip2, items2_copy));
-        L.items2 = (uint2 *)ip2;
+        for (int pr = 0; pr < 2; ++pr) {
+            std::vector<uint32_t> cp = pr ? L.h_items2f : L.h_items2;
+            uint32_t *ip2 = nullptr;
+            if (cp.empty()) cp.assign(2, 0u);  // never read when the count is 0
+            TRY(upload(c, &ip2, cp));
+            (pr ? L.items2f : L.items2) = (uint2 *)ip2;
+        }
         TRY(upload(c, &L.bnd, L.h_bnd));
     }
 
@@ -1460,8 +1465,11 @@ hhg_status hhg_create_macro(const double *vert_xyz, int32_t n_vert, const int32_
         for (int l = 0; l <= max_level; ++l) {
             const Level &L = c->lv[l];
             const int64_t bp2 = (L.n_bnd + BLOCK - 1) / BLOCK;
-            const int64_t gm = std::max((int64_t)tp.nt * ((L.n_items + 3) / 4 + bp2),
-                                        (int64_t)tp.nt * ((L.n_items2 + 3) / 4 + bp2));
+            const int64_t gm = std::max({(int64_t)tp.nt * ((L.n_items + 3) / 4 + bp2),
+                                         (int64_t)tp.nt * ((L.n_items2 + 3) / 4 + bp2),
+                                         (int64_t)tp.nt * ((L.n_items2f + 3) / 4 + bp2),
+                                         (int64_t)tp.nt * (L.n_items2 + (L.n_bnd + 63) / 64),
+                                         (int64_t)tp.nt * (L.n_items2f + (L.n_bnd + 63) / 64)});
             const int64_t gv = (std::max((int64_t)tp.nt * L.bpt, gm) + 7) / 8 * 8;
             pc = std::max(pc, gv + (L.n_shared + BLOCK - 1) / BLOCK + (L.n_slots + BLOCK - 1) / BLOCK + 8);
         }

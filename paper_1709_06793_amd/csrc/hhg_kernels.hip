@@ -2,15 +2,19 @@
 // nodal-integration operator application on tetrahedral-index lattices,
 // residual norms, smoother updates, grid transfer and the coarse solve.
 //
-// Work decomposition.  Slot vectors hold one closed tet lattice per macro tet.
-// The "volume" kernels give one thread to one lattice slot: interior slots
-// compute their row from the 14 lattice neighbours, Dirichlet boundary slots
-// are written 0, and slots on primitives shared with other tets are left to
-// the "shared" kernels, which give one thread to one unique shared node and
-// sum the tet-restricted rows of all its copies, writing the result to every
-// copy.  Volume grids are remapped so that each of the 8 XCDs of the chip
-// walks one contiguous eighth of the slot range (neighbouring planes then hit
-// in that XCD's L2).
+// Work decomposition.  Slot vectors hold one closed tet lattice per macro tet
+// (planes k in turn, inside a plane the anti-diagonals i + j in turn).
+// Interior rows are computed by column marching (k_march2 for the scaled
+// operator, two rows per lane; k_march for the nodal one): a wave owns a run
+// of consecutive in-plane offsets, walks a chunk of planes with three planes
+// held in registers, and takes the i +- 1 neighbours from the adjacent lanes.
+// Rows of nodes on primitives shared by several tets (macro faces, edges,
+// vertices) come from merged neighbour lists built once per coefficient
+// field (k_shared_rows) and are written to every copy, so every slot vector
+// stays consistent.  Extra blocks of the marching launches write 0 to the
+// Dirichlet slots.  Marching grids are remapped so that each of the 8 XCDs
+// walks one contiguous eighth of the work items (neighbouring diagonals of
+// the same planes then meet in that XCD's L2).
 #include <hip/hip_runtime.h>
 
 #include <cstdlib>
@@ -135,6 +139,12 @@ __device__ __forceinline__ T row_value(const T uu[NDIR + 1], const T kk[NDIR + 1
 #pragma unroll
         for (int d = 0; d < NDIR; ++d) acc += w[d] * (k0 + kk[d]) * (uu[d] - u0);
     } else {
+        // per direction d: C_d = sum over the incident elements t holding the
+        // edge (node, node + d) of (sum of k at t's vertices) (A_t / 4)[a, b];
+        // then y = sum_d C_d (u_d - u_0)
+        T cd[NDIR];
+#pragma unroll
+        for (int d = 0; d < NDIR; ++d) cd[d] = T(0);
 #pragma unroll
         for (int t = 0; t < NTYPE; ++t)
 #pragma unroll
@@ -143,10 +153,13 @@ __device__ __forceinline__ T row_value(const T uu[NDIR + 1], const T kk[NDIR + 1
                 const int d2 = ELEM_DIR.v[t][a][2], d3 = ELEM_DIR.v[t][a][3];
                 const T ks = (kk[d0] + kk[d1]) + (kk[d2] + kk[d3]);
                 const T *e = w + t * 16 + a * 4;
-                const T sv = e[0] * (uu[d0] - u0) + e[1] * (uu[d1] - u0) + e[2] * (uu[d2] - u0) +
-                             e[3] * (uu[d3] - u0);
-                acc += ks * sv;
+                if (d0 != NDIR) cd[d0 < NDIR ? d0 : 0] += ks * e[0];
+                if (d1 != NDIR) cd[d1 < NDIR ? d1 : 0] += ks * e[1];
+                if (d2 != NDIR) cd[d2 < NDIR ? d2 : 0] += ks * e[2];
+                if (d3 != NDIR) cd[d3 < NDIR ? d3 : 0] += ks * e[3];
             }
+#pragma unroll
+        for (int d = 0; d < NDIR; ++d) acc += cd[d] * (uu[d] - u0);
     }
     return acc;
 }
@@ -391,21 +404,29 @@ __device__ __forceinline__ void gather2(const P2<T> *M, const P2<T> *C, const P2
 __device__ __forceinline__ void bstore_drop(double v, __amdgpu_buffer_rsrc_t r, int voff) { bstore(v, r, voff); }
 __device__ __forceinline__ void bstore_drop(float v, __amdgpu_buffer_rsrc_t r, int voff) { bstore(v, r, voff); }
 
-template <typename T, int MODE, int OP, int PF, int WPE>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) void k_march2(
+// WPB waves per block (4: BLOCK threads; 1: one wave per block)
+template <int WPB>
+static inline int march2_blocks_per_tet(int n_items2, int n_bnd)
+{
+    return (n_items2 + WPB - 1) / WPB + (n_bnd + 64 * WPB - 1) / (64 * WPB);
+}
+
+template <typename T, int MODE, int OP, int PF, int WPE, int WPB = 4>
+__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE))) void k_march2(
     LevelView<T> L, const T *__restrict__ u, const T *__restrict__ f, T *__restrict__ y,
     double *__restrict__ partial)
 {
     constexpr int NS = PF + 3;
-    const int per_tet = L.vpt2 + L.bpt2;
+    const int vb = (L.n_items2 + WPB - 1) / WPB;
+    const int per_tet = vb + (L.n_bnd + 64 * WPB - 1) / (64 * WPB);
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
     double sq = 0.0;
     if (lb < L.n_tet * per_tet) {
         const int tet = lb / per_tet;
         const int b = lb - tet * per_tet;
         const int64_t base = (int64_t)tet * L.Spad;
-        if (b < L.vpt2) {
-            const int item = __builtin_amdgcn_readfirstlane(b * 4 + (threadIdx.x >> 6));
+        if (b < vb) {
+            const int item = __builtin_amdgcn_readfirstlane(b * WPB + (threadIdx.x >> 6));
             if (item < L.n_items2) {
                 const uint2 it = L.items2[item];
                 const int n = L.n, lane = threadIdx.x & 63;
@@ -478,7 +499,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
                 }
             }
         } else {
-            const int e = (b - L.vpt2) * BLOCK + threadIdx.x;
+            const int e = (b - vb) * (64 * WPB) + threadIdx.x;
             if (e < L.n_bnd) {
                 const uint32_t v = L.bnd[e];
                 if ((L.dmask[tet] >> (v & 15u)) & 1) y[base + (v >> 4)] = T(0);
@@ -486,7 +507,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
         }
     }
     if (MODE == MODE_RESID) {
-        sq = block_reduce(sq, 0);
+        if (WPB == 4) sq = block_reduce(sq, 0);
+        else sq = warp_sum(sq);
         if (threadIdx.x == 0) partial[blockIdx.x] = sq;
     }
 }
@@ -505,19 +527,24 @@ static int march_variant()
     if (v < 0) {
         const char *e = getenv("HHG_MARCH_VARIANT");
         v = e ? atoi(e) : 0;
-        if (v < 0 || v > 8) v = 0;
+        if (v < 0 || v > 9) v = 0;
     }
     return v;
 }
 
-// variants 0 (default) and 6 run scaled rows two per lane; 1-5 and 7 one per lane
-static inline bool two_rows(int v) { return v == 0 || v == 6 || v == 8; }
+// scaled rows: variants 6, 8, 9 run two rows per lane, 1-5 and 7 one per
+// lane; the default (0) runs FP64 two per lane and FP32 one per lane with
+// shifts recomputed at each use (variant 1), the fastest of each measured
+template <typename T>
+static inline bool two_rows(int v) { return v == 6 || v == 8 || v == 9 || (v == 0 && sizeof(T) == 8); }
 
 // blocks of the interior launch (one partial sum each in residual mode)
 template <typename T>
 static int march_blocks(const LevelView<T> &L)
 {
-    return two_rows(march_variant()) ? march_grid(L.n_tet, L.vpt2, L.bpt2) : march_grid(L.n_tet, L.vpt, L.bpt2);
+    const int v = march_variant();
+    if (v == 9) return ((L.n_tet * march2_blocks_per_tet<1>(L.n_items2, L.n_bnd) + 7) / 8) * 8;
+    return two_rows<T>(v) ? march_grid(L.n_tet, L.vpt2, L.bpt2) : march_grid(L.n_tet, L.vpt, L.bpt2);
 }
 // the nodal rows keep the one-row-per-lane kernel (their element sums need
 // too many registers for two rows per lane)
@@ -528,10 +555,14 @@ static void launch_march(const LevelView<T> &L, const T *u, const T *f, T *y, do
 {
     if constexpr (OP == 0) {
         const int v = march_variant();
-        if (two_rows(v)) {
+        if (two_rows<T>(v)) {
             const int g2 = march_grid(L.n_tet, L.vpt2, L.bpt2);
             if (v == 6) k_march2<T, MODE, OP, 0, 3><<<g2, BLOCK, 0, st>>>(L, u, f, y, partial);
             else if (v == 8) k_march2<T, MODE, OP, 2, 2><<<g2, BLOCK, 0, st>>>(L, u, f, y, partial);
+            else if (v == 9) {
+                const int g1 = ((L.n_tet * march2_blocks_per_tet<1>(L.n_items2, L.n_bnd) + 7) / 8) * 8;
+                k_march2<T, MODE, OP, 1, 2, 1><<<g1, 64, 0, st>>>(L, u, f, y, partial);
+            }
             else k_march2<T, MODE, OP, 1, 2><<<g2, BLOCK, 0, st>>>(L, u, f, y, partial);
             return;
         }
@@ -542,7 +573,9 @@ static void launch_march(const LevelView<T> &L, const T *u, const T *f, T *y, do
     constexpr bool big = sizeof(T) == 8 && (MODE == MODE_RESID || OP == 1);
     constexpr int W4 = big ? 3 : 4;
     constexpr bool f64 = sizeof(T) == 8;
-    switch (march_variant()) {
+    int v = march_variant();
+    if (v == 0 && OP == 0 && sizeof(T) == 4) v = 1;
+    switch (v) {
     case 1: k_march<T, MODE, OP, 1, big ? 3 : (f64 ? 5 : 8), 1><<<g, BLOCK, 0, st>>>(L, u, f, y, partial); break;
     case 2: k_march<T, MODE, OP, 2, W4, 0><<<g, BLOCK, 0, st>>>(L, u, f, y, partial); break;
     case 3: k_march<T, MODE, OP, 2, big ? 3 : (f64 ? 4 : 6), 1><<<g, BLOCK, 0, st>>>(L, u, f, y, partial); break;
