@@ -141,13 +141,15 @@ hhg_status hhg_level_info(hhg_ctx ctx, int32_t level, double *lambda_max,
  * Sec. 4.1 where triggered).  u, y: device slot vectors of dtype; u != y. */
 hhg_status hhg_apply_scaled(hhg_ctx ctx, int32_t level, hhg_dtype dtype,
                             const void *u, void *y, void *stream);
-/* Instrumentation (not part of the method): while enabled, every
- * hhg_apply_scaled records a HIP event pair on its stream around its stencil
- * kernels (the interior kernel and, on multi-tet meshes, the shared-row
- * kernel; not the sparse modification correction).  hhg_read_timing
- * synchronises on the recorded events, returns the summed kernel time in ms
- * and the number of timed applies, and clears the record.  Enabling or
- * disabling also clears it. */
+/* Instrumentation (not part of the method): while enabled, the first
+ * hhg_apply_scaled records a HIP start event on its stream before its
+ * stencil kernels and every hhg_apply_scaled counts itself.
+ * hhg_read_timing records the end event on that stream, synchronises on it,
+ * and returns the time from start to end in ms (everything the stream ran in
+ * between: for back-to-back applies whose apply is a single kernel, as on a
+ * one-tet mesh without modified edges, that kernel's launch period) and the
+ * number of timed applies, and clears the record.  Enabling or disabling also
+ * clears it.  The timed applies must all use one stream. */
 hhg_status hhg_set_timing(hhg_ctx ctx, int32_t enable);
 hhg_status hhg_read_timing(hhg_ctx ctx, double *ms_total, int64_t *launches);
 /* y = A~ u with the nodal-integration operator (eq. (standardfe), Sec. 6.2). */

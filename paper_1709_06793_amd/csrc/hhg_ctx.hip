@@ -298,6 +298,7 @@ struct hhg_ctx_s {
     bool timing = false;
     std::vector<hipEvent_t> tev;
     size_t tev_used = 0;
+    hipStream_t tev_stream = nullptr;
 };
 
 namespace {
@@ -933,17 +934,21 @@ hhg_status apply_scaled_t(hhg_ctx c, int l, const T *u, T *y, hipStream_t st)
 {
     LevelView<T> V = view<T>(c, l);
     if (c->timing) {
-        if (c->tev_used + 2 > c->tev.size()) {
+        // one start event before the first timed apply; hhg_read_timing
+        // records the end event, so nothing is inserted between the applies
+        if (c->tev.empty()) {
             for (int q = 0; q < 2; ++q) {
                 hipEvent_t e;
                 HIPCHK(c, hipEventCreate(&e));
                 c->tev.push_back(e);
             }
         }
-        HIPCHK(c, hipEventRecord(c->tev[c->tev_used], st));
+        if (c->tev_used == 0) {
+            HIPCHK(c, hipEventRecord(c->tev[0], st));
+            c->tev_stream = st;
+        }
         HIPCHK(c, launch_scaled<T>(V, MODE_APPLY, u, nullptr, y, nullptr, nullptr, st));
-        HIPCHK(c, hipEventRecord(c->tev[c->tev_used + 1], st));
-        c->tev_used += 2;
+        ++c->tev_used;
     } else {
         HIPCHK(c, launch_scaled<T>(V, MODE_APPLY, u, nullptr, y, nullptr, nullptr, st));
     }
@@ -1666,14 +1671,15 @@ hhg_status hhg_read_timing(hhg_ctx c, double *ms_total, int64_t *launches)
 {
     if (!c || !ms_total || !launches) return HHG_EINVAL;
     double tot = 0.0;
-    for (size_t q = 0; q + 1 < c->tev_used; q += 2) {
-        HIPCHK(c, hipEventSynchronize(c->tev[q + 1]));
+    if (c->tev_used > 0) {
+        HIPCHK(c, hipEventRecord(c->tev[1], c->tev_stream));
+        HIPCHK(c, hipEventSynchronize(c->tev[1]));
         float ms = 0.0f;
-        HIPCHK(c, hipEventElapsedTime(&ms, c->tev[q], c->tev[q + 1]));
-        tot += ms;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->tev[0], c->tev[1]));
+        tot = ms;
     }
     *ms_total = tot;
-    *launches = (int64_t)(c->tev_used / 2);
+    *launches = (int64_t)c->tev_used;
     c->tev_used = 0;
     return HHG_OK;
 }
