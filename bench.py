@@ -79,14 +79,8 @@ def time_op(fn, steps, warmup, torch):
 
 
 def lognormal_on_device(xyz, prm, torch):
-    x = torch.tensor(xyz, dtype=torch.float64, device="cuda")
-    om = torch.tensor(prm["omega"], dtype=torch.float64, device="cuda")
-    ph = torch.tensor(prm["phi"], dtype=torch.float64, device="cuda")
-    g = torch.zeros(x.shape[0], dtype=torch.float64, device="cuda")
-    for a in range(0, x.shape[0], 1 << 24):
-        g[a:a + (1 << 24)] = torch.cos(x[a:a + (1 << 24)] @ om.T + ph).sum(dim=1)
-    M = om.shape[0]
-    return torch.exp(prm["sigma"] * np.sqrt(2.0 / M) * g)
+    from hhg_inputs import lognormal_k_torch
+    return lognormal_k_torch(xyz, prm, torch)
 
 
 def cpu_baseline(level=7, seconds=8.0):

@@ -51,6 +51,19 @@ def lognormal_k(xyz, params, chunk=1 << 20):
     return out
 
 
+def lognormal_k_torch(xyz, params, torch, device="cuda", chunk=1 << 24):
+    """lognormal_k evaluated with torch on `device` (same formula, FP64), for
+    node sets too large for the numpy version; returns a device tensor."""
+    x = torch.as_tensor(xyz, dtype=torch.float64, device=device)
+    om = torch.tensor(params["omega"], dtype=torch.float64, device=device)
+    ph = torch.tensor(params["phi"], dtype=torch.float64, device=device)
+    g = torch.empty(x.shape[0], dtype=torch.float64, device=device)
+    for a in range(0, x.shape[0], chunk):
+        g[a:a + chunk] = torch.cos(x[a:a + chunk] @ om.T + ph).sum(dim=1)
+    M = om.shape[0]
+    return torch.exp(params["sigma"] * np.sqrt(2.0 / M) * g)
+
+
 def uniform_vector(n, seed=None, rng=None, lo=-1.0, hi=1.0):
     """n values uniform in [lo, hi) from default_rng(seed) (or a given stream)."""
     if rng is None:

@@ -151,6 +151,14 @@ hhg_status hhg_apply_scaled(hhg_ctx ctx, int32_t level, hhg_dtype dtype,
  * number of timed applies, and clears the record.  Enabling or disabling also
  * clears it.  The timed applies must all use one stream. */
 hhg_status hhg_set_timing(hhg_ctx ctx, int32_t enable);
+/* Tuning and tests (not part of the method): selects the variant of the
+ * interior marching kernels for every context of the process; 0 (the
+ * default, initial value from the environment variable HHG_MARCH_VARIANT)
+ * chooses per precision and working-set size, 1..10 force one variant
+ * (10: the LDS-staged FP64 scaled apply where a level fits it).  Results of
+ * all variants agree to rounding.  HHG_EINVAL outside 0..10.  Not
+ * thread-safe against concurrent applies. */
+hhg_status hhg_set_kernel_variant(int32_t variant);
 hhg_status hhg_read_timing(hhg_ctx ctx, double *ms_total, int64_t *launches);
 /* y = A~ u with the nodal-integration operator (eq. (standardfe), Sec. 6.2). */
 hhg_status hhg_apply_nodal(hhg_ctx ctx, int32_t level, hhg_dtype dtype,

@@ -227,6 +227,9 @@ struct Level {
     std::vector<uint32_t> h_items;  // pairs (t0, k0 | k1 << 16)
     std::vector<uint32_t> h_bnd;
     uint2 *items = nullptr;
+    std::vector<uint32_t> h_itemsL;  // block items of the LDS-staged kernel
+    uint2 *itemsL = nullptr;
+    int n_itemsL = 0, kcL = 0;
     std::vector<uint32_t> h_items2, h_items2f;  // two-rows-per-lane kernel (FP64, FP32)
     uint2 *items2 = nullptr, *items2f = nullptr;
     int n_items2 = 0, kc2 = 0, n_items2f = 0, kc2f = 0;
@@ -470,6 +473,7 @@ LevelView<double> view<double>(const hhg_ctx c, int l)
     v.sh_w = L.sh_w; v.sh_nb = L.sh_nb; v.sh_self = L.sh_self; v.sh_cslot = L.sh_cslot;
     v.sh_cs = L.sh_cs64; v.sh_cn = L.sh_cn64;
     v.items2 = L.items2; v.n_items2 = L.n_items2; v.vpt2 = (L.n_items2 + 3) / 4;
+    v.itemsL = L.itemsL; v.n_itemsL = L.n_itemsL;
     v.bnd = L.bnd; v.n_bnd = L.n_bnd; v.bpt2 = (L.n_bnd + BLOCK - 1) / BLOCK;
     return v;
 }
@@ -486,6 +490,7 @@ LevelView<float> view<float>(const hhg_ctx c, int l)
     v.sh_w = L.sh_w; v.sh_nb = L.sh_nb; v.sh_self = L.sh_self; v.sh_cslot = L.sh_cslot;
     v.sh_cs = L.sh_cs32; v.sh_cn = L.sh_cn32;
     v.items2 = L.items2f; v.n_items2 = L.n_items2f; v.vpt2 = (L.n_items2f + 3) / 4;
+    v.itemsL = L.itemsL; v.n_itemsL = 0;
     v.bnd = L.bnd; v.n_bnd = L.n_bnd; v.bpt2 = (L.n_bnd + BLOCK - 1) / BLOCK;
     return v;
 }
@@ -837,6 +842,14 @@ hhg_status build_level(hhg_ctx c, int l)
         L.n_items2 = (int)(L.h_items2.size() / 2);
         build_items(126, 4096, L.h_items2f, L.kc2f);
         L.n_items2f = (int)(L.h_items2f.size() / 2);
+        // LDS-staged kernel: blocks of 1008 consecutive offsets (the plane
+        // region it stages must fit 1536 elements: n <= 256)
+        L.h_itemsL.clear();
+        L.n_itemsL = 0;
+        if (n >= 4 && n <= 256) {
+            build_items(1008, 2048, L.h_itemsL, L.kcL);
+            L.n_itemsL = (int)(L.h_itemsL.size() / 2);
+        }
         L.n_items = (int)(L.h_items.size() / 2);
         L.h_bnd.clear();
         for (int k = 0; k <= n; ++k)
@@ -850,6 +863,13 @@ hhg_status build_level(hhg_ctx c, int l)
         uint32_t *ip = nullptr;
         TRY(upload(c, &ip, items_copy));
         L.items = (uint2 *)ip;
+        {
+            std::vector<uint32_t> cp = L.h_itemsL;
+            uint32_t *ipl = nullptr;
+            if (cp.empty()) cp.assign(2, 0u);
+            TRY(upload(c, &ipl, cp));
+            L.itemsL = (uint2 *)ipl;
+        }
         for (int pr = 0; pr < 2; ++pr) {
             std::vector<uint32_t> cp = pr ? L.h_items2f : L.h_items2;
             uint32_t *ip2 = nullptr;
@@ -1474,7 +1494,8 @@ hhg_status hhg_create_macro(const double *vert_xyz, int32_t n_vert, const int32_
                                          (int64_t)tp.nt * ((L.n_items2 + 3) / 4 + bp2),
                                          (int64_t)tp.nt * ((L.n_items2f + 3) / 4 + bp2),
                                          (int64_t)tp.nt * (L.n_items2 + (L.n_bnd + 63) / 64),
-                                         (int64_t)tp.nt * (L.n_items2f + (L.n_bnd + 63) / 64)});
+                                         (int64_t)tp.nt * (L.n_items2f + (L.n_bnd + 63) / 64),
+                                         (int64_t)tp.nt * (L.n_itemsL + (L.n_bnd + 511) / 512)});
             const int64_t gv = (std::max((int64_t)tp.nt * L.bpt, gm) + 7) / 8 * 8;
             pc = std::max(pc, gv + (L.n_shared + BLOCK - 1) / BLOCK + (L.n_slots + BLOCK - 1) / BLOCK + 8);
         }
@@ -1657,6 +1678,11 @@ hhg_status hhg_apply_scaled(hhg_ctx c, int32_t level, hhg_dtype dt, const void *
     if (dt == HHG_F64) return apply_scaled_t<double>(c, level, (const double *)u, (double *)y, st);
     if (dt == HHG_F32) return apply_scaled_t<float>(c, level, (const float *)u, (float *)y, st);
     return fail(c, HHG_EINVAL, "bad dtype");
+}
+
+hhg_status hhg_set_kernel_variant(int32_t variant)
+{
+    return set_march_variant(variant) == 0 ? HHG_OK : HHG_EINVAL;
 }
 
 hhg_status hhg_set_timing(hhg_ctx c, int32_t enable)

@@ -28,6 +28,10 @@ struct LevelView {
     const uint2 *items2;
     int n_items2;
     int vpt2;
+    // block items of the LDS-staged kernel (8 waves: first row offset of
+    // 1008 consecutive offsets, k0 | k1 << 16); 0 when the level is too large
+    const uint2 *itemsL;
+    int n_itemsL;
     const uint32_t *bnd;
     int n_bnd;
     int bpt2;       // boundary blocks per tet
@@ -107,6 +111,8 @@ template <typename T>
 hipError_t launch_fill(T *x, T v, int64_t n, hipStream_t st);
 template <typename Ti, typename To>
 hipError_t launch_convert(const Ti *in, To *out, int64_t n, hipStream_t st);
+// kernel variant of the interior marches (0 = default policy); -1 if out of range
+int set_march_variant(int v);
 // merged coefficients of the shared rows for the current k (scaled and nodal)
 hipError_t launch_shared_coef(const LevelView<double> &L, const int8_t *map, double *cs, double *cn,
                               hipStream_t st);

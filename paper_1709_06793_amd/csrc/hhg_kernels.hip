@@ -513,23 +513,199 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
     }
 }
 
+// ---------------------------------------------------------------- LDS-staged block march
+// Eight waves march 1008 consecutive offsets of a plane chunk together (each
+// wave two rows per lane as in k_march2).  Per plane the block copies the
+// region of offsets its rows touch (at most 1536 elements per array) straight
+// from HBM into an LDS ring with 16-byte-per-lane buffer-to-LDS loads, so
+// every value of the plane is fetched once per block instead of once per
+// diagonal and wave; each wave then reads its three diagonal pairs per array
+// from LDS.  Two planes are in flight; one barrier per plane orders the ring.
+// The LDS reads are written as inline asm that waits for its own data, and the
+// waits for the LDS loads are explicit (counted per wave): the compiler would
+// otherwise wait for every outstanding load before each LDS read.
+constexpr int LW = 8;               // waves per block
+constexpr int LCH = 12;             // 128-element chunks per array and plane
+constexpr int LELEM = LCH * 128;    // staged elements per array and plane
+constexpr int LRS = 3;              // ring slots (two planes in flight)
+
+typedef double d2v __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ unsigned lds_addr(const double *p)
+{
+    return (unsigned)(size_t)((__attribute__((address_space(3))) const double *)p);
+}
+
+// the six pairs (diagonals s-1, s, s+1 of u and k) of one plane from LDS
+__device__ __forceinline__ void lds_read_plane(unsigned au, unsigned ak, const int e[3], P2<double> uu[3],
+                                               P2<double> kk[3])
+{
+    d2v a0, a1, a2, b0, b1, b2;
+    asm volatile(
+        "ds_read2_b64 %0, %6 offset1:1\n\t"
+        "ds_read2_b64 %1, %7 offset1:1\n\t"
+        "ds_read2_b64 %2, %8 offset1:1\n\t"
+        "ds_read2_b64 %3, %9 offset1:1\n\t"
+        "ds_read2_b64 %4, %10 offset1:1\n\t"
+        "ds_read2_b64 %5, %11 offset1:1\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(a0), "=&v"(a1), "=&v"(a2), "=&v"(b0), "=&v"(b1), "=&v"(b2)
+        : "v"(au + e[0] * 8), "v"(au + e[1] * 8), "v"(au + e[2] * 8), "v"(ak + e[0] * 8), "v"(ak + e[1] * 8),
+          "v"(ak + e[2] * 8)
+        : "memory");
+    uu[0] = {a0.x, a0.y}; uu[1] = {a1.x, a1.y}; uu[2] = {a2.x, a2.y};
+    kk[0] = {b0.x, b0.y}; kk[1] = {b1.x, b1.y}; kk[2] = {b2.x, b2.y};
+}
+
+template <int MODE>
+__global__ __launch_bounds__(64 * LW) __attribute__((amdgpu_waves_per_eu(4))) void k_march_lds(
+    LevelView<double> L, const double *__restrict__ u, double *__restrict__ y)
+{
+    __shared__ __attribute__((aligned(16))) double ring[LRS][2][LELEM];
+    const int nbb = (L.n_bnd + 64 * LW - 1) / (64 * LW);
+    const int per_tet = L.n_itemsL + nbb;
+    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    if (lb >= L.n_tet * per_tet) return;  // whole block
+    const int tet = lb / per_tet;
+    const int b = lb - tet * per_tet;
+    const int64_t base = (int64_t)tet * L.Spad;
+    if (b >= L.n_itemsL) {  // whole block: Dirichlet zeros
+        const int e = (b - L.n_itemsL) * (64 * LW) + threadIdx.x;
+        if (e < L.n_bnd) {
+            const uint32_t v = L.bnd[e];
+            if ((L.dmask[tet] >> (v & 15u)) & 1) y[base + (v >> 4)] = 0.0;
+        }
+        return;
+    }
+    const uint2 it = L.itemsL[b];
+    const int n = L.n;
+    const int t0 = __builtin_amdgcn_readfirstlane((int)it.x);
+    const int k0 = __builtin_amdgcn_readfirstlane((int)(it.y & 0xffffu));
+    const int k1 = __builtin_amdgcn_readfirstlane((int)(it.y >> 16));
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    auto diag = [](int t) {
+        int d = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+        while ((d + 1) * (d + 2) / 2 <= t) ++d;
+        while (d > 0 && d * (d + 1) / 2 > t) --d;
+        return d;
+    };
+    const int tx = t0 - 1 + 126 * wave + 2 * lane, ty = tx + 1;
+    const int sdx = tx >= 0 ? diag(tx) : -1, sdy = diag(ty);
+    const int ix = tx - sdx * (sdx + 1) / 2, iy = ty - sdy * (sdy + 1) / 2;
+    const bool row_x = tx >= 0 && lane >= 1 && ix >= 1 && ix <= sdx - 1;
+    const bool row_y = lane <= 62 && iy >= 1 && iy <= sdy - 1;
+    const int lastx = row_x ? min(n - 1 - sdx, k1) : -1;
+    const int lasty = row_y ? min(n - 1 - sdy, k1) : -1;
+    // staged region of every plane: in-plane offsets [lo, lo + LELEM)
+    const int lo = __builtin_amdgcn_readfirstlane(t0 - diag(t0) - 1);
+    const int osm = ty - sdy - 1, oc = tx, osp = tx + sdx + 1;
+    const int e[3] = {(osm >= 0 ? osm : 0) - lo, (oc >= 0 ? oc : 0) - lo, (osp >= 0 ? osp : 0) - lo};
+    const __amdgpu_buffer_rsrc_t ru = tet_rsrc(u + base, (int64_t)L.S * 8);
+    const __amdgpu_buffer_rsrc_t rk = tet_rsrc(L.kap + base, (int64_t)L.S * 8);
+    const __amdgpu_buffer_rsrc_t ry = tet_rsrc(y + base, (int64_t)L.S * 8);
+    const int Sn = tc32(n);
+    auto plane = [&](int p) { return Sn - tc32(n - p); };
+    // this wave's three 16-byte-per-lane LDS loads of plane p into slot p % LRS
+    auto stage = [&](int p) {
+        const int sl = p % LRS;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int Q = wave * 3 + q, arr = Q / LCH, ch = Q - arr * LCH;
+            const int voff = (plane(p) + lo + ch * 128 + 2 * lane) * 8;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(arr ? rk : ru,
+                                                     (__attribute__((address_space(3))) void *)&ring[sl][arr][ch * 128],
+                                                     16, voff, 0, 0, 0);
+        }
+    };
+    auto addr = [&](int p, int arr) { return lds_addr(&ring[p % LRS][arr][0]); };
+    double wr[NDIR / 2];
+    const double *__restrict__ w = L.sten + (int64_t)tet * TET_STENCIL;
+#pragma unroll
+    for (int d = 0; d < NDIR / 2; ++d) wr[d] = w[d];
+    struct Pl {
+        P2<double> u[3], k[3];
+    } R[3];
+    // prologue: planes k0-1 and k0 into registers, then k0+1 and k0+2 in flight
+    stage(k0 - 1);
+    stage(k0);
+    // s_waitcnt immediates: vmcnt in bits 3:0, expcnt 6:4 (7 = no wait),
+    // lgkmcnt 11:8 (15 = no wait)
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_sched_barrier(0);
+    lds_read_plane(addr(k0 - 1, 0), addr(k0 - 1, 1), e, R[0].u, R[0].k);
+    lds_read_plane(addr(k0, 0), addr(k0, 1), e, R[1].u, R[1].k);
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_sched_barrier(0);
+    stage(k0 + 1);
+    stage(k0 + 2);
+    constexpr int DROP = 0x7ffffff0;
+    for (int kb = k0; kb <= k1; kb += 3) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int k = kb + q;
+            if (k > k1) break;  // block-uniform
+            Pl &M = R[q % 3], &C = R[(q + 1) % 3], &P = R[(q + 2) % 3];
+            // plane k+1 has landed once at most the later loads and stores
+            // are outstanding: 3 at the first step, 5 after
+            __builtin_amdgcn_sched_barrier(0);
+            if (k == k0) __builtin_amdgcn_s_waitcnt(0x0F73);  // vmcnt(3)
+            else __builtin_amdgcn_s_waitcnt(0x0F75);          // vmcnt(5)
+            __builtin_amdgcn_s_barrier();
+            __builtin_amdgcn_sched_barrier(0);
+            lds_read_plane(addr(k + 1, 0), addr(k + 1, 1), e, P.u, P.k);
+            double ux[NDIR + 1], uy[NDIR + 1], kx[NDIR + 1], ky[NDIR + 1];
+            gather2<double>(M.u, C.u, P.u, ux, uy);
+            gather2<double>(M.k, C.k, P.k, kx, ky);
+            const double ax = scaled_row_paired<double>(ux, kx, wr);
+            const double ay = scaled_row_paired<double>(uy, ky, wr);
+            const int Pk = plane(k);
+            const int sx = k <= lastx ? (Pk + tx) * 8 : DROP, sy = k <= lasty ? (Pk + ty) * 8 : DROP;
+            bstore(ax, ry, sx);
+            bstore(ay, ry, sy);
+            // the slot of plane k (read one step ago by every wave, which all
+            // passed this step's barrier) takes plane k+3
+            stage(k + 3);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    // drain: every LDS load has landed before the block's LDS is released
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+}
+
+static int lds_grid(const LevelView<double> &L)
+{
+    const int nbb = (L.n_bnd + 64 * LW - 1) / (64 * LW);
+    return ((L.n_tet * (L.n_itemsL + nbb) + 7) / 8) * 8;
+}
+
 static inline int march_grid(int n_tet, int vpt, int bpt2)
 {
     const int nb = n_tet * (vpt + bpt2);
     return ((nb + 7) / 8) * 8;
 }
 
-// variant of the marching kernel (rows per lane, prefetch depth, occupancy);
-// HHG_MARCH_VARIANT overrides the default for tuning runs
+// variant of the marching kernels (rows per lane, prefetch depth, occupancy,
+// LDS staging): 0 = the default policy; the initial value comes from
+// HHG_MARCH_VARIANT, hhg_set_kernel_variant changes it (tuning and tests)
+static int g_variant = -1;
 static int march_variant()
 {
-    static int v = -1;
-    if (v < 0) {
+    if (g_variant < 0) {
         const char *e = getenv("HHG_MARCH_VARIANT");
-        v = e ? atoi(e) : 0;
-        if (v < 0 || v > 9) v = 0;
+        int v = e ? atoi(e) : 0;
+        if (v < 0 || v > 10) v = 0;
+        g_variant = v;
     }
-    return v;
+    return g_variant;
+}
+int set_march_variant(int v)
+{
+    if (v < 0 || v > 10) return -1;
+    g_variant = v;
+    return 0;
 }
 
 // scaled rows: variants 6, 8, 9 run two rows per lane, 1-5 and 7 one per
@@ -553,6 +729,17 @@ template <typename T, int MODE, int OP>
 static void launch_march(const LevelView<T> &L, const T *u, const T *f, T *y, double *partial,
                          hipStream_t st)
 {
+    if constexpr (OP == 0 && MODE == MODE_APPLY && sizeof(T) == 8) {
+        // the LDS-staged block march where the level fits it: forced by
+        // variant 10, chosen by default for working sets far beyond the
+        // last-level cache (it measured faster there and slower below)
+        const int v = march_variant();
+        const bool big_set = (int64_t)L.n_tet * L.Spad >= ((int64_t)32 << 20);
+        if (L.n_itemsL > 0 && (v == 10 || (v == 0 && big_set))) {
+            k_march_lds<MODE_APPLY><<<lds_grid(L), 64 * LW, 0, st>>>(L, u, y);
+            return;
+        }
+    }
     if constexpr (OP == 0) {
         const int v = march_variant();
         if (two_rows<T>(v)) {

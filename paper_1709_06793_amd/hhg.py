@@ -23,7 +23,7 @@ WFALLBACK = 1
 EXPORTS = [
     "hhg_create_macro", "hhg_destroy", "hhg_last_error", "hhg_vector_size", "hhg_node_coords",
     "hhg_to_canonical", "hhg_from_canonical", "hhg_set_coefficient", "hhg_set_coarse_level",
-    "hhg_level_info", "hhg_apply_scaled", "hhg_set_timing", "hhg_read_timing", "hhg_apply_nodal", "hhg_residual", "hhg_smooth",
+    "hhg_level_info", "hhg_apply_scaled", "hhg_set_timing", "hhg_read_timing", "hhg_set_kernel_variant", "hhg_apply_nodal", "hhg_residual", "hhg_smooth",
     "hhg_vcycle", "hhg_solve", "hhg_learned_set_weights", "hhg_learned_set_fallback",
     "hhg_learned_forward", "hhg_learned_backward", "hhg_learned_loss_grad", "hhg_training_pair",
     "hhg_adam_update",
@@ -66,6 +66,7 @@ def load():
         "hhg_level_info": [P, I32, P, P, P],
         "hhg_apply_scaled": [P, I32, I32, P, P, P],
         "hhg_set_timing": [P, I32],
+        "hhg_set_kernel_variant": [I32],
         "hhg_read_timing": [P, P, P],
         "hhg_apply_nodal": [P, I32, I32, P, P, P],
         "hhg_residual": [P, I32, I32, P, P, P, P, P],
@@ -260,6 +261,13 @@ class Context:
     def training_pair(self, level, f, u, u_star, r_out, e_out):
         self._check(load().hhg_training_pair(self._h, level, _ptr(f), _ptr(u), _ptr(u_star), _ptr(r_out),
                                              _ptr(e_out), _stream()))
+
+
+def set_kernel_variant(variant):
+    """Interior-kernel variant for the whole process (0 = default policy)."""
+    s = load().hhg_set_kernel_variant(int(variant))
+    if s < 0:
+        raise HHGError(s, "kernel variant out of range")
 
 
 def adam_update(w, m, v, g, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):

@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 from hhg_inputs import (kuhn_cube, kuhn_cube_2x2x2, smooth_k, lognormal_params, lognormal_k,
-                        uniform_vector, manufactured_u, manufactured_f)
+                        lognormal_k_torch, uniform_vector, manufactured_u, manufactured_f)
 from oracle import oracle as O
 
 torch = pytest.importorskip("torch")
@@ -102,6 +102,49 @@ def test_c4_geometry_sampled_rows(dtype, tol):
         ref = O.apply_rows(om, k, uu, nodes, kind)
         assert np.abs(got[nodes] - ref).max() <= tol * np.abs(ref).max(), kind
         assert np.all(got[om.dirichlet] == 0.0)
+
+
+def test_c4_full_size_sampled_rows():
+    """48 Kuhn tets at level 8 (135M nodes, 3.3 GB FP64 working set), the
+    launch the default policy makes there (the LDS-staged scaled march):
+    sampled rows against the oracle's row-by-row evaluation (random rows and
+    every node near the 24-tet centre vertex), the whole output against the
+    two-rows-per-lane march, and zero interior rows for a constant input."""
+    X, T = kuhn_cube_2x2x2()
+    level = 8
+    om = O.Mesh(X, T, level)
+    print(f"C4 full size level {level}: {om.n_nodes} nodes", flush=True)
+    k = lognormal_k_torch(om.xyz, lognormal_params(2, 1.5, 0.05), torch).cpu().numpy()
+    u = uniform_vector(om.n_nodes, seed=12)
+    u[om.dirichlet] = 0.0
+    ctx = hhg.Context(X, T, level)
+    ctx.set_coefficient(k)
+    ud = ctx.from_canonical(level, _dev(u))
+    rng = np.random.default_rng(8)
+    centre = np.where(np.abs(om.xyz - 0.5).max(axis=1) <= 2.5 / 2 ** (level + 1))[0]
+    nodes = np.unique(np.concatenate([rng.choice(om.n_nodes, 300, replace=False), centre]))
+    y0, y1 = ctx.vector(level), ctx.vector(level)
+    try:
+        hhg.set_kernel_variant(0)
+        ctx.apply_scaled(level, ud, y0)
+        hhg.set_kernel_variant(6)
+        ctx.apply_scaled(level, ud, y1)
+    finally:
+        hhg.set_kernel_variant(0)
+    got = ctx.to_canonical(level, y0).cpu().numpy()
+    ref = O.apply_rows(om, k, u, nodes, "scaled")
+    assert np.abs(got[nodes] - ref).max() <= 1e-12 * np.abs(ref).max()
+    assert np.all(got[om.dirichlet] == 0.0)
+    d = (y1 - y0).abs().max().item() / y0.abs().max().item()
+    print(f"LDS march vs two-row march: max rel difference {d:.3e}", flush=True)
+    assert d <= 1e-12
+    del y1, ud
+    one = ctx.from_canonical(level, _dev(np.where(om.dirichlet, 0.0, 1.0)))
+    ctx.apply_scaled(level, one, y0)
+    v = ctx.to_canonical(level, y0).cpu().numpy()
+    h = 1.5 / 2 ** (level + 1)
+    inner = (om.xyz.min(axis=1) > h) & (om.xyz.max(axis=1) < 1 - h)
+    assert np.abs(v[inner]).max() <= 1e-13 * np.abs(v).max()
 
 
 @pytest.mark.parametrize("mode", [hhg.SOLVE_F64, hhg.SOLVE_MIXED])

@@ -63,6 +63,31 @@ def test_apply_fp64_matches_oracle(mesh_fn, level, kind):
     assert np.all(got[om.dirichlet] == 0.0)
 
 
+@pytest.mark.parametrize("mesh_fn,level", [(unit_tet, 5), (kuhn_cube_2x2x2, 3), (flat_tet, 4), (kuhn_cube, 6)])
+@pytest.mark.parametrize("variant", [1, 6, 10])
+def test_apply_fp64_kernel_variants(mesh_fn, level, variant):
+    """Every interior-kernel variant the default policy can choose (1: one row
+    per lane, 6: two rows per lane, 10: LDS-staged blocks), forced, with the
+    modification on: the oracle's operator, and the default variant's output."""
+    om, k, u, ctx = _setup(mesh_fn, level, kfun=lambda x: lognormal_k(x, lognormal_params(3, 1.5, 0.1)))
+    ud = ctx.from_canonical(level, _dev(u))
+    y0, y1 = ctx.vector(level), ctx.vector(level)
+    try:
+        hhg.set_kernel_variant(0)
+        ctx.apply_scaled(level, ud, y0)
+        hhg.set_kernel_variant(variant)
+        ctx.apply_scaled(level, ud, y1)
+    finally:
+        hhg.set_kernel_variant(0)
+    got = ctx.to_canonical(level, y1).cpu().numpy()
+    ref = O.make_operator(om, k, "scaled", modification=True).apply(u)
+    assert _rel(got, ref) <= TOL64 and _elem(got, ref) <= TOL64, (_rel(got, ref), _elem(got, ref))
+    assert np.all(got[om.dirichlet] == 0.0)
+    d = (y1 - y0).abs().max().item() / y0.abs().max().item()
+    print(f"variant {variant} vs default: max rel difference {d:.3e}", flush=True)
+    assert d <= TOL64
+
+
 @pytest.mark.parametrize("mesh_fn,level", [(unit_tet, 5), (kuhn_cube_2x2x2, 3)])
 @pytest.mark.parametrize("kind", ["scaled", "nodal"])
 def test_apply_fp32_matches_oracle(mesh_fn, level, kind):
