@@ -596,8 +596,11 @@ __global__ __launch_bounds__(64 * LW) __attribute__((amdgpu_waves_per_eu(4))) vo
     const bool row_y = lane <= 62 && iy >= 1 && iy <= sdy - 1;
     const int lastx = row_x ? min(n - 1 - sdx, k1) : -1;
     const int lasty = row_y ? min(n - 1 - sdy, k1) : -1;
-    // staged region of every plane: in-plane offsets [lo, lo + LELEM)
+    // staged region of every plane: in-plane offsets [lo, lo + need), need <=
+    // LELEM: from diagonal s-1 of the first row to diagonal s+1 of the last
+    // (x of the last lane of the last wave sits at t0 + 1007)
     const int lo = __builtin_amdgcn_readfirstlane(t0 - diag(t0) - 1);
+    const int need = __builtin_amdgcn_readfirstlane(t0 + 1007 + diag(t0 + 1007) + 3 - lo);
     const int osm = ty - sdy - 1, oc = tx, osp = tx + sdx + 1;
     const int e[3] = {(osm >= 0 ? osm : 0) - lo, (oc >= 0 ? oc : 0) - lo, (osp >= 0 ? osp : 0) - lo};
     const __amdgpu_buffer_rsrc_t ru = tet_rsrc(u + base, (int64_t)L.S * 8);
@@ -611,7 +614,10 @@ __global__ __launch_bounds__(64 * LW) __attribute__((amdgpu_waves_per_eu(4))) vo
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
             const int Q = wave * 3 + q, arr = Q / LCH, ch = Q - arr * LCH;
-            const int voff = (plane(p) + lo + ch * 128 + 2 * lane) * 8;
+            // a chunk past the needed length, or a plane past the last one the
+            // chunk's rows use, is still issued (the waits count three loads
+            // per wave and plane) but reads nothing
+            const int voff = ch * 128 < need && p <= k1 + 1 ? (plane(p) + lo + ch * 128 + 2 * lane) * 8 : 0x7ffffff0;
             __builtin_amdgcn_raw_ptr_buffer_load_lds(arr ? rk : ru,
                                                      (__attribute__((address_space(3))) void *)&ring[sl][arr][ch * 128],
                                                      16, voff, 0, 0, 0);
@@ -805,6 +811,14 @@ __global__ __launch_bounds__(BLOCK) void k_shared_rows(LevelView<T> L, const T *
     }
 }
 
+template <typename T, int MODE>
+static void launch_shared_rows(const LevelView<T> &L, const T *coef, const T *u, const T *f, T *y,
+                               double *partial, hipStream_t st)
+{
+    const int gs = blocks_for(L.n_shared);
+    if (gs) k_shared_rows<T, MODE><<<gs, BLOCK, 0, st>>>(L, coef, u, f, y, partial);
+}
+
 // merged coefficients of the shared rows (FP64, once per coefficient field):
 // scaled  c_m = sum over copies and directions d onto m of w_d (k_q + k_m);
 // nodal   c_m = sum over copies, elements t holding the node and m of
@@ -870,10 +884,10 @@ hipError_t launch_scaled(const LevelView<T> &L, int mode, const T *u, const T *f
     const int gs = blocks_for(L.n_shared);
     if (mode == MODE_APPLY) {
         launch_march<T, MODE_APPLY, 0>(L, u, f, y, partial, st);
-        if (gs) k_shared_rows<T, MODE_APPLY><<<gs, BLOCK, 0, st>>>(L, L.sh_cs, u, f, y, partial);
+        launch_shared_rows<T, MODE_APPLY>(L, L.sh_cs, u, f, y, partial, st);
     } else {
         launch_march<T, MODE_RESID, 0>(L, u, f, y, partial, st);
-        if (gs) k_shared_rows<T, MODE_RESID><<<gs, BLOCK, 0, st>>>(L, L.sh_cs, u, f, y, partial + gv);
+        launch_shared_rows<T, MODE_RESID>(L, L.sh_cs, u, f, y, partial + gv, st);
         if (n_partial) *n_partial = gv + gs;
     }
     return hipGetLastError();
@@ -883,7 +897,7 @@ template <typename T>
 hipError_t launch_nodal(const LevelView<T> &L, const T *u, T *y, hipStream_t st)
 {
     launch_march<T, MODE_APPLY, 1>(L, u, nullptr, y, nullptr, st);
-    if (L.n_shared) k_shared_rows<T, MODE_APPLY><<<blocks_for(L.n_shared), BLOCK, 0, st>>>(L, L.sh_cn, u, nullptr, y, nullptr);
+    launch_shared_rows<T, MODE_APPLY>(L, L.sh_cn, u, nullptr, y, nullptr, st);
     return hipGetLastError();
 }
 
@@ -1135,6 +1149,10 @@ __global__ __launch_bounds__(BLOCK) void k_restrict_shared(LevelView<T> Lc, Leve
     const int q = blockIdx.x * BLOCK + threadIdx.x;
     if (q >= Lc.n_shared) return;
     T acc = T(0);
+    // a direction with weight 0 (outside the copy's tet) gathers the centre
+    // instead and adds an exact zero, so every gather of a copy is issued at
+    // once (no branch per direction)
+#pragma unroll 2
     for (int c = Lc.sh_off[q]; c < Lc.sh_off[q + 1]; ++c) {
         int tet, kind, i, j, k;
         unpack_copy(Lc.sh_copy[c], tet, kind, i, j, k);
@@ -1143,9 +1161,15 @@ __global__ __launch_bounds__(BLOCK) void k_restrict_shared(LevelView<T> Lc, Leve
         const int sf = slot32(Lf.n, 2 * i, 2 * j, 2 * k);
         int nb[NDIR];
         neighbour_slots(sf, 2 * (i + j), Lf.n - 2 * k, nb);
-        acc += w[NDIR] * fb[sf];
-        for (int d = 0; d < NDIR; ++d)
-            if (w[d] != T(0)) acc += w[d] * fb[nb[d]];
+        T wv[NDIR + 1], fv[NDIR + 1];
+#pragma unroll
+        for (int d = 0; d <= NDIR; ++d) wv[d] = w[d];
+#pragma unroll
+        for (int d = 0; d < NDIR; ++d) fv[d] = fb[wv[d] != T(0) ? nb[d] : sf];
+        fv[NDIR] = fb[sf];
+        acc += wv[NDIR] * fv[NDIR];
+#pragma unroll
+        for (int d = 0; d < NDIR; ++d) acc += wv[d] * fv[d];
     }
     for (int c = Lc.sh_off[q]; c < Lc.sh_off[q + 1]; ++c) {
         int tet, kind, i, j, k;
