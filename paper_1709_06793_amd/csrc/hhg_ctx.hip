@@ -1009,21 +1009,34 @@ hhg_status smooth_t(hhg_ctx c, int l, hhg_smoother sm, int sweeps, double omega,
         }
         return HHG_OK;
     }
-    // Chebyshev iteration on D^{-1} A over [0.1, 1] x lambda_max
+    // Chebyshev iteration on D^{-1} A over [0.1, 1] x lambda_max.  Each sweep
+    // is one fused pass (residual, direction and next iterate together): the
+    // iterate alternates between u and the level's residual vector, which
+    // the smoother does not otherwise need; an odd sweep count copies back.
     const double a = 0.1 * L.lam, b = L.lam;
     const double theta = 0.5 * (b + a), delta = 0.5 * (b - a), sigma = theta / delta;
     double rho = 1.0 / sigma;
+    const LevelView<T> V = view<T>(c, l);
+    const CorrView<T> C = corr<T>(c, l);
+    T *cur = u, *nxt = r;
     for (int s = 0; s < sweeps; ++s) {
-        TRY(residual_t<T>(c, l, f, u, r, nullptr, st));
+        ChebArgs<T> cb;
+        cb.d = d;
+        cb.invd = id;
         if (s == 0) {
-            HIPCHK(c, launch_cheb_update<T>(u, d, r, id, T(0), (T)(1.0 / theta), L.n_slots, st));
+            cb.first = 1;
+            cb.c_r = (T)(1.0 / theta);
         } else {
             const double rn = 1.0 / (2.0 * sigma - rho);
-            HIPCHK(c, launch_cheb_update<T>(u, d, r, id, (T)(rn * rho), (T)(2.0 * rn / delta),
-                                            L.n_slots, st));
+            cb.c_old = (T)(rn * rho);
+            cb.c_r = (T)(2.0 * rn / delta);
             rho = rn;
         }
+        HIPCHK(c, launch_cheb_sweep<T>(V, C, cur, f, nxt, cb, st));
+        std::swap(cur, nxt);
     }
+    if (cur != u)
+        HIPCHK(c, hipMemcpyAsync(u, cur, L.n_slots * sizeof(T), hipMemcpyDeviceToDevice, st));
     return HHG_OK;
 }
 

@@ -72,13 +72,29 @@ struct CorrView {
 };
 
 // kernel launchers (hhg_kernels.hip); every launcher returns hipGetLastError()
-enum ApplyMode { MODE_APPLY = 0, MODE_RESID = 1 };
+enum ApplyMode { MODE_APPLY = 0, MODE_RESID = 1, MODE_CHEB = 2 };
+
+// one fused Chebyshev sweep: with r = f - A u (modification included),
+// d <- c_old d + c_r D^{-1} r (d taken as 0 when `first`) and u_new = u + d
+template <typename T>
+struct ChebArgs {
+    T *d = nullptr;
+    const T *invd = nullptr;
+    T c_old = T(0), c_r = T(0);
+    int first = 0;
+};
 
 template <typename T>
 hipError_t launch_scaled(const LevelView<T> &L, int mode, const T *u, const T *f, T *y,
                          double *partial, int *n_partial, hipStream_t st);
 template <typename T>
 hipError_t launch_nodal(const LevelView<T> &L, const T *u, T *y, hipStream_t st);
+// fused Chebyshev sweep (interior march, shared rows, modification rows):
+// reads u, f, d, D^{-1}; writes d and u_new (every slot of u_new: rows,
+// copies, Dirichlet zeros).  u_new must not alias u.
+template <typename T>
+hipError_t launch_cheb_sweep(const LevelView<T> &L, const CorrView<T> &C, const T *u, const T *f, T *u_new,
+                             const ChebArgs<T> &cb, hipStream_t st);
 template <typename T>
 hipError_t launch_correction(const LevelView<T> &L, const CorrView<T> &C, int mode, const T *u,
                              T *y, double *partial, hipStream_t st);

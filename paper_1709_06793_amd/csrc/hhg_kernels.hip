@@ -208,7 +208,7 @@ __device__ __forceinline__ void mplane_renew(MPlane<T> &p)
 template <typename T, int MODE, int OP, int PF, int WPE, int SH>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) void k_march(
     LevelView<T> L, const T *__restrict__ u, const T *__restrict__ f, T *__restrict__ y,
-    double *__restrict__ partial)
+    double *__restrict__ partial, ChebArgs<T> cb)
 {
     constexpr int NS = PF + 3;
     const int per_tet = L.vpt + L.bpt2;
@@ -237,7 +237,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
                 constexpr int B = (int)sizeof(T);
                 const __amdgpu_buffer_rsrc_t ru = tet_rsrc(u + base, (int64_t)L.S * B);
                 const __amdgpu_buffer_rsrc_t rk = tet_rsrc(L.kap + base, (int64_t)L.S * B);
-                const __amdgpu_buffer_rsrc_t rf = tet_rsrc(MODE == MODE_RESID ? f + base : u + base,
+                const __amdgpu_buffer_rsrc_t rf = tet_rsrc(MODE != MODE_APPLY ? f + base : u + base,
+                                                           (int64_t)L.S * B);
+                const __amdgpu_buffer_rsrc_t rd = tet_rsrc(MODE == MODE_CHEB ? cb.d + base : u + base,
+                                                           (int64_t)L.S * B);
+                const __amdgpu_buffer_rsrc_t ri = tet_rsrc(MODE == MODE_CHEB ? cb.invd + base : u + base,
                                                            (int64_t)L.S * B);
                 const __amdgpu_buffer_rsrc_t ry = tet_rsrc(y + base, (int64_t)L.S * B);
                 // in-plane offsets of diagonals s-1, s, s+1 at position i (a
@@ -258,7 +262,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
                 MPlane<T> R[NS];
 #pragma unroll
                 for (int q = 0; q < NS; ++q) {
-                    mplane_load<T, MODE>(R[q], ru, rk, rf, vo, plane(k0 - 1 + q));
+                    mplane_load<T, MODE>(R[q], ru, rk, rf, rd, ri, vo, plane(k0 - 1 + q));
                     // keep the sets in issue order (waits go by issue order)
                     __builtin_amdgcn_sched_barrier(0);
                 }
@@ -297,13 +301,18 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
                         const int so = live ? (plane(k) + vo[1]) * B : DROP;
                         if (MODE == MODE_APPLY) {
                             bstore(acc, ry, so);
-                        } else {
+                        } else if (MODE == MODE_RESID) {
                             const T r = C.f - acc;
                             bstore(r, ry, so);
                             sq += live ? (double)r * (double)r : 0.0;
+                        } else {
+                            const T r = C.f - acc;
+                            const T dn = (cb.first ? T(0) : cb.c_old * C.d) + cb.c_r * C.id * r;
+                            bstore(dn, rd, so);
+                            bstore(C.u[1] + dn, ry, so);
                         }
                         // plane k-1 is done with: its set takes plane k-1+NS
-                        mplane_load<T, MODE>(M, ru, rk, rf, vo, plane(k - 1 + NS));
+                        mplane_load<T, MODE>(M, ru, rk, rf, rd, ri, vo, plane(k - 1 + NS));
                         __builtin_amdgcn_sched_barrier(0);
                     }
                 }
@@ -359,18 +368,23 @@ __device__ __forceinline__ P2<float> bload2<float>(__amdgpu_buffer_rsrc_t r, int
 
 template <typename T>
 struct MPlane2 {
-    P2<T> u[3], k[3], f;
+    P2<T> u[3], k[3], f, d, id;
 };
 
 template <typename T, int MODE>
 __device__ __forceinline__ void mplane2_load(MPlane2<T> &p, __amdgpu_buffer_rsrc_t ru, __amdgpu_buffer_rsrc_t rk,
-                                             __amdgpu_buffer_rsrc_t rf, const int o[3], int P)
+                                             __amdgpu_buffer_rsrc_t rf, __amdgpu_buffer_rsrc_t rd,
+                                             __amdgpu_buffer_rsrc_t ri, const int o[3], int P)
 {
 #pragma unroll
     for (int c = 0; c < 3; ++c) p.u[c] = bload2<T>(ru, P + o[c]);
 #pragma unroll
     for (int c = 0; c < 3; ++c) p.k[c] = bload2<T>(rk, P + o[c]);
-    if (MODE == MODE_RESID) p.f = bload2<T>(rf, P + o[1]);
+    if (MODE != MODE_APPLY) p.f = bload2<T>(rf, P + o[1]);
+    if (MODE == MODE_CHEB) {
+        p.d = bload2<T>(rd, P + o[1]);
+        p.id = bload2<T>(ri, P + o[1]);
+    }
 }
 
 // the 15 values of x's and y's rows for one array: planes M (k-1), C (k), P (k+1)
@@ -414,7 +428,7 @@ static inline int march2_blocks_per_tet(int n_items2, int n_bnd)
 template <typename T, int MODE, int OP, int PF, int WPE, int WPB = 4>
 __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE))) void k_march2(
     LevelView<T> L, const T *__restrict__ u, const T *__restrict__ f, T *__restrict__ y,
-    double *__restrict__ partial)
+    double *__restrict__ partial, ChebArgs<T> cb)
 {
     constexpr int NS = PF + 3;
     const int vb = (L.n_items2 + WPB - 1) / WPB;
@@ -448,7 +462,11 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
                 constexpr int B = (int)sizeof(T);
                 const __amdgpu_buffer_rsrc_t ru = tet_rsrc(u + base, (int64_t)L.S * B);
                 const __amdgpu_buffer_rsrc_t rk = tet_rsrc(L.kap + base, (int64_t)L.S * B);
-                const __amdgpu_buffer_rsrc_t rf = tet_rsrc(MODE == MODE_RESID ? f + base : u + base,
+                const __amdgpu_buffer_rsrc_t rf = tet_rsrc(MODE != MODE_APPLY ? f + base : u + base,
+                                                           (int64_t)L.S * B);
+                const __amdgpu_buffer_rsrc_t rd = tet_rsrc(MODE == MODE_CHEB ? cb.d + base : u + base,
+                                                           (int64_t)L.S * B);
+                const __amdgpu_buffer_rsrc_t ri = tet_rsrc(MODE == MODE_CHEB ? cb.invd + base : u + base,
                                                            (int64_t)L.S * B);
                 const __amdgpu_buffer_rsrc_t ry = tet_rsrc(y + base, (int64_t)L.S * B);
                 // pair start offsets of diagonals s-1 (from y), s, s+1 (from x); a
@@ -467,7 +485,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
                 MPlane2<T> R[NS];
 #pragma unroll
                 for (int q = 0; q < NS; ++q) {
-                    mplane2_load<T, MODE>(R[q], ru, rk, rf, vo, plane(k0 - 1 + q));
+                    mplane2_load<T, MODE>(R[q], ru, rk, rf, rd, ri, vo, plane(k0 - 1 + q));
                     __builtin_amdgcn_sched_barrier(0);
                 }
                 constexpr int DROP = 0x7ffffff0;
@@ -487,13 +505,21 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
                         if (MODE == MODE_APPLY) {
                             bstore(ax, ry, sx);
                             bstore(ay, ry, sy);
-                        } else {
+                        } else if (MODE == MODE_RESID) {
                             const T rx = C.f.x - ax, rv = C.f.y - ay;
                             bstore(rx, ry, sx);
                             bstore(rv, ry, sy);
                             sq += (lx ? (double)rx * (double)rx : 0.0) + (ly ? (double)rv * (double)rv : 0.0);
+                        } else {
+                            const T rx = C.f.x - ax, rv = C.f.y - ay;
+                            const T dx = (cb.first ? T(0) : cb.c_old * C.d.x) + cb.c_r * C.id.x * rx;
+                            const T dy = (cb.first ? T(0) : cb.c_old * C.d.y) + cb.c_r * C.id.y * rv;
+                            bstore(dx, rd, sx);
+                            bstore(dy, rd, sy);
+                            bstore(C.u[1].x + dx, ry, sx);
+                            bstore(C.u[1].y + dy, ry, sy);
                         }
-                        mplane2_load<T, MODE>(M, ru, rk, rf, vo, plane(k - 1 + NS));
+                        mplane2_load<T, MODE>(M, ru, rk, rf, rd, ri, vo, plane(k - 1 + NS));
                         __builtin_amdgcn_sched_barrier(0);
                     }
                 }
@@ -732,8 +758,32 @@ static int march_blocks(const LevelView<T> &L)
 // too many registers for two rows per lane)
 
 template <typename T, int MODE, int OP>
+static void launch_march_std(const LevelView<T> &L, const T *u, const T *f, T *y, double *partial,
+                             hipStream_t st, const ChebArgs<T> &cb);
+
+template <typename T, int MODE, int OP>
 static void launch_march(const LevelView<T> &L, const T *u, const T *f, T *y, double *partial,
-                         hipStream_t st)
+                         hipStream_t st, const ChebArgs<T> &cb = ChebArgs<T>())
+{
+    if constexpr (MODE == MODE_CHEB) {
+        // the fused smoother sweep: FP64 two rows per lane (variant 6: no
+        // plane in flight, fewer registers), FP32 one row per lane
+        if constexpr (sizeof(T) == 8) {
+            const int g2 = march_grid(L.n_tet, L.vpt2, L.bpt2);
+            if (march_variant() == 6) k_march2<T, MODE_CHEB, 0, 0, 3><<<g2, BLOCK, 0, st>>>(L, u, f, y, partial, cb);
+            else k_march2<T, MODE_CHEB, 0, 1, 2><<<g2, BLOCK, 0, st>>>(L, u, f, y, partial, cb);
+        } else {
+            k_march<T, MODE_CHEB, 0, 1, 8, 1><<<march_grid(L.n_tet, L.vpt, L.bpt2), BLOCK, 0, st>>>(L, u, f, y,
+                                                                                                   partial, cb);
+        }
+    } else {
+        launch_march_std<T, MODE, OP>(L, u, f, y, partial, st, cb);
+    }
+}
+
+template <typename T, int MODE, int OP>
+static void launch_march_std(const LevelView<T> &L, const T *u, const T *f, T *y, double *partial,
+                             hipStream_t st, const ChebArgs<T> &cb)
 {
     if constexpr (OP == 0 && MODE == MODE_APPLY && sizeof(T) == 8) {
         // the LDS-staged block march where the level fits it: forced by
@@ -750,13 +800,13 @@ static void launch_march(const LevelView<T> &L, const T *u, const T *f, T *y, do
         const int v = march_variant();
         if (two_rows<T>(v)) {
             const int g2 = march_grid(L.n_tet, L.vpt2, L.bpt2);
-            if (v == 6) k_march2<T, MODE, OP, 0, 3><<<g2, BLOCK, 0, st>>>(L, u, f, y, partial);
-            else if (v == 8) k_march2<T, MODE, OP, 2, 2><<<g2, BLOCK, 0, st>>>(L, u, f, y, partial);
+            if (v == 6) k_march2<T, MODE, OP, 0, 3><<<g2, BLOCK, 0, st>>>(L, u, f, y, partial, cb);
+            else if (v == 8) k_march2<T, MODE, OP, 2, 2><<<g2, BLOCK, 0, st>>>(L, u, f, y, partial, cb);
             else if (v == 9) {
                 const int g1 = ((L.n_tet * march2_blocks_per_tet<1>(L.n_items2, L.n_bnd) + 7) / 8) * 8;
-                k_march2<T, MODE, OP, 1, 2, 1><<<g1, 64, 0, st>>>(L, u, f, y, partial);
+                k_march2<T, MODE, OP, 1, 2, 1><<<g1, 64, 0, st>>>(L, u, f, y, partial, cb);
             }
-            else k_march2<T, MODE, OP, 1, 2><<<g2, BLOCK, 0, st>>>(L, u, f, y, partial);
+            else k_march2<T, MODE, OP, 1, 2><<<g2, BLOCK, 0, st>>>(L, u, f, y, partial, cb);
             return;
         }
     }
@@ -769,12 +819,12 @@ static void launch_march(const LevelView<T> &L, const T *u, const T *f, T *y, do
     int v = march_variant();
     if (v == 0 && OP == 0 && sizeof(T) == 4) v = 1;
     switch (v) {
-    case 1: k_march<T, MODE, OP, 1, big ? 3 : (f64 ? 5 : 8), 1><<<g, BLOCK, 0, st>>>(L, u, f, y, partial); break;
-    case 2: k_march<T, MODE, OP, 2, W4, 0><<<g, BLOCK, 0, st>>>(L, u, f, y, partial); break;
-    case 3: k_march<T, MODE, OP, 2, big ? 3 : (f64 ? 4 : 6), 1><<<g, BLOCK, 0, st>>>(L, u, f, y, partial); break;
-    case 4: k_march<T, MODE, OP, 0, 8, 1><<<g, BLOCK, 0, st>>>(L, u, f, y, partial); break;
-    case 5: k_march<T, MODE, OP, 0, big ? 5 : 6, 0><<<g, BLOCK, 0, st>>>(L, u, f, y, partial); break;
-    default: k_march<T, MODE, OP, 1, W4, 0><<<g, BLOCK, 0, st>>>(L, u, f, y, partial); break;
+    case 1: k_march<T, MODE, OP, 1, big ? 3 : (f64 ? 5 : 8), 1><<<g, BLOCK, 0, st>>>(L, u, f, y, partial, cb); break;
+    case 2: k_march<T, MODE, OP, 2, W4, 0><<<g, BLOCK, 0, st>>>(L, u, f, y, partial, cb); break;
+    case 3: k_march<T, MODE, OP, 2, big ? 3 : (f64 ? 4 : 6), 1><<<g, BLOCK, 0, st>>>(L, u, f, y, partial, cb); break;
+    case 4: k_march<T, MODE, OP, 0, 8, 1><<<g, BLOCK, 0, st>>>(L, u, f, y, partial, cb); break;
+    case 5: k_march<T, MODE, OP, 0, big ? 5 : 6, 0><<<g, BLOCK, 0, st>>>(L, u, f, y, partial, cb); break;
+    default: k_march<T, MODE, OP, 1, W4, 0><<<g, BLOCK, 0, st>>>(L, u, f, y, partial, cb); break;
     }
 }
 
@@ -785,7 +835,8 @@ static void launch_march(const LevelView<T> &L, const T *u, const T *f, T *y, do
 template <typename T, int MODE>
 __global__ __launch_bounds__(BLOCK) void k_shared_rows(LevelView<T> L, const T *__restrict__ coef,
                                                         const T *__restrict__ u, const T *__restrict__ f,
-                                                        T *__restrict__ y, double *__restrict__ partial)
+                                                        T *__restrict__ y, double *__restrict__ partial,
+                                                        ChebArgs<T> cb)
 {
     const int q = blockIdx.x * BLOCK + threadIdx.x;
     const int ns = L.n_shared;
@@ -803,7 +854,16 @@ __global__ __launch_bounds__(BLOCK) void k_shared_rows(LevelView<T> L, const T *
             out = f[self] - acc;
             sq = (double)out * (double)out;
         }
-        for (int c = L.sh_off[q]; c < L.sh_off[q + 1]; ++c) y[L.sh_cslot[c]] = out;
+        if (MODE == MODE_CHEB) {
+            const T r = f[self] - acc;
+            const T dn = (cb.first ? T(0) : cb.c_old * cb.d[self]) + cb.c_r * cb.invd[self] * r;
+            for (int c = L.sh_off[q]; c < L.sh_off[q + 1]; ++c) {
+                cb.d[L.sh_cslot[c]] = dn;
+                y[L.sh_cslot[c]] = u0 + dn;
+            }
+        } else {
+            for (int c = L.sh_off[q]; c < L.sh_off[q + 1]; ++c) y[L.sh_cslot[c]] = out;
+        }
     }
     if (MODE == MODE_RESID) {
         sq = block_reduce(sq, 0);
@@ -813,10 +873,10 @@ __global__ __launch_bounds__(BLOCK) void k_shared_rows(LevelView<T> L, const T *
 
 template <typename T, int MODE>
 static void launch_shared_rows(const LevelView<T> &L, const T *coef, const T *u, const T *f, T *y,
-                               double *partial, hipStream_t st)
+                               double *partial, hipStream_t st, const ChebArgs<T> &cb = ChebArgs<T>())
 {
     const int gs = blocks_for(L.n_shared);
-    if (gs) k_shared_rows<T, MODE><<<gs, BLOCK, 0, st>>>(L, coef, u, f, y, partial);
+    if (gs) k_shared_rows<T, MODE><<<gs, BLOCK, 0, st>>>(L, coef, u, f, y, partial, cb);
 }
 
 // merged coefficients of the shared rows (FP64, once per coefficient field):
@@ -904,10 +964,12 @@ hipError_t launch_nodal(const LevelView<T> &L, const T *u, T *y, hipStream_t st)
 // ---------------------------------------------------------------- modification
 // Row q gets sum_c delta_c (u_nb - u_self) added (MODE_APPLY) or subtracted
 // from the residual (MODE_RESID, with the change of r^2 per block).
+// In the fused Chebyshev mode y is the new iterate: the row's residual
+// changes by -acc, so d and u_new both change by -c_r D^{-1} acc.
 template <typename T, int MODE>
 __global__ __launch_bounds__(BLOCK) void k_correction(CorrView<T> C, const T *__restrict__ u,
                                                       T *__restrict__ y,
-                                                      double *__restrict__ partial)
+                                                      double *__restrict__ partial, ChebArgs<T> cb)
 {
     const int q = blockIdx.x * BLOCK + threadIdx.x;
     double dsq = 0.0;
@@ -915,10 +977,20 @@ __global__ __launch_bounds__(BLOCK) void k_correction(CorrView<T> C, const T *__
         T acc = T(0);
         for (int c = C.c_off[q]; c < C.c_off[q + 1]; ++c)
             acc += C.c_delta[c] * (u[C.c_nb[c]] - u[C.c_self[c]]);
-        const T old = y[C.p_slot[C.p_off[q]]];
-        const T nw = MODE == MODE_APPLY ? old + acc : old - acc;
-        for (int p = C.p_off[q]; p < C.p_off[q + 1]; ++p) y[C.p_slot[p]] = nw;
-        dsq = (double)nw * (double)nw - (double)old * (double)old;
+        const int64_t p0 = C.p_slot[C.p_off[q]];
+        if (MODE == MODE_CHEB) {
+            const T delta = cb.c_r * cb.invd[p0] * acc;
+            const T dn = cb.d[p0] - delta, un = y[p0] - delta;
+            for (int p = C.p_off[q]; p < C.p_off[q + 1]; ++p) {
+                cb.d[C.p_slot[p]] = dn;
+                y[C.p_slot[p]] = un;
+            }
+        } else {
+            const T old = y[p0];
+            const T nw = MODE == MODE_APPLY ? old + acc : old - acc;
+            for (int p = C.p_off[q]; p < C.p_off[q + 1]; ++p) y[C.p_slot[p]] = nw;
+            dsq = (double)nw * (double)nw - (double)old * (double)old;
+        }
     }
     if (MODE == MODE_RESID) {
         dsq = block_reduce(dsq, 0);
@@ -933,9 +1005,20 @@ hipError_t launch_correction(const LevelView<T> &L, const CorrView<T> &C, int mo
     (void)L;
     if (!C.n_rows) return hipSuccess;
     if (mode == MODE_APPLY)
-        k_correction<T, MODE_APPLY><<<blocks_for(C.n_rows), BLOCK, 0, st>>>(C, u, y, partial);
+        k_correction<T, MODE_APPLY><<<blocks_for(C.n_rows), BLOCK, 0, st>>>(C, u, y, partial, ChebArgs<T>());
     else
-        k_correction<T, MODE_RESID><<<blocks_for(C.n_rows), BLOCK, 0, st>>>(C, u, y, partial);
+        k_correction<T, MODE_RESID><<<blocks_for(C.n_rows), BLOCK, 0, st>>>(C, u, y, partial, ChebArgs<T>());
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cheb_sweep(const LevelView<T> &L, const CorrView<T> &C, const T *u, const T *f, T *u_new,
+                             const ChebArgs<T> &cb, hipStream_t st)
+{
+    launch_march<T, MODE_CHEB, 0>(L, u, f, u_new, nullptr, st, cb);
+    launch_shared_rows<T, MODE_CHEB>(L, L.sh_cs, u, f, u_new, nullptr, st, cb);
+    if (C.n_rows)
+        k_correction<T, MODE_CHEB><<<blocks_for(C.n_rows), BLOCK, 0, st>>>(C, u, u_new, nullptr, cb);
     return hipGetLastError();
 }
 
@@ -1368,6 +1451,8 @@ hipError_t launch_positive_check(const double *k, int64_t n, int *bad, hipStream
     template hipError_t launch_nodal<T>(const LevelView<T> &, const T *, T *, hipStream_t);        \
     template hipError_t launch_correction<T>(const LevelView<T> &, const CorrView<T> &, int,       \
                                              const T *, T *, double *, hipStream_t);               \
+    template hipError_t launch_cheb_sweep<T>(const LevelView<T> &, const CorrView<T> &, const T *, \
+                                             const T *, T *, const ChebArgs<T> &, hipStream_t);    \
     template hipError_t launch_diag<T>(const LevelView<T> &, T *, double *, double *, double *,    \
                                        int *, hipStream_t);                                        \
     template hipError_t launch_invert_diag<T>(T *, int64_t, hipStream_t);                          \

@@ -91,23 +91,38 @@ __device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r, int vo
 // position for u and k (and f), plus the lane-shifted copies the rows use
 template <typename T>
 struct MPlane {
-    T u[3], k[3], f;
+    T u[3], k[3], f, d, id;
     T u_sm_l, u_s_l, u_s_r, u_sp_r;
     T k_sm_l, k_s_l, k_s_r, k_sp_r;
 };
 
 // plane starting at slot P: in-plane offsets o[3] (slots).  Every load of a
 // slot outside the tet's range (planes past the top included) returns 0.
+// (residual and Chebyshev modes: f at the row; Chebyshev mode also the
+// direction d and D^{-1} at the row)
 template <typename T, int MODE>
 __device__ __forceinline__ void mplane_load(MPlane<T> &p, __amdgpu_buffer_rsrc_t ru,
                                             __amdgpu_buffer_rsrc_t rk, __amdgpu_buffer_rsrc_t rf,
+                                            __amdgpu_buffer_rsrc_t rd, __amdgpu_buffer_rsrc_t ri,
                                             const int o[3], int P)
 {
 #pragma unroll
     for (int c = 0; c < 3; ++c) p.u[c] = bload<T>(ru, P + o[c]);
 #pragma unroll
     for (int c = 0; c < 3; ++c) p.k[c] = bload<T>(rk, P + o[c]);
-    if (MODE == MODE_RESID) p.f = bload<T>(rf, P + o[1]);
+    if (MODE != MODE_APPLY) p.f = bload<T>(rf, P + o[1]);
+    if (MODE == MODE_CHEB) {
+        p.d = bload<T>(rd, P + o[1]);
+        p.id = bload<T>(ri, P + o[1]);
+    }
+}
+template <typename T, int MODE>
+__device__ __forceinline__ void mplane_load(MPlane<T> &p, __amdgpu_buffer_rsrc_t ru,
+                                            __amdgpu_buffer_rsrc_t rk, __amdgpu_buffer_rsrc_t rf,
+                                            const int o[3], int P)
+{
+    static_assert(MODE != MODE_CHEB, "Chebyshev mode needs the d and D^{-1} resources");
+    mplane_load<T, MODE>(p, ru, rk, rf, rf, rf, o, P);
 }
 
 // shifted copies a plane needs as plane k+1 (and again as plane k) ...

@@ -187,6 +187,34 @@ def test_vcycle_fp64_matches_oracle(mesh_fn, level, coarse):
         assert _rel(got, u) <= 1e-11, (it, _rel(got, u))
 
 
+@pytest.mark.parametrize("mesh_fn,level,coarse,eta,pre,post", [(flat_tet, 4, 2, 100.0, 2, 2),
+                                                              (unit_tet, 5, 2, 100.0, 3, 1),
+                                                              (kuhn_cube, 4, 2, None, 1, 3)])
+def test_vcycle_smoother_sweeps_and_modification(mesh_fn, level, coarse, eta, pre, post):
+    """V-cycles whose Chebyshev sweeps run with the Sec. 4.1 modification
+    triggered (steep sigmoid k) and with odd sweep counts, against the
+    oracle's V-cycle."""
+    X, T = mesh_fn()
+    kfun = smooth_k if eta is None else (lambda x: sigmoid_k(x, eta))
+    mg = O.Multigrid(X, T, level, coarse, kfun=kfun, modification=True)
+    om = mg.meshes[level]
+    ctx = hhg.Context(X, T, level)
+    ctx.set_coefficient(kfun(om.xyz))
+    ctx.set_coarse_level(coarse)
+    if eta is not None:
+        assert sum(ctx.level_info(l)["n_modified"] for l in range(coarse + 1, level + 1)) > 0
+    f = uniform_vector(om.n_nodes, seed=12)
+    f[om.dirichlet] = 0.0
+    u = np.zeros(om.n_nodes)
+    fd = ctx.from_canonical(level, _dev(f))
+    ud = ctx.from_canonical(level, _dev(u))
+    for it in range(2):
+        u = mg.vcycle(level, f, u, pre=pre, post=post)
+        ctx.vcycle(level, fd, ud, pre, post, hhg.CHEBYSHEV)
+        got = ctx.to_canonical(level, ud).cpu().numpy()
+        assert _rel(got, u) <= 1e-11, (it, _rel(got, u))
+
+
 @pytest.mark.parametrize("mode", [hhg.SOLVE_F64, hhg.SOLVE_MIXED])
 def test_solve_reaches_tolerance_and_oracle_solution(mode):
     X, T = kuhn_cube()
