@@ -1272,37 +1272,83 @@ hipError_t launch_restrict(const LevelView<T> &Lc, const LevelView<T> &Lf, const
 
 // P1 interpolation and add: a fine node with all-even lattice coordinates is a
 // coarse node; any other fine node is the midpoint of the coarse edge whose
-// direction has the same parity pattern.
-__constant__ int PARITY_DIR[8][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {1, -1, 0},
-                                     {0, 0, 1}, {1, 0, -1}, {0, 1, -1}, {1, -1, 1}};
+// direction has the parity pattern of (i, j, k): (i odd) -> (1,0,0),
+// (j) -> (0,1,0), (i,j) -> (1,-1,0), (k) -> (0,0,1), (i,k) -> (1,0,-1),
+// (j,k) -> (0,1,-1), (i,j,k) -> (1,-1,1).
+// Column marching: a lane owns one in-plane
+// position t = (s, i) of the fine lattice and walks a chunk of planes; its
+// coarse in-plane offsets are fixed per plane parity (even planes: both
+// edge ends in coarse plane k/2; odd planes: one end in plane (k-1)/2, the
+// other in (k+1)/2), so a plane costs the fine read-modify-write and two
+// coarse reads with no per-point index arithmetic.
+constexpr int PKC = 16;  // fine planes per wave
 
 template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_prolong_add(LevelView<T> Lc, LevelView<T> Lf,
-                                                        const T *__restrict__ uc,
-                                                        T *__restrict__ uf)
+__global__ __launch_bounds__(BLOCK) void k_prolong_march(LevelView<T> Lc, LevelView<T> Lf,
+                                                          const T *__restrict__ uc, T *__restrict__ uf,
+                                                          int n_seg)
 {
-    int i, j, k, s;
-    if (!plane_point(Lf.n, i, j, k, s)) return;
-    const int tet = blockIdx.z;
-    const T *__restrict__ cb = uc + (int64_t)tet * Lc.Spad;
-    const int p = (i & 1) | ((j & 1) << 1) | ((k & 1) << 2);
-    T v;
-    if (p == 0) {
-        v = cb[slot32(Lc.n, i >> 1, j >> 1, k >> 1)];
-    } else {
-        const int di = PARITY_DIR[p][0], dj = PARITY_DIR[p][1], dk = PARITY_DIR[p][2];
-        const T a = cb[slot32(Lc.n, (i - di) >> 1, (j - dj) >> 1, (k - dk) >> 1)];
-        const T b = cb[slot32(Lc.n, (i + di) >> 1, (j + dj) >> 1, (k + dk) >> 1)];
-        v = T(0.5) * (a + b);
+    const int tet = blockIdx.y;
+    const int w = __builtin_amdgcn_readfirstlane(blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6));
+    const int ch = w / n_seg, seg = w - ch * n_seg;
+    const int n = Lf.n, nc = Lc.n;
+    const int k0 = ch * PKC;
+    const int t0 = seg * 64;
+    auto diag = [](int t) {
+        int d = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+        while ((d + 1) * (d + 2) / 2 <= t) ++d;
+        while (d > 0 && d * (d + 1) / 2 > t) --d;
+        return d;
+    };
+    // whole wave: chunk past the top or past every column of the segment
+    if (k0 > n || k0 > n - diag(t0)) return;
+    const int k1 = min(n, k0 + PKC - 1);
+    const int t = t0 + (int)(threadIdx.x & 63);
+    const int s = diag(t), i = t - s * (s + 1) / 2, j = s - i;
+    const int kmax = t < tr32(n) ? n - s : -1;  // last plane holding this column
+    const int pi = i & 1, pj = j & 1;
+    auto off = [](int a, int b) { return (a + b) * (a + b + 1) / 2 + a; };
+    // even planes: direction (pi, pj ? (pi ? -1 : 1) : 0, 0)
+    const int dje = pj ? (pi ? -1 : 1) : 0;
+    const int ea = off((i - pi) >> 1, (j - dje) >> 1), eb = off((i + pi) >> 1, (j + dje) >> 1);
+    // odd planes: k component +1 for (0,0) and (1,1) parities, -1 otherwise;
+    // lo is the end in the lower coarse plane
+    const int dko = (pi == pj) ? 1 : -1;
+    const int lo_i = dko == 1 ? (i - pi) >> 1 : (i + pi) >> 1, lo_j = dko == 1 ? (j - dje) >> 1 : (j + dje) >> 1;
+    const int hi_i = dko == 1 ? (i + pi) >> 1 : (i - pi) >> 1, hi_j = dko == 1 ? (j + dje) >> 1 : (j - dje) >> 1;
+    const int olo = off(lo_i, lo_j), ohi = off(hi_i, hi_j);
+    constexpr int B = (int)sizeof(T);
+    const __amdgpu_buffer_rsrc_t rc = tet_rsrc(uc + (int64_t)tet * Lc.Spad, (int64_t)Lc.S * B);
+    const __amdgpu_buffer_rsrc_t rf = tet_rsrc(uf + (int64_t)tet * Lf.Spad, (int64_t)Lf.S * B);
+    const int Sf = tc32(n), Sc = tc32(nc);
+    constexpr int DROP = 0x7ffffff0;
+#pragma unroll 4
+    for (int k = k0; k <= k1; ++k) {
+        const int fs = Sf - tc32(n - k) + t;
+        int ca, cb;
+        if (k & 1) {
+            ca = Sc - tc32(nc - ((k - 1) >> 1)) + olo;
+            cb = Sc - tc32(nc - ((k + 1) >> 1)) + ohi;
+        } else {
+            const int P = Sc - tc32(nc - (k >> 1));
+            ca = P + ea;
+            cb = P + eb;
+        }
+        const T a = bload<T>(rc, ca), b = bload<T>(rc, cb);
+        const T old = bload<T>(rf, fs);
+        bstore(old + T(0.5) * (a + b), rf, k <= kmax ? fs * B : DROP);
     }
-    uf[(int64_t)tet * Lf.Spad + s] += v;
 }
 
 template <typename T>
 hipError_t launch_prolong_add(const LevelView<T> &Lc, const LevelView<T> &Lf, const T *uc, T *uf,
                               hipStream_t st)
 {
-    k_prolong_add<T><<<plane_grid(Lf.n, Lf.n_tet), BLOCK, 0, st>>>(Lc, Lf, uc, uf);
+    const int n = Lf.n;
+    const int n_seg = (int)((tri_count(n) + 63) / 64);
+    const int waves = n_seg * ((n + PKC) / PKC);
+    k_prolong_march<T><<<dim3((unsigned)((waves + BLOCK / 64 - 1) / (BLOCK / 64)), (unsigned)Lf.n_tet), BLOCK, 0,
+                         st>>>(Lc, Lf, uc, uf, n_seg);
     return hipGetLastError();
 }
 
