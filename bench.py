@@ -112,9 +112,9 @@ def cpu_baseline(level=7, seconds=8.0):
 
 
 
-def kuhn48_applies(hhg, torch, steps, solves=True):
+def kuhn48_applies(hhg, torch, steps, solves=True, applies=True):
     """HBM-resident working set: 48 Kuhn tets, level 8 (133M unknowns): apply
-    throughputs and, if asked, multigrid time to solution."""
+    throughputs and/or multigrid time to solution."""
     from hhg_inputs import kuhn_cube_2x2x2, lognormal_params
     level = 8
     log("bench: 48-tet cube level 8")
@@ -133,24 +133,26 @@ def kuhn48_applies(hhg, torch, steps, solves=True):
     f64 = ctx.from_canonical(level, f)
     del f
     y = ctx.vector(level)
-    steps48 = max(10, steps // 10)
-    m1 = time_op(lambda: ctx.apply_scaled(level, f64, y), steps48, 3, torch)
-    f32 = f64.float()
-    y32 = ctx.vector(level, torch.float32)
-    m2 = time_op(lambda: ctx.apply_scaled(level, f32, y32), steps48, 3, torch)
-    m3 = time_op(lambda: ctx.apply_nodal(level, f64, y), steps48, 3, torch)
-    m4 = time_op(lambda: ctx.apply_nodal(level, f32, y32), steps48, 3, torch)
-    del y32
-    out = {
-        "unknowns": nu48,
-        "scaled_f64_gdofs": round(nu48 / m1 / 1e6, 2),
-        "scaled_f64_hbm_frac": round(BYTES_PER_DOF["f64"] * nu48 / m1 / 1e6 / HBM_PEAK_GBS, 4),
-        "scaled_f32_gdofs": round(nu48 / m2 / 1e6, 2),
-        "scaled_f32_hbm_frac": round(BYTES_PER_DOF["f32"] * nu48 / m2 / 1e6 / HBM_PEAK_GBS, 4),
-        "nodal_f64_gdofs": round(nu48 / m3 / 1e6, 2),
-        "nodal_f32_gdofs": round(nu48 / m4 / 1e6, 2),
-        "note": "48 Kuhn macro tets (2x2x2 cubes), lognormal sigma 1.5, l_c 0.05, seed 2; "
-                "3.3 GB FP64 working set, HBM-resident"}
+    out = {"unknowns": nu48,
+           "note": "48 Kuhn macro tets (2x2x2 cubes), lognormal sigma 1.5, l_c 0.05, seed 2; "
+                   "3.3 GB FP64 working set, HBM-resident"}
+    f32 = None
+    if applies:
+        steps48 = max(10, steps // 10)
+        m1 = time_op(lambda: ctx.apply_scaled(level, f64, y), steps48, 3, torch)
+        f32 = f64.float()
+        y32 = ctx.vector(level, torch.float32)
+        m2 = time_op(lambda: ctx.apply_scaled(level, f32, y32), steps48, 3, torch)
+        m3 = time_op(lambda: ctx.apply_nodal(level, f64, y), steps48, 3, torch)
+        m4 = time_op(lambda: ctx.apply_nodal(level, f32, y32), steps48, 3, torch)
+        del y32
+        out.update({
+            "scaled_f64_gdofs": round(nu48 / m1 / 1e6, 2),
+            "scaled_f64_hbm_frac": round(BYTES_PER_DOF["f64"] * nu48 / m1 / 1e6 / HBM_PEAK_GBS, 4),
+            "scaled_f32_gdofs": round(nu48 / m2 / 1e6, 2),
+            "scaled_f32_hbm_frac": round(BYTES_PER_DOF["f32"] * nu48 / m2 / 1e6 / HBM_PEAK_GBS, 4),
+            "nodal_f64_gdofs": round(nu48 / m3 / 1e6, 2),
+            "nodal_f32_gdofs": round(nu48 / m4 / 1e6, 2)})
     if solves:
         res = {}
         for name, mode, tol in (("f64", hhg.SOLVE_F64, 1e-8), ("mixed", hhg.SOLVE_MIXED, 1e-8),
@@ -218,6 +220,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--k48-apply-only", action="store_true",
                     help="only time the 48-tet level-8 applies (tuning runs)")
+    ap.add_argument("--k48-solves", action="store_true",
+                    help="only run the 48-tet level-8 V-cycle solves (profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
@@ -240,6 +244,9 @@ def main():
 
     if args.k48_apply_only:
         print(json.dumps(kuhn48_applies(hhg, torch, args.steps, solves=False)))
+        return
+    if args.k48_solves:
+        print(json.dumps(kuhn48_applies(hhg, torch, args.steps, solves=True, applies=False)))
         return
 
     # ---------------- main workload: unit tet, level 8, lognormal k
