@@ -5,10 +5,10 @@ coordinates and tetrahedra), coefficient fields evaluated at given points, and
 seeded random vectors.  Both the oracle and the GPU path consume what it
 produces; neither side's code lives here.
 """
-from .meshes import unit_tet, regular_tet, flat_tet, kuhn_cube, kuhn_cube_2x2x2, MESHES
+from .meshes import unit_tet, regular_tet, flat_tet, kuhn_cube, kuhn_cube_2x2x2, cube12, MESHES
 from .fields import (smooth_k, lognormal_params, lognormal_k, lognormal_k_torch, sigmoid_k,
                      affine_k, uniform_vector, manufactured_u, manufactured_f)
 
-__all__ = ["unit_tet", "regular_tet", "flat_tet", "kuhn_cube", "kuhn_cube_2x2x2", "MESHES",
+__all__ = ["unit_tet", "regular_tet", "flat_tet", "kuhn_cube", "kuhn_cube_2x2x2", "cube12", "MESHES",
            "smooth_k", "lognormal_params", "lognormal_k", "lognormal_k_torch", "sigmoid_k", "affine_k",
            "uniform_vector", "manufactured_u", "manufactured_f"]

@@ -60,10 +60,42 @@ def kuhn_cube_2x2x2():
     return X, np.array(T, dtype=np.int32)
 
 
+def cube12():
+    """Unit cube split into 12 tetrahedra around one interior macro vertex at
+    (0.5, 0.5, 0.5): every cube face is cut along a diagonal into two
+    triangles (through (0,0,0) on the faces holding it, through (1,1,1) on
+    the others) and each triangle is joined to the centre.  Tetrahedra are
+    positively oriented."""
+    X = np.array([[a, b, c] for c in (0, 1) for b in (0, 1) for a in (0, 1)] + [[0.5, 0.5, 0.5]],
+                 dtype=np.float64)
+    vid = lambda a, b, c: a + 2 * b + 4 * c
+    T = []
+    for ax in range(3):
+        for side in (0, 1):
+            # the face's corners in cyclic order, starting at the diagonal's end
+            o, p, q = ax, (ax + 1) % 3, (ax + 2) % 3
+            def corner(u, v):
+                c = [0, 0, 0]
+                c[o], c[p], c[q] = side, u, v
+                return vid(*c)
+            if side == 0:
+                ring = [corner(0, 0), corner(1, 0), corner(1, 1), corner(0, 1)]
+            else:
+                ring = [corner(1, 1), corner(0, 1), corner(0, 0), corner(1, 0)]
+            for tri in ((ring[0], ring[1], ring[2]), (ring[0], ring[2], ring[3])):
+                t = [tri[0], tri[1], tri[2], 8]
+                e = X[t[1:]] - X[t[0]]
+                if np.linalg.det(e) < 0:
+                    t[1], t[2] = t[2], t[1]
+                T.append(t)
+    return X, np.array(T, dtype=np.int32)
+
+
 MESHES = {
     "unit_tet": unit_tet,
     "regular_tet": regular_tet,
     "flat_tet": flat_tet,
     "kuhn_cube": kuhn_cube,
     "kuhn_cube_2x2x2": kuhn_cube_2x2x2,
+    "cube12": cube12,
 }

@@ -18,6 +18,8 @@ Paper passages followed (arXiv 1709.06793):
 * nodal form        eq. (standardfe): mean vertex k times A_t            (Sec. 3.2)
 * modification      Sec. 4.1 (MA2 and k_mod), read for 3D as listed in
                     modification_factors()
+* primitive mix     Sec. 5 eq. (modst): nodal-integration rows on the nodes
+                    of the chosen macro primitives, scaled rows elsewhere
 * rates             Lemma 3.1 (O(h^2) in L2, O(h) in H1)
 """
 import ctypes
@@ -412,6 +414,40 @@ class Operator:
 
 def make_operator(mesh, k, kind="scaled", modification=False):
     return Operator(mesh, assemble(mesh, k, kind, modification))
+
+
+def primitive_dims(mesh):
+    """Dimension of the macro primitive that holds each node (Sec. 5: the
+    node sets W_V, W_E, W_F of the vertex, edge and face primitives; 3 = the
+    interior of a macro tet): the number of nonzero barycentric weights of the
+    node in a macro tet containing it, minus one."""
+    conn, macro = mesh.elements()
+    owner = np.full(mesh.n_nodes, -1, dtype=np.int64)
+    owner[conn.ravel()] = np.repeat(macro, 4)
+    dims = np.empty(mesh.n_nodes, dtype=np.int64)
+    for t in range(mesh.T.shape[0]):
+        idx = np.flatnonzero(owner == t)
+        if len(idx) == 0:
+            continue
+        B = np.vstack([mesh.X[mesh.T[t]].T, np.ones(4)])
+        lam = np.linalg.solve(B, np.vstack([mesh.xyz[idx].T, np.ones(len(idx))]))
+        dims[idx] = (np.abs(lam) > 1e-9).sum(axis=0) - 1
+    return dims
+
+
+def assemble_mixed(mesh, k, nodal_dims, modification=False):
+    """Sec. 5 eq. (modst): the row of node i is its nodal-integration row
+    (eq. standardfe) when i lies on a macro primitive whose dimension is in
+    `nodal_dims` (0 vertices, 1 edges, 2 faces), its stencil-scaling row
+    (eq. discrete, with the Sec. 4.1 modification if asked) otherwise."""
+    S = assemble(mesh, k, "scaled", modification)
+    N = assemble(mesh, k, "nodal")
+    sel = np.isin(primitive_dims(mesh), list(nodal_dims)).astype(np.float64)
+    return (sp.diags(sel) @ N + sp.diags(1.0 - sel) @ S).tocsr()
+
+
+def make_mixed_operator(mesh, k, nodal_dims, modification=False):
+    return Operator(mesh, assemble_mixed(mesh, k, nodal_dims, modification))
 
 
 def jacobi(op, f, u, sweeps, omega=2.0 / 3.0, history=False):

@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 import scipy.sparse.linalg as spla
 
-from hhg_inputs import (unit_tet, regular_tet, flat_tet, kuhn_cube, kuhn_cube_2x2x2, smooth_k,
+from hhg_inputs import (unit_tet, regular_tet, flat_tet, kuhn_cube, kuhn_cube_2x2x2, cube12, smooth_k,
                         affine_k, sigmoid_k, manufactured_u, manufactured_f,
                         lognormal_params, lognormal_k)
 from oracle import oracle as O
@@ -305,3 +305,54 @@ def test_canonical_order_convention():
     X, T = kuhn_cube_2x2x2()
     m = O.Mesh(X, T, 1)
     assert len(m.unknowns) == 27 and m.n_nodes == 125
+
+
+def test_primitive_dims_match_closed_form_counts():
+    """Sec. 5 node sets of the 12-tet cube (9 vertices, 26 edges, 30 faces):
+    per level n = 2^l, (n-1) nodes per edge, (n-1)(n-2)/2 per face,
+    (n-1)(n-2)(n-3)/6 per tet interior."""
+    X, T = cube12()
+    for level in (2, 3):
+        n = 2 ** level
+        m = O.Mesh(X, T, level)
+        counts = np.bincount(O.primitive_dims(m), minlength=4).tolist()
+        assert counts == [9, 26 * (n - 1), 30 * (n - 1) * (n - 2) // 2, 12 * (n - 1) * (n - 2) * (n - 3) // 6]
+        # the interior of the cube: 1 vertex, 8 edges, 18 faces, 12 tets
+        d = O.primitive_dims(m)[m.unknowns]
+        assert np.bincount(d, minlength=4).tolist() == [1, 8 * (n - 1), 18 * (n - 1) * (n - 2) // 2,
+                                                        12 * (n - 1) * (n - 2) * (n - 3) // 6]
+
+
+@pytest.mark.parametrize("level", [2, 3])
+def test_primitive_mix_reproduces_affine_solutions(level):
+    """Lemma 5.1 on the 12-tet unit cube with u = -7x+y+3z, k = 2x+3y+5z+1
+    (the paper's example; f = -div(k grad u) = -4): the nodal-integration
+    operator and a_{h;I} with I = W or W_V u W_E reproduce u to rounding, both
+    as a solve with the exact Dirichlet data and in the operator form
+    a_{h;I}(u, phi_i) = a~_h(u, phi_i) on the interior rows; stencil scaling
+    alone and the mixes without edges (or without vertices) do not."""
+    X, T = cube12()
+    m = O.Mesh(X, T, level)
+    x = m.xyz
+    k = affine_k(x)
+    u = -7.0 * x[:, 0] + x[:, 1] + 3.0 * x[:, 2]
+    b = O.assemble_mass(m) @ np.full(m.n_nodes, -4.0)
+    I, D = m.unknowns, np.flatnonzero(m.dirichlet)
+    N = O.assemble(m, k, "nodal")
+    scale = np.abs((N @ u)[I]).max()
+
+    def err(A):
+        A = A.tocsr()
+        uh = u.copy()
+        uh[I] = spla.spsolve(A[I][:, I].tocsc(), b[I] - A[I][:, D] @ u[D])
+        return np.sqrt(m.h ** 3 * np.sum((uh - u) ** 2))
+
+    assert err(N) < 1e-13
+    for dims in ((0, 1, 2), (0, 1)):
+        A = O.assemble_mixed(m, k, dims)
+        assert err(A) < 1e-13, dims
+        assert np.abs(((A - N) @ u)[I]).max() <= 1e-10 * scale, dims
+    for dims in ((), (0,), (0, 2), (1,), (1, 2)):
+        A = O.assemble_mixed(m, k, dims) if dims else O.assemble(m, k, "scaled")
+        assert err(A) > 1e-5, dims
+        assert np.abs(((A - N) @ u)[I]).max() > 1e-2 * scale, dims
