@@ -145,6 +145,9 @@ def kuhn48_applies(hhg, torch, steps, solves=True, applies=True):
         m2 = time_op(lambda: ctx.apply_scaled(level, f32, y32), steps48, 3, torch)
         m3 = time_op(lambda: ctx.apply_nodal(level, f64, y), steps48, 3, torch)
         m4 = time_op(lambda: ctx.apply_nodal(level, f32, y32), steps48, 3, torch)
+        # primitive-mixed operator, nodal rows on macro vertices and edges
+        m5 = time_op(lambda: ctx.apply_mixed(level, f64, y, hhg.PRIM_VERTICES | hhg.PRIM_EDGES), steps48, 3, torch)
+        m6 = time_op(lambda: ctx.apply_mixed(level, f32, y32, hhg.PRIM_VERTICES | hhg.PRIM_EDGES), steps48, 3, torch)
         del y32
         out.update({
             "scaled_f64_gdofs": round(nu48 / m1 / 1e6, 2),
@@ -152,7 +155,9 @@ def kuhn48_applies(hhg, torch, steps, solves=True, applies=True):
             "scaled_f32_gdofs": round(nu48 / m2 / 1e6, 2),
             "scaled_f32_hbm_frac": round(BYTES_PER_DOF["f32"] * nu48 / m2 / 1e6 / HBM_PEAK_GBS, 4),
             "nodal_f64_gdofs": round(nu48 / m3 / 1e6, 2),
-            "nodal_f32_gdofs": round(nu48 / m4 / 1e6, 2)})
+            "nodal_f32_gdofs": round(nu48 / m4 / 1e6, 2),
+            "mixed_vertices_edges_f64_gdofs": round(nu48 / m5 / 1e6, 2),
+            "mixed_vertices_edges_f32_gdofs": round(nu48 / m6 / 1e6, 2)})
     if solves:
         res = {}
         for name, mode, tol in (("f64", hhg.SOLVE_F64, 1e-8), ("mixed", hhg.SOLVE_MIXED, 1e-8),

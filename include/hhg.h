@@ -163,6 +163,17 @@ hhg_status hhg_read_timing(hhg_ctx ctx, double *ms_total, int64_t *launches);
 /* y = A~ u with the nodal-integration operator (eq. (standardfe), Sec. 6.2). */
 hhg_status hhg_apply_nodal(hhg_ctx ctx, int32_t level, hhg_dtype dtype,
                            const void *u, void *y, void *stream);
+/* y = A_I u with the primitive-mixed operator a_{h;I} (Sec. 5 eq. (modst)):
+ * the row of a node on a macro primitive of a kind selected in
+ * nodal_primitives (bit 0 vertices, bit 1 edges, bit 2 faces: I = W_V u W_E
+ * is 3, I = W is 7) is its nodal-integration row (eq. (standardfe)); every
+ * other row (tet interiors and unselected primitives) is the stencil-scaling
+ * row, with the Sec. 4.1 modification where it is triggered (unless the
+ * context was created with HHG_FLAG_NO_MODIFICATION).  0 gives
+ * hhg_apply_scaled's result.  Same vector layout and rules as
+ * hhg_apply_scaled; HHG_EINVAL for nodal_primitives outside 0..7. */
+hhg_status hhg_apply_mixed(hhg_ctx ctx, int32_t level, hhg_dtype dtype, int32_t nodal_primitives,
+                           const void *u, void *y, void *stream);
 /* r = f - A u (scaled operator).  If norm2_out is not NULL it receives the
  * Euclidean norm of r over the unknowns (each unique node once, accumulated
  * in double) and the stream is synchronised.  r may alias neither f nor u. */

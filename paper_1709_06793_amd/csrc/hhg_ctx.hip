@@ -244,6 +244,8 @@ struct Level {
     int sh_w = 0;
     int64_t *sh_nb = nullptr, *sh_self = nullptr, *sh_cslot = nullptr;
     int8_t *sh_map = nullptr;  // [copy][16]: entry of direction d, -1 if none
+    std::vector<uint8_t> h_sh_prim;  // macro primitive of each shared node (1 vertex, 2 edge, 4 face)
+    uint8_t *sh_prim = nullptr;
     double *sh_cs64 = nullptr, *sh_cn64 = nullptr;
     float *sh_cs32 = nullptr, *sh_cn32 = nullptr;
     // coefficient dependent
@@ -261,6 +263,7 @@ struct Level {
     double *c_d64 = nullptr, *c_base = nullptr;
     float *c_d32 = nullptr;
     uint8_t *c_nbdir = nullptr;
+    uint8_t *c_prim = nullptr;
     // learned correction: log k (FP32), ownership mask and FP32 scratch
     float *logk32 = nullptr;
     uint8_t *own = nullptr;
@@ -471,7 +474,7 @@ LevelView<double> view<double>(const hhg_ctx c, int l)
     v.n_shared = L.n_shared; v.sh_off = L.sh_off; v.sh_copy = L.sh_copy;
     v.items = L.items; v.n_items = L.n_items; v.vpt = (L.n_items + 3) / 4;
     v.sh_w = L.sh_w; v.sh_nb = L.sh_nb; v.sh_self = L.sh_self; v.sh_cslot = L.sh_cslot;
-    v.sh_cs = L.sh_cs64; v.sh_cn = L.sh_cn64;
+    v.sh_cs = L.sh_cs64; v.sh_cn = L.sh_cn64; v.sh_prim = L.sh_prim;
     v.items2 = L.items2; v.n_items2 = L.n_items2; v.vpt2 = (L.n_items2 + 3) / 4;
     v.itemsL = L.itemsL; v.n_itemsL = L.n_itemsL;
     v.bnd = L.bnd; v.n_bnd = L.n_bnd; v.bpt2 = (L.n_bnd + BLOCK - 1) / BLOCK;
@@ -488,7 +491,7 @@ LevelView<float> view<float>(const hhg_ctx c, int l)
     v.n_shared = L.n_shared; v.sh_off = L.sh_off; v.sh_copy = L.sh_copy;
     v.items = L.items; v.n_items = L.n_items; v.vpt = (L.n_items + 3) / 4;
     v.sh_w = L.sh_w; v.sh_nb = L.sh_nb; v.sh_self = L.sh_self; v.sh_cslot = L.sh_cslot;
-    v.sh_cs = L.sh_cs32; v.sh_cn = L.sh_cn32;
+    v.sh_cs = L.sh_cs32; v.sh_cn = L.sh_cn32; v.sh_prim = L.sh_prim;
     v.items2 = L.items2f; v.n_items2 = L.n_items2f; v.vpt2 = (L.n_items2f + 3) / 4;
     v.itemsL = L.itemsL; v.n_itemsL = 0;
     v.bnd = L.bnd; v.n_bnd = L.n_bnd; v.bpt2 = (L.n_bnd + BLOCK - 1) / BLOCK;
@@ -502,14 +505,14 @@ CorrView<double> corr<double>(const hhg_ctx c, int l)
 {
     const Level &L = c->lv[l];
     return CorrView<double>{L.n_corr_rows, L.c_off, L.c_self, L.c_nb, L.c_d64, L.c_base, L.c_nbdir,
-                            L.p_off, L.p_slot};
+                            L.p_off, L.p_slot, L.c_prim};
 }
 template <>
 CorrView<float> corr<float>(const hhg_ctx c, int l)
 {
     const Level &L = c->lv[l];
     return CorrView<float>{L.n_corr_rows, L.c_off, L.c_self, L.c_nb, L.c_d32, L.c_base, L.c_nbdir,
-                           L.p_off, L.p_slot};
+                           L.p_off, L.p_slot, L.c_prim};
 }
 
 template <typename T> T *&work_r(Level &L);
@@ -773,6 +776,20 @@ hhg_status build_level(hhg_ctx c, int l)
             enb.insert(enb.end(), slots.begin(), slots.end());
         }
         L.sh_w = width;
+        // macro primitive of each shared node from the zero pattern of its
+        // barycentric weights: three zero weights = vertex, two = edge, one = face
+        L.h_sh_prim.assign((size_t)L.n_shared, 0);
+        for (int q = 0; q < L.n_shared; ++q) {
+            int t, kind, i, j, k;
+            unpack_copy(L.h_sh_copy[L.h_sh_off[q]], t, kind, i, j, k);
+            const int zeros = __builtin_popcount((unsigned)kind);
+            L.h_sh_prim[q] = (uint8_t)(zeros == 3 ? 1 : zeros == 2 ? 2 : 4);
+        }
+        {
+            std::vector<uint8_t> cp = L.h_sh_prim;
+            if (cp.empty()) cp.assign(1, 0);
+            TRY(upload(c, &L.sh_prim, cp));
+        }
         std::vector<int64_t> ell((size_t)width * L.n_shared);
         int64_t pos = 0;
         for (int q = 0; q < L.n_shared; ++q) {
@@ -1172,8 +1189,9 @@ hhg_status build_modification(hhg_ctx c, int l)
     std::vector<int64_t> cself, cnb, pslot;
     std::vector<double> cd, cbase;
     std::vector<float> cd32;
-    std::vector<uint8_t> cnbd;
+    std::vector<uint8_t> cnbd, cprim;
     for (auto &kv : rows) {
+        cprim.push_back(kv.first >= 0 ? (uint8_t)0 : L.h_sh_prim[(size_t)(-kv.first - 1)]);
         for (const Corr &q : kv.second) {
             cself.push_back(q.self); cnb.push_back(q.nb); cd.push_back(q.delta);
             cd32.push_back((float)q.delta); cbase.push_back(q.base); cnbd.push_back(q.nbdir);
@@ -1197,6 +1215,7 @@ hhg_status build_modification(hhg_ctx c, int l)
     TRY(upload(c, &L.c_self, cself));
     TRY(upload(c, &L.c_nb, cnb));
     TRY(upload(c, &L.p_slot, pslot));
+    TRY(upload(c, &L.c_prim, cprim));
     TRY(upload(c, &L.c_d64, cd));
     TRY(upload(c, &L.c_d32, cd32));
     TRY(upload(c, &L.c_base, cbase));
@@ -1731,6 +1750,24 @@ hhg_status hhg_apply_nodal(hhg_ctx c, int32_t level, hhg_dtype dt, const void *u
     hipStream_t st = pick(c, stream);
     if (dt == HHG_F64) HIPCHK(c, launch_nodal<double>(view<double>(c, level), (const double *)u, (double *)y, st));
     else if (dt == HHG_F32) HIPCHK(c, launch_nodal<float>(view<float>(c, level), (const float *)u, (float *)y, st));
+    else return fail(c, HHG_EINVAL, "bad dtype");
+    return HHG_OK;
+}
+
+hhg_status hhg_apply_mixed(hhg_ctx c, int32_t level, hhg_dtype dt, int32_t nodal_primitives, const void *u,
+                           void *y, void *stream)
+{
+    TRY(check_level(c, level));
+    NEED_K(c);
+    if (!u || !y || u == y) return fail(c, HHG_EINVAL, "u and y must be distinct non-NULL vectors");
+    if (nodal_primitives < 0 || nodal_primitives > 7) return fail(c, HHG_EINVAL, "nodal_primitives must be in 0..7");
+    hipStream_t st = pick(c, stream);
+    if (dt == HHG_F64)
+        HIPCHK(c, launch_mixed<double>(view<double>(c, level), corr<double>(c, level), (const double *)u, (double *)y,
+                                       nodal_primitives, st));
+    else if (dt == HHG_F32)
+        HIPCHK(c, launch_mixed<float>(view<float>(c, level), corr<float>(c, level), (const float *)u, (float *)y,
+                                      nodal_primitives, st));
     else return fail(c, HHG_EINVAL, "bad dtype");
     return HHG_OK;
 }

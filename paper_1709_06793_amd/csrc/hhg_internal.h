@@ -55,6 +55,7 @@ struct LevelView {
     const int64_t *sh_cslot;  // global slot of every copy (sh_off order)
     const T *sh_cs;           // scaled-operator coefficients
     const T *sh_cn;           // nodal-operator coefficients
+    const uint8_t *sh_prim;   // macro primitive of node q: 1 vertex, 2 edge, 4 face
 };
 
 // sparse corrections of the modification (Sec. 4.1) at one level
@@ -69,6 +70,7 @@ struct CorrView {
     const uint8_t *c_nbdir;   // 1 if the other end is a Dirichlet node
     const int32_t *p_off;     // copies of row q: [p_off[q], p_off[q+1])
     const int64_t *p_slot;
+    const uint8_t *c_prim;    // macro primitive of the row's node (1/2/4 as sh_prim; 0 tet interior)
 };
 
 // kernel launchers (hhg_kernels.hip); every launcher returns hipGetLastError()
@@ -89,6 +91,12 @@ hipError_t launch_scaled(const LevelView<T> &L, int mode, const T *u, const T *f
                          double *partial, int *n_partial, hipStream_t st);
 template <typename T>
 hipError_t launch_nodal(const LevelView<T> &L, const T *u, T *y, hipStream_t st);
+// the primitive-mixed operator (Sec. 5 eq. (modst)): nodal-integration rows
+// for the nodes of the primitives in nodal_mask (1 vertices, 2 edges, 4
+// faces), scaled rows (with their modification corrections) elsewhere
+template <typename T>
+hipError_t launch_mixed(const LevelView<T> &L, const CorrView<T> &C, const T *u, T *y, int nodal_mask,
+                        hipStream_t st);
 // fused Chebyshev sweep (interior march, shared rows, modification rows):
 // reads u, f, d, D^{-1}; writes d and u_new (every slot of u_new: rows,
 // copies, Dirichlet zeros).  u_new must not alias u.

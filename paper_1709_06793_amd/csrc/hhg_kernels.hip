@@ -836,7 +836,7 @@ template <typename T, int MODE>
 __global__ __launch_bounds__(BLOCK) void k_shared_rows(LevelView<T> L, const T *__restrict__ coef,
                                                         const T *__restrict__ u, const T *__restrict__ f,
                                                         T *__restrict__ y, double *__restrict__ partial,
-                                                        ChebArgs<T> cb)
+                                                        ChebArgs<T> cb, const T *__restrict__ coefn, int nodal_mask)
 {
     const int q = blockIdx.x * BLOCK + threadIdx.x;
     const int ns = L.n_shared;
@@ -844,10 +844,12 @@ __global__ __launch_bounds__(BLOCK) void k_shared_rows(LevelView<T> L, const T *
     if (q < ns) {
         const int64_t self = L.sh_self[q];
         const T u0 = u[self];
+        // primitive-mixed operator: the nodal coefficients on the chosen primitives
+        const T *__restrict__ cp = nodal_mask && (L.sh_prim[q] & nodal_mask) ? coefn : coef;
         T acc = T(0);
         for (int m = 0; m < L.sh_w; ++m) {
             const int64_t e = (int64_t)m * ns + q;
-            acc += coef[e] * (u[L.sh_nb[e]] - u0);
+            acc += cp[e] * (u[L.sh_nb[e]] - u0);
         }
         T out = acc;
         if (MODE == MODE_RESID) {
@@ -873,10 +875,11 @@ __global__ __launch_bounds__(BLOCK) void k_shared_rows(LevelView<T> L, const T *
 
 template <typename T, int MODE>
 static void launch_shared_rows(const LevelView<T> &L, const T *coef, const T *u, const T *f, T *y,
-                               double *partial, hipStream_t st, const ChebArgs<T> &cb = ChebArgs<T>())
+                               double *partial, hipStream_t st, const ChebArgs<T> &cb = ChebArgs<T>(),
+                               const T *coefn = nullptr, int nodal_mask = 0)
 {
     const int gs = blocks_for(L.n_shared);
-    if (gs) k_shared_rows<T, MODE><<<gs, BLOCK, 0, st>>>(L, coef, u, f, y, partial, cb);
+    if (gs) k_shared_rows<T, MODE><<<gs, BLOCK, 0, st>>>(L, coef, u, f, y, partial, cb, coefn, nodal_mask);
 }
 
 // merged coefficients of the shared rows (FP64, once per coefficient field):
@@ -969,11 +972,13 @@ hipError_t launch_nodal(const LevelView<T> &L, const T *u, T *y, hipStream_t st)
 template <typename T, int MODE>
 __global__ __launch_bounds__(BLOCK) void k_correction(CorrView<T> C, const T *__restrict__ u,
                                                       T *__restrict__ y,
-                                                      double *__restrict__ partial, ChebArgs<T> cb)
+                                                      double *__restrict__ partial, ChebArgs<T> cb, int nodal_mask)
 {
     const int q = blockIdx.x * BLOCK + threadIdx.x;
     double dsq = 0.0;
-    if (q < C.n_rows) {
+    // rows of the primitive-mixed operator's nodal primitives are not scaled
+    // rows and get no correction
+    if (q < C.n_rows && !(nodal_mask && (C.c_prim[q] & nodal_mask))) {
         T acc = T(0);
         for (int c = C.c_off[q]; c < C.c_off[q + 1]; ++c)
             acc += C.c_delta[c] * (u[C.c_nb[c]] - u[C.c_self[c]]);
@@ -1005,9 +1010,21 @@ hipError_t launch_correction(const LevelView<T> &L, const CorrView<T> &C, int mo
     (void)L;
     if (!C.n_rows) return hipSuccess;
     if (mode == MODE_APPLY)
-        k_correction<T, MODE_APPLY><<<blocks_for(C.n_rows), BLOCK, 0, st>>>(C, u, y, partial, ChebArgs<T>());
+        k_correction<T, MODE_APPLY><<<blocks_for(C.n_rows), BLOCK, 0, st>>>(C, u, y, partial, ChebArgs<T>(), 0);
     else
-        k_correction<T, MODE_RESID><<<blocks_for(C.n_rows), BLOCK, 0, st>>>(C, u, y, partial, ChebArgs<T>());
+        k_correction<T, MODE_RESID><<<blocks_for(C.n_rows), BLOCK, 0, st>>>(C, u, y, partial, ChebArgs<T>(), 0);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_mixed(const LevelView<T> &L, const CorrView<T> &C, const T *u, T *y, int nodal_mask,
+                        hipStream_t st)
+{
+    launch_march<T, MODE_APPLY, 0>(L, u, nullptr, y, nullptr, st);
+    launch_shared_rows<T, MODE_APPLY>(L, L.sh_cs, u, nullptr, y, nullptr, st, ChebArgs<T>(), L.sh_cn, nodal_mask);
+    if (C.n_rows)
+        k_correction<T, MODE_APPLY><<<blocks_for(C.n_rows), BLOCK, 0, st>>>(C, u, y, nullptr, ChebArgs<T>(),
+                                                                           nodal_mask);
     return hipGetLastError();
 }
 
@@ -1018,7 +1035,7 @@ hipError_t launch_cheb_sweep(const LevelView<T> &L, const CorrView<T> &C, const 
     launch_march<T, MODE_CHEB, 0>(L, u, f, u_new, nullptr, st, cb);
     launch_shared_rows<T, MODE_CHEB>(L, L.sh_cs, u, f, u_new, nullptr, st, cb);
     if (C.n_rows)
-        k_correction<T, MODE_CHEB><<<blocks_for(C.n_rows), BLOCK, 0, st>>>(C, u, u_new, nullptr, cb);
+        k_correction<T, MODE_CHEB><<<blocks_for(C.n_rows), BLOCK, 0, st>>>(C, u, u_new, nullptr, cb, 0);
     return hipGetLastError();
 }
 
@@ -1497,6 +1514,8 @@ hipError_t launch_positive_check(const double *k, int64_t n, int *bad, hipStream
     template hipError_t launch_nodal<T>(const LevelView<T> &, const T *, T *, hipStream_t);        \
     template hipError_t launch_correction<T>(const LevelView<T> &, const CorrView<T> &, int,       \
                                              const T *, T *, double *, hipStream_t);               \
+    template hipError_t launch_mixed<T>(const LevelView<T> &, const CorrView<T> &, const T *, T *, int, \
+                                        hipStream_t);                                              \
     template hipError_t launch_cheb_sweep<T>(const LevelView<T> &, const CorrView<T> &, const T *, \
                                              const T *, T *, const ChebArgs<T> &, hipStream_t);    \
     template hipError_t launch_diag<T>(const LevelView<T> &, T *, double *, double *, double *,    \

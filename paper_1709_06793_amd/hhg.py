@@ -16,6 +16,8 @@ F64, F32 = 0, 1
 JACOBI, CHEBYSHEV, LEARNED = 0, 1, 2
 SOLVE_F64, SOLVE_MIXED, SOLVE_LEARNED = 0, 1, 2
 FLAG_NO_MODIFICATION = 1
+# macro primitives whose rows use nodal integration in apply_mixed (Sec. 5)
+PRIM_VERTICES, PRIM_EDGES, PRIM_FACES = 1, 2, 4
 LEARNED_NPARAM = 817
 WFALLBACK = 1
 
@@ -23,7 +25,7 @@ WFALLBACK = 1
 EXPORTS = [
     "hhg_create_macro", "hhg_destroy", "hhg_last_error", "hhg_vector_size", "hhg_node_coords",
     "hhg_to_canonical", "hhg_from_canonical", "hhg_set_coefficient", "hhg_set_coarse_level",
-    "hhg_level_info", "hhg_apply_scaled", "hhg_set_timing", "hhg_read_timing", "hhg_set_kernel_variant", "hhg_apply_nodal", "hhg_residual", "hhg_smooth",
+    "hhg_level_info", "hhg_apply_scaled", "hhg_set_timing", "hhg_read_timing", "hhg_set_kernel_variant", "hhg_apply_nodal", "hhg_apply_mixed", "hhg_residual", "hhg_smooth",
     "hhg_vcycle", "hhg_solve", "hhg_learned_set_weights", "hhg_learned_set_fallback",
     "hhg_learned_forward", "hhg_learned_backward", "hhg_learned_loss_grad", "hhg_training_pair",
     "hhg_adam_update",
@@ -69,6 +71,7 @@ def load():
         "hhg_set_kernel_variant": [I32],
         "hhg_read_timing": [P, P, P],
         "hhg_apply_nodal": [P, I32, I32, P, P, P],
+        "hhg_apply_mixed": [P, I32, I32, I32, P, P, P],
         "hhg_residual": [P, I32, I32, P, P, P, P, P],
         "hhg_smooth": [P, I32, I32, I32, I32, D, P, P, P],
         "hhg_vcycle": [P, I32, I32, I32, I32, I32, P, P, P, P],
@@ -205,6 +208,11 @@ class Context:
         ms, n = ctypes.c_double(), ctypes.c_int64()
         self._check(load().hhg_read_timing(self._h, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+    def apply_mixed(self, level, u, y, nodal_primitives=PRIM_VERTICES | PRIM_EDGES):
+        self._check(load().hhg_apply_mixed(self._h, level, _dtype_code(u), int(nodal_primitives), _ptr(u), _ptr(y),
+                                           _stream()))
+        return y
 
     def apply_nodal(self, level, u, y):
         self._check(load().hhg_apply_nodal(self._h, level, _dtype_code(u), _ptr(u), _ptr(y), _stream()))

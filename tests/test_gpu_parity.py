@@ -7,7 +7,7 @@ bounded by the FP32 rounding of inputs and of 15-term sums.
 import numpy as np
 import pytest
 
-from hhg_inputs import (unit_tet, regular_tet, flat_tet, kuhn_cube, kuhn_cube_2x2x2, smooth_k,
+from hhg_inputs import (unit_tet, regular_tet, flat_tet, kuhn_cube, kuhn_cube_2x2x2, cube12, smooth_k,
                         sigmoid_k, lognormal_params, lognormal_k, uniform_vector, affine_k)
 from oracle import oracle as O
 
@@ -86,6 +86,52 @@ def test_apply_fp64_kernel_variants(mesh_fn, level, variant):
     d = (y1 - y0).abs().max().item() / y0.abs().max().item()
     print(f"variant {variant} vs default: max rel difference {d:.3e}", flush=True)
     assert d <= TOL64
+
+
+MIX = [(3, (0, 1)), (7, (0, 1, 2)), (4, (2,)), (1, (0,)), (0, ())]
+
+
+@pytest.mark.parametrize("mesh_fn,level", [(cube12, 3), (cube12, 4), (kuhn_cube_2x2x2, 3), (unit_tet, 4)])
+@pytest.mark.parametrize("mask,dims", MIX)
+def test_apply_mixed_fp64_matches_oracle(mesh_fn, level, mask, dims):
+    """Sec. 5 eq. (modst): nodal-integration rows on the selected macro
+    primitives, scaled rows (modification on) elsewhere."""
+    om, k, u, ctx = _setup(mesh_fn, level, kfun=lambda x: lognormal_k(x, lognormal_params(4, 1.0, 0.2)))
+    y = ctx.vector(level)
+    ctx.apply_mixed(level, ctx.from_canonical(level, _dev(u)), y, mask)
+    got = ctx.to_canonical(level, y).cpu().numpy()
+    ref = O.make_mixed_operator(om, k, dims, modification=True).apply(u)
+    assert _rel(got, ref) <= TOL64 and _elem(got, ref) <= TOL64, (_rel(got, ref), _elem(got, ref))
+    assert np.all(got[om.dirichlet] == 0.0)
+
+
+@pytest.mark.parametrize("mask,dims", [(3, (0, 1)), (7, (0, 1, 2)), (0, ())])
+def test_apply_mixed_with_modification_triggered(mask, dims):
+    """Steep sigmoid k on the 12-tet cube: modified edges touch vertex, edge,
+    face and interior rows; rows switched to nodal integration carry no
+    modification."""
+    om, k, u, ctx = _setup(cube12, 3, kfun=lambda x: sigmoid_k(x, 100.0))
+    assert ctx.level_info(3)["n_modified"] > 0
+    y = ctx.vector(3)
+    ctx.apply_mixed(3, ctx.from_canonical(3, _dev(u)), y, mask)
+    got = ctx.to_canonical(3, y).cpu().numpy()
+    ref = O.make_mixed_operator(om, k, dims, modification=True).apply(u)
+    assert _rel(got, ref) <= TOL64 and _elem(got, ref) <= TOL64, (_rel(got, ref), _elem(got, ref))
+    if mask == 0:
+        ys = ctx.vector(3)
+        ctx.apply_scaled(3, ctx.from_canonical(3, _dev(u)), ys)
+        assert torch.equal(ys, y)
+
+
+def test_apply_mixed_fp32_and_bad_mask():
+    om, k, u, ctx = _setup(cube12, 4, kfun=lambda x: lognormal_k(x, lognormal_params(4, 1.0, 0.2)))
+    y = ctx.vector(4, torch.float32)
+    ctx.apply_mixed(4, ctx.from_canonical(4, _dev(u, torch.float32)), y, 3)
+    got = ctx.to_canonical(4, y).cpu().numpy().astype(np.float64)
+    ref = O.make_mixed_operator(om, k, (0, 1), modification=True).apply(u)
+    assert _rel(got, ref) <= 2e-6, _rel(got, ref)
+    with pytest.raises(hhg.HHGError):
+        ctx.apply_mixed(4, ctx.from_canonical(4, _dev(u)), ctx.vector(4), 8)
 
 
 @pytest.mark.parametrize("mesh_fn,level", [(unit_tet, 5), (kuhn_cube_2x2x2, 3)])
