@@ -148,8 +148,16 @@ def kuhn48_applies(hhg, torch, steps, solves=True, applies=True):
         # primitive-mixed operator, nodal rows on macro vertices and edges
         m5 = time_op(lambda: ctx.apply_mixed(level, f64, y, hhg.PRIM_VERTICES | hhg.PRIM_EDGES), steps48, 3, torch)
         m6 = time_op(lambda: ctx.apply_mixed(level, f32, y32, hhg.PRIM_VERTICES | hhg.PRIM_EDGES), steps48, 3, torch)
+        # stored stencils (15 coefficients per row): the memory-bound baseline
+        ctx.store_stencils(level)
+        m7 = time_op(lambda: ctx.apply_stored(level, f64, y), steps48, 3, torch)
+        m8 = time_op(lambda: ctx.apply_stored(level, f32, y32), steps48, 3, torch)
         del y32
         out.update({
+            "stored_f64_gdofs": round(nu48 / m7 / 1e6, 2),
+            "stored_f64_hbm_frac": round(136 * nu48 / m7 / 1e6 / HBM_PEAK_GBS, 4),
+            "stored_f32_gdofs": round(nu48 / m8 / 1e6, 2),
+            "stored_f32_hbm_frac": round(68 * nu48 / m8 / 1e6 / HBM_PEAK_GBS, 4),
             "scaled_f64_gdofs": round(nu48 / m1 / 1e6, 2),
             "scaled_f64_hbm_frac": round(BYTES_PER_DOF["f64"] * nu48 / m1 / 1e6 / HBM_PEAK_GBS, 4),
             "scaled_f32_gdofs": round(nu48 / m2 / 1e6, 2),

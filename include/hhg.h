@@ -163,6 +163,19 @@ hhg_status hhg_read_timing(hhg_ctx ctx, double *ms_total, int64_t *launches);
 /* y = A~ u with the nodal-integration operator (eq. (standardfe), Sec. 6.2). */
 hhg_status hhg_apply_nodal(hhg_ctx ctx, int32_t level, hhg_dtype dtype,
                            const void *u, void *y, void *stream);
+/* Stored stencils: the memory-bound baseline that stencil scaling avoids
+ * (Sec. 6.4, the stored-stencil load model: 15 values per node).  Allocates
+ * (first call; 15 FP64 + 15 FP32 values per slot of `level`) and fills the
+ * rows of the interior nodes of every macro tet with the scaled operator's
+ * coefficients w_d (k_i + k_{i+d}) and the centre -sum of them; the coefficient
+ * must be set, and hhg_set_coefficient refreshes stored levels.  HHG_ENOMEM
+ * if the allocation fails (nothing is kept then). */
+hhg_status hhg_store_stencils(hhg_ctx ctx, int32_t level);
+/* y = A u with the stored stencils of `level` on the interior rows (plain
+ * 15-term products; inter-tet rows, Dirichlet zeros and the modification as
+ * in hhg_apply_scaled).  HHG_EINVAL if the level's stencils are not stored. */
+hhg_status hhg_apply_stored(hhg_ctx ctx, int32_t level, hhg_dtype dtype, const void *u, void *y,
+                            void *stream);
 /* y = A_I u with the primitive-mixed operator a_{h;I} (Sec. 5 eq. (modst)):
  * the row of a node on a macro primitive of a kind selected in
  * nodal_primitives (bit 0 vertices, bit 1 edges, bit 2 faces: I = W_V u W_E

@@ -264,6 +264,9 @@ struct Level {
     float *c_d32 = nullptr;
     uint8_t *c_nbdir = nullptr;
     uint8_t *c_prim = nullptr;
+    // stored stencils (allocated by hhg_store_stencils, refreshed with k)
+    double *st64 = nullptr;
+    float *st32 = nullptr;
     // learned correction: log k (FP32), ownership mask and FP32 scratch
     float *logk32 = nullptr;
     uint8_t *own = nullptr;
@@ -1672,6 +1675,11 @@ hhg_status hhg_set_coefficient(hhg_ctx c, const double *k, int on_device, void *
     for (int l = 0; l <= Lmax; ++l) {
         TRY(build_modification(c, l));
         TRY(build_diag(c, l, st));
+        Level &L = c->lv[l];
+        if (L.st64) {
+            HIPCHK(c, launch_store_stencils<double>(view<double>(c, l), L.st64, st));
+            HIPCHK(c, launch_store_stencils<float>(view<double>(c, l), L.st32, st));
+        }
     }
     c->have_k = true;
     TRY(build_coarse(c, st));
@@ -1750,6 +1758,45 @@ hhg_status hhg_apply_nodal(hhg_ctx c, int32_t level, hhg_dtype dt, const void *u
     hipStream_t st = pick(c, stream);
     if (dt == HHG_F64) HIPCHK(c, launch_nodal<double>(view<double>(c, level), (const double *)u, (double *)y, st));
     else if (dt == HHG_F32) HIPCHK(c, launch_nodal<float>(view<float>(c, level), (const float *)u, (float *)y, st));
+    else return fail(c, HHG_EINVAL, "bad dtype");
+    return HHG_OK;
+}
+
+hhg_status hhg_store_stencils(hhg_ctx c, int32_t level)
+{
+    TRY(check_level(c, level));
+    NEED_K(c);
+    Level &L = c->lv[level];
+    hipStream_t st = c->stream;
+    if (!L.st64) {
+        TRY(dalloc(c, &L.st64, (int64_t)15 * L.n_slots));
+        hhg_status s = dalloc(c, &L.st32, (int64_t)15 * L.n_slots);
+        if (s != HHG_OK) {
+            dfree(c, L.st64);
+            L.st64 = nullptr;
+            return s;
+        }
+    }
+    HIPCHK(c, launch_store_stencils<double>(view<double>(c, level), L.st64, st));
+    HIPCHK(c, launch_store_stencils<float>(view<double>(c, level), L.st32, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    return HHG_OK;
+}
+
+hhg_status hhg_apply_stored(hhg_ctx c, int32_t level, hhg_dtype dt, const void *u, void *y, void *stream)
+{
+    TRY(check_level(c, level));
+    NEED_K(c);
+    if (!u || !y || u == y) return fail(c, HHG_EINVAL, "u and y must be distinct non-NULL vectors");
+    const Level &L = c->lv[level];
+    if (!L.st64) return fail(c, HHG_EINVAL, "stencils of level %d are not stored (hhg_store_stencils)", level);
+    hipStream_t st = pick(c, stream);
+    if (dt == HHG_F64)
+        HIPCHK(c, launch_stored<double>(view<double>(c, level), corr<double>(c, level), L.st64, (const double *)u,
+                                        (double *)y, st));
+    else if (dt == HHG_F32)
+        HIPCHK(c, launch_stored<float>(view<float>(c, level), corr<float>(c, level), L.st32, (const float *)u,
+                                       (float *)y, st));
     else return fail(c, HHG_EINVAL, "bad dtype");
     return HHG_OK;
 }

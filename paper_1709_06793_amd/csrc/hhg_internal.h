@@ -91,6 +91,15 @@ hipError_t launch_scaled(const LevelView<T> &L, int mode, const T *u, const T *f
                          double *partial, int *n_partial, hipStream_t st);
 template <typename T>
 hipError_t launch_nodal(const LevelView<T> &L, const T *u, T *y, hipStream_t st);
+// stored stencils (the baseline the method avoids: 15 weights per interior
+// row, weight-major per tet, st[(tet * 15 + d) * Spad + slot], d < 14 the
+// directions, 14 the centre) from the scaled operator's coefficients, and the
+// apply that streams them
+template <typename T>
+hipError_t launch_store_stencils(const LevelView<double> &L, T *st, hipStream_t strm);
+template <typename T>
+hipError_t launch_stored(const LevelView<T> &L, const CorrView<T> &C, const T *st, const T *u, T *y,
+                         hipStream_t strm);
 // the primitive-mixed operator (Sec. 5 eq. (modst)): nodal-integration rows
 // for the nodes of the primitives in nodal_mask (1 vertices, 2 edges, 4
 // faces), scaled rows (with their modification corrections) elsewhere

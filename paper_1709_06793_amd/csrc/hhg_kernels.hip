@@ -1369,6 +1369,128 @@ hipError_t launch_prolong_add(const LevelView<T> &Lc, const LevelView<T> &Lf, co
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- stored stencils
+// Interior rows by column marching (a lane owns one in-plane offset t and
+// walks a chunk of planes; neighbour slots from neighbour_slots with the
+// plane's size).  Filling stores c_d = w_d (k_0 + k_d) for the 14 directions
+// (the scaled row's coefficients, eq. (discrete) with the half reference
+// entries) and the centre -sum_d c_d; the apply is the plain 15-term product
+// of the stored row with u.
+constexpr int SKC = 16;  // planes per wave
+
+__device__ __forceinline__ bool stored_lane(int n, int n_seg, int &t, int &sd, int &k0, int &k1, int &tet)
+{
+    tet = blockIdx.y;
+    const int w = __builtin_amdgcn_readfirstlane(blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6));
+    const int ch = w / n_seg, seg = w - ch * n_seg;
+    k0 = ch * SKC + 1;
+    if (k0 > n - 3) return false;
+    k1 = min(n - 3, k0 + SKC - 1);
+    t = seg * 64 + (int)(threadIdx.x & 63);
+    int d = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+    while ((d + 1) * (d + 2) / 2 <= t) ++d;
+    while (d > 0 && d * (d + 1) / 2 > t) --d;
+    sd = d;
+    return true;
+}
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_store_stencil(LevelView<double> L, T *__restrict__ st, int n_seg)
+{
+    int t, sd, k0, k1, tet;
+    const int n = L.n;
+    if (!stored_lane(n, n_seg, t, sd, k0, k1, tet)) return;
+    const int i = t - sd * (sd + 1) / 2, j = sd - i;
+    if (i < 1 || j < 1) return;
+    const int64_t base = (int64_t)tet * L.Spad;
+    const double *__restrict__ kb = L.kap + base;
+    const double *w = L.sten + (int64_t)tet * TET_STENCIL;
+    T *__restrict__ sb = st + (int64_t)tet * 15 * L.Spad;
+    const int Sn = tc32(n);
+    for (int k = k0; k <= min(k1, n - 1 - sd); ++k) {
+        const int s = Sn - tc32(n - k) + t;
+        int nb[NDIR];
+        neighbour_slots(s, sd, n - k, nb);
+        const double k0v = kb[s];
+        double diag = 0.0;
+        for (int d = 0; d < NDIR; ++d) {
+            const double c = w[d] * (k0v + kb[nb[d]]);
+            sb[(int64_t)d * L.Spad + s] = (T)c;
+            diag -= c;
+        }
+        sb[(int64_t)NDIR * L.Spad + s] = (T)diag;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_stored_apply(LevelView<T> L, const T *__restrict__ st,
+                                                         const T *__restrict__ u, T *__restrict__ y, int n_seg)
+{
+    int t, sd, k0, k1, tet;
+    const int n = L.n;
+    if (!stored_lane(n, n_seg, t, sd, k0, k1, tet)) return;
+    const int i = t - sd * (sd + 1) / 2, j = sd - i;
+    if (i < 1 || j < 1) return;
+    const int64_t base = (int64_t)tet * L.Spad;
+    const T *__restrict__ ub = u + base;
+    const T *__restrict__ sb = st + (int64_t)tet * 15 * L.Spad;
+    const int Sn = tc32(n);
+#pragma unroll 2
+    for (int k = k0; k <= min(k1, n - 1 - sd); ++k) {
+        const int s = Sn - tc32(n - k) + t;
+        int nb[NDIR];
+        neighbour_slots(s, sd, n - k, nb);
+        T acc = sb[(int64_t)NDIR * L.Spad + s] * ub[s];
+#pragma unroll
+        for (int d = 0; d < NDIR; ++d) acc += sb[(int64_t)d * L.Spad + s] * ub[nb[d]];
+        y[base + s] = acc;
+    }
+}
+
+// Dirichlet slots of y to 0 (the marches do this in their boundary blocks)
+template <typename T>
+__global__ void k_dirichlet_zero(LevelView<T> L, T *__restrict__ y)
+{
+    const int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (e >= (int64_t)L.n_tet * L.n_bnd) return;
+    const int tet = (int)(e / L.n_bnd);
+    const uint32_t v = L.bnd[e - (int64_t)tet * L.n_bnd];
+    if ((L.dmask[tet] >> (v & 15u)) & 1) y[(int64_t)tet * L.Spad + (v >> 4)] = T(0);
+}
+
+static inline dim3 stored_grid(int n, int n_tet, int &n_seg)
+{
+    n_seg = (int)((tri_count(n) + 63) / 64);
+    const int chunks = n > 3 ? (n - 3 + SKC - 1) / SKC : 0;
+    return dim3((unsigned)((n_seg * chunks + BLOCK / 64 - 1) / (BLOCK / 64)), (unsigned)n_tet);
+}
+
+template <typename T>
+hipError_t launch_store_stencils(const LevelView<double> &L, T *st, hipStream_t strm)
+{
+    int n_seg = 0;
+    const dim3 g = stored_grid(L.n, L.n_tet, n_seg);
+    if (g.x) k_store_stencil<T><<<g, BLOCK, 0, strm>>>(L, st, n_seg);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_stored(const LevelView<T> &L, const CorrView<T> &C, const T *st, const T *u, T *y,
+                         hipStream_t strm)
+{
+    int n_seg = 0;
+    const dim3 g = stored_grid(L.n, L.n_tet, n_seg);
+    if (g.x) k_stored_apply<T><<<g, BLOCK, 0, strm>>>(L, st, u, y, n_seg);
+    launch_shared_rows<T, MODE_APPLY>(L, L.sh_cs, u, nullptr, y, nullptr, strm);
+    const int64_t nb = (int64_t)L.n_tet * L.n_bnd;
+    if (nb) k_dirichlet_zero<T><<<blocks_for(nb), BLOCK, 0, strm>>>(L, y);
+    if (C.n_rows)
+        k_correction<T, MODE_APPLY><<<blocks_for(C.n_rows), BLOCK, 0, strm>>>(C, u, y, nullptr, ChebArgs<T>(), 0);
+    return hipGetLastError();
+}
+template hipError_t launch_store_stencils<double>(const LevelView<double> &, double *, hipStream_t);
+template hipError_t launch_store_stencils<float>(const LevelView<double> &, float *, hipStream_t);
+
 // ---------------------------------------------------------------- coarse solve
 // u[copies of row r] = sum_c Ainv[r][c] f[gather[c]] in FP64 (u zeroed
 // before): one wave per row, lanes stride over the columns (coalesced row
@@ -1514,6 +1636,8 @@ hipError_t launch_positive_check(const double *k, int64_t n, int *bad, hipStream
     template hipError_t launch_nodal<T>(const LevelView<T> &, const T *, T *, hipStream_t);        \
     template hipError_t launch_correction<T>(const LevelView<T> &, const CorrView<T> &, int,       \
                                              const T *, T *, double *, hipStream_t);               \
+    template hipError_t launch_stored<T>(const LevelView<T> &, const CorrView<T> &, const T *, const T *, \
+                                         T *, hipStream_t);                                        \
     template hipError_t launch_mixed<T>(const LevelView<T> &, const CorrView<T> &, const T *, T *, int, \
                                         hipStream_t);                                              \
     template hipError_t launch_cheb_sweep<T>(const LevelView<T> &, const CorrView<T> &, const T *, \

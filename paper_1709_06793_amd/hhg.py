@@ -25,7 +25,7 @@ WFALLBACK = 1
 EXPORTS = [
     "hhg_create_macro", "hhg_destroy", "hhg_last_error", "hhg_vector_size", "hhg_node_coords",
     "hhg_to_canonical", "hhg_from_canonical", "hhg_set_coefficient", "hhg_set_coarse_level",
-    "hhg_level_info", "hhg_apply_scaled", "hhg_set_timing", "hhg_read_timing", "hhg_set_kernel_variant", "hhg_apply_nodal", "hhg_apply_mixed", "hhg_residual", "hhg_smooth",
+    "hhg_level_info", "hhg_apply_scaled", "hhg_set_timing", "hhg_read_timing", "hhg_set_kernel_variant", "hhg_apply_nodal", "hhg_apply_mixed", "hhg_store_stencils", "hhg_apply_stored", "hhg_residual", "hhg_smooth",
     "hhg_vcycle", "hhg_solve", "hhg_learned_set_weights", "hhg_learned_set_fallback",
     "hhg_learned_forward", "hhg_learned_backward", "hhg_learned_loss_grad", "hhg_training_pair",
     "hhg_adam_update",
@@ -72,6 +72,8 @@ def load():
         "hhg_read_timing": [P, P, P],
         "hhg_apply_nodal": [P, I32, I32, P, P, P],
         "hhg_apply_mixed": [P, I32, I32, I32, P, P, P],
+        "hhg_store_stencils": [P, I32],
+        "hhg_apply_stored": [P, I32, I32, P, P, P],
         "hhg_residual": [P, I32, I32, P, P, P, P, P],
         "hhg_smooth": [P, I32, I32, I32, I32, D, P, P, P],
         "hhg_vcycle": [P, I32, I32, I32, I32, I32, P, P, P, P],
@@ -212,6 +214,13 @@ class Context:
     def apply_mixed(self, level, u, y, nodal_primitives=PRIM_VERTICES | PRIM_EDGES):
         self._check(load().hhg_apply_mixed(self._h, level, _dtype_code(u), int(nodal_primitives), _ptr(u), _ptr(y),
                                            _stream()))
+        return y
+
+    def store_stencils(self, level):
+        self._check(load().hhg_store_stencils(self._h, level))
+
+    def apply_stored(self, level, u, y):
+        self._check(load().hhg_apply_stored(self._h, level, _dtype_code(u), _ptr(u), _ptr(y), _stream()))
         return y
 
     def apply_nodal(self, level, u, y):

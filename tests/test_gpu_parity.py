@@ -134,6 +134,37 @@ def test_apply_mixed_fp32_and_bad_mask():
         ctx.apply_mixed(4, ctx.from_canonical(4, _dev(u)), ctx.vector(4), 8)
 
 
+@pytest.mark.parametrize("mesh_fn,level,kfun", [(unit_tet, 5, None), (kuhn_cube, 4, None), (kuhn_cube_2x2x2, 3, None),
+                                               (cube12, 3, None), (cube12, 3, "sigmoid"), (flat_tet, 4, "sigmoid")])
+def test_apply_stored_matches_oracle(mesh_fn, level, kfun):
+    """Stored stencils (15 coefficients per interior row) against the
+    oracle's scaled operator, FP64 and FP32, modification included; refreshed
+    by a new coefficient."""
+    kf = (lambda x: sigmoid_k(x, 100.0)) if kfun == "sigmoid" else (lambda x: lognormal_k(x, lognormal_params(5, 1.0, 0.2)))
+    om, k, u, ctx = _setup(mesh_fn, level, kfun=kf)
+    if kfun == "sigmoid":
+        assert ctx.level_info(level)["n_modified"] > 0
+    with pytest.raises(hhg.HHGError):
+        ctx.apply_stored(level, ctx.from_canonical(level, _dev(u)), ctx.vector(level))
+    ctx.store_stencils(level)
+    ref = O.make_operator(om, k, "scaled", modification=True).apply(u)
+    y = ctx.vector(level)
+    ctx.apply_stored(level, ctx.from_canonical(level, _dev(u)), y)
+    got = ctx.to_canonical(level, y).cpu().numpy()
+    assert _rel(got, ref) <= TOL64 and _elem(got, ref) <= TOL64, (_rel(got, ref), _elem(got, ref))
+    assert np.all(got[om.dirichlet] == 0.0)
+    y32 = ctx.vector(level, torch.float32)
+    ctx.apply_stored(level, ctx.from_canonical(level, _dev(u, torch.float32)), y32)
+    got32 = ctx.to_canonical(level, y32).cpu().numpy().astype(np.float64)
+    assert _rel(got32, ref) <= 2e-6, _rel(got32, ref)
+    k2 = smooth_k(om.xyz)
+    ctx.set_coefficient(k2)
+    ctx.apply_stored(level, ctx.from_canonical(level, _dev(u)), y)
+    got = ctx.to_canonical(level, y).cpu().numpy()
+    ref = O.make_operator(om, k2, "scaled", modification=True).apply(u)
+    assert _rel(got, ref) <= TOL64, _rel(got, ref)
+
+
 @pytest.mark.parametrize("mesh_fn,level", [(unit_tet, 5), (kuhn_cube_2x2x2, 3)])
 @pytest.mark.parametrize("kind", ["scaled", "nodal"])
 def test_apply_fp32_matches_oracle(mesh_fn, level, kind):
