@@ -216,10 +216,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
     double sq = 0.0;
     if (lb < L.n_tet * per_tet) {
         const int tet = lb / per_tet;
-        const int b = lb - tet * per_tet;
+        int bi;
+        const bool marching = march_block(lb - tet * per_tet, L.vpt, L.bpt2, bi);
         const int64_t base = (int64_t)tet * L.Spad;
-        if (b < L.vpt) {
-            const int item = __builtin_amdgcn_readfirstlane(b * 4 + (threadIdx.x >> 6));
+        if (marching) {
+            const int item = __builtin_amdgcn_readfirstlane(bi * 4 + (threadIdx.x >> 6));
             if (item < L.n_items) {
                 const uint2 it = L.items[item];
                 const int n = L.n, lane = threadIdx.x & 63;
@@ -318,7 +319,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
                 }
             }
         } else {
-            const int e = (b - L.vpt) * BLOCK + threadIdx.x;
+            const int e = bi * BLOCK + threadIdx.x;
             if (e < L.n_bnd) {
                 const uint32_t v = L.bnd[e];
                 if ((L.dmask[tet] >> (v & 15u)) & 1) y[base + (v >> 4)] = T(0);
@@ -437,10 +438,11 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
     double sq = 0.0;
     if (lb < L.n_tet * per_tet) {
         const int tet = lb / per_tet;
-        const int b = lb - tet * per_tet;
+        int bi;
+        const bool marching = march_block(lb - tet * per_tet, vb, per_tet - vb, bi);
         const int64_t base = (int64_t)tet * L.Spad;
-        if (b < vb) {
-            const int item = __builtin_amdgcn_readfirstlane(b * WPB + (threadIdx.x >> 6));
+        if (marching) {
+            const int item = __builtin_amdgcn_readfirstlane(bi * WPB + (threadIdx.x >> 6));
             if (item < L.n_items2) {
                 const uint2 it = L.items2[item];
                 const int n = L.n, lane = threadIdx.x & 63;
@@ -525,7 +527,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
                 }
             }
         } else {
-            const int e = (b - vb) * (64 * WPB) + threadIdx.x;
+            const int e = bi * (64 * WPB) + threadIdx.x;
             if (e < L.n_bnd) {
                 const uint32_t v = L.bnd[e];
                 if ((L.dmask[tet] >> (v & 15u)) & 1) y[base + (v >> 4)] = T(0);
@@ -593,10 +595,11 @@ __global__ __launch_bounds__(64 * LW) __attribute__((amdgpu_waves_per_eu(4))) vo
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
     if (lb >= L.n_tet * per_tet) return;  // whole block
     const int tet = lb / per_tet;
-    const int b = lb - tet * per_tet;
+    int b;
+    const bool marching = march_block(lb - tet * per_tet, L.n_itemsL, nbb, b);
     const int64_t base = (int64_t)tet * L.Spad;
-    if (b >= L.n_itemsL) {  // whole block: Dirichlet zeros
-        const int e = (b - L.n_itemsL) * (64 * LW) + threadIdx.x;
+    if (!marching) {  // whole block: Dirichlet zeros
+        const int e = b * (64 * LW) + threadIdx.x;
         if (e < L.n_bnd) {
             const uint32_t v = L.bnd[e];
             if ((L.dmask[tet] >> (v & 15u)) & 1) y[base + (v >> 4)] = 0.0;

@@ -132,10 +132,11 @@ __global__ __launch_bounds__(BLOCK) void k_learned_fwd_march(LevelView<float> L,
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
     if (lb >= L.n_tet * per_tet) return;
     const int tet = lb / per_tet;
-    const int b = lb - tet * per_tet;
+    int b;
+    const bool marching = march_block(lb - tet * per_tet, L.vpt, L.bpt2, b);
     const int64_t base = (int64_t)tet * L.Spad;
-    if (b >= L.vpt) {
-        const int e = (b - L.vpt) * BLOCK + threadIdx.x;
+    if (!marching) {
+        const int e = b * BLOCK + threadIdx.x;
         if (e < L.n_bnd) {
             const int64_t sl = base + (L.bnd[e] >> 4);
             if (c_out) c_out[sl] = 0.0f;

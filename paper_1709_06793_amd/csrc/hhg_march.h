@@ -26,6 +26,24 @@ __device__ __forceinline__ int xcd_remap(int b, int grid)
     return (b & 7) * per + (b >> 3);
 }
 
+// Blocks of one tet: nv marching blocks and nb blocks that write the Dirichlet
+// zeros.  The zeroing blocks are spread evenly among the marching ones (block
+// p zeroes iff floor((p+1) nb / P) > floor(p nb / P), P = nv + nb), so that
+// each XCD's contiguous share of the blocks holds its share of the marching
+// work even on a single tet.  Returns true for a marching block; idx is the
+// block's index among its kind.
+__device__ __forceinline__ bool march_block(int p, int nv, int nb, int &idx)
+{
+    const int P = nv + nb;
+    const int c1 = (int)(((int64_t)(p + 1) * nb) / P), c0 = (int)(((int64_t)p * nb) / P);
+    if (c1 > c0) {
+        idx = c0;
+        return false;
+    }
+    idx = p - c1;
+    return true;
+}
+
 // lane shifts by one position (DPP wave_shr:1 / wave_shl:1; a lane without a
 // source lane gets 0)
 __device__ __forceinline__ float dpp_prev(float v)  // value of lane-1
