@@ -219,6 +219,9 @@ def learned_solves(hhg, torch):
         out["held_out_32_fields"] = {k2: {"mean_iterations": v["mean_iterations"],
                                           "mean_seconds": round(v["mean_seconds"], 5)}
                                      for k2, v in ev.items() if isinstance(v, dict)}
+        out["held_out_32_fields"]["source"] = ("evaluation record stored with the shipped weights "
+                                               "(python -m paper_1709_06793_amd.learned_train eval), "
+                                               "not re-timed in this run")
     del ctx
     torch.cuda.empty_cache()
     return out
