@@ -64,6 +64,37 @@ def lognormal_k_torch(xyz, params, torch, device="cuda", chunk=1 << 24):
     return torch.exp(params["sigma"] * np.sqrt(2.0 / M) * g)
 
 
+# directions c_m of the tensor operator's components D_m = c_m . grad
+TENSOR_DIRS = np.array([[1, 0, 0], [0, 1, 0], [0, 0, 1], [1, 1, 0], [1, 0, 1], [0, 1, 1]], dtype=np.float64)
+
+
+def tensor_K(xyz):
+    """A smooth symmetric positive definite 3x3 field (n, 3, 3):
+    K = s R diag(1, 1.5, 2.5) R^T, s = smooth_k, R the rotation about
+    (1,1,1)/sqrt(3) by 0.8 sin(2 pi x) + 0.5 cos(2 pi z)."""
+    n = xyz.shape[0]
+    th = 0.8 * np.sin(2 * np.pi * xyz[:, 0]) + 0.5 * np.cos(2 * np.pi * xyz[:, 2])
+    a = np.ones(3) / np.sqrt(3.0)
+    A = np.array([[0, -a[2], a[1]], [a[2], 0, -a[0]], [-a[1], a[0], 0]])
+    R = (np.eye(3)[None] + np.sin(th)[:, None, None] * A[None]
+         + (1 - np.cos(th))[:, None, None] * (A @ A)[None])
+    D = np.diag([1.0, 1.5, 2.5])
+    return smooth_k(xyz)[:, None, None] * (R @ D[None] @ np.transpose(R, (0, 2, 1)))
+
+
+def tensor_fields(K):
+    """The six coefficient fields (6, n) of K in the components D_m = c_m.grad
+    (TENSOR_DIRS): k_i = K_ii - sum_{j != i} K_ij for D = d/dx_i, and
+    k_ij = K_ij for D = d/dx_i + d/dx_j, so that
+    sum_m k_m (c_m.a)(c_m.b) = a^T K b."""
+    K = np.asarray(K, dtype=np.float64)
+    out = np.empty((6, K.shape[0]))
+    for i in range(3):
+        out[i] = K[:, i, i] - sum(K[:, i, j] for j in range(3) if j != i)
+    out[3], out[4], out[5] = K[:, 0, 1], K[:, 0, 2], K[:, 1, 2]
+    return out
+
+
 def uniform_vector(n, seed=None, rng=None, lo=-1.0, hi=1.0):
     """n values uniform in [lo, hi) from default_rng(seed) (or a given stream)."""
     if rng is None:

@@ -20,6 +20,9 @@ Paper passages followed (arXiv 1709.06793):
                     modification_factors()
 * primitive mix     Sec. 5 eq. (modst): nodal-integration rows on the nodes
                     of the chosen macro primitives, scaled rows elsewhere
+* tensor K          Sec. 2.1 eq. (integral): a = sum_m a_m, a_m with its own
+                    coefficient k_m and D_m = c_m.grad; each a_m scaled as the
+                    scalar form (or nodal integration)
 * rates             Lemma 3.1 (O(h^2) in L2, O(h) in H1)
 """
 import ctypes
@@ -164,6 +167,64 @@ def element_matrices(xyz, conn):
     vol = np.abs(det) / 6.0
     A = vol[:, None, None] * np.einsum("eai,ebi->eab", G, G)
     return A, vol
+
+
+# directions c_m of the six components D_m = c_m . grad of the tensor form
+_TDIRS = np.array([[1, 0, 0], [0, 1, 0], [0, 0, 1], [1, 1, 0], [1, 0, 1], [0, 1, 1]], dtype=np.float64)
+
+
+def tensor_element_matrices(xyz, conn):
+    """A^m_t[a,b] = |t| (c_m . grad lambda_a)(c_m . grad lambda_b), (6,ne,4,4),
+    and the element gradients (ne,4,3) and volumes."""
+    P = xyz[conn]
+    J = np.stack([P[:, 1] - P[:, 0], P[:, 2] - P[:, 0], P[:, 3] - P[:, 0]], axis=2)
+    Jinv = np.linalg.inv(J)
+    G = np.concatenate([-Jinv.sum(axis=1, keepdims=True), Jinv], axis=1)
+    vol = np.abs(np.linalg.det(J)) / 6.0
+    D = np.einsum("eai,mi->mea", G, _TDIRS)
+    return vol[None, :, None, None] * D[:, :, :, None] * D[:, :, None, :], G, vol
+
+
+def assemble_tensor(mesh, K6, kind="scaled"):
+    """Global matrix over all nodes of sum_m a_m (Sec. 2.1 eq. (integral)) with
+    the six coefficient fields K6 (6, n_nodes): per component, scaled =
+    off-diagonal factor (k_m,a + k_m,b)/2 and zero element row sums (the scalar
+    form of Lemma 3.2 applied to a_m), nodal = mean vertex k_m times A^m_t."""
+    conn, _ = mesh.elements()
+    Am, _, _ = tensor_element_matrices(mesh.xyz, conn)
+    KA = np.zeros(Am.shape[1:])
+    idx = np.arange(4)
+    for m in range(6):
+        kv = K6[m][conn]
+        if kind == "nodal":
+            KA += kv.mean(axis=1)[:, None, None] * Am[m]
+        else:
+            T = (kv[:, :, None] + kv[:, None, :]) / 2.0 * Am[m]
+            T[:, idx, idx] = 0.0
+            T[:, idx, idx] = -T.sum(axis=2)
+            KA += T
+    rows = np.repeat(conn, 4, axis=1).ravel()
+    cols = np.tile(conn, (1, 4)).ravel()
+    M = sp.coo_matrix((KA.ravel(), (rows, cols)), shape=(mesh.n_nodes, mesh.n_nodes)).tocsr()
+    M.sum_duplicates()
+    return M
+
+
+def make_tensor_operator(mesh, K6, kind="scaled"):
+    return Operator(mesh, assemble_tensor(mesh, K6, kind))
+
+
+def assemble_galerkin_constant_tensor(mesh, K):
+    """Exact Galerkin matrix of int grad(v) . K grad(w) for a constant K:
+    |t| G K G^T per element."""
+    conn, _ = mesh.elements()
+    _, G, vol = tensor_element_matrices(mesh.xyz, conn)
+    KA = vol[:, None, None] * np.einsum("eai,ij,ebj->eab", G, np.asarray(K, dtype=np.float64), G)
+    rows = np.repeat(conn, 4, axis=1).ravel()
+    cols = np.tile(conn, (1, 4)).ravel()
+    M = sp.coo_matrix((KA.ravel(), (rows, cols)), shape=(mesh.n_nodes, mesh.n_nodes)).tocsr()
+    M.sum_duplicates()
+    return M
 
 
 def _lambda_min(A):

@@ -15,7 +15,7 @@ import scipy.sparse.linalg as spla
 
 from hhg_inputs import (unit_tet, regular_tet, flat_tet, kuhn_cube, kuhn_cube_2x2x2, cube12, smooth_k,
                         affine_k, sigmoid_k, manufactured_u, manufactured_f,
-                        lognormal_params, lognormal_k)
+                        lognormal_params, lognormal_k, tensor_K, tensor_fields)
 from oracle import oracle as O
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -356,3 +356,53 @@ def test_primitive_mix_reproduces_affine_solutions(level):
         A = O.assemble_mixed(m, k, dims) if dims else O.assemble(m, k, "scaled")
         assert err(A) > 1e-5, dims
         assert np.abs(((A - N) @ u)[I]).max() > 1e-2 * scale, dims
+
+
+@pytest.mark.parametrize("mesh_fn", [cube12, kuhn_cube])
+def test_tensor_constant_K_is_exact_galerkin(mesh_fn):
+    """Sec. 2.1 eq. (integral) with constant K: every component's coefficient
+    is constant, so scaling and nodal integration both give the exact
+    Galerkin matrix of grad v . K grad w (|t| G K G^T); this also pins the
+    six-component decomposition of K."""
+    X, T = mesh_fn()
+    m = O.Mesh(X, T, 2)
+    K = np.array([[2.0, 0.3, -0.2], [0.3, 1.5, 0.4], [-0.2, 0.4, 1.2]])
+    K6 = tensor_fields(np.broadcast_to(K, (m.n_nodes, 3, 3)))
+    G = O.assemble_galerkin_constant_tensor(m, K)
+    for kind in ("scaled", "nodal"):
+        A = O.assemble_tensor(m, K6, kind)
+        assert abs(A - G).max() <= 1e-13 * abs(G).max(), kind
+
+
+def test_tensor_scalar_K_is_the_scalar_operator():
+    """K = k I: the tensor form reduces to -div(k grad u) (M = 1, Sec. 2.1)."""
+    X, T = cube12()
+    m = O.Mesh(X, T, 3)
+    k = smooth_k(m.xyz)
+    K6 = tensor_fields(k[:, None, None] * np.eye(3)[None])
+    for kind in ("scaled", "nodal"):
+        A, S = O.assemble_tensor(m, K6, kind), O.assemble(m, k, kind)
+        assert abs(A - S).max() <= 1e-13 * abs(S).max(), kind
+
+
+def test_tensor_operator_symmetric_with_zero_row_sums():
+    """Variable SPD K: the scaled tensor matrix is symmetric (Lemma 3.2 per
+    component), its rows sum to zero and it is positive definite on the
+    unknowns; on macro-interior rows scaling and nodal integration differ by
+    O(h^2) for smooth u (ratio -> 4 per level)."""
+    X, T = kuhn_cube()
+    gaps = []
+    for level in (3, 4, 5):
+        m = O.Mesh(X, T, level)
+        K6 = tensor_fields(tensor_K(m.xyz))
+        A = O.assemble_tensor(m, K6)
+        assert abs(A - A.T).max() <= 1e-13 * abs(A).max()
+        assert np.abs(A @ np.ones(m.n_nodes)).max() <= 1e-12 * abs(A).max()
+        if level == 3:
+            Au = A[m.unknowns][:, m.unknowns].toarray()
+            assert np.linalg.eigvalsh(Au).min() > 0
+        N = O.assemble_tensor(m, K6, "nodal")
+        u = manufactured_u(m.xyz)
+        inner = np.flatnonzero((O.primitive_dims(m) == 3) & ~m.dirichlet)
+        gaps.append(np.abs(((A - N) @ u)[inner]).max() / np.abs((N @ u)[inner]).max())
+    assert gaps[0] > gaps[1] > gaps[2] and gaps[1] / gaps[2] > 3.3, gaps
