@@ -129,6 +129,10 @@ def kuhn48_applies(hhg, torch, steps, solves=True, applies=True):
     nu48 = sz["n_unknowns"]
     f = torch.tensor(prm2["rng"].uniform(-1, 1, xyz.shape[0]), device="cuda")
     f[torch.tensor(dirichlet, device="cuda")] = 0.0
+    if applies:
+        from hhg_inputs import tensor_fields_torch
+        ctx.set_tensor_coefficient(tensor_fields_torch(xyz, torch))
+        torch.cuda.empty_cache()
     del xyz
     f64 = ctx.from_canonical(level, f)
     del f
@@ -148,12 +152,19 @@ def kuhn48_applies(hhg, torch, steps, solves=True, applies=True):
         # primitive-mixed operator, nodal rows on macro vertices and edges
         m5 = time_op(lambda: ctx.apply_mixed(level, f64, y, hhg.PRIM_VERTICES | hhg.PRIM_EDGES), steps48, 3, torch)
         m6 = time_op(lambda: ctx.apply_mixed(level, f32, y32, hhg.PRIM_VERTICES | hhg.PRIM_EDGES), steps48, 3, torch)
+        # tensor coefficient (six component fields), every component scaled
+        m9 = time_op(lambda: ctx.apply_tensor(level, f64, y), steps48, 3, torch)
+        m10 = time_op(lambda: ctx.apply_tensor(level, f32, y32), steps48, 3, torch)
         # stored stencils (15 coefficients per row): the memory-bound baseline
         ctx.store_stencils(level)
         m7 = time_op(lambda: ctx.apply_stored(level, f64, y), steps48, 3, torch)
         m8 = time_op(lambda: ctx.apply_stored(level, f32, y32), steps48, 3, torch)
         del y32
         out.update({
+            "tensor_f64_gdofs": round(nu48 / m9 / 1e6, 2),
+            "tensor_f64_hbm_frac": round(64 * nu48 / m9 / 1e6 / HBM_PEAK_GBS, 4),
+            "tensor_f32_gdofs": round(nu48 / m10 / 1e6, 2),
+            "tensor_f32_hbm_frac": round(32 * nu48 / m10 / 1e6 / HBM_PEAK_GBS, 4),
             "stored_f64_gdofs": round(nu48 / m7 / 1e6, 2),
             "stored_f64_hbm_frac": round(136 * nu48 / m7 / 1e6 / HBM_PEAK_GBS, 4),
             "stored_f32_gdofs": round(nu48 / m8 / 1e6, 2),

@@ -95,6 +95,31 @@ def tensor_fields(K):
     return out
 
 
+def tensor_fields_torch(xyz, torch, device="cuda", chunk=1 << 22):
+    """tensor_fields(tensor_K(xyz)) evaluated with torch on `device` in
+    chunks (same formulas, FP64); returns a (6, n) device tensor."""
+    x = torch.as_tensor(xyz, dtype=torch.float64, device=device)
+    n = x.shape[0]
+    out = torch.empty((6, n), dtype=torch.float64, device=device)
+    a = torch.ones(3, dtype=torch.float64, device=device) / np.sqrt(3.0)
+    A = torch.tensor([[0.0, -a[2].item(), a[1].item()], [a[2].item(), 0.0, -a[0].item()],
+                      [-a[1].item(), a[0].item(), 0.0]], dtype=torch.float64, device=device)
+    D = torch.diag(torch.tensor([1.0, 1.5, 2.5], dtype=torch.float64, device=device))
+    I3 = torch.eye(3, dtype=torch.float64, device=device)
+    for c0 in range(0, n, chunk):
+        xc = x[c0:c0 + chunk]
+        th = 0.8 * torch.sin(2 * np.pi * xc[:, 0]) + 0.5 * torch.cos(2 * np.pi * xc[:, 2])
+        R = I3[None] + torch.sin(th)[:, None, None] * A[None] + (1 - torch.cos(th))[:, None, None] * (A @ A)[None]
+        s = 1.0 + 0.5 * torch.sin(2 * np.pi * xc[:, 0]) * torch.sin(2 * np.pi * xc[:, 1]) * torch.sin(2 * np.pi * xc[:, 2])
+        K = s[:, None, None] * (R @ D[None] @ R.transpose(1, 2))
+        for i in range(3):
+            out[i, c0:c0 + chunk] = K[:, i, i] - sum(K[:, i, j] for j in range(3) if j != i)
+        out[3, c0:c0 + chunk] = K[:, 0, 1]
+        out[4, c0:c0 + chunk] = K[:, 0, 2]
+        out[5, c0:c0 + chunk] = K[:, 1, 2]
+    return out
+
+
 def uniform_vector(n, seed=None, rng=None, lo=-1.0, hi=1.0):
     """n values uniform in [lo, hi) from default_rng(seed) (or a given stream)."""
     if rng is None:

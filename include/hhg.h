@@ -163,6 +163,20 @@ hhg_status hhg_read_timing(hhg_ctx ctx, double *ms_total, int64_t *launches);
 /* y = A~ u with the nodal-integration operator (eq. (standardfe), Sec. 6.2). */
 hhg_status hhg_apply_nodal(hhg_ctx ctx, int32_t level, hhg_dtype dtype,
                            const void *u, void *y, void *stream);
+/* Tensor coefficient (Sec. 2.1 eq. (integral)): a(v,w) = sum_m int k_m (D_m v)(D_m w)
+ * with six components D_m = c_m.grad, c_m = e_x, e_y, e_z, e_x+e_y, e_x+e_z,
+ * e_y+e_z; for a symmetric K, k_i = K_ii - sum_{j!=i} K_ij (D = d/dx_i) and
+ * k_ij = K_ij (D = d/dx_i + d/dx_j) give grad v . K grad w.  k6: 6 x n_nodes
+ * values (component-major, canonical node order of the finest level; any
+ * sign), host or device memory as for hhg_set_coefficient; coarser levels
+ * take the values at their nodes.  Independent of the scalar coefficient. */
+hhg_status hhg_set_tensor_coefficient(hhg_ctx ctx, const double *k6, int on_device, void *stream);
+/* y = A_K u with every component scaled as the scalar operator (no Sec. 4.1
+ * modification, which the paper defines for a scalar k only): row of node i =
+ * sum_m sum_j (k_m(x_i) + k_m(x_j))/2 (s^m_i)_j (u_j - u_i).  Same vector
+ * rules as hhg_apply_scaled; HHG_ESTATE before hhg_set_tensor_coefficient. */
+hhg_status hhg_apply_tensor(hhg_ctx ctx, int32_t level, hhg_dtype dtype, const void *u, void *y,
+                            void *stream);
 /* Stored stencils: the memory-bound baseline that stencil scaling avoids
  * (Sec. 6.4, the stored-stencil load model: 15 values per node).  Allocates
  * (first call; 15 FP64 + 15 FP32 values per slot of `level`) and fills the

@@ -249,6 +249,10 @@ struct Level {
     double *sh_cs64 = nullptr, *sh_cn64 = nullptr;
     float *sh_cs32 = nullptr, *sh_cn32 = nullptr;
     // coefficient dependent
+    // tensor operator: per-tet component stencils and the six coefficient fields
+    std::vector<double> h_tsten;
+    double *tsten64 = nullptr, *kt64 = nullptr;
+    float *tsten32 = nullptr, *kt32 = nullptr;
     double *k64 = nullptr, *invd64 = nullptr;
     float *k32 = nullptr, *invd32 = nullptr;
     double lam = 0.0;
@@ -288,6 +292,7 @@ struct hhg_ctx_s {
     hipStream_t stream = nullptr;
     std::vector<Level> lv;
     bool have_k = false;
+    bool have_tk = false;  // tensor coefficient set
     std::vector<void *> allocs;
     double *partial = nullptr;
     int64_t partial_cap = 0;
@@ -403,6 +408,34 @@ void lattice_point(const Topology &tp, int t, int n, double i, double j, double 
 }
 
 // the six element matrices of tet t at n intervals
+// element matrix of one tensor component D = c.grad: |t| (c.g_a)(c.g_b)
+bool element_matrix_dir(const double p[4][3], const double cdir[3], double E[4][4])
+{
+    double L[4][4];
+    if (!element_matrix(p, L)) return false;  // validity (non-zero volume)
+    Mat3 J;
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) J.a[r][c] = p[c + 1][r] - p[0][r];
+    const double det = det3(J);
+    const auto &a = J.a;
+    const double inv[3][3] = {
+        {a[1][1] * a[2][2] - a[1][2] * a[2][1], a[0][2] * a[2][1] - a[0][1] * a[2][2],
+         a[0][1] * a[1][2] - a[0][2] * a[1][1]},
+        {a[1][2] * a[2][0] - a[1][0] * a[2][2], a[0][0] * a[2][2] - a[0][2] * a[2][0],
+         a[0][2] * a[1][0] - a[0][0] * a[1][2]},
+        {a[1][0] * a[2][1] - a[1][1] * a[2][0], a[0][1] * a[2][0] - a[0][0] * a[2][1],
+         a[0][0] * a[1][1] - a[0][1] * a[1][0]}};
+    double dg[4] = {0, 0, 0, 0};
+    for (int r = 0; r < 3; ++r) {
+        dg[r + 1] = (inv[r][0] * cdir[0] + inv[r][1] * cdir[1] + inv[r][2] * cdir[2]) / det;
+        dg[0] -= dg[r + 1];
+    }
+    const double vol = std::fabs(det) / 6.0;
+    for (int x = 0; x < 4; ++x)
+        for (int y = 0; y < 4; ++y) E[x][y] = vol * dg[x] * dg[y];
+    return true;
+}
+
 bool type_matrices(const Topology &tp, int t, int n, double E[NTYPE][4][4])
 {
     for (int ty = 0; ty < NTYPE; ++ty) {
@@ -478,6 +511,7 @@ LevelView<double> view<double>(const hhg_ctx c, int l)
     v.items = L.items; v.n_items = L.n_items; v.vpt = (L.n_items + 3) / 4;
     v.sh_w = L.sh_w; v.sh_nb = L.sh_nb; v.sh_self = L.sh_self; v.sh_cslot = L.sh_cslot;
     v.sh_cs = L.sh_cs64; v.sh_cn = L.sh_cn64; v.sh_prim = L.sh_prim;
+    v.tsten = L.tsten64; v.kt = L.kt64;
     v.items2 = L.items2; v.n_items2 = L.n_items2; v.vpt2 = (L.n_items2 + 3) / 4;
     v.itemsL = L.itemsL; v.n_itemsL = L.n_itemsL;
     v.bnd = L.bnd; v.n_bnd = L.n_bnd; v.bpt2 = (L.n_bnd + BLOCK - 1) / BLOCK;
@@ -495,6 +529,7 @@ LevelView<float> view<float>(const hhg_ctx c, int l)
     v.items = L.items; v.n_items = L.n_items; v.vpt = (L.n_items + 3) / 4;
     v.sh_w = L.sh_w; v.sh_nb = L.sh_nb; v.sh_self = L.sh_self; v.sh_cslot = L.sh_cslot;
     v.sh_cs = L.sh_cs32; v.sh_cn = L.sh_cn32; v.sh_prim = L.sh_prim;
+    v.tsten = L.tsten32; v.kt = L.kt32;
     v.items2 = L.items2f; v.n_items2 = L.n_items2f; v.vpt2 = (L.n_items2f + 3) / 4;
     v.itemsL = L.itemsL; v.n_itemsL = 0;
     v.bnd = L.bnd; v.n_bnd = L.n_bnd; v.bpt2 = (L.n_bnd + BLOCK - 1) / BLOCK;
@@ -623,6 +658,43 @@ hhg_status build_level(hhg_ctx c, int l)
                 rw[d] = 0.5 / tp.valence(t, zp & zq);
             }
         }
+    }
+    // tensor components D_m = c_m.grad: per tet and kind the half reference
+    // entries of each a_m (the same sums as the scalar stencil above)
+    {
+        static const double CD[6][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {1, 1, 0}, {1, 0, 1}, {0, 1, 1}};
+        L.h_tsten.assign((size_t)tp.nt * 6 * TET_STENCIL, 0.0);
+        for (int t = 0; t < tp.nt; ++t)
+            for (int m = 0; m < 6; ++m) {
+                double E[NTYPE][4][4];
+                for (int ty = 0; ty < NTYPE; ++ty) {
+                    double p[4][3];
+                    for (int a = 0; a < 4; ++a)
+                        lattice_point(tp, t, L.n, TYPE_OFF[ty][a][0], TYPE_OFF[ty][a][1], TYPE_OFF[ty][a][2], p[a]);
+                    if (!element_matrix_dir(p, CD[m], E[ty])) return fail(c, HHG_EMESH, "tet %d is degenerate", t);
+                }
+                for (int zp = 0; zp < 15; ++zp) {
+                    if (popcount4(zp) == 4) continue;
+                    int ri, rj, rk;
+                    representative(zp, ri, rj, rk);
+                    double st[NDIR + 1] = {0};
+                    for (int ty = 0; ty < NTYPE; ++ty)
+                        for (int a = 0; a < 4; ++a) {
+                            if (!element_valid(8, ri - TYPE_OFF[ty][a][0], rj - TYPE_OFF[ty][a][1],
+                                               rk - TYPE_OFF[ty][a][2], ty))
+                                continue;
+                            for (int b = 0; b < 4; ++b) {
+                                const int d = dir_index(TYPE_OFF[ty][b][0] - TYPE_OFF[ty][a][0],
+                                                        TYPE_OFF[ty][b][1] - TYPE_OFF[ty][a][1],
+                                                        TYPE_OFF[ty][b][2] - TYPE_OFF[ty][a][2]);
+                                st[d] += E[ty][a][b];
+                            }
+                        }
+                    double *row = &L.h_tsten[((size_t)t * 6 + m) * TET_STENCIL + zp * KIND_STRIDE];
+                    for (int d = 0; d < NDIR; ++d) row[d] = 0.5 * st[d];
+                    row[NDIR] = st[NDIR];
+                }
+            }
     }
     // nodes on shared primitives: every non-Dirichlet vertex / edge / face of
     // the macro mesh that is not inside one tet, with all tets holding it
@@ -903,6 +975,11 @@ hhg_status build_level(hhg_ctx c, int l)
     std::vector<float> s32(L.h_sten.begin(), L.h_sten.end()), e32(L.h_emat.begin(), L.h_emat.end()),
         r32(L.h_rstw.begin(), L.h_rstw.end());
     TRY(upload(c, &L.sten64, L.h_sten));
+    {
+        std::vector<float> t32(L.h_tsten.begin(), L.h_tsten.end());
+        TRY(upload(c, &L.tsten64, L.h_tsten));
+        TRY(upload(c, &L.tsten32, t32));
+    }
     TRY(upload(c, &L.emat64, L.h_emat));
     TRY(upload(c, &L.rstw64, L.h_rstw));
     TRY(upload(c, &L.sten32, s32));
@@ -1758,6 +1835,59 @@ hhg_status hhg_apply_nodal(hhg_ctx c, int32_t level, hhg_dtype dt, const void *u
     hipStream_t st = pick(c, stream);
     if (dt == HHG_F64) HIPCHK(c, launch_nodal<double>(view<double>(c, level), (const double *)u, (double *)y, st));
     else if (dt == HHG_F32) HIPCHK(c, launch_nodal<float>(view<float>(c, level), (const float *)u, (float *)y, st));
+    else return fail(c, HHG_EINVAL, "bad dtype");
+    return HHG_OK;
+}
+
+hhg_status hhg_set_tensor_coefficient(hhg_ctx c, const double *k6, int on_device, void *stream)
+{
+    if (!c || !k6) return fail(c, HHG_EINVAL, "NULL argument");
+    hipStream_t st = pick(c, stream);
+    const int Lmax = c->max_level;
+    Level &F = c->lv[Lmax];
+    TRY(ensure_canon_maps(c, Lmax));
+    for (int l = 0; l <= Lmax; ++l) {
+        Level &L = c->lv[l];
+        if (!L.kt64) {
+            TRY(dalloc(c, &L.kt64, 6 * L.n_slots));
+            TRY(dalloc(c, &L.kt32, 6 * L.n_slots));
+        }
+    }
+    double *dk = nullptr;
+    TRY(dalloc(c, &dk, 6 * F.n_nodes));
+    HIPCHK(c, hipMemcpyAsync(dk, k6, 6 * F.n_nodes * 8, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                             st));
+    for (int m = 0; m < 6; ++m) {
+        // every slot from its node, Dirichlet ones included (rows next to the
+        // boundary read them); padding slots 0
+        double *km = F.kt64 + (int64_t)m * F.n_slots;
+        HIPCHK(c, launch_fill<double>(km, 0.0, F.n_slots, st));
+        HIPCHK(c, launch_from_canonical<double>(dk + (int64_t)m * F.n_nodes, F.slot2canon, km, F.n_slots, 1, F.S,
+                                                F.Spad, st));
+        for (int l = Lmax - 1; l >= 0; --l) {
+            Level &Lc = c->lv[l], &Lf = c->lv[l + 1];
+            double *kc = Lc.kt64 + (int64_t)m * Lc.n_slots;
+            HIPCHK(c, launch_fill<double>(kc, 0.0, Lc.n_slots, st));
+            HIPCHK(c, launch_inject<double>(Lf.kt64 + (int64_t)m * Lf.n_slots, Lf.n, kc, Lc.n, c->topo.nt, Lf.Spad,
+                                            Lc.Spad, st));
+        }
+    }
+    for (int l = 0; l <= Lmax; ++l)
+        HIPCHK(c, launch_convert<double, float>(c->lv[l].kt64, c->lv[l].kt32, 6 * c->lv[l].n_slots, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    dfree(c, dk);
+    c->have_tk = true;
+    return HHG_OK;
+}
+
+hhg_status hhg_apply_tensor(hhg_ctx c, int32_t level, hhg_dtype dt, const void *u, void *y, void *stream)
+{
+    TRY(check_level(c, level));
+    if (!c->have_tk) return fail(c, HHG_ESTATE, "no tensor coefficient set");
+    if (!u || !y || u == y) return fail(c, HHG_EINVAL, "u and y must be distinct non-NULL vectors");
+    hipStream_t st = pick(c, stream);
+    if (dt == HHG_F64) HIPCHK(c, launch_tensor<double>(view<double>(c, level), (const double *)u, (double *)y, st));
+    else if (dt == HHG_F32) HIPCHK(c, launch_tensor<float>(view<float>(c, level), (const float *)u, (float *)y, st));
     else return fail(c, HHG_EINVAL, "bad dtype");
     return HHG_OK;
 }

@@ -56,6 +56,11 @@ struct LevelView {
     const T *sh_cs;           // scaled-operator coefficients
     const T *sh_cn;           // nodal-operator coefficients
     const uint8_t *sh_prim;   // macro primitive of node q: 1 vertex, 2 edge, 4 face
+    // tensor operator: [tet][6 components][16 kinds][16] half reference entries
+    // of the components D_m = c_m.grad, and the six coefficient fields
+    // (component m at kt + m * n_tet * Spad), null until set
+    const T *tsten;
+    const T *kt;
 };
 
 // sparse corrections of the modification (Sec. 4.1) at one level
@@ -100,6 +105,11 @@ hipError_t launch_store_stencils(const LevelView<double> &L, T *st, hipStream_t 
 template <typename T>
 hipError_t launch_stored(const LevelView<T> &L, const CorrView<T> &C, const T *st, const T *u, T *y,
                          hipStream_t strm);
+// tensor-coefficient operator (Sec. 2.1 eq. (integral)), every component
+// scaled: interior rows, inter-tet rows (sum over the copies' tet-restricted
+// stencils) and Dirichlet zeros
+template <typename T>
+hipError_t launch_tensor(const LevelView<T> &L, const T *u, T *y, hipStream_t st);
 // the primitive-mixed operator (Sec. 5 eq. (modst)): nodal-integration rows
 // for the nodes of the primitives in nodal_mask (1 vertices, 2 edges, 4
 // faces), scaled rows (with their modification corrections) elsewhere

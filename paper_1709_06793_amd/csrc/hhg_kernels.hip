@@ -1450,6 +1450,75 @@ __global__ __launch_bounds__(BLOCK) void k_stored_apply(LevelView<T> L, const T 
     }
 }
 
+// ---------------------------------------------------------------- tensor coefficient
+// Row of node 0: sum_m sum_d w^m_d (k_m,0 + k_m,d) (u_d - u_0) with the
+// half reference entries w^m of component m (Sec. 2.1 eq. (integral), each
+// a_m scaled as the scalar form).  Interior rows by column marching (a lane
+// per in-plane offset, neighbour slots from the plane size), inter-tet rows
+// as the sum of their copies' tet-restricted stencils.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_tensor_interior(LevelView<T> L, const T *__restrict__ u,
+                                                            T *__restrict__ y, int n_seg)
+{
+    int t, sd, k0, k1, tet;
+    const int n = L.n;
+    if (!stored_lane(n, n_seg, t, sd, k0, k1, tet)) return;
+    const int i = t - sd * (sd + 1) / 2, j = sd - i;
+    if (i < 1 || j < 1) return;
+    const int64_t base = (int64_t)tet * L.Spad, ns = (int64_t)L.n_tet * L.Spad;
+    const T *__restrict__ ub = u + base;
+    const T *__restrict__ w = L.tsten + (int64_t)tet * 6 * TET_STENCIL;  // kind 0 of each component
+    const int Sn = tc32(n);
+    for (int k = k0; k <= min(k1, n - 1 - sd); ++k) {
+        const int s = Sn - tc32(n - k) + t;
+        int nb[NDIR];
+        neighbour_slots(s, sd, n - k, nb);
+        const T u0 = ub[s];
+        T du[NDIR];
+#pragma unroll
+        for (int d = 0; d < NDIR; ++d) du[d] = ub[nb[d]] - u0;
+        T acc = T(0);
+        for (int m = 0; m < 6; ++m) {
+            const T *__restrict__ km = L.kt + m * ns + base;
+            const T *__restrict__ wm = w + m * TET_STENCIL;
+            const T k0v = km[s];
+#pragma unroll
+            for (int d = 0; d < NDIR; ++d) acc += wm[d] * (k0v + km[nb[d]]) * du[d];
+        }
+        y[base + s] = acc;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_tensor_shared(LevelView<T> L, const T *__restrict__ u,
+                                                          T *__restrict__ y)
+{
+    const int q = blockIdx.x * BLOCK + threadIdx.x;
+    if (q >= L.n_shared) return;
+    const int64_t ns = (int64_t)L.n_tet * L.Spad;
+    const T u0 = u[L.sh_self[q]];
+    T acc = T(0);
+    for (int c = L.sh_off[q]; c < L.sh_off[q + 1]; ++c) {
+        int tet, kind, i, j, k;
+        unpack_copy(L.sh_copy[c], tet, kind, i, j, k);
+        const int64_t base = (int64_t)tet * L.Spad;
+        const int s = slot32(L.n, i, j, k);
+        int nb[NDIR];
+        neighbour_slots(s, i + j, L.n - k, nb);
+        for (int d = 0; d < NDIR; ++d) {
+            if (!in_lattice(L.n, i + DIR[d][0], j + DIR[d][1], k + DIR[d][2])) continue;
+            const T du = u[base + nb[d]] - u0;
+            for (int m = 0; m < 6; ++m) {
+                const T wv = L.tsten[((int64_t)tet * 6 + m) * TET_STENCIL + kind * KIND_STRIDE + d];
+                if (wv == T(0)) continue;
+                const T *__restrict__ km = L.kt + m * ns + base;
+                acc += wv * (km[s] + km[nb[d]]) * du;
+            }
+        }
+    }
+    for (int c = L.sh_off[q]; c < L.sh_off[q + 1]; ++c) y[L.sh_cslot[c]] = acc;
+}
+
 // Dirichlet slots of y to 0 (the marches do this in their boundary blocks)
 template <typename T>
 __global__ void k_dirichlet_zero(LevelView<T> L, T *__restrict__ y)
@@ -1491,6 +1560,19 @@ hipError_t launch_stored(const LevelView<T> &L, const CorrView<T> &C, const T *s
         k_correction<T, MODE_APPLY><<<blocks_for(C.n_rows), BLOCK, 0, strm>>>(C, u, y, nullptr, ChebArgs<T>(), 0);
     return hipGetLastError();
 }
+template <typename T>
+hipError_t launch_tensor(const LevelView<T> &L, const T *u, T *y, hipStream_t st)
+{
+    int n_seg = 0;
+    const dim3 g = stored_grid(L.n, L.n_tet, n_seg);
+    if (g.x) k_tensor_interior<T><<<g, BLOCK, 0, st>>>(L, u, y, n_seg);
+    if (L.n_shared) k_tensor_shared<T><<<blocks_for(L.n_shared), BLOCK, 0, st>>>(L, u, y);
+    const int64_t nb = (int64_t)L.n_tet * L.n_bnd;
+    if (nb) k_dirichlet_zero<T><<<blocks_for(nb), BLOCK, 0, st>>>(L, y);
+    return hipGetLastError();
+}
+template hipError_t launch_tensor<double>(const LevelView<double> &, const double *, double *, hipStream_t);
+template hipError_t launch_tensor<float>(const LevelView<float> &, const float *, float *, hipStream_t);
 template hipError_t launch_store_stencils<double>(const LevelView<double> &, double *, hipStream_t);
 template hipError_t launch_store_stencils<float>(const LevelView<double> &, float *, hipStream_t);
 

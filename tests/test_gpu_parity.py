@@ -8,7 +8,8 @@ import numpy as np
 import pytest
 
 from hhg_inputs import (unit_tet, regular_tet, flat_tet, kuhn_cube, kuhn_cube_2x2x2, cube12, smooth_k,
-                        sigmoid_k, lognormal_params, lognormal_k, uniform_vector, affine_k)
+                        sigmoid_k, lognormal_params, lognormal_k, uniform_vector, affine_k, tensor_K,
+                        tensor_fields)
 from oracle import oracle as O
 
 torch = pytest.importorskip("torch")
@@ -163,6 +164,52 @@ def test_apply_stored_matches_oracle(mesh_fn, level, kfun):
     got = ctx.to_canonical(level, y).cpu().numpy()
     ref = O.make_operator(om, k2, "scaled", modification=True).apply(u)
     assert _rel(got, ref) <= TOL64, _rel(got, ref)
+
+
+@pytest.mark.parametrize("mesh_fn,level", [(unit_tet, 4), (kuhn_cube, 3), (cube12, 3), (kuhn_cube_2x2x2, 3),
+                                           (flat_tet, 4)])
+def test_apply_tensor_matches_oracle(mesh_fn, level):
+    """Sec. 2.1 eq. (integral), six components each scaled, on a rotating SPD K
+    field: FP64 at the finest and the next coarser level (fields injected),
+    FP32."""
+    X, T = mesh_fn()
+    ctx = hhg.Context(X, T, level)
+    with pytest.raises(hhg.HHGError):
+        ctx.apply_tensor(level, ctx.vector(level), ctx.vector(level))
+    om = O.Mesh(X, T, level)
+    ctx.set_tensor_coefficient(tensor_fields(tensor_K(om.xyz)))
+    for lv in (level, level - 1):
+        m = O.Mesh(X, T, lv)
+        K6 = tensor_fields(tensor_K(m.xyz))
+        u = uniform_vector(m.n_nodes, seed=3)
+        u[m.dirichlet] = 0.0
+        y = ctx.vector(lv)
+        ctx.apply_tensor(lv, ctx.from_canonical(lv, _dev(u)), y)
+        got = ctx.to_canonical(lv, y).cpu().numpy()
+        ref = O.make_tensor_operator(m, K6).apply(u)
+        assert _rel(got, ref) <= TOL64 and _elem(got, ref) <= TOL64, (lv, _rel(got, ref), _elem(got, ref))
+        assert np.all(got[m.dirichlet] == 0.0)
+    y32 = ctx.vector(level, torch.float32)
+    u = uniform_vector(om.n_nodes, seed=3)
+    u[om.dirichlet] = 0.0
+    ctx.apply_tensor(level, ctx.from_canonical(level, _dev(u, torch.float32)), y32)
+    got = ctx.to_canonical(level, y32).cpu().numpy().astype(np.float64)
+    ref = O.make_tensor_operator(om, tensor_fields(tensor_K(om.xyz))).apply(u)
+    assert _rel(got, ref) <= 4e-6, _rel(got, ref)
+
+
+def test_apply_tensor_with_scalar_K_is_apply_scaled():
+    """K = k I reduces the tensor operator to -div(k grad u)."""
+    X, T = cube12()
+    level = 4
+    om, k, u, ctx = _setup(cube12, level, kfun=lambda x: lognormal_k(x, lognormal_params(6, 1.0, 0.2)),
+                           flags=hhg.FLAG_NO_MODIFICATION)
+    ctx.set_tensor_coefficient(tensor_fields(k[:, None, None] * np.eye(3)[None]))
+    ud = ctx.from_canonical(level, _dev(u))
+    y1, y2 = ctx.vector(level), ctx.vector(level)
+    ctx.apply_tensor(level, ud, y1)
+    ctx.apply_scaled(level, ud, y2)
+    assert ((y1 - y2).abs().max() / y2.abs().max()).item() <= 1e-13
 
 
 @pytest.mark.parametrize("mesh_fn,level", [(unit_tet, 5), (kuhn_cube_2x2x2, 3)])
