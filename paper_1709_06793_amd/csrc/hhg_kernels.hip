@@ -1457,9 +1457,17 @@ __global__ __launch_bounds__(BLOCK) void k_stored_apply(LevelView<T> L, const T 
 // per in-plane offset, neighbour slots from the plane size), inter-tet rows
 // as the sum of their copies' tet-restricted stencils.
 template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_tensor_interior(LevelView<T> L, const T *__restrict__ u,
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void k_tensor_interior(
+    LevelView<T> L, const T *__restrict__ u,
                                                             T *__restrict__ y, int n_seg)
 {
+    // the interior (kind 0) weights of the six components, once per block
+    __shared__ T ws[6 * NDIR];
+    if (threadIdx.x < 6 * NDIR) {
+        const int m = threadIdx.x / NDIR, d = threadIdx.x - m * NDIR;
+        ws[threadIdx.x] = L.tsten[((int64_t)blockIdx.y * 6 + m) * TET_STENCIL + d];
+    }
+    __syncthreads();
     int t, sd, k0, k1, tet;
     const int n = L.n;
     if (!stored_lane(n, n_seg, t, sd, k0, k1, tet)) return;
@@ -1467,8 +1475,8 @@ __global__ __launch_bounds__(BLOCK) void k_tensor_interior(LevelView<T> L, const
     if (i < 1 || j < 1) return;
     const int64_t base = (int64_t)tet * L.Spad, ns = (int64_t)L.n_tet * L.Spad;
     const T *__restrict__ ub = u + base;
-    const T *__restrict__ w = L.tsten + (int64_t)tet * 6 * TET_STENCIL;  // kind 0 of each component
     const int Sn = tc32(n);
+#pragma unroll 1
     for (int k = k0; k <= min(k1, n - 1 - sd); ++k) {
         const int s = Sn - tc32(n - k) + t;
         int nb[NDIR];
@@ -1478,12 +1486,22 @@ __global__ __launch_bounds__(BLOCK) void k_tensor_interior(LevelView<T> L, const
 #pragma unroll
         for (int d = 0; d < NDIR; ++d) du[d] = ub[nb[d]] - u0;
         T acc = T(0);
-        for (int m = 0; m < 6; ++m) {
-            const T *__restrict__ km = L.kt + m * ns + base;
-            const T *__restrict__ wm = w + m * TET_STENCIL;
-            const T k0v = km[s];
+        // two components per batch: 30 loads in flight per row
+#pragma unroll 1
+        for (int m = 0; m < 6; m += 2) {
+            T kv[2][NDIR + 1];
 #pragma unroll
-            for (int d = 0; d < NDIR; ++d) acc += wm[d] * (k0v + km[nb[d]]) * du[d];
+            for (int q = 0; q < 2; ++q) {
+                const T *__restrict__ km = L.kt + (m + q) * ns + base;
+                kv[q][NDIR] = km[s];
+#pragma unroll
+                for (int d = 0; d < NDIR; ++d) kv[q][d] = km[nb[d]];
+            }
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int d = 0; d < NDIR; ++d)
+                    acc += ws[(m + q) * NDIR + d] * (kv[q][NDIR] + kv[q][d]) * du[d];
         }
         y[base + s] = acc;
     }
