@@ -177,6 +177,13 @@ hhg_status hhg_set_tensor_coefficient(hhg_ctx ctx, const double *k6, int on_devi
  * rules as hhg_apply_scaled; HHG_ESTATE before hhg_set_tensor_coefficient. */
 hhg_status hhg_apply_tensor(hhg_ctx ctx, int32_t level, hhg_dtype dtype, const void *u, void *y,
                             void *stream);
+/* y = A~_K u, the comparison form of hhg_apply_tensor: every component
+ * nodally integrated (eq. (standardfe) applied to each a_m): element t
+ * contributes (mean of k_m over t's vertices) times its element matrix of
+ * a_m, summed over m.  Same vector rules and state requirement as
+ * hhg_apply_tensor. */
+hhg_status hhg_apply_tensor_nodal(hhg_ctx ctx, int32_t level, hhg_dtype dtype, const void *u, void *y,
+                                  void *stream);
 /* Stored stencils: the memory-bound baseline that stencil scaling avoids
  * (Sec. 6.4, the stored-stencil load model: 15 values per node).  Allocates
  * (first call; 15 FP64 + 15 FP32 values per slot of `level`) and fills the

@@ -185,13 +185,10 @@ def tensor_element_matrices(xyz, conn):
     return vol[None, :, None, None] * D[:, :, :, None] * D[:, :, None, :], G, vol
 
 
-def assemble_tensor(mesh, K6, kind="scaled"):
-    """Global matrix over all nodes of sum_m a_m (Sec. 2.1 eq. (integral)) with
-    the six coefficient fields K6 (6, n_nodes): per component, scaled =
-    off-diagonal factor (k_m,a + k_m,b)/2 and zero element row sums (the scalar
-    form of Lemma 3.2 applied to a_m), nodal = mean vertex k_m times A^m_t."""
-    conn, _ = mesh.elements()
-    Am, _, _ = tensor_element_matrices(mesh.xyz, conn)
+def _tensor_element_blocks(xyz, conn, K6, kind):
+    """Per-element 4x4 blocks of sum_m a_m for the elements conn (see
+    assemble_tensor for the two forms)."""
+    Am, _, _ = tensor_element_matrices(xyz, conn)
     KA = np.zeros(Am.shape[1:])
     idx = np.arange(4)
     for m in range(6):
@@ -203,6 +200,36 @@ def assemble_tensor(mesh, K6, kind="scaled"):
             T[:, idx, idx] = 0.0
             T[:, idx, idx] = -T.sum(axis=2)
             KA += T
+    return KA
+
+
+def apply_tensor_rows(mesh, K6_at, u, nodes, kind="scaled"):
+    """(A_K u)_p of the tensor operator for the given nodes, each row summed
+    from the elements holding that node only (for sizes the full assembly
+    cannot reach).  K6_at maps points (n, 3) to the six fields (6, n) there;
+    u's Dirichlet entries read as 0, Dirichlet rows 0."""
+    uu = np.where(mesh.dirichlet, 0.0, u)
+    res = np.zeros(len(nodes))
+    for i, p in enumerate(nodes):
+        if mesh.dirichlet[p]:
+            continue
+        conn, _ = mesh.incident(p)
+        loc = np.unique(conn)
+        xl = mesh.xyz[loc]
+        cl = np.searchsorted(loc, conn)
+        KA = _tensor_element_blocks(xl, cl, K6_at(xl), kind)
+        a = np.argmax(conn == p, axis=1)
+        res[i] = float(np.einsum("eb,eb->", KA[np.arange(conn.shape[0]), a], uu[conn]))
+    return res
+
+
+def assemble_tensor(mesh, K6, kind="scaled"):
+    """Global matrix over all nodes of sum_m a_m (Sec. 2.1 eq. (integral)) with
+    the six coefficient fields K6 (6, n_nodes): per component, scaled =
+    off-diagonal factor (k_m,a + k_m,b)/2 and zero element row sums (the scalar
+    form of Lemma 3.2 applied to a_m), nodal = mean vertex k_m times A^m_t."""
+    conn, _ = mesh.elements()
+    KA = _tensor_element_blocks(mesh.xyz, conn, K6, kind)
     rows = np.repeat(conn, 4, axis=1).ravel()
     cols = np.tile(conn, (1, 4)).ravel()
     M = sp.coo_matrix((KA.ravel(), (rows, cols)), shape=(mesh.n_nodes, mesh.n_nodes)).tocsr()

@@ -244,15 +244,19 @@ struct Level {
     int sh_w = 0;
     int64_t *sh_nb = nullptr, *sh_self = nullptr, *sh_cslot = nullptr;
     int8_t *sh_map = nullptr;  // [copy][16]: entry of direction d, -1 if none
+    // the same for the tensor operator's (wider) pattern
+    int sh_wt = 0;
+    int64_t *sh_nbt = nullptr;
+    int8_t *sh_mapt = nullptr;
     std::vector<uint8_t> h_sh_prim;  // macro primitive of each shared node (1 vertex, 2 edge, 4 face)
     uint8_t *sh_prim = nullptr;
-    double *sh_cs64 = nullptr, *sh_cn64 = nullptr;
-    float *sh_cs32 = nullptr, *sh_cn32 = nullptr;
+    double *sh_cs64 = nullptr, *sh_cn64 = nullptr, *sh_ct64 = nullptr, *sh_ctn64 = nullptr;
+    float *sh_cs32 = nullptr, *sh_cn32 = nullptr, *sh_ct32 = nullptr, *sh_ctn32 = nullptr;
     // coefficient dependent
     // tensor operator: per-tet component stencils and the six coefficient fields
-    std::vector<double> h_tsten;
-    double *tsten64 = nullptr, *kt64 = nullptr;
-    float *tsten32 = nullptr, *kt32 = nullptr;
+    std::vector<double> h_tsten, h_temat;
+    double *tsten64 = nullptr, *kt64 = nullptr, *kp64 = nullptr, *temat64 = nullptr;
+    float *tsten32 = nullptr, *kt32 = nullptr, *kp32 = nullptr, *temat32 = nullptr;
     double *k64 = nullptr, *invd64 = nullptr;
     float *k32 = nullptr, *invd32 = nullptr;
     double lam = 0.0;
@@ -511,7 +515,8 @@ LevelView<double> view<double>(const hhg_ctx c, int l)
     v.items = L.items; v.n_items = L.n_items; v.vpt = (L.n_items + 3) / 4;
     v.sh_w = L.sh_w; v.sh_nb = L.sh_nb; v.sh_self = L.sh_self; v.sh_cslot = L.sh_cslot;
     v.sh_cs = L.sh_cs64; v.sh_cn = L.sh_cn64; v.sh_prim = L.sh_prim;
-    v.tsten = L.tsten64; v.kt = L.kt64;
+    v.sh_wt = L.sh_wt; v.sh_nbt = L.sh_nbt; v.sh_ct = L.sh_ct64; v.sh_ctn = L.sh_ctn64;
+    v.tsten = L.tsten64; v.kt = L.kt64; v.kp = L.kp64; v.temat = L.temat64;
     v.items2 = L.items2; v.n_items2 = L.n_items2; v.vpt2 = (L.n_items2 + 3) / 4;
     v.itemsL = L.itemsL; v.n_itemsL = L.n_itemsL;
     v.bnd = L.bnd; v.n_bnd = L.n_bnd; v.bpt2 = (L.n_bnd + BLOCK - 1) / BLOCK;
@@ -529,7 +534,8 @@ LevelView<float> view<float>(const hhg_ctx c, int l)
     v.items = L.items; v.n_items = L.n_items; v.vpt = (L.n_items + 3) / 4;
     v.sh_w = L.sh_w; v.sh_nb = L.sh_nb; v.sh_self = L.sh_self; v.sh_cslot = L.sh_cslot;
     v.sh_cs = L.sh_cs32; v.sh_cn = L.sh_cn32; v.sh_prim = L.sh_prim;
-    v.tsten = L.tsten32; v.kt = L.kt32;
+    v.sh_wt = L.sh_wt; v.sh_nbt = L.sh_nbt; v.sh_ct = L.sh_ct32; v.sh_ctn = L.sh_ctn32;
+    v.tsten = L.tsten32; v.kt = L.kt32; v.kp = L.kp32; v.temat = L.temat32;
     v.items2 = L.items2f; v.n_items2 = L.n_items2f; v.vpt2 = (L.n_items2f + 3) / 4;
     v.itemsL = L.itemsL; v.n_itemsL = 0;
     v.bnd = L.bnd; v.n_bnd = L.n_bnd; v.bpt2 = (L.n_bnd + BLOCK - 1) / BLOCK;
@@ -664,6 +670,7 @@ hhg_status build_level(hhg_ctx c, int l)
     {
         static const double CD[6][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {1, 1, 0}, {1, 0, 1}, {0, 1, 1}};
         L.h_tsten.assign((size_t)tp.nt * 6 * TET_STENCIL, 0.0);
+        L.h_temat.assign((size_t)tp.nt * 6 * TET_EMAT, 0.0);
         for (int t = 0; t < tp.nt; ++t)
             for (int m = 0; m < 6; ++m) {
                 double E[NTYPE][4][4];
@@ -672,6 +679,9 @@ hhg_status build_level(hhg_ctx c, int l)
                     for (int a = 0; a < 4; ++a)
                         lattice_point(tp, t, L.n, TYPE_OFF[ty][a][0], TYPE_OFF[ty][a][1], TYPE_OFF[ty][a][2], p[a]);
                     if (!element_matrix_dir(p, CD[m], E[ty])) return fail(c, HHG_EMESH, "tet %d is degenerate", t);
+                    for (int a = 0; a < 4; ++a)
+                        for (int b = 0; b < 4; ++b)
+                            L.h_temat[((size_t)t * 6 + m) * TET_EMAT + ty * 16 + a * 4 + b] = E[ty][a][b] / 4.0;
                 }
                 for (int zp = 0; zp < 15; ++zp) {
                     if (popcount4(zp) == 4) continue;
@@ -694,6 +704,12 @@ hhg_status build_level(hhg_ctx c, int l)
                     for (int d = 0; d < NDIR; ++d) row[d] = 0.5 * st[d];
                     row[NDIR] = st[NDIR];
                 }
+                // the interior rows' pair fields take w_d = w_{d+7}
+                const double *w0 = &L.h_tsten[((size_t)t * 6 + m) * TET_STENCIL];
+                for (int d = 0; d < NDIR / 2; ++d)
+                    if (std::fabs(w0[d] - w0[d + NDIR / 2]) > 1e-12 * (std::fabs(w0[d]) + std::fabs(w0[d + NDIR / 2])))
+                        return fail(c, HHG_EMESH, "tet %d: interior stencil of component %d is not point-symmetric",
+                                    t, m);
             }
     }
     // nodes on shared primitives: every non-Dirichlet vertex / edge / face of
@@ -793,12 +809,45 @@ hhg_status build_level(hhg_ctx c, int l)
                     }
             }
         }
+        // the tensor operator's pattern: every component's tet-restricted
+        // weights and element matrices (wider than the scalar one where a
+        // component couples a direction the scalar stencil does not)
+        std::vector<uint8_t> need_t((size_t)tp.nt * 16 * NDIR, 0);
+        for (int t = 0; t < tp.nt; ++t) {
+            double ms = 0.0, me = 0.0;
+            for (int q = 0; q < 6 * TET_STENCIL; ++q)
+                ms = std::max(ms, std::fabs(L.h_tsten[(size_t)t * 6 * TET_STENCIL + q]));
+            for (int q = 0; q < 6 * TET_EMAT; ++q) me = std::max(me, std::fabs(L.h_temat[(size_t)t * 6 * TET_EMAT + q]));
+            for (int zp = 0; zp < 15; ++zp) {
+                if (popcount4(zp) == 4) continue;
+                uint8_t *nd = &need_t[((size_t)t * 16 + zp) * NDIR];
+                for (int m = 0; m < 6; ++m) {
+                    const double *row = &L.h_tsten[((size_t)t * 6 + m) * TET_STENCIL + zp * KIND_STRIDE];
+                    for (int d = 0; d < NDIR; ++d)
+                        if (std::fabs(row[d]) > 1e-14 * ms) nd[d] = 1;
+                }
+                int ri, rj, rk;
+                representative(zp, ri, rj, rk);
+                for (int ty = 0; ty < NTYPE; ++ty)
+                    for (int a = 0; a < 4; ++a) {
+                        if (!element_valid(8, ri - TYPE_OFF[ty][a][0], rj - TYPE_OFF[ty][a][1],
+                                           rk - TYPE_OFF[ty][a][2], ty))
+                            continue;
+                        for (int b = 0; b < 4; ++b) {
+                            if (b == a) continue;
+                            const int d = dir_index(TYPE_OFF[ty][b][0] - TYPE_OFF[ty][a][0],
+                                                    TYPE_OFF[ty][b][1] - TYPE_OFF[ty][a][1],
+                                                    TYPE_OFF[ty][b][2] - TYPE_OFF[ty][a][2]);
+                            for (int m = 0; m < 6; ++m)
+                                if (std::fabs(L.h_temat[((size_t)t * 6 + m) * TET_EMAT + ty * 16 + a * 4 + b]) >
+                                    1e-14 * me)
+                                    nd[d] = 1;
+                        }
+                    }
+            }
+        }
         const int64_t ncopy = (int64_t)L.h_sh_copy.size();
-        std::vector<int8_t> hmap((size_t)ncopy * 16, -1);
         std::vector<int64_t> hcslot(ncopy), hself(L.n_shared);
-        std::vector<int32_t> ecount(L.n_shared);
-        std::vector<int64_t> enb;  // entries of all nodes, node after node
-        enb.reserve((size_t)L.n_shared * 8);
         struct Key { int v[4], w[4]; };
         auto key_of = [&](int t, int i, int j, int k, Key &K) {
             const int wt[4] = {L.n - i - j - k, i, j, k};
@@ -817,39 +866,61 @@ hhg_status build_level(hhg_ctx c, int l)
                 if (A.v[a] != B.v[a] || A.w[a] != B.w[a]) return false;
             return true;
         };
-        int width = 0;
-        std::vector<Key> keys;
-        std::vector<int64_t> slots;
-        for (int q = 0; q < L.n_shared; ++q) {
-            keys.clear();
-            slots.clear();
-            for (int p = L.h_sh_off[q]; p < L.h_sh_off[q + 1]; ++p) {
-                int t, kind, i, j, k;
-                unpack_copy(L.h_sh_copy[p], t, kind, i, j, k);
-                hcslot[p] = (int64_t)t * L.Spad + slot_of(L.n, i, j, k);
-                if (p == L.h_sh_off[q]) hself[q] = hcslot[p];
-                const uint8_t *nd = &need[((size_t)t * 16 + kind) * NDIR];
-                for (int d = 0; d < NDIR; ++d) {
-                    const int i2 = i + DIR[d][0], j2 = j + DIR[d][1], k2 = k + DIR[d][2];
-                    if (!nd[d] || !in_lattice(L.n, i2, j2, k2)) continue;
-                    Key K;
-                    key_of(t, i2, j2, k2, K);
-                    int m = -1;
-                    for (size_t e = 0; e < keys.size(); ++e)
-                        if (same(keys[e], K)) { m = (int)e; break; }
-                    if (m < 0) {
-                        m = (int)keys.size();
-                        keys.push_back(K);
-                        slots.push_back((int64_t)t * L.Spad + slot_of(L.n, i2, j2, k2));
+        // one merged pattern per `need`: map[copy][d] = entry, the ELL table of
+        // neighbour slots (padding entries = the node itself) and its width
+        auto build_ell = [&](const std::vector<uint8_t> &need, std::vector<int8_t> &hmap, std::vector<int64_t> &ell,
+                             int &width) -> hhg_status {
+            hmap.assign((size_t)ncopy * 16, -1);
+            std::vector<int32_t> ecount(L.n_shared);
+            std::vector<int64_t> enb;  // entries of all nodes, node after node
+            enb.reserve((size_t)L.n_shared * 8);
+            width = 0;
+            std::vector<Key> keys;
+            std::vector<int64_t> slots;
+            for (int q = 0; q < L.n_shared; ++q) {
+                keys.clear();
+                slots.clear();
+                for (int p = L.h_sh_off[q]; p < L.h_sh_off[q + 1]; ++p) {
+                    int t, kind, i, j, k;
+                    unpack_copy(L.h_sh_copy[p], t, kind, i, j, k);
+                    hcslot[p] = (int64_t)t * L.Spad + slot_of(L.n, i, j, k);
+                    if (p == L.h_sh_off[q]) hself[q] = hcslot[p];
+                    const uint8_t *nd = &need[((size_t)t * 16 + kind) * NDIR];
+                    for (int d = 0; d < NDIR; ++d) {
+                        const int i2 = i + DIR[d][0], j2 = j + DIR[d][1], k2 = k + DIR[d][2];
+                        if (!nd[d] || !in_lattice(L.n, i2, j2, k2)) continue;
+                        Key K;
+                        key_of(t, i2, j2, k2, K);
+                        int m = -1;
+                        for (size_t e = 0; e < keys.size(); ++e)
+                            if (same(keys[e], K)) { m = (int)e; break; }
+                        if (m < 0) {
+                            m = (int)keys.size();
+                            keys.push_back(K);
+                            slots.push_back((int64_t)t * L.Spad + slot_of(L.n, i2, j2, k2));
+                        }
+                        if (m > 127) return fail(c, HHG_EMESH, "shared node with more than 128 neighbours");
+                        hmap[(size_t)p * 16 + d] = (int8_t)m;
                     }
-                    if (m > 127) return fail(c, HHG_EMESH, "shared node with more than 128 neighbours");
-                    hmap[(size_t)p * 16 + d] = (int8_t)m;
                 }
+                ecount[q] = (int32_t)keys.size();
+                width = std::max(width, (int)keys.size());
+                enb.insert(enb.end(), slots.begin(), slots.end());
             }
-            ecount[q] = (int32_t)keys.size();
-            width = std::max(width, (int)keys.size());
-            enb.insert(enb.end(), slots.begin(), slots.end());
-        }
+            ell.assign((size_t)width * L.n_shared, 0);
+            int64_t pos = 0;
+            for (int q = 0; q < L.n_shared; ++q) {
+                for (int m = 0; m < width; ++m)
+                    ell[(size_t)m * L.n_shared + q] = m < ecount[q] ? enb[pos + m] : hself[q];
+                pos += ecount[q];
+            }
+            return HHG_OK;
+        };
+        std::vector<int8_t> hmap, hmap_t;
+        std::vector<int64_t> ell, ell_t;
+        int width = 0, width_t = 0;
+        TRY(build_ell(need, hmap, ell, width));
+        TRY(build_ell(need_t, hmap_t, ell_t, width_t));
         L.sh_w = width;
         // macro primitive of each shared node from the zero pattern of its
         // barycentric weights: three zero weights = vertex, two = edge, one = face
@@ -865,14 +936,10 @@ hhg_status build_level(hhg_ctx c, int l)
             if (cp.empty()) cp.assign(1, 0);
             TRY(upload(c, &L.sh_prim, cp));
         }
-        std::vector<int64_t> ell((size_t)width * L.n_shared);
-        int64_t pos = 0;
-        for (int q = 0; q < L.n_shared; ++q) {
-            for (int m = 0; m < width; ++m)
-                ell[(size_t)m * L.n_shared + q] = m < ecount[q] ? enb[pos + m] : hself[q];
-            pos += ecount[q];
-        }
+        L.sh_wt = width_t;
         TRY(upload(c, &L.sh_nb, ell));
+        TRY(upload(c, &L.sh_nbt, ell_t));
+        TRY(upload(c, &L.sh_mapt, hmap_t));
         TRY(upload(c, &L.sh_self, hself));
         TRY(upload(c, &L.sh_cslot, hcslot));
         TRY(upload(c, &L.sh_map, hmap));
@@ -976,9 +1043,11 @@ hhg_status build_level(hhg_ctx c, int l)
         r32(L.h_rstw.begin(), L.h_rstw.end());
     TRY(upload(c, &L.sten64, L.h_sten));
     {
-        std::vector<float> t32(L.h_tsten.begin(), L.h_tsten.end());
+        std::vector<float> t32(L.h_tsten.begin(), L.h_tsten.end()), te32(L.h_temat.begin(), L.h_temat.end());
         TRY(upload(c, &L.tsten64, L.h_tsten));
         TRY(upload(c, &L.tsten32, t32));
+        TRY(upload(c, &L.temat64, L.h_temat));
+        TRY(upload(c, &L.temat32, te32));
     }
     TRY(upload(c, &L.emat64, L.h_emat));
     TRY(upload(c, &L.rstw64, L.h_rstw));
@@ -1851,6 +1920,13 @@ hhg_status hhg_set_tensor_coefficient(hhg_ctx c, const double *k6, int on_device
         if (!L.kt64) {
             TRY(dalloc(c, &L.kt64, 6 * L.n_slots));
             TRY(dalloc(c, &L.kt32, 6 * L.n_slots));
+            TRY(dalloc(c, &L.kp64, NDIR / 2 * L.n_slots));
+            TRY(dalloc(c, &L.kp32, NDIR / 2 * L.n_slots));
+            const int64_t ne = (int64_t)L.sh_wt * L.n_shared;
+            TRY(dalloc(c, &L.sh_ct64, ne));
+            TRY(dalloc(c, &L.sh_ctn64, ne));
+            TRY(dalloc(c, &L.sh_ct32, ne));
+            TRY(dalloc(c, &L.sh_ctn32, ne));
         }
     }
     double *dk = nullptr;
@@ -1872,8 +1948,18 @@ hhg_status hhg_set_tensor_coefficient(hhg_ctx c, const double *k6, int on_device
                                             Lc.Spad, st));
         }
     }
-    for (int l = 0; l <= Lmax; ++l)
-        HIPCHK(c, launch_convert<double, float>(c->lv[l].kt64, c->lv[l].kt32, 6 * c->lv[l].n_slots, st));
+    for (int l = 0; l <= Lmax; ++l) {
+        Level &L = c->lv[l];
+        HIPCHK(c, launch_convert<double, float>(L.kt64, L.kt32, 6 * L.n_slots, st));
+        HIPCHK(c, launch_tensor_pairs(view<double>(c, l), L.kp64, st));
+        HIPCHK(c, launch_convert<double, float>(L.kp64, L.kp32, NDIR / 2 * L.n_slots, st));
+        if (L.n_shared > 0) {
+            const int64_t ne = (int64_t)L.sh_wt * L.n_shared;
+            HIPCHK(c, launch_tensor_shared_coef(view<double>(c, l), L.sh_mapt, L.sh_ct64, L.sh_ctn64, st));
+            HIPCHK(c, launch_convert<double, float>(L.sh_ct64, L.sh_ct32, ne, st));
+            HIPCHK(c, launch_convert<double, float>(L.sh_ctn64, L.sh_ctn32, ne, st));
+        }
+    }
     HIPCHK(c, hipStreamSynchronize(st));
     dfree(c, dk);
     c->have_tk = true;
@@ -1888,6 +1974,20 @@ hhg_status hhg_apply_tensor(hhg_ctx c, int32_t level, hhg_dtype dt, const void *
     hipStream_t st = pick(c, stream);
     if (dt == HHG_F64) HIPCHK(c, launch_tensor<double>(view<double>(c, level), (const double *)u, (double *)y, st));
     else if (dt == HHG_F32) HIPCHK(c, launch_tensor<float>(view<float>(c, level), (const float *)u, (float *)y, st));
+    else return fail(c, HHG_EINVAL, "bad dtype");
+    return HHG_OK;
+}
+
+hhg_status hhg_apply_tensor_nodal(hhg_ctx c, int32_t level, hhg_dtype dt, const void *u, void *y, void *stream)
+{
+    TRY(check_level(c, level));
+    if (!c->have_tk) return fail(c, HHG_ESTATE, "no tensor coefficient set");
+    if (!u || !y || u == y) return fail(c, HHG_EINVAL, "u and y must be distinct non-NULL vectors");
+    hipStream_t st = pick(c, stream);
+    if (dt == HHG_F64)
+        HIPCHK(c, launch_tensor_nodal<double>(view<double>(c, level), (const double *)u, (double *)y, st));
+    else if (dt == HHG_F32)
+        HIPCHK(c, launch_tensor_nodal<float>(view<float>(c, level), (const float *)u, (float *)y, st));
     else return fail(c, HHG_EINVAL, "bad dtype");
     return HHG_OK;
 }

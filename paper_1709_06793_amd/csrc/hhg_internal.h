@@ -56,11 +56,26 @@ struct LevelView {
     const T *sh_cs;           // scaled-operator coefficients
     const T *sh_cn;           // nodal-operator coefficients
     const uint8_t *sh_prim;   // macro primitive of node q: 1 vertex, 2 edge, 4 face
+    // tensor operator: its own (wider) pattern sh_wt / sh_nbt in the same
+    // layout, coefficients with every component scaled (sh_ct) or nodally
+    // integrated (sh_ctn)
+    int sh_wt;
+    const int64_t *sh_nbt;
+    const T *sh_ct;
+    const T *sh_ctn;
     // tensor operator: [tet][6 components][16 kinds][16] half reference entries
     // of the components D_m = c_m.grad, and the six coefficient fields
     // (component m at kt + m * n_tet * Spad), null until set
     const T *tsten;
     const T *kt;
+    // the same operator's interior rows as seven direction-pair fields per
+    // slot, K_p = sum_m w^m_p k_m with the tet's interior weights (pair p =
+    // directions p and p + 7, whose interior weights agree): pair p at
+    // kp + p * n_tet * Spad
+    const T *kp;
+    // [tet][6 components][6 types][4][4]: element matrices of the components / 4
+    // (nodal-integration tensor operator)
+    const T *temat;
 };
 
 // sparse corrections of the modification (Sec. 4.1) at one level
@@ -105,11 +120,20 @@ hipError_t launch_store_stencils(const LevelView<double> &L, T *st, hipStream_t 
 template <typename T>
 hipError_t launch_stored(const LevelView<T> &L, const CorrView<T> &C, const T *st, const T *u, T *y,
                          hipStream_t strm);
+// direction-pair fields K_p of the tensor operator from its component fields
+hipError_t launch_tensor_pairs(const LevelView<double> &L, double *kp, hipStream_t st);
+// merged shared-row coefficients of both tensor forms
+hipError_t launch_tensor_shared_coef(const LevelView<double> &L, const int8_t *map, double *cs, double *cn,
+                                     hipStream_t st);
 // tensor-coefficient operator (Sec. 2.1 eq. (integral)), every component
-// scaled: interior rows, inter-tet rows (sum over the copies' tet-restricted
-// stencils) and Dirichlet zeros
+// scaled: interior rows, inter-tet rows (merged coefficients) and Dirichlet
+// zeros
 template <typename T>
 hipError_t launch_tensor(const LevelView<T> &L, const T *u, T *y, hipStream_t st);
+// the same operator with every component nodally integrated (eq. (standardfe)
+// per component): interior rows, inter-tet rows, Dirichlet zeros
+template <typename T>
+hipError_t launch_tensor_nodal(const LevelView<T> &L, const T *u, T *y, hipStream_t st);
 // the primitive-mixed operator (Sec. 5 eq. (modst)): nodal-integration rows
 // for the nodes of the primitives in nodal_mask (1 vertices, 2 edges, 4
 // faces), scaled rows (with their modification corrections) elsewhere

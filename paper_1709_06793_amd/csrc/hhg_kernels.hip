@@ -1453,20 +1453,73 @@ __global__ __launch_bounds__(BLOCK) void k_stored_apply(LevelView<T> L, const T 
 // ---------------------------------------------------------------- tensor coefficient
 // Row of node 0: sum_m sum_d w^m_d (k_m,0 + k_m,d) (u_d - u_0) with the
 // half reference entries w^m of component m (Sec. 2.1 eq. (integral), each
-// a_m scaled as the scalar form).  Interior rows by column marching (a lane
-// per in-plane offset, neighbour slots from the plane size), inter-tet rows
-// as the sum of their copies' tet-restricted stencils.
+// a_m scaled as the scalar form).  On interior rows w^m_d = w^m_{d+7}, so the
+// coefficient of direction d is K_p(node 0) + K_p(node d) with the pair field
+// K_p = sum_m w^m_p k_m (p = d mod 7), formed once per coefficient: seven
+// fields and 28 neighbour gathers per row instead of six fields and 90.
+// Inter-tet rows take merged coefficients (k_tensor_shared_coef) like the
+// scalar operator's.
+__global__ void k_tensor_pairs(LevelView<double> L, double *__restrict__ kp)
+{
+    const int64_t ns = (int64_t)L.n_tet * L.Spad;
+    const int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (e >= ns) return;
+    const int tet = (int)(e / L.Spad);
+    double km[6];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) km[m] = L.kt[m * ns + e];
+#pragma unroll
+    for (int p = 0; p < NDIR / 2; ++p) {
+        double acc = 0.0;
+#pragma unroll
+        for (int m = 0; m < 6; ++m) acc += L.tsten[((int64_t)tet * 6 + m) * TET_STENCIL + p] * km[m];
+        kp[p * ns + e] = acc;
+    }
+}
+
 template <typename T>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void k_tensor_interior(
-    LevelView<T> L, const T *__restrict__ u,
+__global__ __launch_bounds__(BLOCK) void k_tensor_interior(LevelView<T> L, const T *__restrict__ u,
                                                             T *__restrict__ y, int n_seg)
 {
-    // the interior (kind 0) weights of the six components, once per block
-    __shared__ T ws[6 * NDIR];
-    if (threadIdx.x < 6 * NDIR) {
-        const int m = threadIdx.x / NDIR, d = threadIdx.x - m * NDIR;
-        ws[threadIdx.x] = L.tsten[((int64_t)blockIdx.y * 6 + m) * TET_STENCIL + d];
+    int t, sd, k0, k1, tet;
+    const int n = L.n;
+    if (!stored_lane(n, n_seg, t, sd, k0, k1, tet)) return;
+    const int i = t - sd * (sd + 1) / 2, j = sd - i;
+    if (i < 1 || j < 1) return;
+    const int64_t base = (int64_t)tet * L.Spad, ns = (int64_t)L.n_tet * L.Spad;
+    const T *__restrict__ ub = u + base;
+    const T *__restrict__ kb = L.kp + base;
+    const int Sn = tc32(n);
+#pragma unroll 2
+    for (int k = k0; k <= min(k1, n - 1 - sd); ++k) {
+        const int s = Sn - tc32(n - k) + t;
+        int nb[NDIR];
+        neighbour_slots(s, sd, n - k, nb);
+        const T u0 = ub[s];
+        T acc = T(0);
+#pragma unroll
+        for (int p = 0; p < NDIR / 2; ++p) {
+            const T *__restrict__ kq = kb + p * ns;
+            const int a = nb[p], b = nb[p + NDIR / 2];
+            const T c0 = kq[s];
+            acc += (c0 + kq[a]) * (ub[a] - u0) + (c0 + kq[b]) * (ub[b] - u0);
+        }
+        y[base + s] = acc;
     }
+}
+
+// Nodal-integration tensor operator: per component the row of eq.
+// (standardfe) with that component's element matrices and field, summed over
+// the six components.  Interior rows gather u and each k_m over the 15-point
+// neighbourhood (all 24 incident elements lie in the tet); inter-tet rows take
+// merged coefficients (k_tensor_shared_coef).
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_tensor_nodal_interior(LevelView<T> L, const T *__restrict__ u,
+                                                                  T *__restrict__ y, int n_seg)
+{
+    __shared__ T es[6 * TET_EMAT];
+    for (int q = threadIdx.x; q < 6 * TET_EMAT; q += BLOCK)
+        es[q] = L.temat[(int64_t)blockIdx.y * 6 * TET_EMAT + q];
     __syncthreads();
     int t, sd, k0, k1, tet;
     const int n = L.n;
@@ -1481,60 +1534,91 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
         const int s = Sn - tc32(n - k) + t;
         int nb[NDIR];
         neighbour_slots(s, sd, n - k, nb);
-        const T u0 = ub[s];
-        T du[NDIR];
+        T uu[NDIR + 1];
 #pragma unroll
-        for (int d = 0; d < NDIR; ++d) du[d] = ub[nb[d]] - u0;
+        for (int d = 0; d < NDIR; ++d) uu[d] = ub[nb[d]];
+        uu[NDIR] = ub[s];
         T acc = T(0);
-        // two components per batch: 30 loads in flight per row
 #pragma unroll 1
-        for (int m = 0; m < 6; m += 2) {
-            T kv[2][NDIR + 1];
+        for (int m = 0; m < 6; ++m) {
+            const T *__restrict__ km = L.kt + m * ns + base;
+            T kk[NDIR + 1];
 #pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const T *__restrict__ km = L.kt + (m + q) * ns + base;
-                kv[q][NDIR] = km[s];
-#pragma unroll
-                for (int d = 0; d < NDIR; ++d) kv[q][d] = km[nb[d]];
-            }
-#pragma unroll
-            for (int q = 0; q < 2; ++q)
-#pragma unroll
-                for (int d = 0; d < NDIR; ++d)
-                    acc += ws[(m + q) * NDIR + d] * (kv[q][NDIR] + kv[q][d]) * du[d];
+            for (int d = 0; d < NDIR; ++d) kk[d] = km[nb[d]];
+            kk[NDIR] = km[s];
+            acc += row_value<T, 1>(uu, kk, es + m * TET_EMAT);
         }
         y[base + s] = acc;
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_tensor_shared(LevelView<T> L, const T *__restrict__ u,
-                                                          T *__restrict__ y)
+// merged coefficients of the tensor operator's shared rows (FP64, once per
+// tensor coefficient), on the scalar operator's sparsity pattern:
+// scaled  c_e = sum over copies, components m and directions d onto e of
+//         w^m_d (k_m,q + k_m,e) with the copy's tet-restricted stencils;
+// nodal   c_e = sum over copies, elements t holding the node and m of
+//         (sum of k_m at t's vertices) (A^m_t / 4)[node, e]
+__global__ __launch_bounds__(BLOCK) void k_tensor_shared_coef(LevelView<double> L, const int8_t *__restrict__ map,
+                                                              double *__restrict__ cs, double *__restrict__ cn)
 {
     const int q = blockIdx.x * BLOCK + threadIdx.x;
-    if (q >= L.n_shared) return;
-    const int64_t ns = (int64_t)L.n_tet * L.Spad;
-    const T u0 = u[L.sh_self[q]];
-    T acc = T(0);
+    const int ns = L.n_shared;
+    if (q >= ns) return;
+    const int64_t nsl = (int64_t)L.n_tet * L.Spad;
+    for (int e = 0; e < L.sh_w; ++e) {
+        cs[(int64_t)e * ns + q] = 0.0;
+        cn[(int64_t)e * ns + q] = 0.0;
+    }
     for (int c = L.sh_off[q]; c < L.sh_off[q + 1]; ++c) {
         int tet, kind, i, j, k;
         unpack_copy(L.sh_copy[c], tet, kind, i, j, k);
         const int64_t base = (int64_t)tet * L.Spad;
         const int s = slot32(L.n, i, j, k);
+        const int8_t *mp = map + (int64_t)c * 16;
         int nb[NDIR];
         neighbour_slots(s, i + j, L.n - k, nb);
-        for (int d = 0; d < NDIR; ++d) {
-            if (!in_lattice(L.n, i + DIR[d][0], j + DIR[d][1], k + DIR[d][2])) continue;
-            const T du = u[base + nb[d]] - u0;
-            for (int m = 0; m < 6; ++m) {
-                const T wv = L.tsten[((int64_t)tet * 6 + m) * TET_STENCIL + kind * KIND_STRIDE + d];
-                if (wv == T(0)) continue;
-                const T *__restrict__ km = L.kt + m * ns + base;
-                acc += wv * (km[s] + km[nb[d]]) * du;
+        for (int m = 0; m < 6; ++m) {
+            const double *km = L.kt + m * nsl + base;
+            const double *w = L.tsten + ((int64_t)tet * 6 + m) * TET_STENCIL + kind * KIND_STRIDE;
+            for (int d = 0; d < NDIR; ++d) {
+                const int e = mp[d];
+                if (e >= 0 && w[d] != 0.0) cs[(int64_t)e * ns + q] += w[d] * (km[s] + km[nb[d]]);
             }
         }
+        for (int t = 0; t < NTYPE; ++t)
+            for (int a = 0; a < 4; ++a) {
+                // element of shape t whose vertex a is this node
+                int sl[4];
+                bool ok = true;
+                for (int v = 0; v < 4; ++v) {
+                    const int d = ELEM_DIR.v[t][a][v];
+                    if (d == NDIR) { sl[v] = s; continue; }
+                    ok = ok && in_lattice(L.n, i + DIR[d][0], j + DIR[d][1], k + DIR[d][2]);
+                    sl[v] = nb[d];
+                }
+                if (!ok) continue;
+                for (int m = 0; m < 6; ++m) {
+                    const double *km = L.kt + m * nsl + base;
+                    const double ks = (km[sl[0]] + km[sl[1]]) + (km[sl[2]] + km[sl[3]]);
+                    const double *E = L.temat + ((int64_t)tet * 6 + m) * TET_EMAT + t * 16 + a * 4;
+                    for (int v = 0; v < 4; ++v) {
+                        if (v == a) continue;
+                        const int e = mp[ELEM_DIR.v[t][a][v]];
+                        if (e >= 0) cn[(int64_t)e * ns + q] += ks * E[v];
+                    }
+                }
+            }
     }
-    for (int c = L.sh_off[q]; c < L.sh_off[q + 1]; ++c) y[L.sh_cslot[c]] = acc;
+}
+
+hipError_t launch_tensor_shared_coef(const LevelView<double> &L, const int8_t *map, double *cs, double *cn,
+                                     hipStream_t st)
+{
+    LevelView<double> Lt = L;
+    Lt.sh_w = L.sh_wt;
+    Lt.sh_nb = L.sh_nbt;
+    if (L.n_shared) k_tensor_shared_coef<<<blocks_for(L.n_shared), BLOCK, 0, st>>>(Lt, map, cs, cn);
+    return hipGetLastError();
 }
 
 // Dirichlet slots of y to 0 (the marches do this in their boundary blocks)
@@ -1578,17 +1662,43 @@ hipError_t launch_stored(const LevelView<T> &L, const CorrView<T> &C, const T *s
         k_correction<T, MODE_APPLY><<<blocks_for(C.n_rows), BLOCK, 0, strm>>>(C, u, y, nullptr, ChebArgs<T>(), 0);
     return hipGetLastError();
 }
+hipError_t launch_tensor_pairs(const LevelView<double> &L, double *kp, hipStream_t st)
+{
+    const int64_t ns = (int64_t)L.n_tet * L.Spad;
+    if (ns) k_tensor_pairs<<<blocks_for(ns), BLOCK, 0, st>>>(L, kp);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_tensor(const LevelView<T> &L, const T *u, T *y, hipStream_t st)
 {
     int n_seg = 0;
     const dim3 g = stored_grid(L.n, L.n_tet, n_seg);
     if (g.x) k_tensor_interior<T><<<g, BLOCK, 0, st>>>(L, u, y, n_seg);
-    if (L.n_shared) k_tensor_shared<T><<<blocks_for(L.n_shared), BLOCK, 0, st>>>(L, u, y);
+    LevelView<T> Lt = L;  // the tensor pattern
+    Lt.sh_w = L.sh_wt;
+    Lt.sh_nb = L.sh_nbt;
+    launch_shared_rows<T, MODE_APPLY>(Lt, L.sh_ct, u, nullptr, y, nullptr, st);
     const int64_t nb = (int64_t)L.n_tet * L.n_bnd;
     if (nb) k_dirichlet_zero<T><<<blocks_for(nb), BLOCK, 0, st>>>(L, y);
     return hipGetLastError();
 }
+template <typename T>
+hipError_t launch_tensor_nodal(const LevelView<T> &L, const T *u, T *y, hipStream_t st)
+{
+    int n_seg = 0;
+    const dim3 g = stored_grid(L.n, L.n_tet, n_seg);
+    if (g.x) k_tensor_nodal_interior<T><<<g, BLOCK, 0, st>>>(L, u, y, n_seg);
+    LevelView<T> Lt = L;  // the tensor pattern
+    Lt.sh_w = L.sh_wt;
+    Lt.sh_nb = L.sh_nbt;
+    launch_shared_rows<T, MODE_APPLY>(Lt, L.sh_ctn, u, nullptr, y, nullptr, st);
+    const int64_t nb = (int64_t)L.n_tet * L.n_bnd;
+    if (nb) k_dirichlet_zero<T><<<blocks_for(nb), BLOCK, 0, st>>>(L, y);
+    return hipGetLastError();
+}
+template hipError_t launch_tensor_nodal<double>(const LevelView<double> &, const double *, double *, hipStream_t);
+template hipError_t launch_tensor_nodal<float>(const LevelView<float> &, const float *, float *, hipStream_t);
 template hipError_t launch_tensor<double>(const LevelView<double> &, const double *, double *, hipStream_t);
 template hipError_t launch_tensor<float>(const LevelView<float> &, const float *, float *, hipStream_t);
 template hipError_t launch_store_stencils<double>(const LevelView<double> &, double *, hipStream_t);

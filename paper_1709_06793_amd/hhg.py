@@ -25,7 +25,7 @@ WFALLBACK = 1
 EXPORTS = [
     "hhg_create_macro", "hhg_destroy", "hhg_last_error", "hhg_vector_size", "hhg_node_coords",
     "hhg_to_canonical", "hhg_from_canonical", "hhg_set_coefficient", "hhg_set_coarse_level",
-    "hhg_level_info", "hhg_apply_scaled", "hhg_set_timing", "hhg_read_timing", "hhg_set_kernel_variant", "hhg_apply_nodal", "hhg_apply_mixed", "hhg_store_stencils", "hhg_apply_stored", "hhg_set_tensor_coefficient", "hhg_apply_tensor", "hhg_residual", "hhg_smooth",
+    "hhg_level_info", "hhg_apply_scaled", "hhg_set_timing", "hhg_read_timing", "hhg_set_kernel_variant", "hhg_apply_nodal", "hhg_apply_mixed", "hhg_store_stencils", "hhg_apply_stored", "hhg_set_tensor_coefficient", "hhg_apply_tensor", "hhg_apply_tensor_nodal", "hhg_residual", "hhg_smooth",
     "hhg_vcycle", "hhg_solve", "hhg_learned_set_weights", "hhg_learned_set_fallback",
     "hhg_learned_forward", "hhg_learned_backward", "hhg_learned_loss_grad", "hhg_training_pair",
     "hhg_adam_update",
@@ -75,6 +75,7 @@ def load():
         "hhg_store_stencils": [P, I32],
         "hhg_set_tensor_coefficient": [P, P, ctypes.c_int, P],
         "hhg_apply_tensor": [P, I32, I32, P, P, P],
+        "hhg_apply_tensor_nodal": [P, I32, I32, P, P, P],
         "hhg_apply_stored": [P, I32, I32, P, P, P],
         "hhg_residual": [P, I32, I32, P, P, P, P, P],
         "hhg_smooth": [P, I32, I32, I32, I32, D, P, P, P],
@@ -230,6 +231,10 @@ class Context:
 
     def apply_tensor(self, level, u, y):
         self._check(load().hhg_apply_tensor(self._h, level, _dtype_code(u), _ptr(u), _ptr(y), _stream()))
+        return y
+
+    def apply_tensor_nodal(self, level, u, y):
+        self._check(load().hhg_apply_tensor_nodal(self._h, level, _dtype_code(u), _ptr(u), _ptr(y), _stream()))
         return y
 
     def store_stencils(self, level):

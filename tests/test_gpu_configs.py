@@ -14,7 +14,8 @@ import numpy as np
 import pytest
 
 from hhg_inputs import (kuhn_cube, kuhn_cube_2x2x2, smooth_k, lognormal_params, lognormal_k,
-                        lognormal_k_torch, uniform_vector, manufactured_u, manufactured_f)
+                        lognormal_k_torch, uniform_vector, manufactured_u, manufactured_f, tensor_K, tensor_fields,
+                        tensor_fields_torch)
 from oracle import oracle as O
 
 torch = pytest.importorskip("torch")
@@ -145,6 +146,35 @@ def test_c4_full_size_sampled_rows():
     h = 1.5 / 2 ** (level + 1)
     inner = (om.xyz.min(axis=1) > h) & (om.xyz.max(axis=1) < 1 - h)
     assert np.abs(v[inner]).max() <= 1e-13 * np.abs(v).max()
+
+
+def test_c4_tensor_full_size_sampled_rows():
+    """48 Kuhn tets at level 8 with the rotating SPD tensor K (six component
+    fields, 6.5 GB FP64 on the finest level), both tensor applies in the
+    launches bench.py times: sampled rows (random and every node near the
+    24-tet centre vertex) against the oracle's row-by-row evaluation, and
+    zero Dirichlet rows."""
+    X, T = kuhn_cube_2x2x2()
+    level = 8
+    om = O.Mesh(X, T, level)
+    print(f"C4 tensor full size level {level}: {om.n_nodes} nodes", flush=True)
+    u = uniform_vector(om.n_nodes, seed=13)
+    u[om.dirichlet] = 0.0
+    ctx = hhg.Context(X, T, level)
+    ctx.set_tensor_coefficient(tensor_fields_torch(om.xyz, torch))
+    ud = ctx.from_canonical(level, _dev(u))
+    rng = np.random.default_rng(9)
+    centre = np.where(np.abs(om.xyz - 0.5).max(axis=1) <= 2.5 / 2 ** (level + 1))[0]
+    nodes = np.unique(np.concatenate([rng.choice(om.n_nodes, 200, replace=False), centre]))
+    y = ctx.vector(level)
+    for form, apply in (("scaled", ctx.apply_tensor), ("nodal", ctx.apply_tensor_nodal)):
+        apply(level, ud, y)
+        got = ctx.to_canonical(level, y).cpu().numpy()
+        ref = O.apply_tensor_rows(om, lambda x: tensor_fields(tensor_K(x)), u, nodes, form)
+        err = np.abs(got[nodes] - ref).max() / np.abs(ref).max()
+        print(f"tensor {form}: {len(nodes)} sampled rows, max rel error {err:.3e}", flush=True)
+        assert err <= 1e-12, form
+        assert np.all(got[om.dirichlet] == 0.0), form
 
 
 @pytest.mark.parametrize("mode", [hhg.SOLVE_F64, hhg.SOLVE_MIXED])

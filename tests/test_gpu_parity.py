@@ -166,16 +166,23 @@ def test_apply_stored_matches_oracle(mesh_fn, level, kfun):
     assert _rel(got, ref) <= TOL64, _rel(got, ref)
 
 
-@pytest.mark.parametrize("mesh_fn,level", [(unit_tet, 4), (kuhn_cube, 3), (cube12, 3), (kuhn_cube_2x2x2, 3),
-                                           (flat_tet, 4)])
-def test_apply_tensor_matches_oracle(mesh_fn, level):
-    """Sec. 2.1 eq. (integral), six components each scaled, on a rotating SPD K
-    field: FP64 at the finest and the next coarser level (fields injected),
-    FP32."""
+def _tensor_apply(ctx, form):
+    return ctx.apply_tensor if form == "scaled" else ctx.apply_tensor_nodal
+
+
+@pytest.mark.parametrize("form", ["scaled", "nodal"])
+@pytest.mark.parametrize("mesh_fn,level", [(unit_tet, 4), (unit_tet, 5), (kuhn_cube, 3), (cube12, 3),
+                                           (kuhn_cube_2x2x2, 3), (flat_tet, 4)])
+def test_apply_tensor_matches_oracle(mesh_fn, level, form):
+    """Sec. 2.1 eq. (integral), six components each scaled (or each nodally
+    integrated), on a rotating SPD K field: FP64 at the finest and the next
+    coarser level (fields injected), FP32.  Unit tet level 5 has two plane
+    chunks, the second ragged."""
     X, T = mesh_fn()
     ctx = hhg.Context(X, T, level)
+    apply = _tensor_apply(ctx, form)
     with pytest.raises(hhg.HHGError):
-        ctx.apply_tensor(level, ctx.vector(level), ctx.vector(level))
+        apply(level, ctx.vector(level), ctx.vector(level))
     om = O.Mesh(X, T, level)
     ctx.set_tensor_coefficient(tensor_fields(tensor_K(om.xyz)))
     for lv in (level, level - 1):
@@ -184,22 +191,23 @@ def test_apply_tensor_matches_oracle(mesh_fn, level):
         u = uniform_vector(m.n_nodes, seed=3)
         u[m.dirichlet] = 0.0
         y = ctx.vector(lv)
-        ctx.apply_tensor(lv, ctx.from_canonical(lv, _dev(u)), y)
+        apply(lv, ctx.from_canonical(lv, _dev(u)), y)
         got = ctx.to_canonical(lv, y).cpu().numpy()
-        ref = O.make_tensor_operator(m, K6).apply(u)
+        ref = O.make_tensor_operator(m, K6, form).apply(u)
         assert _rel(got, ref) <= TOL64 and _elem(got, ref) <= TOL64, (lv, _rel(got, ref), _elem(got, ref))
         assert np.all(got[m.dirichlet] == 0.0)
     y32 = ctx.vector(level, torch.float32)
     u = uniform_vector(om.n_nodes, seed=3)
     u[om.dirichlet] = 0.0
-    ctx.apply_tensor(level, ctx.from_canonical(level, _dev(u, torch.float32)), y32)
+    apply(level, ctx.from_canonical(level, _dev(u, torch.float32)), y32)
     got = ctx.to_canonical(level, y32).cpu().numpy().astype(np.float64)
-    ref = O.make_tensor_operator(om, tensor_fields(tensor_K(om.xyz))).apply(u)
+    ref = O.make_tensor_operator(om, tensor_fields(tensor_K(om.xyz)), form).apply(u)
     assert _rel(got, ref) <= 4e-6, _rel(got, ref)
 
 
-def test_apply_tensor_with_scalar_K_is_apply_scaled():
-    """K = k I reduces the tensor operator to -div(k grad u)."""
+def test_apply_tensor_with_scalar_K_is_the_scalar_operator():
+    """K = k I reduces the tensor operator to -div(k grad u): the scaled form
+    to apply_scaled, the nodal form to apply_nodal."""
     X, T = cube12()
     level = 4
     om, k, u, ctx = _setup(cube12, level, kfun=lambda x: lognormal_k(x, lognormal_params(6, 1.0, 0.2)),
@@ -209,6 +217,9 @@ def test_apply_tensor_with_scalar_K_is_apply_scaled():
     y1, y2 = ctx.vector(level), ctx.vector(level)
     ctx.apply_tensor(level, ud, y1)
     ctx.apply_scaled(level, ud, y2)
+    assert ((y1 - y2).abs().max() / y2.abs().max()).item() <= 1e-13
+    ctx.apply_tensor_nodal(level, ud, y1)
+    ctx.apply_nodal(level, ud, y2)
     assert ((y1 - y2).abs().max() / y2.abs().max()).item() <= 1e-13
 
 
