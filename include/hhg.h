@@ -248,6 +248,20 @@ hhg_status hhg_solve(hhg_ctx ctx, int32_t level, hhg_solve_mode mode, int32_t pr
                      double tol, int32_t max_iter, const double *f, double *u,
                      hhg_solve_stats *stats, void *stream);
 
+/* The same solve for the tensor-coefficient operator (Sec. 2.1 eq.
+ * (integral)) of hhg_set_tensor_coefficient on every level of the cycle:
+ * form 0 every component scaled (hhg_apply_tensor), form 1 every component
+ * nodally integrated (hhg_apply_tensor_nodal), as the comparison of Sec. 7.
+ * Chebyshev smoothing on D^{-1} A over [0.1, 1] x its Gershgorin bound, the
+ * scalar solve's transfers, and a dense coarse inverse of the form (built
+ * with the form's diagonals on the first call after a new tensor coefficient
+ * or coarse level).  mode: HHG_SOLVE_F64 or HHG_SOLVE_MIXED (HHG_EINVAL
+ * otherwise); HHG_ESTATE before hhg_set_tensor_coefficient.  The scalar
+ * coefficient is not needed. */
+hhg_status hhg_solve_tensor(hhg_ctx ctx, int32_t level, int32_t form, hhg_solve_mode mode, int32_t pre,
+                            int32_t post, double tol, int32_t max_iter, const double *f, double *u,
+                            hhg_solve_stats *stats, void *stream);
+
 /* Learned smoothing correction (not in the paper).  Per interior node i of a
  * macro tet, a network maps the 15-point neighbourhood features
  * x_p = r_p * (1/s_i) (reciprocal rounded to FP32) and x_{15+p} = L_p - L_i

@@ -260,6 +260,10 @@ struct Level {
     double *k64 = nullptr, *invd64 = nullptr;
     float *k32 = nullptr, *invd32 = nullptr;
     double lam = 0.0;
+    // tensor forms (0 scaled, 1 nodal): inverse diagonal and Gershgorin bound
+    double *tinvd64[2] = {nullptr, nullptr};
+    float *tinvd32[2] = {nullptr, nullptr};
+    double tlam[2] = {0.0, 0.0};
     // work vectors
     double *r64 = nullptr, *d64 = nullptr, *f64 = nullptr, *u64 = nullptr;
     float *r32 = nullptr, *d32 = nullptr, *f32 = nullptr, *u32 = nullptr;
@@ -289,6 +293,14 @@ struct Level {
 
 }  // namespace
 
+struct CoarseInv {
+    int cu = 0;
+    double *ainv = nullptr;
+    int64_t *cgather = nullptr;
+    int32_t *ccoff = nullptr;
+    int64_t *ccslot = nullptr;
+};
+
 struct hhg_ctx_s {
     Topology topo;
     int max_level = 0, coarse = 0;
@@ -303,12 +315,12 @@ struct hhg_ctx_s {
     double *dscalar = nullptr;  // device scalars
     double *hscalar = nullptr;  // pinned host scalars
     int *dflag = nullptr;
-    // coarse solve
-    int cu = 0;
-    double *ainv = nullptr;
-    int64_t *cgather = nullptr;
-    int32_t *ccoff = nullptr;
-    int64_t *ccslot = nullptr;
+    // coarse solves: dense inverse over the coarse unknowns of the operator
+    // the V-cycle runs on (op: 0 scalar, 1 tensor scaled, 2 tensor nodal)
+    int op = 0;
+    CoarseInv co[3];
+    int tco_level[2] = {-1, -1};  // coarse level of the tensor forms' inverses
+    bool tready[2] = {false, false};
     std::string err;
     // learned correction
     LearnedState learned;
@@ -1148,10 +1160,16 @@ hhg_status residual_t(hhg_ctx c, int l, const T *f, const T *u, T *r, double *no
 {
     LevelView<T> V = view<T>(c, l);
     int np = 0;
-    HIPCHK(c, launch_scaled<T>(V, MODE_RESID, u, f, r, c->partial, &np, st));
-    CorrView<T> C = corr<T>(c, l);
-    HIPCHK(c, launch_correction<T>(V, C, MODE_RESID, u, r, c->partial + np, st));
-    if (C.n_rows) np += (C.n_rows + BLOCK - 1) / BLOCK;
+    if (c->op) {
+        // a tensor form (its partial count was checked against the buffer
+        // when its solver state was built)
+        HIPCHK(c, launch_tensor<T>(V, c->op - 1, MODE_RESID, u, f, r, c->partial, &np, st));
+    } else {
+        HIPCHK(c, launch_scaled<T>(V, MODE_RESID, u, f, r, c->partial, &np, st));
+        CorrView<T> C = corr<T>(c, l);
+        HIPCHK(c, launch_correction<T>(V, C, MODE_RESID, u, r, c->partial + np, st));
+        if (C.n_rows) np += (C.n_rows + BLOCK - 1) / BLOCK;
+    }
     if (norm) {
         HIPCHK(c, launch_reduce(c->partial, np, 0, c->dscalar, st));
         HIPCHK(c, hipMemcpyAsync(c->hscalar, c->dscalar, sizeof(double), hipMemcpyDeviceToHost, st));
@@ -1161,10 +1179,50 @@ hhg_status residual_t(hhg_ctx c, int l, const T *f, const T *u, T *r, double *no
     return HHG_OK;
 }
 
+template <typename T> T *tinvd(Level &L, int form);
+template <> double *tinvd<double>(Level &L, int form) { return L.tinvd64[form]; }
+template <> float *tinvd<float>(Level &L, int form) { return L.tinvd32[form]; }
+
+// smoothing with a tensor form: Jacobi, or the Chebyshev iteration of the
+// scalar operator (same interval from the form's bound) as residual plus
+// update passes
+template <typename T>
+hhg_status smooth_tensor_t(hhg_ctx c, int l, hhg_smoother sm, int sweeps, double omega, const T *f, T *u,
+                           hipStream_t st)
+{
+    Level &L = c->lv[l];
+    const int form = c->op - 1;
+    T *r = work_r<T>(L), *d = work_d<T>(L);
+    const T *id = tinvd<T>(L, form);
+    if (sm == HHG_JACOBI) {
+        for (int s = 0; s < sweeps; ++s) {
+            TRY(residual_t<T>(c, l, f, u, r, nullptr, st));
+            HIPCHK(c, launch_jacobi_update<T>(u, r, id, (T)omega, L.n_slots, st));
+        }
+        return HHG_OK;
+    }
+    const double a = 0.1 * L.tlam[form], b = L.tlam[form];
+    const double theta = 0.5 * (b + a), delta = 0.5 * (b - a), sigma = theta / delta;
+    double rho = 1.0 / sigma;
+    for (int s = 0; s < sweeps; ++s) {
+        T c_old = T(0), c_r = (T)(1.0 / theta);
+        if (s > 0) {
+            const double rn = 1.0 / (2.0 * sigma - rho);
+            c_old = (T)(rn * rho);
+            c_r = (T)(2.0 * rn / delta);
+            rho = rn;
+        }
+        TRY(residual_t<T>(c, l, f, u, r, nullptr, st));
+        HIPCHK(c, launch_cheb_update<T>(u, d, r, id, c_old, c_r, s == 0, L.n_slots, st));
+    }
+    return HHG_OK;
+}
+
 template <typename T>
 hhg_status smooth_t(hhg_ctx c, int l, hhg_smoother sm, int sweeps, double omega, const T *f, T *u,
                     hipStream_t st)
 {
+    if (c->op) return smooth_tensor_t<T>(c, l, sm, sweeps, omega, f, u, st);
     Level &L = c->lv[l];
     T *r = work_r<T>(L), *d = work_d<T>(L);
     const T *id = invd<T>(L);
@@ -1210,8 +1268,9 @@ template <typename T>
 hhg_status coarse_solve_t(hhg_ctx c, const T *f, T *u, hipStream_t st)
 {
     Level &L = c->lv[c->coarse];
+    const CoarseInv &C = c->co[c->op];
     HIPCHK(c, launch_fill<T>(u, T(0), L.n_slots, st));
-    HIPCHK(c, launch_coarse_solve<T>(c->ainv, c->cu, c->cgather, c->ccoff, c->ccslot, f, u, st));
+    HIPCHK(c, launch_coarse_solve<T>(C.ainv, C.cu, C.cgather, C.ccoff, C.ccslot, f, u, st));
     return HHG_OK;
 }
 
@@ -1444,9 +1503,9 @@ hhg_status build_diag(hhg_ctx c, int l, hipStream_t st)
     return HHG_OK;
 }
 
-// dense inverse of the coarse operator over its unknowns, column by column
-// from the FP64 apply kernel
-hhg_status build_coarse(hhg_ctx c, hipStream_t st)
+// dense inverse of the coarse operator (op as hhg_ctx_s::op) over its
+// unknowns, column by column from the FP64 apply kernel
+hhg_status build_coarse(hhg_ctx c, hipStream_t st, int op = 0)
 {
     TRY(ensure_canon_maps(c, c->coarse));
     Level &L = c->lv[c->coarse];
@@ -1480,7 +1539,10 @@ hhg_status build_coarse(hhg_ctx c, hipStream_t st)
         std::fill(e.begin(), e.end(), 0.0);
         for (int p = coff[col]; p < coff[col + 1]; ++p) e[cslot[p]] = 1.0;
         HIPCHK(c, hipMemcpyAsync(de, e.data(), L.n_slots * 8, hipMemcpyHostToDevice, st));
-        TRY(apply_scaled_t<double>(c, c->coarse, de, dy, st));
+        if (op == 0) TRY(apply_scaled_t<double>(c, c->coarse, de, dy, st));
+        else
+            HIPCHK(c, launch_tensor<double>(view<double>(c, c->coarse), op - 1, MODE_APPLY, de, nullptr, dy, nullptr,
+                                            nullptr, st));
         HIPCHK(c, hipMemcpyAsync(y.data(), dy, L.n_slots * 8, hipMemcpyDeviceToHost, st));
         HIPCHK(c, hipStreamSynchronize(st));
         for (int row = 0; row < nu; ++row) A[(size_t)row * nu + col] = y[gather[row]];
@@ -1488,15 +1550,16 @@ hhg_status build_coarse(hhg_ctx c, hipStream_t st)
     HIPCHK(c, hipMemsetAsync(de, 0, L.n_slots * 8, st));
     HIPCHK(c, hipMemsetAsync(dy, 0, L.n_slots * 8, st));
     if (!invert_dense(A, nu)) return fail(c, HHG_ECOEF, "coarse operator is singular");
-    if (c->ainv) {
-        for (void *p : {(void *)c->ainv, (void *)c->cgather, (void *)c->ccoff, (void *)c->ccslot})
-            dfree(c, p);
+    CoarseInv &C = c->co[op];
+    if (C.ainv) {
+        for (void *p : {(void *)C.ainv, (void *)C.cgather, (void *)C.ccoff, (void *)C.ccslot}) dfree(c, p);
+        C = CoarseInv();
     }
-    c->cu = nu;
-    TRY(upload(c, &c->ainv, A));
-    TRY(upload(c, &c->cgather, gather));
-    TRY(upload(c, &c->ccoff, coff));
-    TRY(upload(c, &c->ccslot, cslot));
+    C.cu = nu;
+    TRY(upload(c, &C.ainv, A));
+    TRY(upload(c, &C.cgather, gather));
+    TRY(upload(c, &C.ccoff, coff));
+    TRY(upload(c, &C.ccslot, cslot));
     HIPCHK(c, hipStreamSynchronize(st));
     return HHG_OK;
 }
@@ -1963,6 +2026,7 @@ hhg_status hhg_set_tensor_coefficient(hhg_ctx c, const double *k6, int on_device
     HIPCHK(c, hipStreamSynchronize(st));
     dfree(c, dk);
     c->have_tk = true;
+    c->tready[0] = c->tready[1] = false;
     return HHG_OK;
 }
 
@@ -1972,8 +2036,12 @@ hhg_status hhg_apply_tensor(hhg_ctx c, int32_t level, hhg_dtype dt, const void *
     if (!c->have_tk) return fail(c, HHG_ESTATE, "no tensor coefficient set");
     if (!u || !y || u == y) return fail(c, HHG_EINVAL, "u and y must be distinct non-NULL vectors");
     hipStream_t st = pick(c, stream);
-    if (dt == HHG_F64) HIPCHK(c, launch_tensor<double>(view<double>(c, level), (const double *)u, (double *)y, st));
-    else if (dt == HHG_F32) HIPCHK(c, launch_tensor<float>(view<float>(c, level), (const float *)u, (float *)y, st));
+    if (dt == HHG_F64)
+        HIPCHK(c, launch_tensor<double>(view<double>(c, level), 0, MODE_APPLY, (const double *)u, nullptr, (double *)y,
+                                        nullptr, nullptr, st));
+    else if (dt == HHG_F32)
+        HIPCHK(c, launch_tensor<float>(view<float>(c, level), 0, MODE_APPLY, (const float *)u, nullptr, (float *)y,
+                                       nullptr, nullptr, st));
     else return fail(c, HHG_EINVAL, "bad dtype");
     return HHG_OK;
 }
@@ -1985,9 +2053,11 @@ hhg_status hhg_apply_tensor_nodal(hhg_ctx c, int32_t level, hhg_dtype dt, const 
     if (!u || !y || u == y) return fail(c, HHG_EINVAL, "u and y must be distinct non-NULL vectors");
     hipStream_t st = pick(c, stream);
     if (dt == HHG_F64)
-        HIPCHK(c, launch_tensor_nodal<double>(view<double>(c, level), (const double *)u, (double *)y, st));
+        HIPCHK(c, launch_tensor<double>(view<double>(c, level), 1, MODE_APPLY, (const double *)u, nullptr, (double *)y,
+                                        nullptr, nullptr, st));
     else if (dt == HHG_F32)
-        HIPCHK(c, launch_tensor_nodal<float>(view<float>(c, level), (const float *)u, (float *)y, st));
+        HIPCHK(c, launch_tensor<float>(view<float>(c, level), 1, MODE_APPLY, (const float *)u, nullptr, (float *)y,
+                                       nullptr, nullptr, st));
     else return fail(c, HHG_EINVAL, "bad dtype");
     return HHG_OK;
 }
@@ -2114,14 +2184,15 @@ hhg_status hhg_vcycle(hhg_ctx c, int32_t level, hhg_dtype dt, int32_t pre, int32
     return fail(c, HHG_EINVAL, "bad dtype");
 }
 
-hhg_status hhg_solve(hhg_ctx c, int32_t level, hhg_solve_mode mode, int32_t pre, int32_t post, double tol,
-                     int32_t max_iter, const double *f, double *u, hhg_solve_stats *stats, void *stream)
+namespace {
+// the solve loop of hhg_solve / hhg_solve_tensor on the operator c->op
+hhg_status solve_impl(hhg_ctx c, int32_t level, hhg_solve_mode mode, int32_t pre, int32_t post, double tol,
+                      int32_t max_iter, const double *f, double *u, hhg_solve_stats *stats, void *stream)
 {
-    TRY(check_level(c, level));
-    NEED_K(c);
     if (!f || !u || f == u || max_iter < 0 || pre < 0 || post < 0) return fail(c, HHG_EINVAL, "bad arguments");
     if (level < c->coarse) return fail(c, HHG_EINVAL, "level below the coarse level");
-    if (mode == HHG_SOLVE_LEARNED && !c->learned.ready) return fail(c, HHG_ESTATE, "no learned weights set");
+    if (mode != HHG_SOLVE_F64 && mode != HHG_SOLVE_MIXED && mode != HHG_SOLVE_LEARNED)
+        return fail(c, HHG_EINVAL, "bad solve mode");
     hipStream_t st = pick(c, stream);
     Level &L = c->lv[level];
     HIPCHK(c, hipStreamSynchronize(st));
@@ -2177,6 +2248,70 @@ hhg_status hhg_solve(hhg_ctx c, int32_t level, hhg_solve_mode mode, int32_t pre,
         else stats->rho = 0.0;
     }
     return fallback ? HHG_WFALLBACK : HHG_OK;
+}
+
+// operator selection for the duration of a solve
+struct OpScope {
+    hhg_ctx c;
+    OpScope(hhg_ctx c_, int op) : c(c_) { c->op = op; }
+    ~OpScope() { c->op = 0; }
+};
+
+// inverse diagonals, Gershgorin bounds and the coarse inverse of a tensor form
+hhg_status ensure_tensor_solver(hhg_ctx c, int form)
+{
+    if (c->tready[form] && c->tco_level[form] == c->coarse) return HHG_OK;
+    hipStream_t st = c->stream;
+    // the levels a cycle visits (below the coarse level there may be no rows)
+    for (int l = c->coarse; l <= c->max_level; ++l) {
+        Level &L = c->lv[l];
+        if (tensor_partial_count(L.n, c->topo.nt, L.n_shared) > c->partial_cap)
+            return fail(c, HHG_EINVAL, "level %d: reduction buffer too small for the tensor kernels", l);
+        if (!L.tinvd64[form]) {
+            TRY(dalloc(c, &L.tinvd64[form], L.n_slots));
+            TRY(dalloc(c, &L.tinvd32[form], L.n_slots));
+        }
+        // slots without a row (Dirichlet, padding) keep 1: their residual is 0
+        HIPCHK(c, launch_fill<double>(L.tinvd64[form], 1.0, L.n_slots, st));
+        int np = 0;
+        HIPCHK(c, launch_tensor_diag(view<double>(c, l), form, L.tinvd64[form], c->partial, &np, st));
+        HIPCHK(c, launch_reduce(c->partial, np, 1, c->dscalar, st));
+        HIPCHK(c, hipMemcpyAsync(c->hscalar, c->dscalar, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        L.tlam[form] = c->hscalar[0];
+        if (!(L.tlam[form] > 0.0) || !std::isfinite(L.tlam[form]))
+            return fail(c, HHG_ECOEF, "level %d: tensor operator has a non-positive diagonal", l);
+        HIPCHK(c, launch_invert_diag<double>(L.tinvd64[form], L.n_slots, st));
+        HIPCHK(c, launch_convert<double, float>(L.tinvd64[form], L.tinvd32[form], L.n_slots, st));
+    }
+    TRY(build_coarse(c, st, 1 + form));
+    c->tco_level[form] = c->coarse;
+    c->tready[form] = true;
+    return HHG_OK;
+}
+}  // namespace
+
+hhg_status hhg_solve(hhg_ctx c, int32_t level, hhg_solve_mode mode, int32_t pre, int32_t post, double tol,
+                     int32_t max_iter, const double *f, double *u, hhg_solve_stats *stats, void *stream)
+{
+    TRY(check_level(c, level));
+    NEED_K(c);
+    if (mode == HHG_SOLVE_LEARNED && !c->learned.ready) return fail(c, HHG_ESTATE, "no learned weights set");
+    return solve_impl(c, level, mode, pre, post, tol, max_iter, f, u, stats, stream);
+}
+
+hhg_status hhg_solve_tensor(hhg_ctx c, int32_t level, int32_t form, hhg_solve_mode mode, int32_t pre, int32_t post,
+                            double tol, int32_t max_iter, const double *f, double *u, hhg_solve_stats *stats,
+                            void *stream)
+{
+    TRY(check_level(c, level));
+    if (!c->have_tk) return fail(c, HHG_ESTATE, "no tensor coefficient set");
+    if (form != 0 && form != 1) return fail(c, HHG_EINVAL, "form must be 0 (scaled) or 1 (nodal)");
+    if (mode != HHG_SOLVE_F64 && mode != HHG_SOLVE_MIXED)
+        return fail(c, HHG_EINVAL, "tensor solves take HHG_SOLVE_F64 or HHG_SOLVE_MIXED");
+    TRY(ensure_tensor_solver(c, form));
+    OpScope scope(c, 1 + form);
+    return solve_impl(c, level, mode, pre, post, tol, max_iter, f, u, stats, stream);
 }
 
 hhg_status hhg_learned_set_weights(hhg_ctx c, const float *w, int64_t n)

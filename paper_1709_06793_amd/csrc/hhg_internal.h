@@ -125,15 +125,24 @@ hipError_t launch_tensor_pairs(const LevelView<double> &L, double *kp, hipStream
 // merged shared-row coefficients of both tensor forms
 hipError_t launch_tensor_shared_coef(const LevelView<double> &L, const int8_t *map, double *cs, double *cn,
                                      hipStream_t st);
-// tensor-coefficient operator (Sec. 2.1 eq. (integral)), every component
-// scaled: interior rows, inter-tet rows (merged coefficients) and Dirichlet
-// zeros
+// tensor-coefficient operator (Sec. 2.1 eq. (integral)) with every component
+// scaled (form 0) or nodally integrated (form 1, eq. (standardfe) per
+// component): interior rows, inter-tet rows (merged coefficients) and
+// Dirichlet zeros.  mode MODE_APPLY: y = A u; MODE_RESID: y = f - A u with
+// per-block sums of squares in partial[0 .. *n_partial)
 template <typename T>
-hipError_t launch_tensor(const LevelView<T> &L, const T *u, T *y, hipStream_t st);
-// the same operator with every component nodally integrated (eq. (standardfe)
-// per component): interior rows, inter-tet rows, Dirichlet zeros
+hipError_t launch_tensor(const LevelView<T> &L, int form, int mode, const T *u, const T *f, T *y, double *partial,
+                         int *n_partial, hipStream_t st);
+// partial entries launch_tensor (MODE_RESID) and launch_tensor_diag produce
+int tensor_partial_count(int n, int n_tet, int n_shared);
+// diagonal of a tensor form (interior and shared rows; other slots untouched)
+// and per-block Gershgorin maxima of D^{-1} A in partial[0 .. *n_partial)
+hipError_t launch_tensor_diag(const LevelView<double> &L, int form, double *diag, double *partial, int *n_partial,
+                              hipStream_t st);
+// Chebyshev step from a residual over n slots
 template <typename T>
-hipError_t launch_tensor_nodal(const LevelView<T> &L, const T *u, T *y, hipStream_t st);
+hipError_t launch_cheb_update(T *u, T *d, const T *r, const T *invd, T c_old, T c_r, int first, int64_t n,
+                              hipStream_t st);
 // the primitive-mixed operator (Sec. 5 eq. (modst)): nodal-integration rows
 // for the nodes of the primitives in nodal_mask (1 vertices, 2 edges, 4
 // faces), scaled rows (with their modification corrections) elsewhere

@@ -1477,34 +1477,48 @@ __global__ void k_tensor_pairs(LevelView<double> L, double *__restrict__ kp)
     }
 }
 
-template <typename T>
+// MODE_APPLY: y = A u; MODE_RESID: y = f - A u and the block's sum of
+// squares in partial (one entry per block of the 2D grid)
+template <typename T, int MODE>
 __global__ __launch_bounds__(BLOCK) void k_tensor_interior(LevelView<T> L, const T *__restrict__ u,
-                                                            T *__restrict__ y, int n_seg)
+                                                            const T *__restrict__ f, T *__restrict__ y,
+                                                            double *__restrict__ partial, int n_seg)
 {
-    int t, sd, k0, k1, tet;
+    int t = 0, sd = 0, k0 = 0, k1 = -1, tet;
     const int n = L.n;
-    if (!stored_lane(n, n_seg, t, sd, k0, k1, tet)) return;
-    const int i = t - sd * (sd + 1) / 2, j = sd - i;
-    if (i < 1 || j < 1) return;
-    const int64_t base = (int64_t)tet * L.Spad, ns = (int64_t)L.n_tet * L.Spad;
-    const T *__restrict__ ub = u + base;
-    const T *__restrict__ kb = L.kp + base;
-    const int Sn = tc32(n);
+    double sq = 0.0;
+    if (stored_lane(n, n_seg, t, sd, k0, k1, tet)) {
+        const int i = t - sd * (sd + 1) / 2, j = sd - i;
+        if (i >= 1 && j >= 1) {
+            const int64_t base = (int64_t)tet * L.Spad, ns = (int64_t)L.n_tet * L.Spad;
+            const T *__restrict__ ub = u + base;
+            const T *__restrict__ kb = L.kp + base;
+            const int Sn = tc32(n);
 #pragma unroll 2
-    for (int k = k0; k <= min(k1, n - 1 - sd); ++k) {
-        const int s = Sn - tc32(n - k) + t;
-        int nb[NDIR];
-        neighbour_slots(s, sd, n - k, nb);
-        const T u0 = ub[s];
-        T acc = T(0);
+            for (int k = k0; k <= min(k1, n - 1 - sd); ++k) {
+                const int s = Sn - tc32(n - k) + t;
+                int nb[NDIR];
+                neighbour_slots(s, sd, n - k, nb);
+                const T u0 = ub[s];
+                T acc = T(0);
 #pragma unroll
-        for (int p = 0; p < NDIR / 2; ++p) {
-            const T *__restrict__ kq = kb + p * ns;
-            const int a = nb[p], b = nb[p + NDIR / 2];
-            const T c0 = kq[s];
-            acc += (c0 + kq[a]) * (ub[a] - u0) + (c0 + kq[b]) * (ub[b] - u0);
+                for (int p = 0; p < NDIR / 2; ++p) {
+                    const T *__restrict__ kq = kb + p * ns;
+                    const int a = nb[p], b = nb[p + NDIR / 2];
+                    const T c0 = kq[s];
+                    acc += (c0 + kq[a]) * (ub[a] - u0) + (c0 + kq[b]) * (ub[b] - u0);
+                }
+                if (MODE == MODE_RESID) {
+                    acc = f[base + s] - acc;
+                    sq += (double)acc * (double)acc;
+                }
+                y[base + s] = acc;
+            }
         }
-        y[base + s] = acc;
+    }
+    if (MODE == MODE_RESID) {
+        sq = block_reduce(sq, 0);
+        if (threadIdx.x == 0) partial[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = sq;
     }
 }
 
@@ -1512,48 +1526,140 @@ __global__ __launch_bounds__(BLOCK) void k_tensor_interior(LevelView<T> L, const
 // (standardfe) with that component's element matrices and field, summed over
 // the six components.  Interior rows gather u and each k_m over the 15-point
 // neighbourhood (all 24 incident elements lie in the tet); inter-tet rows take
-// merged coefficients (k_tensor_shared_coef).
-template <typename T>
+// merged coefficients (k_tensor_shared_coef).  Modes as k_tensor_interior.
+template <typename T, int MODE>
 __global__ __launch_bounds__(BLOCK) void k_tensor_nodal_interior(LevelView<T> L, const T *__restrict__ u,
-                                                                  T *__restrict__ y, int n_seg)
+                                                                  const T *__restrict__ f, T *__restrict__ y,
+                                                                  double *__restrict__ partial, int n_seg)
 {
     __shared__ T es[6 * TET_EMAT];
     for (int q = threadIdx.x; q < 6 * TET_EMAT; q += BLOCK)
         es[q] = L.temat[(int64_t)blockIdx.y * 6 * TET_EMAT + q];
     __syncthreads();
-    int t, sd, k0, k1, tet;
+    int t = 0, sd = 0, k0 = 0, k1 = -1, tet;
     const int n = L.n;
-    if (!stored_lane(n, n_seg, t, sd, k0, k1, tet)) return;
-    const int i = t - sd * (sd + 1) / 2, j = sd - i;
-    if (i < 1 || j < 1) return;
-    const int64_t base = (int64_t)tet * L.Spad, ns = (int64_t)L.n_tet * L.Spad;
-    const T *__restrict__ ub = u + base;
-    const int Sn = tc32(n);
+    double sq = 0.0;
+    if (stored_lane(n, n_seg, t, sd, k0, k1, tet)) {
+        const int i = t - sd * (sd + 1) / 2, j = sd - i;
+        if (i >= 1 && j >= 1) {
+            const int64_t base = (int64_t)tet * L.Spad, ns = (int64_t)L.n_tet * L.Spad;
+            const T *__restrict__ ub = u + base;
+            const int Sn = tc32(n);
 #pragma unroll 1
-    for (int k = k0; k <= min(k1, n - 1 - sd); ++k) {
-        const int s = Sn - tc32(n - k) + t;
-        int nb[NDIR];
-        neighbour_slots(s, sd, n - k, nb);
-        T uu[NDIR + 1];
+            for (int k = k0; k <= min(k1, n - 1 - sd); ++k) {
+                const int s = Sn - tc32(n - k) + t;
+                int nb[NDIR];
+                neighbour_slots(s, sd, n - k, nb);
+                T uu[NDIR + 1];
 #pragma unroll
-        for (int d = 0; d < NDIR; ++d) uu[d] = ub[nb[d]];
-        uu[NDIR] = ub[s];
-        T acc = T(0);
+                for (int d = 0; d < NDIR; ++d) uu[d] = ub[nb[d]];
+                uu[NDIR] = ub[s];
+                T acc = T(0);
 #pragma unroll 1
-        for (int m = 0; m < 6; ++m) {
-            const T *__restrict__ km = L.kt + m * ns + base;
-            T kk[NDIR + 1];
+                for (int m = 0; m < 6; ++m) {
+                    const T *__restrict__ km = L.kt + m * ns + base;
+                    T kk[NDIR + 1];
 #pragma unroll
-            for (int d = 0; d < NDIR; ++d) kk[d] = km[nb[d]];
-            kk[NDIR] = km[s];
-            acc += row_value<T, 1>(uu, kk, es + m * TET_EMAT);
+                    for (int d = 0; d < NDIR; ++d) kk[d] = km[nb[d]];
+                    kk[NDIR] = km[s];
+                    acc += row_value<T, 1>(uu, kk, es + m * TET_EMAT);
+                }
+                if (MODE == MODE_RESID) {
+                    acc = f[base + s] - acc;
+                    sq += (double)acc * (double)acc;
+                }
+                y[base + s] = acc;
+            }
         }
-        y[base + s] = acc;
+    }
+    if (MODE == MODE_RESID) {
+        sq = block_reduce(sq, 0);
+        if (threadIdx.x == 0) partial[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = sq;
     }
 }
 
+// Diagonal of either tensor form on interior rows (FP64, at set-up): with the
+// row written as sum_d c_d (u_d - u_0), a_00 = -sum_d c_d and a_0d = c_d.
+// Stores a_00 in diag and the block's largest Gershgorin bound
+// 1 + sum_d |c_d| / a_00 of D^{-1} A in partial.
+template <int FORM>
+__global__ __launch_bounds__(BLOCK) void k_tensor_diag(LevelView<double> L, double *__restrict__ diag,
+                                                       double *__restrict__ partial, int n_seg)
+{
+    int t = 0, sd = 0, k0 = 0, k1 = -1, tet;
+    const int n = L.n;
+    double g = 0.0;
+    if (stored_lane(n, n_seg, t, sd, k0, k1, tet)) {
+        const int i = t - sd * (sd + 1) / 2, j = sd - i;
+        if (i >= 1 && j >= 1) {
+            const int64_t base = (int64_t)tet * L.Spad, ns = (int64_t)L.n_tet * L.Spad;
+            const int Sn = tc32(n);
+            for (int k = k0; k <= min(k1, n - 1 - sd); ++k) {
+                const int s = Sn - tc32(n - k) + t;
+                int nb[NDIR];
+                neighbour_slots(s, sd, n - k, nb);
+                double cd[NDIR];
+                for (int d = 0; d < NDIR; ++d) cd[d] = 0.0;
+                if (FORM == 0) {
+                    for (int d = 0; d < NDIR; ++d) {
+                        const double *kq = L.kp + (d % (NDIR / 2)) * ns + base;
+                        cd[d] = kq[s] + kq[nb[d]];
+                    }
+                } else {
+                    for (int m = 0; m < 6; ++m) {
+                        const double *km = L.kt + m * ns + base;
+                        double kk[NDIR + 1];
+                        for (int d = 0; d < NDIR; ++d) kk[d] = km[nb[d]];
+                        kk[NDIR] = km[s];
+                        const double *w = L.temat + ((int64_t)tet * 6 + m) * TET_EMAT;
+                        for (int ty = 0; ty < NTYPE; ++ty)
+                            for (int a = 0; a < 4; ++a) {
+                                double ks = 0.0;
+                                for (int v = 0; v < 4; ++v) ks += kk[ELEM_DIR.v[ty][a][v]];
+                                for (int v = 0; v < 4; ++v) {
+                                    const int d = ELEM_DIR.v[ty][a][v];
+                                    if (d != NDIR) cd[d] += ks * w[ty * 16 + a * 4 + v];
+                                }
+                            }
+                    }
+                }
+                double dg = 0.0, ab = 0.0;
+                for (int d = 0; d < NDIR; ++d) {
+                    dg -= cd[d];
+                    ab += fabs(cd[d]);
+                }
+                diag[base + s] = dg;
+                g = fmax(g, 1.0 + ab / dg);
+            }
+        }
+    }
+    g = block_reduce(g, 1);
+    if (threadIdx.x == 0) partial[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = g;
+}
+
+// the same for shared rows from their merged coefficients (tensor pattern),
+// written to every copy
+__global__ __launch_bounds__(BLOCK) void k_shared_diag(LevelView<double> L, const double *__restrict__ coef,
+                                                       double *__restrict__ diag, double *__restrict__ partial)
+{
+    const int q = blockIdx.x * BLOCK + threadIdx.x;
+    double g = 0.0;
+    if (q < L.n_shared) {
+        double dg = 0.0, ab = 0.0;
+        for (int e = 0; e < L.sh_wt; ++e) {
+            const double c = coef[(int64_t)e * L.n_shared + q];
+            dg -= c;
+            ab += fabs(c);
+        }
+        for (int c = L.sh_off[q]; c < L.sh_off[q + 1]; ++c) diag[L.sh_cslot[c]] = dg;
+        g = 1.0 + ab / dg;
+    }
+    g = block_reduce(g, 1);
+    if (threadIdx.x == 0) partial[blockIdx.x] = g;
+}
+
 // merged coefficients of the tensor operator's shared rows (FP64, once per
-// tensor coefficient), on the scalar operator's sparsity pattern:
+// tensor coefficient), on the tensor operator's sparsity pattern:
 // scaled  c_e = sum over copies, components m and directions d onto e of
 //         w^m_d (k_m,q + k_m,e) with the copy's tet-restricted stencils;
 // nodal   c_e = sum over copies, elements t holding the node and m of
@@ -1670,37 +1776,83 @@ hipError_t launch_tensor_pairs(const LevelView<double> &L, double *kp, hipStream
 }
 
 template <typename T>
-hipError_t launch_tensor(const LevelView<T> &L, const T *u, T *y, hipStream_t st)
+hipError_t launch_tensor(const LevelView<T> &L, int form, int mode, const T *u, const T *f, T *y, double *partial,
+                         int *n_partial, hipStream_t st)
 {
     int n_seg = 0;
     const dim3 g = stored_grid(L.n, L.n_tet, n_seg);
-    if (g.x) k_tensor_interior<T><<<g, BLOCK, 0, st>>>(L, u, y, n_seg);
+    const int gi = (int)(g.x * g.y);
+    const bool resid = mode == MODE_RESID;
+    if (g.x) {
+        if (form == 0 && !resid) k_tensor_interior<T, MODE_APPLY><<<g, BLOCK, 0, st>>>(L, u, f, y, partial, n_seg);
+        if (form == 0 && resid) k_tensor_interior<T, MODE_RESID><<<g, BLOCK, 0, st>>>(L, u, f, y, partial, n_seg);
+        if (form != 0 && !resid)
+            k_tensor_nodal_interior<T, MODE_APPLY><<<g, BLOCK, 0, st>>>(L, u, f, y, partial, n_seg);
+        if (form != 0 && resid)
+            k_tensor_nodal_interior<T, MODE_RESID><<<g, BLOCK, 0, st>>>(L, u, f, y, partial, n_seg);
+    }
     LevelView<T> Lt = L;  // the tensor pattern
     Lt.sh_w = L.sh_wt;
     Lt.sh_nb = L.sh_nbt;
-    launch_shared_rows<T, MODE_APPLY>(Lt, L.sh_ct, u, nullptr, y, nullptr, st);
+    const T *coef = form == 0 ? L.sh_ct : L.sh_ctn;
+    if (resid) launch_shared_rows<T, MODE_RESID>(Lt, coef, u, f, y, partial + gi, st);
+    else launch_shared_rows<T, MODE_APPLY>(Lt, coef, u, f, y, nullptr, st);
     const int64_t nb = (int64_t)L.n_tet * L.n_bnd;
     if (nb) k_dirichlet_zero<T><<<blocks_for(nb), BLOCK, 0, st>>>(L, y);
+    if (n_partial) *n_partial = gi + blocks_for(L.n_shared);
     return hipGetLastError();
+}
+template hipError_t launch_tensor<double>(const LevelView<double> &, int, int, const double *, const double *,
+                                          double *, double *, int *, hipStream_t);
+template hipError_t launch_tensor<float>(const LevelView<float> &, int, int, const float *, const float *, float *,
+                                         double *, int *, hipStream_t);
+
+int tensor_partial_count(int n, int n_tet, int n_shared)
+{
+    int n_seg = 0;
+    const dim3 g = stored_grid(n, n_tet, n_seg);
+    return (int)(g.x * g.y) + blocks_for(n_shared);
+}
+
+hipError_t launch_tensor_diag(const LevelView<double> &L, int form, double *diag, double *partial, int *n_partial,
+                              hipStream_t st)
+{
+    int n_seg = 0;
+    const dim3 g = stored_grid(L.n, L.n_tet, n_seg);
+    const int gi = (int)(g.x * g.y);
+    if (g.x) {
+        if (form == 0) k_tensor_diag<0><<<g, BLOCK, 0, st>>>(L, diag, partial, n_seg);
+        else k_tensor_diag<1><<<g, BLOCK, 0, st>>>(L, diag, partial, n_seg);
+    }
+    const int gs = blocks_for(L.n_shared);
+    if (gs) k_shared_diag<<<gs, BLOCK, 0, st>>>(L, form == 0 ? L.sh_ct : L.sh_ctn, diag, partial + gi);
+    *n_partial = gi + gs;
+    return hipGetLastError();
+}
+
+// Chebyshev step from a residual: d = c_old d + c_r D^{-1} r (d = c_r D^{-1} r
+// on the first step), u += d
+template <typename T>
+__global__ void k_cheb_update(T *__restrict__ u, T *__restrict__ d, const T *__restrict__ r,
+                              const T *__restrict__ invd, T c_old, T c_r, int first, int64_t n)
+{
+    const int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (e >= n) return;
+    const T dn = (first ? T(0) : c_old * d[e]) + c_r * invd[e] * r[e];
+    d[e] = dn;
+    u[e] += dn;
 }
 template <typename T>
-hipError_t launch_tensor_nodal(const LevelView<T> &L, const T *u, T *y, hipStream_t st)
+hipError_t launch_cheb_update(T *u, T *d, const T *r, const T *invd, T c_old, T c_r, int first, int64_t n,
+                              hipStream_t st)
 {
-    int n_seg = 0;
-    const dim3 g = stored_grid(L.n, L.n_tet, n_seg);
-    if (g.x) k_tensor_nodal_interior<T><<<g, BLOCK, 0, st>>>(L, u, y, n_seg);
-    LevelView<T> Lt = L;  // the tensor pattern
-    Lt.sh_w = L.sh_wt;
-    Lt.sh_nb = L.sh_nbt;
-    launch_shared_rows<T, MODE_APPLY>(Lt, L.sh_ctn, u, nullptr, y, nullptr, st);
-    const int64_t nb = (int64_t)L.n_tet * L.n_bnd;
-    if (nb) k_dirichlet_zero<T><<<blocks_for(nb), BLOCK, 0, st>>>(L, y);
+    if (n) k_cheb_update<T><<<blocks_for(n), BLOCK, 0, st>>>(u, d, r, invd, c_old, c_r, first, n);
     return hipGetLastError();
 }
-template hipError_t launch_tensor_nodal<double>(const LevelView<double> &, const double *, double *, hipStream_t);
-template hipError_t launch_tensor_nodal<float>(const LevelView<float> &, const float *, float *, hipStream_t);
-template hipError_t launch_tensor<double>(const LevelView<double> &, const double *, double *, hipStream_t);
-template hipError_t launch_tensor<float>(const LevelView<float> &, const float *, float *, hipStream_t);
+template hipError_t launch_cheb_update<double>(double *, double *, const double *, const double *, double, double,
+                                               int, int64_t, hipStream_t);
+template hipError_t launch_cheb_update<float>(float *, float *, const float *, const float *, float, float, int,
+                                              int64_t, hipStream_t);
 template hipError_t launch_store_stencils<double>(const LevelView<double> &, double *, hipStream_t);
 template hipError_t launch_store_stencils<float>(const LevelView<double> &, float *, hipStream_t);
 
