@@ -246,6 +246,45 @@ def learned_solves(hhg, torch):
     return out
 
 
+def tensor_solves(hhg, torch):
+    """Time to a 1e-9 relative residual with the tensor operator (the
+    tensor-coefficient comparison of Sec. 7: 12 macro tets around the cube
+    centre, level 8, 33.4M unknowns, rotating SPD K of the test inputs,
+    f ~ U[-1,1]): V(3,3) cycles with every component scaled and with every
+    component nodally integrated, FP64 and FP32-in-FP64; best of two runs
+    each (the first run also builds the form's diagonals and coarse inverse)."""
+    from hhg_inputs import cube12, tensor_fields_torch
+    level = 8
+    log("bench: tensor solves, 12-tet cube level 8")
+    X, T = cube12()
+    ctx = hhg.Context(X, T, level)
+    xyz, dirichlet = ctx.node_coords(level)
+    ctx.set_tensor_coefficient(tensor_fields_torch(xyz, torch))
+    f = np.random.default_rng(5).uniform(-1, 1, xyz.shape[0])
+    f[dirichlet] = 0.0
+    fd = ctx.from_canonical(level, torch.tensor(f, device="cuda"))
+    del xyz
+    out = {"unknowns": ctx.sizes(level)["n_unknowns"], "tol": 1e-9, "cycle": "V(3,3)"}
+    for form in ("scaled", "nodal"):
+        for mname, mode in (("f64", hhg.SOLVE_F64), ("mixed", hhg.SOLVE_MIXED)):
+            best = None
+            for _ in range(2):
+                u = ctx.vector(level)
+                torch.cuda.synchronize()
+                st = ctx.solve_tensor(level, fd, u, form=form, mode=mode, tol=1e-9, max_iter=200, pre=3, post=3)
+                if best is None or st["seconds"] < best["seconds"]:
+                    best = st
+                del u
+            out[f"{form}_{mname}"] = {k2: (float(f"{v:.4g}") if isinstance(v, float) else v)
+                                      for k2, v in best.items()}
+            log(f"bench: tensor {form} {mname}: {best}")
+    for mname in ("f64", "mixed"):
+        out[f"relative_tts_{mname}"] = round(out[f"scaled_{mname}"]["seconds"] / out[f"nodal_{mname}"]["seconds"], 3)
+    del ctx, fd
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -255,6 +294,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--k48-apply-only", action="store_true",
                     help="only time the 48-tet level-8 applies (tuning runs)")
+    ap.add_argument("--tensor-solves", action="store_true",
+                    help="only the tensor-operator solves (12-tet cube, level 8)")
     ap.add_argument("--k48-solves", action="store_true",
                     help="only run the 48-tet level-8 V-cycle solves (profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -279,6 +320,9 @@ def main():
 
     if args.k48_apply_only:
         print(json.dumps(kuhn48_applies(hhg, torch, args.steps, solves=False)))
+        return
+    if args.tensor_solves:
+        print(json.dumps(tensor_solves(hhg, torch)))
         return
     if args.k48_solves:
         print(json.dumps(kuhn48_applies(hhg, torch, args.steps, solves=True, applies=False)))
@@ -355,6 +399,7 @@ def main():
 
         extra["kuhn48_l8"] = kuhn48_applies(hhg, torch, args.steps, solves=True)
         extra["learned_l8"] = learned_solves(hhg, torch)
+        extra["tensor_cube12_l8"] = tensor_solves(hhg, torch)
     out["extra"] = extra
     if not args.no_cpu:
         log("bench: CPU oracle baseline")

@@ -256,6 +256,23 @@ def test_solve_tensor_matches_oracle(form, mode):
     assert np.all(got[om.dirichlet] == 0.0)
 
 
+def test_solve_tensor_with_scalar_K_is_the_scalar_solve():
+    """K = k I: the scaled tensor solve takes the scalar solve's cycles (same
+    operator on every level, same diagonals and bounds up to rounding)."""
+    X, T = cube12()
+    level = 5
+    om, k, u, ctx = _setup(cube12, level, kfun=smooth_k, flags=hhg.FLAG_NO_MODIFICATION)
+    ctx.set_tensor_coefficient(tensor_fields(k[:, None, None] * np.eye(3)[None]))
+    f = uniform_vector(om.n_nodes, seed=6)
+    f[om.dirichlet] = 0.0
+    fd = ctx.from_canonical(level, _dev(f))
+    u1, u2 = ctx.vector(level), ctx.vector(level)
+    s1 = ctx.solve(level, fd, u1, tol=1e-10, max_iter=60, pre=3, post=3)
+    s2 = ctx.solve_tensor(level, fd, u2, tol=1e-10, max_iter=60, pre=3, post=3)
+    assert s1["iterations"] == s2["iterations"] and abs(s1["rho"] - s2["rho"]) <= 1e-6, (s1, s2)
+    assert ((u1 - u2).abs().max() / u1.abs().max()).item() <= 1e-9
+
+
 @pytest.mark.parametrize("mesh_fn,level", [(unit_tet, 5), (kuhn_cube_2x2x2, 3)])
 @pytest.mark.parametrize("kind", ["scaled", "nodal"])
 def test_apply_fp32_matches_oracle(mesh_fn, level, kind):
