@@ -248,23 +248,25 @@ def learned_solves(hhg, torch):
 
 def tensor_solves(hhg, torch):
     """Time to a 1e-9 relative residual with the tensor operator (the
-    tensor-coefficient comparison of Sec. 7: 12 macro tets around the cube
-    centre, level 8, 33.4M unknowns, rotating SPD K of the test inputs,
-    f ~ U[-1,1]): V(3,3) cycles with every component scaled and with every
-    component nodally integrated, FP64 and FP32-in-FP64; best of two runs
-    each (the first run also builds the form's diagonals and coarse inverse)."""
-    from hhg_inputs import cube12, tensor_fields_torch
+    tensor-coefficient comparison of Sec. 7.3: 12 macro tets around the cube
+    centre, level 8, 33.4M unknowns, that comparison's polynomial SPD K,
+    homogeneous Dirichlet data, f ~ U[-1,1]): V(3,3) cycles with every
+    component scaled and with every component nodally integrated, FP64 and
+    FP32-in-FP64; best of two runs each (the first run also builds the form's
+    diagonals and coarse inverse)."""
+    from hhg_inputs import cube12, polynomial_tensor_fields_torch
     level = 8
     log("bench: tensor solves, 12-tet cube level 8")
     X, T = cube12()
     ctx = hhg.Context(X, T, level)
     xyz, dirichlet = ctx.node_coords(level)
-    ctx.set_tensor_coefficient(tensor_fields_torch(xyz, torch))
+    ctx.set_tensor_coefficient(polynomial_tensor_fields_torch(xyz, torch))
     f = np.random.default_rng(5).uniform(-1, 1, xyz.shape[0])
     f[dirichlet] = 0.0
     fd = ctx.from_canonical(level, torch.tensor(f, device="cuda"))
     del xyz
-    out = {"unknowns": ctx.sizes(level)["n_unknowns"], "tol": 1e-9, "cycle": "V(3,3)"}
+    out = {"unknowns": ctx.sizes(level)["n_unknowns"], "tol": 1e-9, "cycle": "V(3,3)",
+           "K": "polynomial SPD tensor of the paper's tensor comparison"}
     for form in ("scaled", "nodal"):
         for mname, mode in (("f64", hhg.SOLVE_F64), ("mixed", hhg.SOLVE_MIXED)):
             best = None

@@ -120,6 +120,34 @@ def tensor_fields_torch(xyz, torch, device="cuda", chunk=1 << 22):
     return out
 
 
+def polynomial_tensor_K(xyz, lib=np):
+    """The polynomial SPD permeability of the paper's tensor comparison
+    (Sec. 7.3): diagonal x^2+2y^2+3z^2+1, 2x^2+3y^2+z^2+1, 3x^2+y^2+2z^2+1,
+    off-diagonal K_xy = -y^2, K_xz = -z^2, K_yz = -x^2.  (n, 3, 3); `lib`
+    numpy or torch (xyz of that library)."""
+    x, y, z = xyz[:, 0], xyz[:, 1], xyz[:, 2]
+    rows = [[x * x + 2 * y * y + 3 * z * z + 1, -y * y, -z * z],
+            [-y * y, 2 * x * x + 3 * y * y + z * z + 1, -x * x],
+            [-z * z, -x * x, 3 * x * x + y * y + 2 * z * z + 1]]
+    return lib.stack([lib.stack(r, 1) for r in rows], 1)
+
+
+def polynomial_tensor_fields_torch(xyz, torch, device="cuda", chunk=1 << 22):
+    """tensor_fields(polynomial_tensor_K(xyz)) with torch on `device` in
+    chunks (same formulas, FP64); returns a (6, n) device tensor."""
+    x = torch.as_tensor(xyz, dtype=torch.float64, device=device)
+    n = x.shape[0]
+    out = torch.empty((6, n), dtype=torch.float64, device=device)
+    for c0 in range(0, n, chunk):
+        K = polynomial_tensor_K(x[c0:c0 + chunk], torch)
+        for i in range(3):
+            out[i, c0:c0 + chunk] = K[:, i, i] - sum(K[:, i, j] for j in range(3) if j != i)
+        out[3, c0:c0 + chunk] = K[:, 0, 1]
+        out[4, c0:c0 + chunk] = K[:, 0, 2]
+        out[5, c0:c0 + chunk] = K[:, 1, 2]
+    return out
+
+
 def uniform_vector(n, seed=None, rng=None, lo=-1.0, hi=1.0):
     """n values uniform in [lo, hi) from default_rng(seed) (or a given stream)."""
     if rng is None:

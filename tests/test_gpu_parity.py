@@ -9,7 +9,7 @@ import pytest
 
 from hhg_inputs import (unit_tet, regular_tet, flat_tet, kuhn_cube, kuhn_cube_2x2x2, cube12, smooth_k,
                         sigmoid_k, lognormal_params, lognormal_k, uniform_vector, affine_k, tensor_K,
-                        tensor_fields)
+                        tensor_fields, polynomial_tensor_K)
 from oracle import oracle as O
 
 torch = pytest.importorskip("torch")
@@ -254,6 +254,33 @@ def test_solve_tensor_matches_oracle(form, mode):
     assert np.linalg.norm(r) <= 1.01e-10 * np.linalg.norm(f[om.unknowns])
     assert np.linalg.norm(got - ref) <= 1e-7 * np.linalg.norm(ref)
     assert np.all(got[om.dirichlet] == 0.0)
+
+
+@pytest.mark.parametrize("form", ["scaled", "nodal"])
+def test_solve_tensor_polynomial_K_matches_oracle(form):
+    """The polynomial permeability of the paper's tensor comparison (negative
+    off-diagonal entries, so three of the six component fields are negative):
+    FP64 solve to 1e-10 against the oracle's direct solution."""
+    import scipy.sparse.linalg as spla
+    X, T = cube12()
+    level = 5
+    om = O.Mesh(X, T, level)
+    K6 = tensor_fields(polynomial_tensor_K(om.xyz))
+    assert K6[3:].max() <= 0.0
+    f = uniform_vector(om.n_nodes, seed=7)
+    f[om.dirichlet] = 0.0
+    ctx = hhg.Context(X, T, level)
+    ctx.set_tensor_coefficient(K6)
+    u = ctx.vector(level)
+    st = ctx.solve_tensor(level, ctx.from_canonical(level, _dev(f)), u, form=form, tol=1e-10, max_iter=60,
+                          pre=3, post=3)
+    print(f"polynomial K tensor solve {form}: {st}", flush=True)
+    assert st["rel_residual"] <= 1e-10 and st["status"] == 0
+    op = O.make_tensor_operator(om, K6, form)
+    ref = np.zeros(om.n_nodes)
+    ref[om.unknowns] = spla.spsolve(op.A.tocsc(), f[om.unknowns])
+    got = ctx.to_canonical(level, u).cpu().numpy()
+    assert np.linalg.norm(got - ref) <= 1e-7 * np.linalg.norm(ref)
 
 
 def test_solve_tensor_with_scalar_K_is_the_scalar_solve():

@@ -1,0 +1,41 @@
+"""The seeded input generators: their torch versions (used for node sets too
+large for numpy) give the numpy versions' values, and the tensor fields
+describe SPD tensors."""
+import numpy as np
+import pytest
+
+from hhg_inputs import (lognormal_params, lognormal_k, lognormal_k_torch, tensor_K, tensor_fields,
+                        tensor_fields_torch, polynomial_tensor_K, polynomial_tensor_fields_torch, TENSOR_DIRS)
+
+torch = pytest.importorskip("torch")
+
+
+def _pts(n=2000, seed=0):
+    return np.random.default_rng(seed).uniform(0.0, 1.0, (n, 3))
+
+
+def test_torch_generators_match_numpy():
+    x = _pts()
+    prm = lognormal_params(3, 1.2, 0.1)
+    a = lognormal_k(x, prm)
+    b = lognormal_k_torch(x, lognormal_params(3, 1.2, 0.1), torch, device="cpu").numpy()
+    assert np.abs(a - b).max() <= 1e-13 * np.abs(a).max()
+    a = tensor_fields(tensor_K(x))
+    b = tensor_fields_torch(x, torch, device="cpu").numpy()
+    assert np.abs(a - b).max() <= 1e-13 * np.abs(a).max()
+    a = tensor_fields(polynomial_tensor_K(x))
+    b = polynomial_tensor_fields_torch(x, torch, device="cpu").numpy()
+    assert np.abs(a - b).max() <= 1e-14 * np.abs(a).max()
+
+
+@pytest.mark.parametrize("Kfun", [tensor_K, polynomial_tensor_K])
+def test_tensor_fields_recompose_an_spd_K(Kfun):
+    """sum_m k_m c_m c_m^T gives K back, and K is SPD on the unit cube."""
+    x = _pts(500, 1)
+    K = Kfun(x)
+    k6 = tensor_fields(K)
+    C = np.asarray(TENSOR_DIRS, dtype=np.float64)
+    R = np.einsum("mn,mi,mj->nij", k6, C, C)
+    assert np.abs(R - K).max() <= 1e-13 * np.abs(K).max()
+    assert np.abs(K - np.transpose(K, (0, 2, 1))).max() <= 1e-15 * np.abs(K).max()
+    assert np.linalg.eigvalsh(K).min() > 0.0
