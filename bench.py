@@ -246,6 +246,47 @@ def learned_solves(hhg, torch):
     return out
 
 
+def scalar_form_solves(hhg, torch):
+    """Ten V(3,3) cycles per operator as in the paper's 3D scalar comparison
+    (Sec. 7.2: 6-tet unit cube, level 8 here = 16.6M unknowns,
+    k = cos(m pi xyz) + 2 for m = 3 and 8; homogeneous Dirichlet data,
+    f ~ U[-1,1]): stencil scaling everywhere, the primitive-mixed operator
+    with nodal rows on macro vertices and edges ("scale Vol+Face") and nodal
+    integration, FP64; best of two runs each (the first also builds the
+    operator's diagonals and coarse inverse)."""
+    from hhg_inputs import kuhn_cube, cosine_k
+    level = 8
+    log("bench: scalar operator comparison, 6-tet cube level 8")
+    X, T = kuhn_cube()
+    ctx = hhg.Context(X, T, level)
+    xyz, dirichlet = ctx.node_coords(level)
+    f = np.random.default_rng(6).uniform(-1, 1, xyz.shape[0])
+    f[dirichlet] = 0.0
+    fd = ctx.from_canonical(level, torch.tensor(f, device="cuda"))
+    out = {"unknowns": ctx.sizes(level)["n_unknowns"], "cycles": 10, "cycle": "V(3,3)"}
+    for m in (3, 8):
+        ctx.set_coefficient(cosine_k(xyz, m))
+        res = {}
+        for name, form in (("scaled", "scaled"), ("scale_vol_face", "mixed"), ("nodal", "nodal")):
+            best = None
+            for _ in range(2):
+                u = ctx.vector(level)
+                torch.cuda.synchronize()
+                st = ctx.solve_form(level, fd, u, form=form, nodal_primitives=hhg.PRIM_VERTICES | hhg.PRIM_EDGES,
+                                    tol=0.0, max_iter=10, pre=3, post=3)
+                if best is None or st["seconds"] < best["seconds"]:
+                    best = st
+                del u
+            res[name] = {k2: (float(f"{v:.4g}") if isinstance(v, float) else v) for k2, v in best.items()}
+            log(f"bench: m={m} {name}: {best}")
+        res["relative_tts_scaled"] = round(res["scaled"]["seconds"] / res["nodal"]["seconds"], 3)
+        res["relative_tts_scale_vol_face"] = round(res["scale_vol_face"]["seconds"] / res["nodal"]["seconds"], 3)
+        out[f"m{m}"] = res
+    del ctx, fd
+    torch.cuda.empty_cache()
+    return out
+
+
 def tensor_solves(hhg, torch):
     """Time to a 1e-9 relative residual with the tensor operator (the
     tensor-coefficient comparison of Sec. 7.3: 12 macro tets around the cube
@@ -296,6 +337,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--k48-apply-only", action="store_true",
                     help="only time the 48-tet level-8 applies (tuning runs)")
+    ap.add_argument("--form-solves", action="store_true",
+                    help="only the scalar operator comparison (6-tet cube, level 8, ten V(3,3) cycles)")
     ap.add_argument("--tensor-solves", action="store_true",
                     help="only the tensor-operator solves (12-tet cube, level 8)")
     ap.add_argument("--k48-solves", action="store_true",
@@ -322,6 +365,9 @@ def main():
 
     if args.k48_apply_only:
         print(json.dumps(kuhn48_applies(hhg, torch, args.steps, solves=False)))
+        return
+    if args.form_solves:
+        print(json.dumps(scalar_form_solves(hhg, torch)))
         return
     if args.tensor_solves:
         print(json.dumps(tensor_solves(hhg, torch)))
@@ -401,6 +447,7 @@ def main():
 
         extra["kuhn48_l8"] = kuhn48_applies(hhg, torch, args.steps, solves=True)
         extra["learned_l8"] = learned_solves(hhg, torch)
+        extra["forms_6tet_l8"] = scalar_form_solves(hhg, torch)
         extra["tensor_cube12_l8"] = tensor_solves(hhg, torch)
     out["extra"] = extra
     if not args.no_cpu:

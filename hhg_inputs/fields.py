@@ -13,6 +13,12 @@ def smooth_k(xyz):
     return 1.0 + 0.5 * np.sin(2 * np.pi * x) * np.sin(2 * np.pi * y) * np.sin(2 * np.pi * z)
 
 
+def cosine_k(xyz, m):
+    """k = cos(m pi x y z) + 2, in [1, 3] (the scalar coefficient of the
+    paper's 3D scalar comparison, Sec. 7.2, with m = 3 or 8)."""
+    return np.cos(m * np.pi * xyz[:, 0] * xyz[:, 1] * xyz[:, 2]) + 2.0
+
+
 def affine_k(xyz, c=(2.0, 3.0, 5.0), c0=1.0):
     """k = 2x + 3y + 5z + 1 (the affine coefficient of the reproduction example)."""
     return c0 + xyz @ np.asarray(c, dtype=np.float64)

@@ -75,6 +75,8 @@ typedef struct hhg_ctx_s *hhg_ctx;
 typedef enum { HHG_F64 = 0, HHG_F32 = 1 } hhg_dtype;
 typedef enum { HHG_JACOBI = 0, HHG_CHEBYSHEV = 1, HHG_LEARNED = 2 } hhg_smoother;
 typedef enum { HHG_SOLVE_F64 = 0, HHG_SOLVE_MIXED = 1, HHG_SOLVE_LEARNED = 2 } hhg_solve_mode;
+/* scalar operator of hhg_solve_form */
+typedef enum { HHG_FORM_SCALED = 0, HHG_FORM_NODAL = 1, HHG_FORM_MIXED = 2 } hhg_form;
 
 /* flags of hhg_create_macro */
 #define HHG_FLAG_NO_MODIFICATION 1u  /* disable the Sec. 4.1 modification (on by default) */
@@ -261,6 +263,21 @@ hhg_status hhg_solve(hhg_ctx ctx, int32_t level, hhg_solve_mode mode, int32_t pr
 hhg_status hhg_solve_tensor(hhg_ctx ctx, int32_t level, int32_t form, hhg_solve_mode mode, int32_t pre,
                             int32_t post, double tol, int32_t max_iter, const double *f, double *u,
                             hhg_solve_stats *stats, void *stream);
+
+/* hhg_solve with the scalar coefficient on another discretisation of the
+ * same problem on every level of the cycle (the comparison of Sec. 7):
+ *   HHG_FORM_SCALED  exactly hhg_solve (all modes);
+ *   HHG_FORM_NODAL   the nodal-integration operator (eq. (standardfe));
+ *   HHG_FORM_MIXED   the primitive-mixed a_{h;I} of Sec. 5 eq. (modst), nodal
+ *                    rows on the primitives in nodal_primitives (1 vertices,
+ *                    2 edges, 4 faces; the paper's "scale Vol+Face" is 1|2).
+ * The nodal and mixed forms take HHG_SOLVE_F64 or HHG_SOLVE_MIXED, smooth
+ * with Chebyshev on their own diagonal and Gershgorin bound and build their
+ * dense coarse inverse on first use (again after a new coefficient, coarse
+ * level or primitive set).  HHG_EINVAL for other forms, modes or bits. */
+hhg_status hhg_solve_form(hhg_ctx ctx, int32_t level, int32_t form, int32_t nodal_primitives,
+                          hhg_solve_mode mode, int32_t pre, int32_t post, double tol, int32_t max_iter,
+                          const double *f, double *u, hhg_solve_stats *stats, void *stream);
 
 /* Learned smoothing correction (not in the paper).  Per interior node i of a
  * macro tet, a network maps the 15-point neighbourhood features

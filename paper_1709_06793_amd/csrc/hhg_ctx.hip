@@ -260,10 +260,11 @@ struct Level {
     double *k64 = nullptr, *invd64 = nullptr;
     float *k32 = nullptr, *invd32 = nullptr;
     double lam = 0.0;
-    // tensor forms (0 scaled, 1 nodal): inverse diagonal and Gershgorin bound
-    double *tinvd64[2] = {nullptr, nullptr};
-    float *tinvd32[2] = {nullptr, nullptr};
-    double tlam[2] = {0.0, 0.0};
+    // the other operators a cycle can run on (index op - 1, op as
+    // hhg_ctx_s::op): inverse diagonal and Gershgorin bound
+    double *oinvd64[4] = {nullptr, nullptr, nullptr, nullptr};
+    float *oinvd32[4] = {nullptr, nullptr, nullptr, nullptr};
+    double olam[4] = {0.0, 0.0, 0.0, 0.0};
     // work vectors
     double *r64 = nullptr, *d64 = nullptr, *f64 = nullptr, *u64 = nullptr;
     float *r32 = nullptr, *d32 = nullptr, *f32 = nullptr, *u32 = nullptr;
@@ -315,12 +316,17 @@ struct hhg_ctx_s {
     double *dscalar = nullptr;  // device scalars
     double *hscalar = nullptr;  // pinned host scalars
     int *dflag = nullptr;
-    // coarse solves: dense inverse over the coarse unknowns of the operator
-    // the V-cycle runs on (op: 0 scalar, 1 tensor scaled, 2 tensor nodal)
+    // the operator residuals, smoothers and coarse solves run on: 0 scalar
+    // scaled (with the modification), 1 tensor scaled, 2 tensor nodal, 3
+    // scalar nodal, 4 primitive-mixed with nodal rows on mix_mask
     int op = 0;
-    CoarseInv co[3];
-    int tco_level[2] = {-1, -1};  // coarse level of the tensor forms' inverses
-    bool tready[2] = {false, false};
+    int mix_mask = 0;
+    CoarseInv co[5];  // dense coarse inverses per operator
+    // solver state of operators 1..4 (index op - 1): built, for which coarse
+    // level, and for the mixed operator which primitive mask
+    bool oready[4] = {false, false, false, false};
+    int oco_level[4] = {-1, -1, -1, -1};
+    int omask = 0;
     std::string err;
     // learned correction
     LearnedState learned;
@@ -1160,10 +1166,14 @@ hhg_status residual_t(hhg_ctx c, int l, const T *f, const T *u, T *r, double *no
 {
     LevelView<T> V = view<T>(c, l);
     int np = 0;
-    if (c->op) {
+    if (c->op == 1 || c->op == 2) {
         // a tensor form (its partial count was checked against the buffer
         // when its solver state was built)
         HIPCHK(c, launch_tensor<T>(V, c->op - 1, MODE_RESID, u, f, r, c->partial, &np, st));
+    } else if (c->op == 3 || c->op == 4) {
+        // the scalar nodal or primitive-mixed form (the scaled residual's grids)
+        HIPCHK(c, launch_scalar_form<T>(V, corr<T>(c, l), c->op - 2, MODE_RESID, c->mix_mask, u, f, r, c->partial,
+                                        &np, st));
     } else {
         HIPCHK(c, launch_scaled<T>(V, MODE_RESID, u, f, r, c->partial, &np, st));
         CorrView<T> C = corr<T>(c, l);
@@ -1179,21 +1189,21 @@ hhg_status residual_t(hhg_ctx c, int l, const T *f, const T *u, T *r, double *no
     return HHG_OK;
 }
 
-template <typename T> T *tinvd(Level &L, int form);
-template <> double *tinvd<double>(Level &L, int form) { return L.tinvd64[form]; }
-template <> float *tinvd<float>(Level &L, int form) { return L.tinvd32[form]; }
+template <typename T> T *oinvd(Level &L, int q);
+template <> double *oinvd<double>(Level &L, int q) { return L.oinvd64[q]; }
+template <> float *oinvd<float>(Level &L, int q) { return L.oinvd32[q]; }
 
-// smoothing with a tensor form: Jacobi, or the Chebyshev iteration of the
-// scalar operator (same interval from the form's bound) as residual plus
-// update passes
+// smoothing with an operator other than the scaled one: Jacobi, or the
+// Chebyshev iteration of the scaled operator (same interval from the
+// operator's own bound) as residual plus update passes
 template <typename T>
-hhg_status smooth_tensor_t(hhg_ctx c, int l, hhg_smoother sm, int sweeps, double omega, const T *f, T *u,
-                           hipStream_t st)
+hhg_status smooth_other_t(hhg_ctx c, int l, hhg_smoother sm, int sweeps, double omega, const T *f, T *u,
+                          hipStream_t st)
 {
     Level &L = c->lv[l];
     const int form = c->op - 1;
     T *r = work_r<T>(L), *d = work_d<T>(L);
-    const T *id = tinvd<T>(L, form);
+    const T *id = oinvd<T>(L, form);
     if (sm == HHG_JACOBI) {
         for (int s = 0; s < sweeps; ++s) {
             TRY(residual_t<T>(c, l, f, u, r, nullptr, st));
@@ -1201,9 +1211,35 @@ hhg_status smooth_tensor_t(hhg_ctx c, int l, hhg_smoother sm, int sweeps, double
         }
         return HHG_OK;
     }
-    const double a = 0.1 * L.tlam[form], b = L.tlam[form];
+    const double a = 0.1 * L.olam[form], b = L.olam[form];
     const double theta = 0.5 * (b + a), delta = 0.5 * (b - a), sigma = theta / delta;
     double rho = 1.0 / sigma;
+    if (c->op == 4) {
+        // the mixed form: fused sweeps as for the scaled operator (the
+        // iterate alternates between u and r)
+        const LevelView<T> V = view<T>(c, l);
+        const CorrView<T> C = corr<T>(c, l);
+        T *cur = u, *nxt = r;
+        for (int s = 0; s < sweeps; ++s) {
+            ChebArgs<T> cb;
+            cb.d = d;
+            cb.invd = id;
+            if (s == 0) {
+                cb.first = 1;
+                cb.c_r = (T)(1.0 / theta);
+            } else {
+                const double rn = 1.0 / (2.0 * sigma - rho);
+                cb.c_old = (T)(rn * rho);
+                cb.c_r = (T)(2.0 * rn / delta);
+                rho = rn;
+            }
+            HIPCHK(c, launch_cheb_sweep_mixed<T>(V, C, c->mix_mask, cur, f, nxt, cb, st));
+            std::swap(cur, nxt);
+        }
+        if (cur != u)
+            HIPCHK(c, hipMemcpyAsync(u, cur, L.n_slots * sizeof(T), hipMemcpyDeviceToDevice, st));
+        return HHG_OK;
+    }
     for (int s = 0; s < sweeps; ++s) {
         T c_old = T(0), c_r = (T)(1.0 / theta);
         if (s > 0) {
@@ -1213,7 +1249,7 @@ hhg_status smooth_tensor_t(hhg_ctx c, int l, hhg_smoother sm, int sweeps, double
             rho = rn;
         }
         TRY(residual_t<T>(c, l, f, u, r, nullptr, st));
-        HIPCHK(c, launch_cheb_update<T>(u, d, r, id, c_old, c_r, s == 0, L.n_slots, st));
+        HIPCHK(c, launch_cheb_update<T>(u, d, r, id, c_old, c_r, L.n_slots, st));
     }
     return HHG_OK;
 }
@@ -1222,7 +1258,7 @@ template <typename T>
 hhg_status smooth_t(hhg_ctx c, int l, hhg_smoother sm, int sweeps, double omega, const T *f, T *u,
                     hipStream_t st)
 {
-    if (c->op) return smooth_tensor_t<T>(c, l, sm, sweeps, omega, f, u, st);
+    if (c->op) return smooth_other_t<T>(c, l, sm, sweeps, omega, f, u, st);
     Level &L = c->lv[l];
     T *r = work_r<T>(L), *d = work_d<T>(L);
     const T *id = invd<T>(L);
@@ -1540,9 +1576,12 @@ hhg_status build_coarse(hhg_ctx c, hipStream_t st, int op = 0)
         for (int p = coff[col]; p < coff[col + 1]; ++p) e[cslot[p]] = 1.0;
         HIPCHK(c, hipMemcpyAsync(de, e.data(), L.n_slots * 8, hipMemcpyHostToDevice, st));
         if (op == 0) TRY(apply_scaled_t<double>(c, c->coarse, de, dy, st));
-        else
+        else if (op <= 2)
             HIPCHK(c, launch_tensor<double>(view<double>(c, c->coarse), op - 1, MODE_APPLY, de, nullptr, dy, nullptr,
                                             nullptr, st));
+        else
+            HIPCHK(c, launch_scalar_form<double>(view<double>(c, c->coarse), corr<double>(c, c->coarse), op - 2,
+                                                 MODE_APPLY, c->mix_mask, de, nullptr, dy, nullptr, nullptr, st));
         HIPCHK(c, hipMemcpyAsync(y.data(), dy, L.n_slots * 8, hipMemcpyDeviceToHost, st));
         HIPCHK(c, hipStreamSynchronize(st));
         for (int row = 0; row < nu; ++row) A[(size_t)row * nu + col] = y[gather[row]];
@@ -1891,6 +1930,7 @@ hhg_status hhg_set_coefficient(hhg_ctx c, const double *k, int on_device, void *
         }
     }
     c->have_k = true;
+    c->oready[2] = c->oready[3] = false;  // the nodal and mixed solvers depend on k
     TRY(build_coarse(c, st));
     return HHG_OK;
 }
@@ -2026,7 +2066,7 @@ hhg_status hhg_set_tensor_coefficient(hhg_ctx c, const double *k6, int on_device
     HIPCHK(c, hipStreamSynchronize(st));
     dfree(c, dk);
     c->have_tk = true;
-    c->tready[0] = c->tready[1] = false;
+    c->oready[0] = c->oready[1] = false;
     return HHG_OK;
 }
 
@@ -2257,36 +2297,47 @@ struct OpScope {
     ~OpScope() { c->op = 0; }
 };
 
-// inverse diagonals, Gershgorin bounds and the coarse inverse of a tensor form
-hhg_status ensure_tensor_solver(hhg_ctx c, int form)
+// inverse diagonals, Gershgorin bounds and the coarse inverse of operator op
+// (1..4 as hhg_ctx_s::op; the mixed operator for c->mix_mask)
+hhg_status ensure_op_solver(hhg_ctx c, int op)
 {
-    if (c->tready[form] && c->tco_level[form] == c->coarse) return HHG_OK;
+    const int q = op - 1;
+    if (c->oready[q] && c->oco_level[q] == c->coarse && (op != 4 || c->omask == c->mix_mask)) return HHG_OK;
     hipStream_t st = c->stream;
     // the levels a cycle visits (below the coarse level there may be no rows)
     for (int l = c->coarse; l <= c->max_level; ++l) {
         Level &L = c->lv[l];
         if (tensor_partial_count(L.n, c->topo.nt, L.n_shared) > c->partial_cap)
-            return fail(c, HHG_EINVAL, "level %d: reduction buffer too small for the tensor kernels", l);
-        if (!L.tinvd64[form]) {
-            TRY(dalloc(c, &L.tinvd64[form], L.n_slots));
-            TRY(dalloc(c, &L.tinvd32[form], L.n_slots));
+            return fail(c, HHG_EINVAL, "level %d: reduction buffer too small for the diagonal kernels", l);
+        if (!L.oinvd64[q]) {
+            TRY(dalloc(c, &L.oinvd64[q], L.n_slots));
+            TRY(dalloc(c, &L.oinvd32[q], L.n_slots));
         }
-        // slots without a row (Dirichlet, padding) keep 1: their residual is 0
-        HIPCHK(c, launch_fill<double>(L.tinvd64[form], 1.0, L.n_slots, st));
+        if (op == 4) {
+            // the scaled operator's diagonal (with its modification) on every
+            // row, the nodal one on the rows of the chosen primitives
+            HIPCHK(c, hipMemcpyAsync(L.oinvd64[q], L.invd64, L.n_slots * 8, hipMemcpyDeviceToDevice, st));
+            HIPCHK(c, launch_invert_diag<double>(L.oinvd64[q], L.n_slots, st));
+        } else {
+            // slots without a row (Dirichlet, padding) keep 1: their residual is 0
+            HIPCHK(c, launch_fill<double>(L.oinvd64[q], 1.0, L.n_slots, st));
+        }
+        // form q: 0 / 1 the tensor forms, 2 scalar nodal, 3 the mixed operator's nodal rows
         int np = 0;
-        HIPCHK(c, launch_tensor_diag(view<double>(c, l), form, L.tinvd64[form], c->partial, &np, st));
+        HIPCHK(c, launch_form_diag(view<double>(c, l), q, c->mix_mask, L.oinvd64[q], c->partial, &np, st));
         HIPCHK(c, launch_reduce(c->partial, np, 1, c->dscalar, st));
         HIPCHK(c, hipMemcpyAsync(c->hscalar, c->dscalar, sizeof(double), hipMemcpyDeviceToHost, st));
         HIPCHK(c, hipStreamSynchronize(st));
-        L.tlam[form] = c->hscalar[0];
-        if (!(L.tlam[form] > 0.0) || !std::isfinite(L.tlam[form]))
-            return fail(c, HHG_ECOEF, "level %d: tensor operator has a non-positive diagonal", l);
-        HIPCHK(c, launch_invert_diag<double>(L.tinvd64[form], L.n_slots, st));
-        HIPCHK(c, launch_convert<double, float>(L.tinvd64[form], L.tinvd32[form], L.n_slots, st));
+        L.olam[q] = op == 4 ? std::max(L.lam, c->hscalar[0]) : c->hscalar[0];
+        if (!(L.olam[q] > 0.0) || !std::isfinite(L.olam[q]))
+            return fail(c, HHG_ECOEF, "level %d: operator %d has a non-positive diagonal", l, op);
+        HIPCHK(c, launch_invert_diag<double>(L.oinvd64[q], L.n_slots, st));
+        HIPCHK(c, launch_convert<double, float>(L.oinvd64[q], L.oinvd32[q], L.n_slots, st));
     }
-    TRY(build_coarse(c, st, 1 + form));
-    c->tco_level[form] = c->coarse;
-    c->tready[form] = true;
+    TRY(build_coarse(c, st, op));
+    c->oco_level[q] = c->coarse;
+    if (op == 4) c->omask = c->mix_mask;
+    c->oready[q] = true;
     return HHG_OK;
 }
 }  // namespace
@@ -2309,8 +2360,30 @@ hhg_status hhg_solve_tensor(hhg_ctx c, int32_t level, int32_t form, hhg_solve_mo
     if (form != 0 && form != 1) return fail(c, HHG_EINVAL, "form must be 0 (scaled) or 1 (nodal)");
     if (mode != HHG_SOLVE_F64 && mode != HHG_SOLVE_MIXED)
         return fail(c, HHG_EINVAL, "tensor solves take HHG_SOLVE_F64 or HHG_SOLVE_MIXED");
-    TRY(ensure_tensor_solver(c, form));
+    TRY(ensure_op_solver(c, 1 + form));
     OpScope scope(c, 1 + form);
+    return solve_impl(c, level, mode, pre, post, tol, max_iter, f, u, stats, stream);
+}
+
+hhg_status hhg_solve_form(hhg_ctx c, int32_t level, int32_t form, int32_t nodal_primitives, hhg_solve_mode mode,
+                          int32_t pre, int32_t post, double tol, int32_t max_iter, const double *f, double *u,
+                          hhg_solve_stats *stats, void *stream)
+{
+    TRY(check_level(c, level));
+    NEED_K(c);
+    if (form == HHG_FORM_SCALED) {
+        if (mode == HHG_SOLVE_LEARNED && !c->learned.ready) return fail(c, HHG_ESTATE, "no learned weights set");
+        return solve_impl(c, level, mode, pre, post, tol, max_iter, f, u, stats, stream);
+    }
+    if (form != HHG_FORM_NODAL && form != HHG_FORM_MIXED) return fail(c, HHG_EINVAL, "bad form");
+    if (form == HHG_FORM_MIXED && (nodal_primitives & ~7))
+        return fail(c, HHG_EINVAL, "nodal_primitives must be a combination of 1, 2 and 4");
+    if (mode != HHG_SOLVE_F64 && mode != HHG_SOLVE_MIXED)
+        return fail(c, HHG_EINVAL, "nodal and mixed forms take HHG_SOLVE_F64 or HHG_SOLVE_MIXED");
+    const int op = form == HHG_FORM_NODAL ? 3 : 4;
+    c->mix_mask = form == HHG_FORM_MIXED ? nodal_primitives : 0;
+    TRY(ensure_op_solver(c, op));
+    OpScope scope(c, op);
     return solve_impl(c, level, mode, pre, post, tol, max_iter, f, u, stats, stream);
 }
 

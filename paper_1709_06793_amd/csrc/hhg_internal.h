@@ -135,14 +135,21 @@ hipError_t launch_tensor(const LevelView<T> &L, int form, int mode, const T *u, 
                          int *n_partial, hipStream_t st);
 // partial entries launch_tensor (MODE_RESID) and launch_tensor_diag produce
 int tensor_partial_count(int n, int n_tet, int n_shared);
-// diagonal of a tensor form (interior and shared rows; other slots untouched)
-// and per-block Gershgorin maxima of D^{-1} A in partial[0 .. *n_partial)
-hipError_t launch_tensor_diag(const LevelView<double> &L, int form, double *diag, double *partial, int *n_partial,
-                              hipStream_t st);
-// Chebyshev step from a residual over n slots
+// diagonal of a form (0 scaled tensor, 1 nodal tensor, 2 scalar nodal: all
+// interior and shared rows; 3: only the shared rows on the primitives in
+// mask, with nodal coefficients) and per-block Gershgorin maxima of D^{-1} A
+// in partial[0 .. *n_partial); other slots untouched
+hipError_t launch_form_diag(const LevelView<double> &L, int form, int mask, double *diag, double *partial,
+                            int *n_partial, hipStream_t st);
+// one fused Chebyshev sweep (as launch_cheb_sweep) of the primitive-mixed form
 template <typename T>
-hipError_t launch_cheb_update(T *u, T *d, const T *r, const T *invd, T c_old, T c_r, int first, int64_t n,
-                              hipStream_t st);
+hipError_t launch_cheb_sweep_mixed(const LevelView<T> &L, const CorrView<T> &C, int nodal_mask, const T *u,
+                                   const T *f, T *u_new, const ChebArgs<T> &cb, hipStream_t st);
+// the scalar nodal form (form 1) or the primitive-mixed form (form 2) in
+// MODE_APPLY or MODE_RESID (per-block sums of squares in partial)
+template <typename T>
+hipError_t launch_scalar_form(const LevelView<T> &L, const CorrView<T> &C, int form, int mode, int nodal_mask,
+                              const T *u, const T *f, T *y, double *partial, int *n_partial, hipStream_t st);
 // the primitive-mixed operator (Sec. 5 eq. (modst)): nodal-integration rows
 // for the nodes of the primitives in nodal_mask (1 vertices, 2 edges, 4
 // faces), scaled rows (with their modification corrections) elsewhere

@@ -1031,6 +1031,46 @@ hipError_t launch_mixed(const LevelView<T> &L, const CorrView<T> &C, const T *u,
     return hipGetLastError();
 }
 
+// the scalar nodal form (form 1) or the primitive-mixed form (form 2, nodal
+// rows on the primitives in nodal_mask) in MODE_APPLY or MODE_RESID; in
+// residual mode per-block sums of squares go to partial[0 .. *n_partial)
+template <typename T>
+hipError_t launch_scalar_form(const LevelView<T> &L, const CorrView<T> &C, int form, int mode, int nodal_mask,
+                              const T *u, const T *f, T *y, double *partial, int *n_partial, hipStream_t st)
+{
+    const bool resid = mode == MODE_RESID;
+    const int gs = blocks_for(L.n_shared);
+    int gv;
+    if (form == 1) {
+        gv = march_grid(L.n_tet, L.vpt, L.bpt2);  // the nodal rows' one-row-per-lane grid
+        if (resid) {
+            launch_march<T, MODE_RESID, 1>(L, u, f, y, partial, st);
+            launch_shared_rows<T, MODE_RESID>(L, L.sh_cn, u, f, y, partial + gv, st);
+        } else {
+            launch_march<T, MODE_APPLY, 1>(L, u, f, y, partial, st);
+            launch_shared_rows<T, MODE_APPLY>(L, L.sh_cn, u, f, y, partial, st);
+        }
+        if (n_partial) *n_partial = gv + gs;
+        return hipGetLastError();
+    }
+    gv = march_blocks(L);
+    const int gc = blocks_for(C.n_rows);
+    if (resid) {
+        launch_march<T, MODE_RESID, 0>(L, u, f, y, partial, st);
+        launch_shared_rows<T, MODE_RESID>(L, L.sh_cs, u, f, y, partial + gv, st, ChebArgs<T>(), L.sh_cn, nodal_mask);
+        if (C.n_rows)
+            k_correction<T, MODE_RESID><<<gc, BLOCK, 0, st>>>(C, u, y, partial + gv + gs, ChebArgs<T>(), nodal_mask);
+    } else {
+        launch_march<T, MODE_APPLY, 0>(L, u, f, y, partial, st);
+        launch_shared_rows<T, MODE_APPLY>(L, L.sh_cs, u, f, y, partial, st, ChebArgs<T>(), L.sh_cn, nodal_mask);
+        if (C.n_rows)
+            k_correction<T, MODE_APPLY><<<gc, BLOCK, 0, st>>>(C, u, y, partial, ChebArgs<T>(), nodal_mask);
+    }
+    if (n_partial) *n_partial = gv + gs + (C.n_rows ? gc : 0);
+    return hipGetLastError();
+}
+
+
 template <typename T>
 hipError_t launch_cheb_sweep(const LevelView<T> &L, const CorrView<T> &C, const T *u, const T *f, T *u_new,
                              const ChebArgs<T> &cb, hipStream_t st)
@@ -1039,6 +1079,21 @@ hipError_t launch_cheb_sweep(const LevelView<T> &L, const CorrView<T> &C, const 
     launch_shared_rows<T, MODE_CHEB>(L, L.sh_cs, u, f, u_new, nullptr, st, cb);
     if (C.n_rows)
         k_correction<T, MODE_CHEB><<<blocks_for(C.n_rows), BLOCK, 0, st>>>(C, u, u_new, nullptr, cb, 0);
+    return hipGetLastError();
+}
+
+// the same fused sweep for the primitive-mixed form: nodal coefficients on
+// the shared rows of the primitives in nodal_mask, whose modification rows
+// are skipped.  (A fused sweep of the nodal form needs 244 registers per lane
+// and ran slower than its residual plus update passes.)
+template <typename T>
+hipError_t launch_cheb_sweep_mixed(const LevelView<T> &L, const CorrView<T> &C, int nodal_mask, const T *u,
+                                   const T *f, T *u_new, const ChebArgs<T> &cb, hipStream_t st)
+{
+    launch_march<T, MODE_CHEB, 0>(L, u, f, u_new, nullptr, st, cb);
+    launch_shared_rows<T, MODE_CHEB>(L, L.sh_cs, u, f, u_new, nullptr, st, cb, L.sh_cn, nodal_mask);
+    if (C.n_rows)
+        k_correction<T, MODE_CHEB><<<blocks_for(C.n_rows), BLOCK, 0, st>>>(C, u, u_new, nullptr, cb, nodal_mask);
     return hipGetLastError();
 }
 
@@ -1578,13 +1633,14 @@ __global__ __launch_bounds__(BLOCK) void k_tensor_nodal_interior(LevelView<T> L,
     }
 }
 
-// Diagonal of either tensor form on interior rows (FP64, at set-up): with the
+// Diagonal of a form on interior rows (FP64, at set-up): FORM 0 the scaled
+// tensor form, 1 the nodal tensor form, 2 the scalar nodal form.  With the
 // row written as sum_d c_d (u_d - u_0), a_00 = -sum_d c_d and a_0d = c_d.
 // Stores a_00 in diag and the block's largest Gershgorin bound
 // 1 + sum_d |c_d| / a_00 of D^{-1} A in partial.
 template <int FORM>
-__global__ __launch_bounds__(BLOCK) void k_tensor_diag(LevelView<double> L, double *__restrict__ diag,
-                                                       double *__restrict__ partial, int n_seg)
+__global__ __launch_bounds__(BLOCK) void k_form_diag(LevelView<double> L, double *__restrict__ diag,
+                                                     double *__restrict__ partial, int n_seg)
 {
     int t = 0, sd = 0, k0 = 0, k1 = -1, tet;
     const int n = L.n;
@@ -1606,12 +1662,14 @@ __global__ __launch_bounds__(BLOCK) void k_tensor_diag(LevelView<double> L, doub
                         cd[d] = kq[s] + kq[nb[d]];
                     }
                 } else {
-                    for (int m = 0; m < 6; ++m) {
-                        const double *km = L.kt + m * ns + base;
+                    // FORM 1: six components; FORM 2: the scalar k and element matrices
+                    for (int m = 0; m < (FORM == 1 ? 6 : 1); ++m) {
+                        const double *km = (FORM == 1 ? L.kt + m * ns : L.kap) + base;
                         double kk[NDIR + 1];
                         for (int d = 0; d < NDIR; ++d) kk[d] = km[nb[d]];
                         kk[NDIR] = km[s];
-                        const double *w = L.temat + ((int64_t)tet * 6 + m) * TET_EMAT;
+                        const double *w = FORM == 1 ? L.temat + ((int64_t)tet * 6 + m) * TET_EMAT
+                                                    : L.emat + (int64_t)tet * TET_EMAT;
                         for (int ty = 0; ty < NTYPE; ++ty)
                             for (int a = 0; a < 4; ++a) {
                                 double ks = 0.0;
@@ -1637,16 +1695,18 @@ __global__ __launch_bounds__(BLOCK) void k_tensor_diag(LevelView<double> L, doub
     if (threadIdx.x == 0) partial[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = g;
 }
 
-// the same for shared rows from their merged coefficients (tensor pattern),
-// written to every copy
+// the same for shared rows from merged coefficients of `width` entries,
+// written to every copy; with a nonzero mask only the rows of nodes on those
+// macro primitives
 __global__ __launch_bounds__(BLOCK) void k_shared_diag(LevelView<double> L, const double *__restrict__ coef,
-                                                       double *__restrict__ diag, double *__restrict__ partial)
+                                                       int width, int mask, double *__restrict__ diag,
+                                                       double *__restrict__ partial)
 {
     const int q = blockIdx.x * BLOCK + threadIdx.x;
     double g = 0.0;
-    if (q < L.n_shared) {
+    if (q < L.n_shared && (!mask || (L.sh_prim[q] & mask))) {
         double dg = 0.0, ab = 0.0;
-        for (int e = 0; e < L.sh_wt; ++e) {
+        for (int e = 0; e < width; ++e) {
             const double c = coef[(int64_t)e * L.n_shared + q];
             dg -= c;
             ab += fabs(c);
@@ -1814,45 +1874,32 @@ int tensor_partial_count(int n, int n_tet, int n_shared)
     return (int)(g.x * g.y) + blocks_for(n_shared);
 }
 
-hipError_t launch_tensor_diag(const LevelView<double> &L, int form, double *diag, double *partial, int *n_partial,
-                              hipStream_t st)
+hipError_t launch_form_diag(const LevelView<double> &L, int form, int mask, double *diag, double *partial,
+                            int *n_partial, hipStream_t st)
 {
-    int n_seg = 0;
-    const dim3 g = stored_grid(L.n, L.n_tet, n_seg);
-    const int gi = (int)(g.x * g.y);
-    if (g.x) {
-        if (form == 0) k_tensor_diag<0><<<g, BLOCK, 0, st>>>(L, diag, partial, n_seg);
-        else k_tensor_diag<1><<<g, BLOCK, 0, st>>>(L, diag, partial, n_seg);
+    int gi = 0;
+    if (form <= 1) {
+        int n_seg = 0;
+        const dim3 g = stored_grid(L.n, L.n_tet, n_seg);
+        gi = (int)(g.x * g.y);
+        if (g.x) {
+            if (form == 0) k_form_diag<0><<<g, BLOCK, 0, st>>>(L, diag, partial, n_seg);
+            else k_form_diag<1><<<g, BLOCK, 0, st>>>(L, diag, partial, n_seg);
+        }
+    } else if (form == 2) {
+        int n_seg = 0;
+        const dim3 g = stored_grid(L.n, L.n_tet, n_seg);
+        gi = (int)(g.x * g.y);
+        if (g.x) k_form_diag<2><<<g, BLOCK, 0, st>>>(L, diag, partial, n_seg);
     }
     const int gs = blocks_for(L.n_shared);
-    if (gs) k_shared_diag<<<gs, BLOCK, 0, st>>>(L, form == 0 ? L.sh_ct : L.sh_ctn, diag, partial + gi);
+    const double *coef = form == 0 ? L.sh_ct : form == 1 ? L.sh_ctn : L.sh_cn;
+    const int width = form <= 1 ? L.sh_wt : L.sh_w;
+    if (gs) k_shared_diag<<<gs, BLOCK, 0, st>>>(L, coef, width, form == 3 ? mask : 0, diag, partial + gi);
     *n_partial = gi + gs;
     return hipGetLastError();
 }
 
-// Chebyshev step from a residual: d = c_old d + c_r D^{-1} r (d = c_r D^{-1} r
-// on the first step), u += d
-template <typename T>
-__global__ void k_cheb_update(T *__restrict__ u, T *__restrict__ d, const T *__restrict__ r,
-                              const T *__restrict__ invd, T c_old, T c_r, int first, int64_t n)
-{
-    const int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (e >= n) return;
-    const T dn = (first ? T(0) : c_old * d[e]) + c_r * invd[e] * r[e];
-    d[e] = dn;
-    u[e] += dn;
-}
-template <typename T>
-hipError_t launch_cheb_update(T *u, T *d, const T *r, const T *invd, T c_old, T c_r, int first, int64_t n,
-                              hipStream_t st)
-{
-    if (n) k_cheb_update<T><<<blocks_for(n), BLOCK, 0, st>>>(u, d, r, invd, c_old, c_r, first, n);
-    return hipGetLastError();
-}
-template hipError_t launch_cheb_update<double>(double *, double *, const double *, const double *, double, double,
-                                               int, int64_t, hipStream_t);
-template hipError_t launch_cheb_update<float>(float *, float *, const float *, const float *, float, float, int,
-                                              int64_t, hipStream_t);
 template hipError_t launch_store_stencils<double>(const LevelView<double> &, double *, hipStream_t);
 template hipError_t launch_store_stencils<float>(const LevelView<double> &, float *, hipStream_t);
 
@@ -2003,6 +2050,11 @@ hipError_t launch_positive_check(const double *k, int64_t n, int *bad, hipStream
                                              const T *, T *, double *, hipStream_t);               \
     template hipError_t launch_stored<T>(const LevelView<T> &, const CorrView<T> &, const T *, const T *, \
                                          T *, hipStream_t);                                        \
+    template hipError_t launch_cheb_sweep_mixed<T>(const LevelView<T> &, const CorrView<T> &, int,      \
+                                                   const T *, const T *, T *, const ChebArgs<T> &,      \
+                                                   hipStream_t);                                        \
+    template hipError_t launch_scalar_form<T>(const LevelView<T> &, const CorrView<T> &, int, int, int,   \
+                                              const T *, const T *, T *, double *, int *, hipStream_t); \
     template hipError_t launch_mixed<T>(const LevelView<T> &, const CorrView<T> &, const T *, T *, int, \
                                         hipStream_t);                                              \
     template hipError_t launch_cheb_sweep<T>(const LevelView<T> &, const CorrView<T> &, const T *, \

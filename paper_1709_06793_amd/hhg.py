@@ -26,7 +26,7 @@ EXPORTS = [
     "hhg_create_macro", "hhg_destroy", "hhg_last_error", "hhg_vector_size", "hhg_node_coords",
     "hhg_to_canonical", "hhg_from_canonical", "hhg_set_coefficient", "hhg_set_coarse_level",
     "hhg_level_info", "hhg_apply_scaled", "hhg_set_timing", "hhg_read_timing", "hhg_set_kernel_variant", "hhg_apply_nodal", "hhg_apply_mixed", "hhg_store_stencils", "hhg_apply_stored", "hhg_set_tensor_coefficient", "hhg_apply_tensor", "hhg_apply_tensor_nodal", "hhg_residual", "hhg_smooth",
-    "hhg_vcycle", "hhg_solve", "hhg_solve_tensor", "hhg_learned_set_weights", "hhg_learned_set_fallback",
+    "hhg_vcycle", "hhg_solve", "hhg_solve_tensor", "hhg_solve_form", "hhg_learned_set_weights", "hhg_learned_set_fallback",
     "hhg_learned_forward", "hhg_learned_backward", "hhg_learned_loss_grad", "hhg_training_pair",
     "hhg_adam_update",
 ]
@@ -82,6 +82,7 @@ def load():
         "hhg_vcycle": [P, I32, I32, I32, I32, I32, P, P, P, P],
         "hhg_solve": [P, I32, I32, I32, I32, D, I32, P, P, P, P],
         "hhg_solve_tensor": [P, I32, I32, I32, I32, I32, D, I32, P, P, P, P],
+        "hhg_solve_form": [P, I32, I32, I32, I32, I32, I32, D, I32, P, P, P, P],
         "hhg_learned_set_weights": [P, P, I64],
         "hhg_learned_set_fallback": [P, D],
         "hhg_learned_forward": [P, I32, P, P, P],
@@ -280,6 +281,18 @@ class Context:
         st = SolveStats()
         s = self._check(load().hhg_solve_tensor(self._h, level, fc, mode, pre, post, tol, max_iter, _ptr(f), _ptr(u),
                                                 ctypes.byref(st), _stream()))
+        return dict(iterations=st.iterations, fallback=st.fallback, rel_residual=st.rel_residual,
+                    rho=st.rho, seconds=st.seconds, status=s)
+
+    def solve_form(self, level, f, u, form="nodal", nodal_primitives=0, mode=SOLVE_F64, tol=1e-8, max_iter=100,
+                   pre=2, post=2):
+        """hhg_solve_form: the scalar problem on the scaled ("scaled"), nodal
+        ("nodal") or primitive-mixed ("mixed", nodal rows on
+        nodal_primitives) operator."""
+        fc = {"scaled": 0, "nodal": 1, "mixed": 2}[form]
+        st = SolveStats()
+        s = self._check(load().hhg_solve_form(self._h, level, fc, nodal_primitives, mode, pre, post, tol, max_iter,
+                                              _ptr(f), _ptr(u), ctypes.byref(st), _stream()))
         return dict(iterations=st.iterations, fallback=st.fallback, rel_residual=st.rel_residual,
                     rho=st.rho, seconds=st.seconds, status=s)
 

@@ -283,6 +283,42 @@ def test_solve_tensor_polynomial_K_matches_oracle(form):
     assert np.linalg.norm(got - ref) <= 1e-7 * np.linalg.norm(ref)
 
 
+@pytest.mark.parametrize("form,mode", [("nodal", hhg.SOLVE_F64), ("nodal", hhg.SOLVE_MIXED),
+                                       ("mixed", hhg.SOLVE_F64), ("mixed", hhg.SOLVE_MIXED)])
+def test_solve_form_matches_oracle(form, mode):
+    """Multigrid on the nodal-integration operator and on the primitive-mixed
+    a_{h;I} with nodal rows on macro vertices and edges ("scale Vol+Face")
+    on every level: converges to 1e-10 and matches the oracle's direct
+    solution of that operator."""
+    import scipy.sparse.linalg as spla
+    X, T = cube12()
+    level = 5
+    om, k, _, ctx = _setup(cube12, level, kfun=smooth_k)
+    f = uniform_vector(om.n_nodes, seed=8)
+    f[om.dirichlet] = 0.0
+    fd, u = ctx.from_canonical(level, _dev(f)), ctx.vector(level)
+    mask = hhg.PRIM_VERTICES | hhg.PRIM_EDGES
+    with pytest.raises(hhg.HHGError):
+        ctx.solve_form(level, fd, u, form=form, nodal_primitives=mask, mode=hhg.SOLVE_LEARNED)
+    st = ctx.solve_form(level, fd, u, form=form, nodal_primitives=mask, mode=mode, tol=1e-10, max_iter=60,
+                        pre=3, post=3)
+    print(f"{form} solve mode {mode}: {st}", flush=True)
+    assert st["rel_residual"] <= 1e-10 and st["status"] == 0 and st["rho"] < 0.5
+    op = (O.make_operator(om, k, "nodal") if form == "nodal"
+          else O.make_mixed_operator(om, k, (0, 1), modification=True))
+    ref = np.zeros(om.n_nodes)
+    ref[om.unknowns] = spla.spsolve(op.A.tocsc(), f[om.unknowns])
+    got = ctx.to_canonical(level, u).cpu().numpy()
+    r = f[om.unknowns] - op.A @ got[om.unknowns]
+    assert np.linalg.norm(r) <= 1.01e-10 * np.linalg.norm(f[om.unknowns])
+    assert np.linalg.norm(got - ref) <= 1e-7 * np.linalg.norm(ref)
+    # the scaled form through the same entry point is hhg_solve
+    u2, u3 = ctx.vector(level), ctx.vector(level)
+    s2 = ctx.solve_form(level, fd, u2, form="scaled", tol=1e-9, max_iter=40)
+    s3 = ctx.solve(level, fd, u3, tol=1e-9, max_iter=40)
+    assert s2["iterations"] == s3["iterations"] and torch.equal(u2, u3)
+
+
 def test_solve_tensor_with_scalar_K_is_the_scalar_solve():
     """K = k I: the scaled tensor solve takes the scalar solve's cycles (same
     operator on every level, same diagonals and bounds up to rounding)."""
