@@ -99,3 +99,47 @@ MESHES = {
     "kuhn_cube_2x2x2": kuhn_cube_2x2x2,
     "cube12": cube12,
 }
+
+
+# ---------------------------------------------------------------- 2D macro meshes
+# (X, T): X float64 (nv, 2), T int32 (nt, 3), every triangle counter-clockwise.
+
+def _ccw(X, T):
+    T = np.array(T, dtype=np.int32)
+    for t in T:
+        e = X[t[1:]] - X[t[0]]
+        if e[0, 0] * e[1, 1] - e[0, 1] * e[1, 0] < 0:
+            t[1], t[2] = t[2], t[1]
+    return T
+
+
+def obtuse_triangle():
+    """One macro triangle with an obtuse angle (about 120 degrees) at (0.3, 0.25)."""
+    X = np.array([[0.0, 0.0], [1.0, 0.0], [0.3, 0.25]])
+    return X, _ccw(X, [[0, 1, 2]])
+
+
+def square_right4():
+    """Unit square cut into four right isosceles triangles at its centre: no
+    obtuse angle, so the refined Laplacian is an M-matrix."""
+    X = np.array([[0.0, 0.0], [1.0, 0.0], [1.0, 1.0], [0.0, 1.0], [0.5, 0.5]])
+    return X, _ccw(X, [[0, 1, 4], [1, 2, 4], [2, 3, 4], [3, 0, 4]])
+
+
+def square_nondelaunay8():
+    """Unit square in eight triangles that is not Delaunay: the line y = 0.5
+    from (0, 0.5) to (1, 0.5) is an interior macro edge whose two triangles
+    have their obtuse angles (at (0.5, 0.4) and (0.5, 0.6)) facing it; each
+    half of the square is a fan around one of those points."""
+    X = np.array([[0.0, 0.0], [1.0, 0.0], [1.0, 1.0], [0.0, 1.0], [0.0, 0.5], [1.0, 0.5],
+                  [0.5, 0.4], [0.5, 0.6]])
+    T = [[0, 1, 6], [1, 5, 6], [5, 4, 6], [4, 0, 6],
+         [4, 5, 7], [5, 2, 7], [2, 3, 7], [3, 4, 7]]
+    return X, _ccw(X, T)
+
+
+MESHES2D = {
+    "obtuse_triangle": obtuse_triangle,
+    "square_right4": square_right4,
+    "square_nondelaunay8": square_nondelaunay8,
+}
