@@ -287,6 +287,43 @@ def scalar_form_solves(hhg, torch):
     return out
 
 
+def applies_2d(torch, steps):
+    """The 2D variant (Sec. 4.1's exact MA2): the non-Delaunay macro square
+    (8 triangles, four with an obtuse angle) at level 11 (16.8M nodes),
+    sigmoid k with eta = 1000 and slope m = 2000 (steep enough that MA2 still
+    replaces factors at this level); FP64 / FP32 scaled and FP64 nodal
+    applies."""
+    from hhg_inputs import square_nondelaunay8, sigmoid_k
+    from paper_1709_06793_amd import hhg2d
+    level = 11
+    log("bench: 2D applies, non-Delaunay square level 11")
+    X, T = square_nondelaunay8()
+    t0 = time.time()
+    ctx = hhg2d.Context2D(X, T, level)
+    xy, dirichlet = ctx.node_coords()
+    ctx.set_coefficient(sigmoid_k(xy, 1000.0, m=2000.0))
+    setup_s = time.time() - t0
+    sz = ctx.sizes()
+    u = np.random.default_rng(3).uniform(-1, 1, len(xy))
+    u[dirichlet] = 0.0
+    u64 = ctx.from_canonical(torch.tensor(u, device="cuda"))
+    u32 = u64.float()
+    y64, y32 = ctx.vector(), ctx.vector(torch.float32)
+    m1 = time_op(lambda: ctx.apply_scaled(u64, y64), steps, 5, torch)
+    m2 = time_op(lambda: ctx.apply_scaled(u32, y32), steps, 5, torch)
+    m3 = time_op(lambda: ctx.apply_nodal(u64, y64), steps, 5, torch)
+    nu = sz["n_unknowns"]
+    out = {"nodes": sz["n_nodes"], "unknowns": nu, "modified_edges": sz["n_modified"],
+           "setup_s": round(setup_s, 2),
+           "scaled_f64_gdofs": round(nu / m1 / 1e6, 2),
+           "scaled_f64_hbm_frac": round(24 * nu / m1 / 1e6 / HBM_PEAK_GBS, 4),
+           "scaled_f32_gdofs": round(nu / m2 / 1e6, 2),
+           "nodal_f64_gdofs": round(nu / m3 / 1e6, 2)}
+    ctx.close()
+    torch.cuda.empty_cache()
+    return out
+
+
 def tensor_solves(hhg, torch):
     """Time to a 1e-9 relative residual with the tensor operator (the
     tensor-coefficient comparison of Sec. 7.3: 12 macro tets around the cube
@@ -337,6 +374,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--k48-apply-only", action="store_true",
                     help="only time the 48-tet level-8 applies (tuning runs)")
+    ap.add_argument("--applies-2d", action="store_true", help="only the 2D applies (non-Delaunay square, level 11)")
     ap.add_argument("--form-solves", action="store_true",
                     help="only the scalar operator comparison (6-tet cube, level 8, ten V(3,3) cycles)")
     ap.add_argument("--tensor-solves", action="store_true",
@@ -365,6 +403,9 @@ def main():
 
     if args.k48_apply_only:
         print(json.dumps(kuhn48_applies(hhg, torch, args.steps, solves=False)))
+        return
+    if args.applies_2d:
+        print(json.dumps(applies_2d(torch, args.steps)))
         return
     if args.form_solves:
         print(json.dumps(scalar_form_solves(hhg, torch)))
@@ -448,6 +489,7 @@ def main():
         extra["kuhn48_l8"] = kuhn48_applies(hhg, torch, args.steps, solves=True)
         extra["learned_l8"] = learned_solves(hhg, torch)
         extra["forms_6tet_l8"] = scalar_form_solves(hhg, torch)
+        extra["square2d_l11"] = applies_2d(torch, args.steps)
         extra["tensor_cube12_l8"] = tensor_solves(hhg, torch)
     out["extra"] = extra
     if not args.no_cpu:

@@ -6,9 +6,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhhg.so")
-SOURCES = ["hhg_kernels.hip", "hhg_learned.hip", "hhg_ctx.hip"]
+SOURCES = ["hhg_kernels.hip", "hhg_learned.hip", "hhg_ctx.hip", "hhg2d.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
-         # no packed-FP32 instructions (numerics)
+         # no packed-FP32 instructions (some of their forms have given silently
+         # wrong results on this hardware)
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include")]
 

@@ -20,6 +20,8 @@ FLAG_NO_MODIFICATION = 1
 PRIM_VERTICES, PRIM_EDGES, PRIM_FACES = 1, 2, 4
 LEARNED_NPARAM = 817
 WFALLBACK = 1
+# error codes of include/hhg.h
+EINVAL, EMESH, ECOEF, EHIP, ESTATE, ENOMEM = -1, -2, -3, -4, -5, -6
 
 # every symbol include/hhg.h declares
 EXPORTS = [

@@ -16,8 +16,36 @@ def _header_symbols():
     return sorted(set(re.findall(r"^\S.*?\b(hhg_[a-z_0-9]+)\s*\(", src, flags=re.M)))
 
 
+def _header2d_symbols():
+    src = open(os.path.join(ROOT, "include", "hhg2d.h")).read()
+    return sorted(set(re.findall(r"^\S.*?\b(hhg2d_[a-z_0-9]+)\s*\(", src, flags=re.M)))
+
+
 def test_header_and_binding_agree():
     assert _header_symbols() == sorted(hhg.EXPORTS)
+    from paper_1709_06793_amd import hhg2d
+    assert _header2d_symbols() == sorted(hhg2d.EXPORTS2D)
+
+
+def test_library_exports_every_2d_symbol_and_checks_arguments():
+    if not os.path.exists(hhg.LIB_PATH):
+        pytest.skip("libhhg.so not built")
+    import ctypes
+    import numpy as np
+    from paper_1709_06793_amd import hhg2d
+    out = subprocess.run(["nm", "-D", "--defined-only", hhg.LIB_PATH], capture_output=True, text=True).stdout
+    names = {l.split()[-1] for l in out.splitlines() if l.strip()}
+    assert not [s for s in _header2d_symbols() if s not in names]
+    L = hhg2d.load()
+    h = ctypes.c_void_p()
+    X = np.zeros((3, 2))
+    T = np.array([[0, 1, 5]], dtype=np.int32)
+    # bad vertex id and bad level: rejected before any device call
+    assert L.hhg2d_create(X.ctypes.data_as(ctypes.c_void_p), 3, T.ctypes.data_as(ctypes.c_void_p), 1, 2, 0,
+                          ctypes.byref(h)) == hhg.EMESH and not h.value
+    T = np.array([[0, 1, 2]], dtype=np.int32)
+    assert L.hhg2d_create(X.ctypes.data_as(ctypes.c_void_p), 3, T.ctypes.data_as(ctypes.c_void_p), 1, 14, 0,
+                          ctypes.byref(h)) == hhg.EINVAL and not h.value
 
 
 def test_library_exports_every_declared_symbol():
