@@ -188,11 +188,11 @@ double lambda_min_T(const double A[3][3])
 }
 
 // ---------------------------------------------------------------- kernels
-// interior rows: thread = (row j, position i) of triangle blockIdx.y
-template <typename T, int OP>
-__global__ __launch_bounds__(B2) void k2d_interior(int n, int64_t Spad, const T *__restrict__ w,
-                                                   const double *__restrict__ Aall, const T *__restrict__ k,
-                                                   const T *__restrict__ u, T *__restrict__ y)
+// nodal interior rows: thread = (row j, position i) of triangle blockIdx.y;
+// the six incident elements, each mean vertex k times its element row
+template <typename T>
+__global__ __launch_bounds__(B2) void k2d_nodal(int n, int64_t Spad, const double *__restrict__ Aall,
+                                                const T *__restrict__ k, const T *__restrict__ u, T *__restrict__ y)
 {
     const int j = blockIdx.x + 1;
     const int i = blockIdx.z * B2 + threadIdx.x + 1;
@@ -204,42 +204,31 @@ __global__ __launch_bounds__(B2) void k2d_interior(int n, int64_t Spad, const T 
     const int64_t up = n + 1 - j, dn = n + 2 - j;
     const int64_t nb[6] = {s + 1, s + up, s + up - 1, s - 1, s - dn, s - dn + 1};
     const T *ub = u + base, *kb = k + base;
-    const T u0 = ub[s], k0 = kb[s];
+    T uu[7], kk[7];
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+        uu[d] = ub[nb[d]];
+        kk[d] = kb[nb[d]];
+    }
+    uu[6] = ub[s];
+    kk[6] = kb[s];
+    const double *A = Aall + tri * 9;
     T acc = T(0);
-    if (OP == 0) {
-        const T *wt = w + tri * 3;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const T a = (k0 + kb[nb[d]]) * (ub[nb[d]] - u0) + (k0 + kb[nb[d + 3]]) * (ub[nb[d + 3]] - u0);
-            acc += wt[d] * a;
+    for (int e = 0; e < 6; ++e) {
+        int idx[3];
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+            const int di = AROUND[e].off[v][0], dj = AROUND[e].off[v][1];
+            idx[v] = (di == 0 && dj == 0) ? 6 : dir_of(di, dj);
         }
-    } else {
-        // the six incident elements: mean k times the element row
-        T uu[7], kk[7];
+        const int me = AROUND[e].me;
+        const T kbar = (kk[idx[0]] + kk[idx[1]] + kk[idx[2]]) / T(3);
+        T r = T(0);
 #pragma unroll
-        for (int d = 0; d < 6; ++d) {
-            uu[d] = ub[nb[d]];
-            kk[d] = kb[nb[d]];
-        }
-        uu[6] = u0;
-        kk[6] = k0;
-        const double *A = Aall + tri * 9;
-#pragma unroll
-        for (int e = 0; e < 6; ++e) {
-            int idx[3];
-#pragma unroll
-            for (int v = 0; v < 3; ++v) {
-                const int di = AROUND[e].off[v][0], dj = AROUND[e].off[v][1];
-                idx[v] = (di == 0 && dj == 0) ? 6 : dir_of(di, dj);
-            }
-            const int me = AROUND[e].me;
-            const T kbar = (kk[idx[0]] + kk[idx[1]] + kk[idx[2]]) / T(3);
-            T r = T(0);
-#pragma unroll
-            for (int v = 0; v < 3; ++v)
-                if (v != me) r += (T)A[me * 3 + v] * (uu[idx[v]] - u0);
-            acc += kbar * r;
-        }
+        for (int v = 0; v < 3; ++v)
+            if (v != me) r += (T)A[me * 3 + v] * (uu[idx[v]] - uu[6]);
+        acc += kbar * r;
     }
     y[base + s] = acc;
 }
@@ -293,40 +282,37 @@ __global__ __launch_bounds__(B2) void k2d_march(int n, int64_t Spad, int n_seg, 
     }
 }
 
-// shared rows: merged coefficients, written to every copy
+// after the interior kernel, one launch for the rest of the rows (disjoint
+// slot sets): threads [0, n_sh) shared rows from merged coefficients, written
+// to every copy; [n_sh, n_sh + n_corr) the MA2 corrections of interior rows;
+// then the Dirichlet slots (set to 0)
 template <typename T>
-__global__ __launch_bounds__(B2) void k2d_shared(int n_sh, const int32_t *__restrict__ eoff,
-                                                 const int64_t *__restrict__ nbs, const T *__restrict__ coef,
-                                                 const int64_t *__restrict__ self, const int32_t *__restrict__ coff,
-                                                 const int64_t *__restrict__ cslot, const T *__restrict__ u,
-                                                 T *__restrict__ y)
+__global__ __launch_bounds__(B2) void k2d_tail(int n_sh, const int32_t *__restrict__ eoff,
+                                               const int64_t *__restrict__ nbs, const T *__restrict__ coef,
+                                               const int64_t *__restrict__ self, const int32_t *__restrict__ coff,
+                                               const int64_t *__restrict__ cslot, int64_t n_corr,
+                                               const int64_t *__restrict__ crow, const int64_t *__restrict__ cnb,
+                                               const T *__restrict__ cdl, int64_t n_dir,
+                                               const int64_t *__restrict__ dslots, const T *__restrict__ u,
+                                               T *__restrict__ y)
 {
-    const int q = blockIdx.x * B2 + threadIdx.x;
-    if (q >= n_sh) return;
-    const T u0 = u[self[q]];
-    T acc = T(0);
-    for (int e = eoff[q]; e < eoff[q + 1]; ++e) acc += coef[e] * (u[nbs[e]] - u0);
-    for (int c = coff[q]; c < coff[q + 1]; ++c) y[cslot[c]] = acc;
-}
-
-// MA2 corrections of interior rows (after the interior kernel)
-template <typename T>
-__global__ __launch_bounds__(B2) void k2d_corr(int64_t n_corr, const int64_t *__restrict__ row,
-                                               const int64_t *__restrict__ nb, const T *__restrict__ dl,
-                                               const T *__restrict__ u, T *__restrict__ y)
-{
-    const int64_t q = (int64_t)blockIdx.x * B2 + threadIdx.x;
-    if (q >= n_corr) return;
-    const int64_t a = row[q];
-    const T u0 = u[a];
-    y[a] += dl[2 * q] * (u[nb[2 * q]] - u0) + dl[2 * q + 1] * (u[nb[2 * q + 1]] - u0);
-}
-
-template <typename T>
-__global__ void k2d_zero(int64_t n, const int64_t *__restrict__ slots, T *__restrict__ y)
-{
-    const int64_t q = (int64_t)blockIdx.x * B2 + threadIdx.x;
-    if (q < n) y[slots[q]] = T(0);
+    int64_t q = (int64_t)blockIdx.x * B2 + threadIdx.x;
+    if (q < n_sh) {
+        const T u0 = u[self[q]];
+        T acc = T(0);
+        for (int e = eoff[q]; e < eoff[q + 1]; ++e) acc += coef[e] * (u[nbs[e]] - u0);
+        for (int c = coff[q]; c < coff[q + 1]; ++c) y[cslot[c]] = acc;
+        return;
+    }
+    q -= n_sh;
+    if (q < n_corr) {
+        const int64_t a = crow[q];
+        const T u0 = u[a];
+        y[a] += cdl[2 * q] * (u[cnb[2 * q]] - u0) + cdl[2 * q + 1] * (u[cnb[2 * q + 1]] - u0);
+        return;
+    }
+    q -= n_corr;
+    if (q < n_dir) y[dslots[q]] = T(0);
 }
 
 template <typename T>
@@ -367,16 +353,15 @@ hhg_status apply_t(hhg2d_ctx c, int op, const T *u, T *y, hipStream_t st, const 
             k2d_march<T><<<g, B2, 0, st>>>(n, c->Spad, n_seg, jc, D.w, D.k, u, y);
         } else {
             const dim3 g((unsigned)(n - 2), (unsigned)c->nt, nblk(n - 2));
-            k2d_interior<T, 1><<<g, B2, 0, st>>>(n, c->Spad, D.w, c->d_A, D.k, u, y);
+            k2d_nodal<T><<<g, B2, 0, st>>>(n, c->Spad, c->d_A, D.k, u, y);
         }
     }
-    if (c->n_sh)
-        k2d_shared<T><<<nblk(c->n_sh), B2, 0, st>>>(c->n_sh, c->d_sh_eoff, c->d_sh_nb, op == 0 ? D.cs : D.cn,
-                                                    c->d_sh_self, c->d_sh_off, c->d_sh_cslot, u, y);
-    if (op == 0 && c->n_corr)
-        k2d_corr<T><<<nblk(c->n_corr), B2, 0, st>>>(c->n_corr, c->d_c_row, c->d_c_nb, D.dl, u, y);
-    if (!c->dir_slots.empty())
-        k2d_zero<T><<<nblk((int64_t)c->dir_slots.size()), B2, 0, st>>>((int64_t)c->dir_slots.size(), c->d_dir, y);
+    const int64_t n_corr = op == 0 ? c->n_corr : 0, n_dir = (int64_t)c->dir_slots.size();
+    const int64_t n_tail = c->n_sh + n_corr + n_dir;
+    if (n_tail)
+        k2d_tail<T><<<nblk(n_tail), B2, 0, st>>>(c->n_sh, c->d_sh_eoff, c->d_sh_nb, op == 0 ? D.cs : D.cn,
+                                                 c->d_sh_self, c->d_sh_off, c->d_sh_cslot, n_corr, c->d_c_row,
+                                                 c->d_c_nb, D.dl, n_dir, c->d_dir, u, y);
     HIP2(c, hipGetLastError());
     return HHG_OK;
 }
