@@ -152,6 +152,14 @@ hhg_status hhg_apply_scaled(hhg_ctx ctx, int32_t level, hhg_dtype dtype,
  * one-tet mesh without modified edges, that kernel's launch period) and the
  * number of timed applies, and clears the record.  Enabling or disabling also
  * clears it.  The timed applies must all use one stream. */
+/* enable != 0: V-cycles inside hhg_solve, hhg_solve_form and
+ * hhg_solve_tensor run as captured HIP graphs on a stream of the context
+ * (each distinct level, cycle shape, operator, precision and vector pair is
+ * captured once and replayed; a new coefficient, tensor coefficient or coarse
+ * level starts new captures).  Cycles with the learned smoother always run
+ * eagerly.  Default 0: every cycle runs eagerly on the caller's stream.  The
+ * results are identical either way. */
+hhg_status hhg_set_graphs(hhg_ctx ctx, int32_t enable);
 hhg_status hhg_set_timing(hhg_ctx ctx, int32_t enable);
 /* Tuning and tests (not part of the method): selects the variant of the
  * interior marching kernels for every context of the process; 0 (the

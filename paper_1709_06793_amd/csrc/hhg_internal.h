@@ -196,6 +196,8 @@ template <typename Ti, typename To>
 hipError_t launch_convert(const Ti *in, To *out, int64_t n, hipStream_t st);
 // kernel variant of the interior marches (0 = default policy); -1 if out of range
 int set_march_variant(int v);
+// the interior kernels' variant in force (0 = per precision and size)
+int march_variant_now();
 // merged coefficients of the shared rows for the current k (scaled and nodal)
 hipError_t launch_shared_coef(const LevelView<double> &L, const int8_t *map, double *cs, double *cn,
                               hipStream_t st);

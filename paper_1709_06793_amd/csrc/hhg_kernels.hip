@@ -736,6 +736,7 @@ static int march_variant()
     }
     return g_variant;
 }
+int march_variant_now() { return march_variant(); }
 int set_march_variant(int v)
 {
     if (v < 0 || v > 10) return -1;

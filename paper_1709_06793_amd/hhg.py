@@ -27,7 +27,7 @@ EINVAL, EMESH, ECOEF, EHIP, ESTATE, ENOMEM = -1, -2, -3, -4, -5, -6
 EXPORTS = [
     "hhg_create_macro", "hhg_destroy", "hhg_last_error", "hhg_vector_size", "hhg_node_coords",
     "hhg_to_canonical", "hhg_from_canonical", "hhg_set_coefficient", "hhg_set_coarse_level",
-    "hhg_level_info", "hhg_apply_scaled", "hhg_set_timing", "hhg_read_timing", "hhg_set_kernel_variant", "hhg_apply_nodal", "hhg_apply_mixed", "hhg_store_stencils", "hhg_apply_stored", "hhg_set_tensor_coefficient", "hhg_apply_tensor", "hhg_apply_tensor_nodal", "hhg_residual", "hhg_smooth",
+    "hhg_level_info", "hhg_apply_scaled", "hhg_set_graphs", "hhg_set_timing", "hhg_read_timing", "hhg_set_kernel_variant", "hhg_apply_nodal", "hhg_apply_mixed", "hhg_store_stencils", "hhg_apply_stored", "hhg_set_tensor_coefficient", "hhg_apply_tensor", "hhg_apply_tensor_nodal", "hhg_residual", "hhg_smooth",
     "hhg_vcycle", "hhg_solve", "hhg_solve_tensor", "hhg_solve_form", "hhg_learned_set_weights", "hhg_learned_set_fallback",
     "hhg_learned_forward", "hhg_learned_backward", "hhg_learned_loss_grad", "hhg_training_pair",
     "hhg_adam_update",
@@ -70,6 +70,7 @@ def load():
         "hhg_level_info": [P, I32, P, P, P],
         "hhg_apply_scaled": [P, I32, I32, P, P, P],
         "hhg_set_timing": [P, I32],
+        "hhg_set_graphs": [P, I32],
         "hhg_set_kernel_variant": [I32],
         "hhg_read_timing": [P, P, P],
         "hhg_apply_nodal": [P, I32, I32, P, P, P],
@@ -268,6 +269,10 @@ class Context:
         self._check(load().hhg_vcycle(self._h, level, _dtype_code(u), pre, post, smoother, _ptr(f),
                                       _ptr(u), ctypes.byref(rr) if rel_res else None, _stream()))
         return rr.value if rel_res else u
+
+    def set_graphs(self, enable):
+        """hhg_set_graphs: solve-loop V-cycles as captured HIP graphs, or eager (default)."""
+        self._check(load().hhg_set_graphs(self._h, int(bool(enable))))
 
     def solve(self, level, f, u, mode=SOLVE_F64, tol=1e-8, max_iter=100, pre=2, post=2):
         st = SolveStats()

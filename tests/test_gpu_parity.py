@@ -527,3 +527,42 @@ def _touches_boundary(om):
     lo = 1.5 / n
     x = om.xyz
     return (x.min(axis=1) < lo) | (x.sum(axis=1) > 1 - lo)
+
+
+@pytest.mark.parametrize("case", ["scaled", "nodal", "mixed", "tensor"])
+def test_graph_cycles_match_eager_cycles(case):
+    """Solve-loop V-cycles replayed from captured HIP graphs give the same
+    iterates, bit for bit, as eager cycles: many replays per solve with eager
+    residual norms between them, a second solve on the same captures, and a
+    new coefficient between (which must start new captures)."""
+    X, T = cube12()
+    level = 5
+    om, _, _, ctx = _setup(cube12, level, kfun=smooth_k)
+    f = uniform_vector(om.n_nodes, seed=9)
+    f[om.dirichlet] = 0.0
+    fd = ctx.from_canonical(level, _dev(f))
+    mask = hhg.PRIM_VERTICES | hhg.PRIM_EDGES
+
+    def solve(mode):
+        u = ctx.vector(level)
+        if case == "tensor":
+            st = ctx.solve_tensor(level, fd, u, mode=mode, tol=1e-10, max_iter=60, pre=3, post=3)
+        else:
+            st = ctx.solve_form(level, fd, u, form=case, nodal_primitives=mask, mode=mode, tol=1e-10, max_iter=60,
+                                pre=3, post=3)
+        assert st["status"] == 0 and st["rel_residual"] <= 1e-10
+        return st["iterations"], u
+
+    for kfun in (smooth_k, lambda x: lognormal_k(x, lognormal_params(4, 1.0, 0.2))):
+        k = kfun(om.xyz)
+        ctx.set_coefficient(k)
+        if case == "tensor":
+            ctx.set_tensor_coefficient(tensor_fields(k[:, None, None] * tensor_K(om.xyz)))
+        for mode in (hhg.SOLVE_F64, hhg.SOLVE_MIXED):
+            ctx.set_graphs(True)
+            n1, u1 = solve(mode)
+            n2, u2 = solve(mode)
+            ctx.set_graphs(False)
+            n3, u3 = solve(mode)
+            assert n1 == n2 == n3, (n1, n2, n3)
+            assert torch.equal(u1, u3) and torch.equal(u2, u3)
