@@ -188,52 +188,7 @@ double lambda_min_T(const double A[3][3])
 }
 
 // ---------------------------------------------------------------- kernels
-// nodal interior rows: thread = (row j, position i) of triangle blockIdx.y;
-// the six incident elements, each mean vertex k times its element row
-template <typename T>
-__global__ __launch_bounds__(B2) void k2d_nodal(int n, int64_t Spad, const double *__restrict__ Aall,
-                                                const T *__restrict__ k, const T *__restrict__ u, T *__restrict__ y)
-{
-    const int j = blockIdx.x + 1;
-    const int i = blockIdx.z * B2 + threadIdx.x + 1;
-    if (i > n - 1 - j) return;
-    const int tri = blockIdx.y;
-    const int64_t base = (int64_t)tri * Spad;
-    const int64_t s = (int64_t)j * (n + 1) - (int64_t)j * (j - 1) / 2 + i;
-    // neighbour slots in D2 order
-    const int64_t up = n + 1 - j, dn = n + 2 - j;
-    const int64_t nb[6] = {s + 1, s + up, s + up - 1, s - 1, s - dn, s - dn + 1};
-    const T *ub = u + base, *kb = k + base;
-    T uu[7], kk[7];
-#pragma unroll
-    for (int d = 0; d < 6; ++d) {
-        uu[d] = ub[nb[d]];
-        kk[d] = kb[nb[d]];
-    }
-    uu[6] = ub[s];
-    kk[6] = kb[s];
-    const double *A = Aall + tri * 9;
-    T acc = T(0);
-#pragma unroll
-    for (int e = 0; e < 6; ++e) {
-        int idx[3];
-#pragma unroll
-        for (int v = 0; v < 3; ++v) {
-            const int di = AROUND[e].off[v][0], dj = AROUND[e].off[v][1];
-            idx[v] = (di == 0 && dj == 0) ? 6 : dir_of(di, dj);
-        }
-        const int me = AROUND[e].me;
-        const T kbar = (kk[idx[0]] + kk[idx[1]] + kk[idx[2]]) / T(3);
-        T r = T(0);
-#pragma unroll
-        for (int v = 0; v < 3; ++v)
-            if (v != me) r += (T)A[me * 3 + v] * (uu[idx[v]] - uu[6]);
-        acc += kbar * r;
-    }
-    y[base + s] = acc;
-}
-
-// Scaled interior rows by column marching: a wave owns 64 consecutive
+// Interior rows by column marching: a wave owns 64 consecutive
 // columns c = i0 - 1 + lane (lanes 1..62 produce rows, lanes 0 and 63 only
 // feed their neighbours) and walks rows j0..j1 holding u and k of rows j-1,
 // j, j+1 in registers; per row it loads row j+2 once (coalesced along the
@@ -241,10 +196,12 @@ __global__ __launch_bounds__(B2) void k2d_nodal(int n, int64_t Spad, const doubl
 // jc rows per wave: the launcher takes the largest of 64/32/16/8 that still
 // gives about 32K waves (half of them fall beyond the triangle's diagonal;
 // level 11 on 8 triangles: 16 rows, 152 GDoF/s FP64 against 127 with 64 rows).
-template <typename T>
+// OP 0: scaled rows; OP 1: nodal rows (the six incident elements from the
+// same seven values, element matrices of the triangle in Aall).
+template <typename T, int OP>
 __global__ __launch_bounds__(B2) void k2d_march(int n, int64_t Spad, int n_seg, int jc, const T *__restrict__ w,
-                                                const T *__restrict__ k, const T *__restrict__ u,
-                                                T *__restrict__ y)
+                                                const double *__restrict__ Aall, const T *__restrict__ k,
+                                                const T *__restrict__ u, T *__restrict__ y)
 {
     const int wv = blockIdx.x * (B2 / 64) + (threadIdx.x >> 6);
     const int chunks = (n - 2 + jc - 1) / jc;
@@ -272,10 +229,35 @@ __global__ __launch_bounds__(B2) void k2d_march(int n, int64_t Spad, int n_seg, 
         const T unw = __shfl_up(up, 1, 64), knw = __shfl_up(kp, 1, 64);   // (i-1, j+1)
         const T use = __shfl_down(um, 1, 64), kse = __shfl_down(km, 1, 64);  // (i+1, j-1)
         if (lane >= 1 && lane <= 62 && col >= 1 && col <= n - 1 - j) {
-            const T a0 = (kc + ke) * (ue - uc) + (kc + kw) * (uw - uc);
-            const T a1 = (kc + kp) * (up - uc) + (kc + km) * (um - uc);
-            const T a2 = (kc + knw) * (unw - uc) + (kc + kse) * (use - uc);
-            yb[rs(j) + col] = w0 * a0 + w1 * a1 + w2 * a2;
+            if (OP == 0) {
+                const T a0 = (kc + ke) * (ue - uc) + (kc + kw) * (uw - uc);
+                const T a1 = (kc + kp) * (up - uc) + (kc + km) * (um - uc);
+                const T a2 = (kc + knw) * (unw - uc) + (kc + kse) * (use - uc);
+                yb[rs(j) + col] = w0 * a0 + w1 * a1 + w2 * a2;
+            } else {
+                // neighbours in D2 order, centre last
+                const T uu[7] = {ue, up, unw, uw, um, use, uc};
+                const T kk[7] = {ke, kp, knw, kw, km, kse, kc};
+                const double *A = Aall + tri * 9;
+                T acc = T(0);
+#pragma unroll
+                for (int e = 0; e < 6; ++e) {
+                    int idx[3];
+#pragma unroll
+                    for (int v = 0; v < 3; ++v) {
+                        const int di = AROUND[e].off[v][0], dj = AROUND[e].off[v][1];
+                        idx[v] = (di == 0 && dj == 0) ? 6 : dir_of(di, dj);
+                    }
+                    const int me = AROUND[e].me;
+                    const T kbar = (kk[idx[0]] + kk[idx[1]] + kk[idx[2]]) / T(3);
+                    T r = T(0);
+#pragma unroll
+                    for (int v = 0; v < 3; ++v)
+                        if (v != me) r += (T)A[me * 3 + v] * (uu[idx[v]] - uc);
+                    acc += kbar * r;
+                }
+                yb[rs(j) + col] = acc;
+            }
         }
         um = uc; uc = up; up = un;
         km = kc; kc = kp; kp = kn;
@@ -344,17 +326,13 @@ hhg_status apply_t(hhg2d_ctx c, int op, const T *u, T *y, hipStream_t st, const 
 {
     const int n = c->n;
     if (n >= 3) {
-        if (op == 0) {
-            const int n_seg = (n - 1 + 61) / 62;
-            int jc = 64;
-            while (jc > 8 && (int64_t)n_seg * ((n - 2 + jc - 1) / jc) * c->nt < 32768) jc /= 2;
-            const int chunks = (n - 2 + jc - 1) / jc;
-            const dim3 g((unsigned)((n_seg * chunks + B2 / 64 - 1) / (B2 / 64)), (unsigned)c->nt);
-            k2d_march<T><<<g, B2, 0, st>>>(n, c->Spad, n_seg, jc, D.w, D.k, u, y);
-        } else {
-            const dim3 g((unsigned)(n - 2), (unsigned)c->nt, nblk(n - 2));
-            k2d_nodal<T><<<g, B2, 0, st>>>(n, c->Spad, c->d_A, D.k, u, y);
-        }
+        const int n_seg = (n - 1 + 61) / 62;
+        int jc = 64;
+        while (jc > 8 && (int64_t)n_seg * ((n - 2 + jc - 1) / jc) * c->nt < 32768) jc /= 2;
+        const int chunks = (n - 2 + jc - 1) / jc;
+        const dim3 g((unsigned)((n_seg * chunks + B2 / 64 - 1) / (B2 / 64)), (unsigned)c->nt);
+        if (op == 0) k2d_march<T, 0><<<g, B2, 0, st>>>(n, c->Spad, n_seg, jc, D.w, c->d_A, D.k, u, y);
+        else k2d_march<T, 1><<<g, B2, 0, st>>>(n, c->Spad, n_seg, jc, D.w, c->d_A, D.k, u, y);
     }
     const int64_t n_corr = op == 0 ? c->n_corr : 0, n_dir = (int64_t)c->dir_slots.size();
     const int64_t n_tail = c->n_sh + n_corr + n_dir;
