@@ -385,7 +385,7 @@ def main():
                     help="only run a 1 GiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "multi-GPU execution is not implemented: the benchmark runs on one GPU (--gpus 1)"}))
         sys.exit(2)
     import torch
     from hhg_inputs import unit_tet, kuhn_cube, kuhn_cube_2x2x2, lognormal_params, smooth_k
