@@ -26,7 +26,7 @@ typedef struct hhg2d_ctx_s *hhg2d_ctx;
 #define HHG2D_FLAG_NO_MODIFICATION 1u
 
 /* xy: n_vert x 2 macro vertex coordinates; tri: n_tri x 3 vertex ids (any
- * orientation); level 0..13.  Host memory, copied.  HHG_EINVAL for bad sizes,
+ * orientation, n_tri <= 65535); level 0..13.  Host memory, copied.  HHG_EINVAL for bad sizes,
  * HHG_EMESH for a degenerate triangle or bad ids.  *out is NULL on failure. */
 hhg_status hhg2d_create(const double *xy, int32_t n_vert, const int32_t *tri, int32_t n_tri, int32_t level,
                         uint32_t flags, hhg2d_ctx *out);

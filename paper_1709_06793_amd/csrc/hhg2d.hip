@@ -680,7 +680,8 @@ hhg_status hhg2d_create(const double *xy, int32_t n_vert, const int32_t *tri, in
 {
     if (!out) return HHG_EINVAL;
     *out = nullptr;
-    if (!xy || !tri || n_vert < 3 || n_tri < 1 || level < 0 || level > 13) return HHG_EINVAL;
+    // one grid row of blocks per triangle: at most 65535 triangles
+    if (!xy || !tri || n_vert < 3 || n_tri < 1 || n_tri > 65535 || level < 0 || level > 13) return HHG_EINVAL;
     for (int64_t q = 0; q < 3 * (int64_t)n_tri; ++q)
         if (tri[q] < 0 || tri[q] >= n_vert) return HHG_EMESH;
     hhg2d_ctx c = new hhg2d_ctx_s;
