@@ -72,3 +72,21 @@ def test_create_rejects_bad_arguments_without_gpu_work():
     assert e.value.code == -1
     with pytest.raises(hhg.HHGError):
         hhg.Context(X, np.array([[0, 1, 2, 3]], dtype=np.int32), 11)   # level out of range
+
+
+def test_product_and_oracle_are_separate():
+    """The product package never imports or names the oracle, the oracle never
+    imports the product, and the input generators hold no method code from
+    either side."""
+    import glob
+    prod = glob.glob(os.path.join(ROOT, "paper_1709_06793_amd", "*.py")) + \
+        glob.glob(os.path.join(ROOT, "paper_1709_06793_amd", "csrc", "*"))
+    for p in prod:
+        src = open(p, errors="replace").read()
+        assert not re.search(r"\boracle\b", src), p
+    for p in glob.glob(os.path.join(ROOT, "oracle", "*.py")) + glob.glob(os.path.join(ROOT, "oracle", "*.c")):
+        src = open(p).read()
+        assert "paper_1709_06793_amd" not in src and "libhhg" not in src, p
+    for p in glob.glob(os.path.join(ROOT, "hhg_inputs", "*.py")):
+        src = open(p).read()
+        assert "paper_1709_06793_amd" not in src and "from oracle" not in src and "import oracle" not in src, p
