@@ -152,8 +152,8 @@ def test_c4_tensor_full_size_sampled_rows():
     """48 Kuhn tets at level 8 with the rotating SPD tensor K (six component
     fields, 6.5 GB FP64 on the finest level), both tensor applies in the
     launches bench.py times: sampled rows (random and every node near the
-    24-tet centre vertex) against the oracle's row-by-row evaluation, and
-    zero Dirichlet rows."""
+    24-tet centre vertex) against the oracle's row-by-row evaluation, zero
+    Dirichlet rows, and the FP32 applies against the FP64 ones."""
     X, T = kuhn_cube_2x2x2()
     level = 8
     om = O.Mesh(X, T, level)
@@ -175,6 +175,13 @@ def test_c4_tensor_full_size_sampled_rows():
         print(f"tensor {form}: {len(nodes)} sampled rows, max rel error {err:.3e}", flush=True)
         assert err <= 1e-12, form
         assert np.all(got[om.dirichlet] == 0.0), form
+        # FP32 at the same size: within FP32 rounding of the FP64 result
+        y32 = ctx.vector(level, torch.float32)
+        apply(level, ud.float(), y32)
+        d = ((y32.double() - y).abs().max() / y.abs().max()).item()
+        print(f"tensor {form} FP32 vs FP64: max rel difference {d:.3e}", flush=True)
+        assert d <= 4e-6, form
+        del y32
 
 
 @pytest.mark.parametrize("mode", [hhg.SOLVE_F64, hhg.SOLVE_MIXED])
