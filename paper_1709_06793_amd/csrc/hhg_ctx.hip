@@ -992,7 +992,7 @@ hhg_status build_level(hhg_ctx c, int l)
 
     // column-marching work items: waves over 62 in-plane offsets (plus one
     // halo lane each side) and chunks of kc planes; kc is the largest of
-    // 32/16/8/4 that still gives about 8192 waves over all tets
+    // 32/16/8/4 that still gives the target wave count over all tets
     {
         const int n = L.n;
         const int64_t T0 = tri_count(n);
@@ -1035,7 +1035,10 @@ hhg_status build_level(hhg_ctx c, int l)
                 if ((int64_t)tp.nt * (int64_t)(out.size() / 2) >= target) break;
             }
         };
-        build_items(62, 8192, L.h_items, L.kc);
+        // one-row items (FP32 scaled, nodal rows): 4K waves (unit tet level 8:
+        // 8-plane chunks instead of 4, FP32 scaled 222 -> 243 GDoF/s; meshes
+        // of several tets keep 32)
+        build_items(62, 4096, L.h_items, L.kc);
         // two-rows-per-lane items: FP64 prefers more, shorter waves than FP32
         build_items(126, 8192, L.h_items2, L.kc2);
         L.n_items2 = (int)(L.h_items2.size() / 2);
