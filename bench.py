@@ -34,8 +34,8 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# the sources the interior kernel is compiled from (host-side files excluded)
-KERNEL_SOURCES = ("hhg_kernels.hip", "hhg_march.h", "hhg_lattice.h", "hhg_internal.h")
+# the sources the interior kernel and its launch grid come from
+KERNEL_SOURCES = ("hhg_kernels.hip", "hhg_march.h", "hhg_lattice.h", "hhg_internal.h", "hhg_ctx.hip")
 
 
 def kernel_source_hash():

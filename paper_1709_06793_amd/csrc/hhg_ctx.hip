@@ -1040,7 +1040,8 @@ hhg_status build_level(hhg_ctx c, int l)
         // of several tets keep 32)
         build_items(62, 4096, L.h_items, L.kc);
         // two-rows-per-lane items: FP64 prefers more, shorter waves than FP32
-        build_items(126, 8192, L.h_items2, L.kc2);
+        // (a single tet at level 8 gets 8-plane chunks: 2-3% faster than 4)
+        build_items(126, tp.nt >= 4 ? 8192 : (int64_t)2048 * tp.nt, L.h_items2, L.kc2);
         L.n_items2 = (int)(L.h_items2.size() / 2);
         build_items(126, 4096, L.h_items2f, L.kc2f);
         L.n_items2f = (int)(L.h_items2f.size() / 2);
