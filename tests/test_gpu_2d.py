@@ -112,3 +112,23 @@ def test_2d_large_level_properties():
     h = 0.5 / 2 ** level
     inner = (xy.min(axis=1) > 2 * h) & (xy.max(axis=1) < 1 - 2 * h)
     assert np.abs(v[inner]).max() <= 1e-12 * np.abs(v).max()
+
+
+def test_2d_error_paths():
+    """Bad coefficients and vectors are rejected with an error, not run."""
+    X, T = square_nondelaunay8()
+    ctx = hhg2d.Context2D(X, T, 3)
+    xy, _ = ctx.node_coords()
+    k = np.ones(len(xy))
+    k[5] = -1.0
+    with pytest.raises(hhg2d.HHGError):
+        ctx.set_coefficient(k)
+    k[5] = np.nan
+    with pytest.raises(hhg2d.HHGError):
+        ctx.set_coefficient(k)
+    ctx.set_coefficient(np.ones(len(xy)))
+    u = ctx.vector()
+    with pytest.raises(hhg2d.HHGError):
+        ctx.apply_scaled(u, u)
+    with pytest.raises(hhg2d.HHGError):
+        hhg2d.Context2D(X, np.array([[0, 1, 1]]), 3)
