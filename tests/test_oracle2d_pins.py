@@ -134,3 +134,21 @@ def test_l2_rate_on_a_manufactured_solution(kind):
         errs.append(np.sqrt(e @ (Mm @ e)))
     eoc = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert np.all(eoc[1:] > 1.85) and abs(eoc[-1] - 2.0) < 0.1, eoc
+
+
+def test_scaled_quadratic_form_is_the_edge_sum():
+    """The identity in the proof of Lemma 4.1: for the unmodified scaled form,
+    v^T A v = -1/4 sum_{i,j} (k_i + k_j) (v_i - v_j)^2 (A_hat)_{ij} with A_hat
+    the constant-coefficient (k = 1) matrix -- evaluated here pair by pair
+    from A_hat, independently of the element-wise assembly with zero row sums."""
+    X, T = square_nondelaunay8()
+    m = O2.Mesh2D(X, T, 2)
+    k = sigmoid_k(m.xy, 100.0)
+    A = O2.assemble(m, k, "scaled").toarray()
+    Ahat = O2.assemble(m, np.ones(m.n_nodes), "nodal").tocoo()
+    rng = np.random.default_rng(3)
+    for _ in range(3):
+        v = rng.uniform(-1, 1, m.n_nodes)
+        i, j, a = Ahat.row, Ahat.col, Ahat.data
+        edge = -0.25 * np.sum((k[i] + k[j]) * (v[i] - v[j]) ** 2 * a)
+        assert abs(v @ A @ v - edge) <= 1e-12 * abs(edge)
