@@ -39,3 +39,19 @@ def test_tensor_fields_recompose_an_spd_K(Kfun):
     assert np.abs(R - K).max() <= 1e-13 * np.abs(K).max()
     assert np.abs(K - np.transpose(K, (0, 2, 1))).max() <= 1e-15 * np.abs(K).max()
     assert np.linalg.eigvalsh(K).min() > 0.0
+
+
+def test_2d_macro_meshes_are_conforming_and_counter_clockwise():
+    from hhg_inputs import MESHES2D
+    for name, fn in MESHES2D.items():
+        X, T = fn()
+        e1, e2 = X[T[:, 1]] - X[T[:, 0]], X[T[:, 2]] - X[T[:, 0]]
+        assert np.all(e1[:, 0] * e2[:, 1] - e1[:, 1] * e2[:, 0] > 0), name
+        count = {}
+        for t in T:
+            for a in range(3):
+                e = tuple(sorted((int(t[a]), int(t[(a + 1) % 3]))))
+                count[e] = count.get(e, 0) + 1
+        assert max(count.values()) <= 2, name
+        # the boundary edges close into the outline of the domain (Euler: V - E + F = 1)
+        assert X.shape[0] - len(count) + T.shape[0] == 1, name
