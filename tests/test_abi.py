@@ -90,3 +90,11 @@ def test_product_and_oracle_are_separate():
     for p in glob.glob(os.path.join(ROOT, "hhg_inputs", "*.py")):
         src = open(p).read()
         assert "paper_1709_06793_amd" not in src and "from oracle" not in src and "import oracle" not in src, p
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus above 1 exits with a message."""
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode != 0 and "one GPU" in r.stdout
