@@ -28,7 +28,8 @@ def sigmoid_k(xyz, eta, m=50.0):
     """k = eta / (1 + exp(-m (y - x - 0.2))) + 1, the steep coefficient the paper
     uses for its pre-asymptotic counter example, evaluated in 3D."""
     x, y = xyz[:, 0], xyz[:, 1]
-    return eta / (1.0 + np.exp(-m * (y - x - 0.2))) + 1.0
+    # exp's argument is capped where the quotient is below 1e-300 anyway
+    return eta / (1.0 + np.exp(np.minimum(-m * (y - x - 0.2), 700.0))) + 1.0
 
 
 def lognormal_params(seed, sigma=None, corr_len=None, modes=32):

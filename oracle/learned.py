@@ -9,7 +9,8 @@ p = 1..14 the neighbours along the tet-local lattice directions
 (1,0,0),(0,1,0),(0,0,1),(1,-1,0),(1,0,-1),(0,1,-1),(1,-1,1) and their
 negatives, in that order:
     s_i  = max_p |r_p| + 1e-30                                   (float32)
-    x_p  = r_p * fl32(1 / s_i),  x_{15+p} = L_p - L_0,  x_30 = x_31 = 0    (float32)
+    x_p  = r_p / s_i,  x_{15+p} = L_p - L_0,  x_30 = x_31 = 0    (float32,
+           each quotient rounded once)
            with L = float32(log k) (log taken in float64)
     h1   = bf16(relu(float32(W1 bf16(x)) + b1))
     h2   = relu(float32(W2 h1) + b2)
@@ -109,8 +110,7 @@ def features(r32, logk32, pos):
     rp = r32[pos].astype(np.float32)
     s = (np.abs(rp).max(axis=1) + np.float32(1e-30)).astype(np.float32)
     x = np.zeros((pos.shape[0], 32), dtype=np.float32)
-    inv = (np.float32(1.0) / s).astype(np.float32)  # one FP32 reciprocal per node
-    x[:, :15] = rp * inv[:, None]
+    x[:, :15] = rp / s[:, None]
     lk = logk32[pos]
     x[:, 15:30] = lk - lk[:, :1]
     return x, s
@@ -146,3 +146,49 @@ def backward(w, cache, g, round_weights=True):
     dW1 = dz1.T @ xb
     db1 = dz1.sum(axis=0)
     return np.concatenate([dW1.ravel(), db1, dW2.ravel(), db2, dw3, [db3]])
+
+
+def correction(w, r, logk32, pos, nodes, n_nodes, round_activations=True):
+    """s_i c_i on every node (0 off the interior nodes `nodes`), with the
+    features taken from r rounded to float32; also the scales and the
+    network's intermediates."""
+    x, s = features(np.asarray(r, dtype=np.float32), logk32, pos)
+    c, cache = forward(w, x, round_activations)
+    sc = np.zeros(n_nodes)
+    sc[nodes] = s.astype(np.float64) * np.asarray(c, dtype=np.float64)
+    return sc, s, cache
+
+
+def step(op, w, f, u, logk32, pos, nodes, omega=2.0 / 3.0):
+    """One learned smoothing step on the unknowns:
+        r = f - A u,   u <- u + D^{-1} (omega r + s c(r, k)),
+    i.e. a damped Jacobi step plus the network's correction s c scaled by the
+    inverse diagonal (c = 0 off the macro-tet interiors)."""
+    r = op.residual(f, u)
+    sc, _, _ = correction(w, r, logk32, pos, nodes, op.mesh.n_nodes)
+    out = u.copy()
+    idx = op.mesh.unknowns
+    out[idx] += (omega * r[idx] + sc[idx]) / op.diag
+    out[op.mesh.dirichlet] = 0.0
+    return out
+
+
+def loss_and_grad(op, w, r, e, logk32, pos, nodes, omega=2.0 / 3.0, round_activations=True):
+    """Training loss of one sample (r, e) and its gradient in the parameters.
+
+    e1 = e - D^{-1}(omega r + s c) is the error left after one learned step
+    from an iterate with error e and residual r = A e;  L = e1'A e1 / e'A e
+    (energy norms over the unknowns).  With A symmetric,
+        dL/dc_i = -2 (A e1)_i s_i / (D_i e'A e)
+    on the interior nodes, and dL/dw follows through backward()."""
+    sc, s, cache = correction(w, r, logk32, pos, nodes, op.mesh.n_nodes, round_activations)
+    idx = op.mesh.unknowns
+    e1 = np.zeros(op.mesh.n_nodes)
+    e1[idx] = e[idx] - (omega * r[idx] + sc[idx]) / op.diag
+    ae1 = op.apply(e1)
+    e0 = float(e[idx] @ op.apply(e)[idx])
+    loss = float(e1[idx] @ ae1[idx]) / e0
+    dinv = np.zeros(op.mesh.n_nodes)
+    dinv[idx] = 1.0 / op.diag
+    g = -2.0 * ae1[nodes] * s.astype(np.float64) * dinv[nodes] / e0
+    return loss, backward(w, cache, g, round_weights=round_activations)

@@ -425,3 +425,68 @@ def test_tensor_rows_from_incident_elements_match_assembly(kind):
                            + [np.flatnonzero(m.dirichlet)[:3]])
     got = O.apply_tensor_rows(m, lambda x: tensor_fields(tensor_K(x)), u, nodes, kind)
     assert np.abs(got - full[nodes]).max() <= 1e-13 * np.abs(full).max()
+
+
+def _node_at(mesh, lat):
+    """Canonical index of the unit-tet node with lattice coordinates lat."""
+    x = np.asarray(lat, dtype=np.float64) / 2 ** mesh.level
+    d = np.abs(mesh.xyz - x).max(axis=1)
+    j = int(np.argmin(d))
+    assert d[j] < 1e-14
+    return j
+
+
+def test_modification_ratio_and_patch_enumerated_by_hand():
+    """Sec. 4.1 read for 3D.  (i) lambda_min^T / a_plus = 0.1464 on the unit
+    tet at every level: the corner children are the parent scaled by h (their
+    matrix |t| G G^T = h/6 [[3,-1,-1,-1],[-1,1,0,0],[-1,0,1,0],[-1,0,0,1]] has
+    lambda_2/4 = h/24), the octahedral children give the minimum 0.02440 h,
+    and the largest positive element entry is h/6.  (ii) k_emin of one edge
+    is the minimum over exactly the 13 edges of the four elements around it
+    (the edge, its 4 links to each end, the 4-cycle of link vertices):
+    neither the link cycle's diagonals nor edges elsewhere around the end
+    points may enter."""
+    X, T = unit_tet()
+    for L in (2, 3, 4):
+        m = O.Mesh(X, T, L)
+        _, info = O.modification_factors(m, np.ones(m.n_nodes))
+        h = 2.0 ** -L
+        assert info["a_plus"].max() == pytest.approx(h / 6, rel=1e-12)
+        assert info["lam_T"][0] / info["a_plus"].max() == pytest.approx(0.1464, abs=5e-5)
+    ratio = info["lam_T"][0] / info["a_plus"].max()
+    m = O.Mesh(X, T, 3)
+    i = np.array([2, 3, 1])
+    d = np.array([1, -1, 1])                        # the gray Bey diagonal
+    j = i + d
+    la, lb, lc, le = (i + np.array(o) for o in ((0, -1, 1), (0, 0, 1), (1, -1, 0), (1, 0, 0)))
+    o1, o2 = i + np.array([-1, 0, 0]), i + np.array([0, -1, 0])   # neighbours of i off the patch
+    k = np.ones(m.n_nodes)
+    for p, v in ((i, 100.0), (j, 100.0), (la, 0.01), (le, 0.01), (o1, 1e-3), (o2, 1e-3)):
+        k[_node_at(m, p)] = v
+    # patch edges: i-j, i-links, j-links and the cycle a-b-e-c-a; the smallest
+    # average is on a cycle edge with one end at a or e: (0.01 + 1)/2.  The
+    # diagonal a-e would give 0.01, the edge o1-o2 near i would give 1e-3.
+    mods, info = O.modification_factors(m, k)
+    a, b = sorted((_node_at(m, i), _node_at(m, j)))
+    assert (0, a, b) in mods
+    assert mods[(0, a, b)] == pytest.approx(0.505 * (1.0 + ratio), rel=1e-12)
+
+
+def test_mass_matrix_is_the_exact_l2_product():
+    """u'Mv equals the integral of u_h v_h (P1 interpolants), computed by the
+    degree-5 quadrature per element; a lumped or mis-scaled mass fails."""
+    for fn, L in ((unit_tet, 2), (regular_tet, 2), (kuhn_cube, 1)):
+        X, T = fn()
+        m = O.Mesh(X, T, L)
+        M = O.assemble_mass(m)
+        rng = np.random.default_rng(3)
+        u = rng.uniform(-1, 1, m.n_nodes)
+        zero = lambda x: np.zeros(len(x))
+        gzero = lambda x: np.zeros((len(x), 3))
+        quad = O.errors(m, u, zero, gzero)["L2"] ** 2
+        assert u @ (M @ u) == pytest.approx(quad, rel=1e-12)
+        # polarisation: the bilinear form, not just the quadratic one
+        v = rng.uniform(-1, 1, m.n_nodes)
+        q2 = O.errors(m, u + v, zero, gzero)["L2"] ** 2
+        q3 = O.errors(m, u - v, zero, gzero)["L2"] ** 2
+        assert u @ (M @ v) == pytest.approx((q2 - q3) / 4, rel=1e-10, abs=1e-14)
