@@ -9,8 +9,8 @@ p = 1..14 the neighbours along the tet-local lattice directions
 (1,0,0),(0,1,0),(0,0,1),(1,-1,0),(1,0,-1),(0,1,-1),(1,-1,1) and their
 negatives, in that order:
     s_i  = max_p |r_p| + 1e-30                                   (float32)
-    x_p  = r_p / s_i,  x_{15+p} = L_p - L_0,  x_30 = x_31 = 0    (float32,
-           each quotient rounded once)
+    x_p  = r_p * fl32(1 / s_i),  x_{15+p} = L_p - L_0,  x_30 = x_31 = 0
+           (float32: the reciprocal rounded once, each product rounded once)
            with L = float32(log k) (log taken in float64)
     h1   = bf16(relu(float32(W1 bf16(x)) + b1))
     h2   = relu(float32(W2 h1) + b2)
@@ -110,7 +110,8 @@ def features(r32, logk32, pos):
     rp = r32[pos].astype(np.float32)
     s = (np.abs(rp).max(axis=1) + np.float32(1e-30)).astype(np.float32)
     x = np.zeros((pos.shape[0], 32), dtype=np.float32)
-    x[:, :15] = rp / s[:, None]
+    inv = (np.float32(1.0) / s).astype(np.float32)   # one reciprocal per node
+    x[:, :15] = rp * inv[:, None]
     lk = logk32[pos]
     x[:, 15:30] = lk - lk[:, :1]
     return x, s
@@ -192,3 +193,24 @@ def loss_and_grad(op, w, r, e, logk32, pos, nodes, omega=2.0 / 3.0, round_activa
     dinv[idx] = 1.0 / op.diag
     g = -2.0 * ae1[nodes] * s.astype(np.float64) * dinv[nodes] / e0
     return loss, backward(w, cache, g, round_weights=round_activations)
+
+
+def vcycle(mg, w, f, u, logk32, pos, nodes, pre=2, post=2, omega=2.0 / 3.0):
+    """One V(pre,post) cycle of the oracle's multigrid (Multigrid in
+    oracle.py) whose finest level smooths with learned steps; the coarser
+    levels keep Chebyshev smoothing.  logk32, pos, nodes belong to the finest
+    level."""
+    L = mg.levels[-1]
+    op = mg.ops[L]
+    for _ in range(pre):
+        u = step(op, w, f, u, logk32, pos, nodes, omega)
+    r = op.residual(f, u)
+    mc = mg.meshes[L - 1]
+    fc = mg.P[L].T @ r
+    fc[mc.dirichlet] = 0.0
+    uc = mg.vcycle(L - 1, fc, np.zeros(mc.n_nodes), pre, post)
+    u = u + mg.P[L] @ uc
+    u[op.mesh.dirichlet] = 0.0
+    for _ in range(post):
+        u = step(op, w, f, u, logk32, pos, nodes, omega)
+    return u

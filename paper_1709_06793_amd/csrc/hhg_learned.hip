@@ -5,7 +5,7 @@
 //
 // Features of an interior node i (positions p = 0: the node, p = 1..14: the
 // lattice neighbours in DIR order):  s = max_p |r_p| + 1e-30,
-// x_p = r_p * (1/s) (the reciprocal rounded to FP32), x_{15+p} = L_p - L_0
+// x_p = r_p * (1/s) (the reciprocal and each product rounded to FP32), x_{15+p} = L_p - L_0
 // (L = log k rounded to FP32), x_30 = x_31 = 0.
 // Network:  h1 = bf16(relu(W1 bf16(x) + b1)),  h2 = relu(W2 h1 + b2),
 // c = w3 . h2 + b3.  Nodes on macro faces/edges/vertices and Dirichlet nodes

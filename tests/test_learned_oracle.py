@@ -61,8 +61,9 @@ def test_stencil_positions_worked_by_hand():
 
 
 def test_features_worked_by_hand():
-    """s = max |r| over the 15 positions (+1e-30), x_p = r_p / s (one rounding),
-    x_{15+p} = log k_p - log k_0, x_30 = x_31 = 0."""
+    """s = max |r| over the 15 positions (+1e-30), x_p = r_p * fl32(1/s) (one
+    FP32 reciprocal per node, each product rounded once), x_{15+p} =
+    log k_p - log k_0, x_30 = x_31 = 0."""
     r = np.zeros(20, dtype=np.float32)
     pos = np.arange(15)[None, :] + 2
     r[2:17] = [0.5, -2.0, 1.0, 0.25, 0, 0, 1.5, -0.75, 0, 0, 0, 0.125, 0, -1.0, 2.0]
@@ -74,16 +75,16 @@ def test_features_worked_by_hand():
     assert np.array_equal(x[0, :15], want)
     assert np.array_equal(x[0, 15:30], np.arange(15, dtype=np.float32) * 0.5)
     assert x[0, 30] == 0 and x[0, 31] == 0
-    # a quotient that a product with a rounded reciprocal gets wrong by one ulp
+    # s = 3: 1/3 rounds to 0x3EAAAAAB; 0.3 * that rounds differently from 0.3 / 3
     r2 = np.zeros(20, dtype=np.float32)
     r2[2] = np.float32(3.0)
     r2[3] = np.float32(0.3)
-    r2[4] = np.float32(1.3)
-    x2, s2 = LN.features(r2, lk, pos)
-    for p, v in ((1, 0.3), (2, 1.3)):
-        exact = np.float32(np.float64(np.float32(v)) / 3.0)
-        assert x2[0, p] == exact
-        assert np.float32(v) * (np.float32(1) / np.float32(3)) != exact
+    x2, _ = LN.features(r2, lk, pos)
+    inv = np.float32(1.0) / np.float32(3.0)
+    assert inv.view(np.uint32) == 0x3EAAAAAB
+    assert x2[0, 1] == np.float32(np.float64(np.float32(0.3)) * np.float64(inv))
+    assert x2[0, 1] != np.float32(np.float64(np.float32(0.3)) / 3.0)
+    assert x2[0, 0] == np.float32(1.0)
 
 
 def test_loss_gradient_matches_central_differences():
