@@ -91,7 +91,9 @@ typedef enum { HHG_FORM_SCALED = 0, HHG_FORM_NODAL = 1, HHG_FORM_MIXED = 2 } hhg
  *   hip_stream the context's default stream (NULL = null stream).
  *   out       receives the context; NULL on failure.
  * Errors: HHG_EINVAL (null pointers, n_tet <= 0, ids out of range, level),
- * HHG_EMESH (zero-volume tet, a face shared by more than two tets),
+ * HHG_EMESH (zero-volume tet, a face shared by more than two tets,
+ * a non-conforming mesh: two vertex ids at one point, a vertex on an edge or
+ * face of a tet that does not hold it, overlapping coplanar boundary faces),
  * HHG_ENOMEM / HHG_EHIP.  Host setup computes, per macro tet and level, the
  * 15 primitive reference stencils (Sec. 2.2, Remark 2.1), the six element
  * matrices of the nodal kernel (Sec. 6.2) and the inter-tet node tables. */
@@ -143,15 +145,14 @@ hhg_status hhg_level_info(hhg_ctx ctx, int32_t level, double *lambda_max,
  * Sec. 4.1 where triggered).  u, y: device slot vectors of dtype; u != y. */
 hhg_status hhg_apply_scaled(hhg_ctx ctx, int32_t level, hhg_dtype dtype,
                             const void *u, void *y, void *stream);
-/* Instrumentation (not part of the method): while enabled, the first
- * hhg_apply_scaled records a HIP start event on its stream before its
- * stencil kernels and every hhg_apply_scaled counts itself.
- * hhg_read_timing records the end event on that stream, synchronises on it,
- * and returns the time from start to end in ms (everything the stream ran in
- * between: for back-to-back applies whose apply is a single kernel, as on a
- * one-tet mesh without modified edges, that kernel's launch period) and the
- * number of timed applies, and clears the record.  Enabling or disabling also
- * clears it.  The timed applies must all use one stream. */
+/* Instrumentation (not part of the method): while enabled, every
+ * hhg_apply_scaled records a HIP event on its stream right before its stencil
+ * kernels and one right after them (the Sec. 4.1 correction kernel, if any,
+ * is outside the pair).  hhg_read_timing synchronises on the recorded events
+ * and returns the summed start-to-end times in ms (the stencil kernels'
+ * durations, whatever else the stream runs between applies) and the number of
+ * timed applies, and clears the record.  Enabling or disabling also clears
+ * it. */
 /* enable != 0: V-cycles inside hhg_solve, hhg_solve_form and
  * hhg_solve_tensor run as captured HIP graphs on a stream of the context
  * (each distinct level, cycle shape, operator, precision and vector pair is
@@ -226,8 +227,11 @@ hhg_status hhg_residual(hhg_ctx ctx, int32_t level, hhg_dtype dtype, const void 
 /* In-place smoothing of A u = f: `sweeps` steps of weighted Jacobi
  * u <- u + omega D^{-1}(f - A u) (HHG_JACOBI), or a Chebyshev polynomial of
  * degree `sweeps` in D^{-1}A on [0.1, 1] x lambda_max (HHG_CHEBYSHEV; omega
- * ignored), or that Chebyshev step plus the learned correction
- * (HHG_LEARNED).  f, u: device slot vectors. */
+ * ignored), or `sweeps` learned steps (HHG_LEARNED, FP32 only, needs
+ * weights): r = f - A u, then u <- u + D^{-1}(2/3 r + s c) with the network
+ * output c and scale s of each macro-tet interior node (c = 0 elsewhere, so
+ * other rows take the damped Jacobi step; omega ignored).  f, u: device slot
+ * vectors. */
 hhg_status hhg_smooth(hhg_ctx ctx, int32_t level, hhg_dtype dtype, hhg_smoother smoother,
                       int32_t sweeps, double omega, const void *f, void *u, void *stream);
 /* One V(pre,post) cycle from `level` down to the coarse level: smoothing,
@@ -303,9 +307,16 @@ hhg_status hhg_solve_form(hhg_ctx ctx, int32_t level, int32_t form, int32_t noda
  * The learned calls take FP32 slot vectors. */
 #define HHG_LEARNED_NPARAM 817
 hhg_status hhg_learned_set_weights(hhg_ctx ctx, const float *w_host, int64_t n);
-/* Largest per-cycle residual ratio a learned solve accepts before it falls
- * back to Chebyshev smoothing for the rest of the solve (default 1). */
-hhg_status hhg_learned_set_fallback(hhg_ctx ctx, double max_rate);
+/* When a learned solve (HHG_SOLVE_LEARNED) falls back to Chebyshev smoothing
+ * for the rest of the solve.  A learned cycle is rejected when its residual
+ * ratio is not finite, exceeds max_rate (default 1), or exceeds
+ * plain_margin x the plain cycle's ratio (default 1.05; 0 turns this test
+ * off).  The plain ratio is measured once per solve: at cycle 2 a Chebyshev
+ * cycle runs from the same iterate as the learned one (one extra cycle); if
+ * the learned cycle then loses, the solve keeps the plain cycle's result,
+ * otherwise a rejected cycle's result is discarded.  HHG_EINVAL for
+ * max_rate <= 0 or a negative or non-finite margin. */
+hhg_status hhg_learned_set_fallback(hhg_ctx ctx, double max_rate, double plain_margin);
 /* c_out[slot] = network output c_i (consistent FP32 slot vector). */
 hhg_status hhg_learned_forward(hhg_ctx ctx, int32_t level, const float *r, float *c_out,
                                void *stream);

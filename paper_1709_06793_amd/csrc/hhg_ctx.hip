@@ -156,6 +156,160 @@ bool invert_dense(std::vector<double> &A, int n)
 int popcount4(int z) { return (z & 1) + ((z >> 1) & 1) + ((z >> 2) & 1) + ((z >> 3) & 1); }
 
 // ---------------------------------------------------------------- topology
+// Geometric conformity of a macro mesh whose tets already have positive
+// volume and whose faces are each held by at most two tets.  Shared
+// primitives are recognised by vertex ids, so a mesh is non-conforming when
+// geometry meets without ids agreeing:
+//   * two vertex ids at the same point;
+//   * a vertex on an edge or a face of a tet that does not hold it (a hanging
+//     node: the finer side's lattice would not match the coarser side's);
+//   * two faces held by one tet each that lie in one plane and overlap (the
+//     two sides of a quadrilateral split along different diagonals).
+// Candidates are found by sorting vertices and faces by their x extent.
+// Returns an empty string for a conforming mesh, else what was found.
+static std::string conformity_error(const std::vector<double> &X, const std::vector<int> &tet, int nv, int nt,
+                                    const std::vector<std::array<int, 2>> &edges,
+                                    const std::vector<std::array<int, 3>> &faces, const std::vector<int> &f_val)
+{
+    auto P = [&](int v, int a) { return X[3 * v + a]; };
+    std::vector<int> used;
+    {
+        std::vector<uint8_t> u(nv, 0);
+        for (int i = 0; i < 4 * nt; ++i) u[tet[i]] = 1;
+        for (int v = 0; v < nv; ++v)
+            if (u[v]) used.push_back(v);
+    }
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int v : used)
+        for (int a = 0; a < 3; ++a) { lo[a] = std::min(lo[a], P(v, a)); hi[a] = std::max(hi[a], P(v, a)); }
+    double diam = 0.0;
+    for (int a = 0; a < 3; ++a) diam = std::max(diam, hi[a] - lo[a]);
+    const double eps = 1e-10 * diam;
+    std::vector<int> byx = used;
+    std::sort(byx.begin(), byx.end(), [&](int a, int b) { return P(a, 0) < P(b, 0); });
+    auto in_range = [&](double x0, double x1, auto fn) {
+        auto it = std::lower_bound(byx.begin(), byx.end(), x0 - eps, [&](int v, double x) { return P(v, 0) < x; });
+        for (; it != byx.end() && P(*it, 0) <= x1 + eps; ++it)
+            if (fn(*it)) return true;
+        return false;
+    };
+    char buf[160];
+    // coincident vertices
+    for (size_t q = 0; q + 1 < byx.size(); ++q) {
+        const int a = byx[q];
+        bool hit = in_range(P(a, 0), P(a, 0), [&](int b) {
+            if (b == a) return false;
+            double d = 0.0;
+            for (int c = 0; c < 3; ++c) d = std::max(d, std::fabs(P(a, c) - P(b, c)));
+            if (d <= eps) {
+                snprintf(buf, sizeof buf, "vertices %d and %d coincide", std::min(a, b), std::max(a, b));
+                return true;
+            }
+            return false;
+        });
+        if (hit) return buf;
+    }
+    // a vertex inside an edge
+    for (const auto &e : edges) {
+        const int a = e[0], b = e[1];
+        double d[3], len2 = 0.0;
+        for (int c = 0; c < 3; ++c) { d[c] = P(b, c) - P(a, c); len2 += d[c] * d[c]; }
+        bool hit = in_range(std::min(P(a, 0), P(b, 0)), std::max(P(a, 0), P(b, 0)), [&](int v) {
+            if (v == a || v == b) return false;
+            double t = 0.0;
+            for (int c = 0; c < 3; ++c) t += (P(v, c) - P(a, c)) * d[c];
+            t /= len2;
+            if (t <= 0.0 || t >= 1.0) return false;
+            double dist = 0.0;
+            for (int c = 0; c < 3; ++c) dist = std::max(dist, std::fabs(P(a, c) + t * d[c] - P(v, c)));
+            if (dist <= eps) {
+                snprintf(buf, sizeof buf, "vertex %d lies on macro edge (%d,%d)", v, a, b);
+                return true;
+            }
+            return false;
+        });
+        if (hit) return buf;
+    }
+    // barycentric coordinates of point x in the plane of face f (false if
+    // the point is off the plane)
+    auto face_bary = [&](const std::array<int, 3> &f, const double *x, double w[3]) {
+        double e1[3], e2[3], r[3], nrm[3];
+        for (int c = 0; c < 3; ++c) {
+            e1[c] = P(f[1], c) - P(f[0], c);
+            e2[c] = P(f[2], c) - P(f[0], c);
+            r[c] = x[c] - P(f[0], c);
+        }
+        nrm[0] = e1[1] * e2[2] - e1[2] * e2[1];
+        nrm[1] = e1[2] * e2[0] - e1[0] * e2[2];
+        nrm[2] = e1[0] * e2[1] - e1[1] * e2[0];
+        const double n2 = nrm[0] * nrm[0] + nrm[1] * nrm[1] + nrm[2] * nrm[2];
+        const double off = (r[0] * nrm[0] + r[1] * nrm[1] + r[2] * nrm[2]) / std::sqrt(n2);
+        if (std::fabs(off) > eps) return false;
+        const double d11 = e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2];
+        const double d12 = e1[0] * e2[0] + e1[1] * e2[1] + e1[2] * e2[2];
+        const double d22 = e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2];
+        const double r1 = r[0] * e1[0] + r[1] * e1[1] + r[2] * e1[2];
+        const double r2 = r[0] * e2[0] + r[1] * e2[1] + r[2] * e2[2];
+        const double det = d11 * d22 - d12 * d12;
+        w[1] = (d22 * r1 - d12 * r2) / det;
+        w[2] = (d11 * r2 - d12 * r1) / det;
+        w[0] = 1.0 - w[1] - w[2];
+        return true;
+    };
+    const double beps = 1e-10;
+    // a vertex inside a face (edges are covered above)
+    for (const auto &f : faces) {
+        const double x0 = std::min({P(f[0], 0), P(f[1], 0), P(f[2], 0)});
+        const double x1 = std::max({P(f[0], 0), P(f[1], 0), P(f[2], 0)});
+        bool hit = in_range(x0, x1, [&](int v) {
+            if (v == f[0] || v == f[1] || v == f[2]) return false;
+            double x[3] = {P(v, 0), P(v, 1), P(v, 2)}, w[3];
+            if (!face_bary(f, x, w)) return false;
+            if (w[0] > beps && w[1] > beps && w[2] > beps) {
+                snprintf(buf, sizeof buf, "vertex %d lies on macro face (%d,%d,%d)", v, f[0], f[1], f[2]);
+                return true;
+            }
+            return false;
+        });
+        if (hit) return buf;
+    }
+    // coplanar overlapping faces held by one tet each: some point strictly
+    // inside one triangle (its centroid or a point just inside an edge
+    // midpoint or a corner) lies strictly inside the other
+    std::vector<int> bf;
+    for (size_t f = 0; f < faces.size(); ++f)
+        if (f_val[f] == 1) bf.push_back((int)f);
+    std::vector<std::array<double, 2>> fx(faces.size());
+    for (int f : bf) {
+        const auto &F = faces[f];
+        fx[f] = {std::min({P(F[0], 0), P(F[1], 0), P(F[2], 0)}), std::max({P(F[0], 0), P(F[1], 0), P(F[2], 0)})};
+    }
+    std::sort(bf.begin(), bf.end(), [&](int a, int b) { return fx[a][0] < fx[b][0]; });
+    for (size_t qa = 0; qa < bf.size(); ++qa) {
+        const auto &A = faces[bf[qa]];
+        for (size_t qb = qa + 1; qb < bf.size() && fx[bf[qb]][0] <= fx[bf[qa]][1] + eps; ++qb) {
+            const auto &B = faces[bf[qb]];
+            for (int pass = 0; pass < 2; ++pass) {
+                const auto &S = pass ? B : A, &D = pass ? A : B;
+                // sample points strictly inside S
+                const double wts[7][3] = {{1 / 3., 1 / 3., 1 / 3.}, {0.98, 0.01, 0.01}, {0.01, 0.98, 0.01},
+                                          {0.01, 0.01, 0.98},       {0.495, 0.495, 0.01}, {0.01, 0.495, 0.495},
+                                          {0.495, 0.01, 0.495}};
+                for (const auto &wt : wts) {
+                    double x[3], w[3];
+                    for (int c = 0; c < 3; ++c) x[c] = wt[0] * P(S[0], c) + wt[1] * P(S[1], c) + wt[2] * P(S[2], c);
+                    if (face_bary(D, x, w) && w[0] > beps && w[1] > beps && w[2] > beps) {
+                        snprintf(buf, sizeof buf, "macro faces (%d,%d,%d) and (%d,%d,%d) overlap", A[0], A[1], A[2],
+                                 B[0], B[1], B[2]);
+                        return buf;
+                    }
+                }
+            }
+        }
+    }
+    return std::string();
+}
+
 struct Topology {
     int nv = 0, nt = 0;
     std::vector<double> X;
@@ -285,7 +439,9 @@ struct Level {
     float *logk32 = nullptr;
     uint8_t *own = nullptr;
     float *lt[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    int64_t partial_bound = 0;  // block partials any reduction at this level writes
     double *ubak = nullptr;  // last accepted iterate of a learned solve
+    double *uprobe = nullptr;  // a learned solve's plain-cycle probe result
     // canonical maps (built on first use); slot2canon holds -(c+1) for a
     // Dirichlet slot of node c
     int32_t *slot2canon = nullptr;
@@ -354,9 +510,8 @@ struct hhg_ctx_s {
     std::map<GraphKey, std::pair<hipGraph_t, hipGraphExec_t>> gcache;
     // optional timing of the operator kernels of hhg_apply_scaled (event pairs)
     bool timing = false;
-    std::vector<hipEvent_t> tev;
-    size_t tev_used = 0;
-    hipStream_t tev_stream = nullptr;
+    std::vector<hipEvent_t> tev;  // start/end pairs
+    size_t tev_used = 0;          // pairs recorded
 };
 
 namespace {
@@ -1164,20 +1319,17 @@ hhg_status apply_scaled_t(hhg_ctx c, int l, const T *u, T *y, hipStream_t st)
 {
     LevelView<T> V = view<T>(c, l);
     if (c->timing) {
-        // one start event before the first timed apply; hhg_read_timing
-        // records the end event, so nothing is inserted between the applies
-        if (c->tev.empty()) {
-            for (int q = 0; q < 2; ++q) {
-                hipEvent_t e;
-                HIPCHK(c, hipEventCreate(&e));
-                c->tev.push_back(e);
-            }
+        // an event pair around this apply's stencil kernels (events pooled;
+        // the pool grows on the first timed applies)
+        const size_t q = 2 * c->tev_used;
+        while (c->tev.size() < q + 2) {
+            hipEvent_t e;
+            HIPCHK(c, hipEventCreate(&e));
+            c->tev.push_back(e);
         }
-        if (c->tev_used == 0) {
-            HIPCHK(c, hipEventRecord(c->tev[0], st));
-            c->tev_stream = st;
-        }
+        HIPCHK(c, hipEventRecord(c->tev[q], st));
         HIPCHK(c, launch_scaled<T>(V, MODE_APPLY, u, nullptr, y, nullptr, nullptr, st));
+        HIPCHK(c, hipEventRecord(c->tev[q + 1], st));
         ++c->tev_used;
     } else {
         HIPCHK(c, launch_scaled<T>(V, MODE_APPLY, u, nullptr, y, nullptr, nullptr, st));
@@ -1186,29 +1338,35 @@ hhg_status apply_scaled_t(hhg_ctx c, int l, const T *u, T *y, hipStream_t st)
     return HHG_OK;
 }
 
-// r = f - A u; if norm, the Euclidean norm over the unknowns (synchronises)
+// r = f - A u; if norm, the Euclidean norm over the unknowns (synchronises).
+// The norm's per-block partials and the reduced value go to partial_buf and
+// scalar_buf when given (device memory the caller provides), else to the
+// context's buffers.
 template <typename T>
-hhg_status residual_t(hhg_ctx c, int l, const T *f, const T *u, T *r, double *norm, hipStream_t st)
+hhg_status residual_t(hhg_ctx c, int l, const T *f, const T *u, T *r, double *norm, hipStream_t st,
+                      double *partial_buf = nullptr, double *scalar_buf = nullptr)
 {
     LevelView<T> V = view<T>(c, l);
+    double *const partial = partial_buf ? partial_buf : c->partial;
+    double *const dscalar = scalar_buf ? scalar_buf : c->dscalar;
     int np = 0;
     if (c->op == 1 || c->op == 2) {
         // a tensor form (its partial count was checked against the buffer
         // when its solver state was built)
-        HIPCHK(c, launch_tensor<T>(V, c->op - 1, MODE_RESID, u, f, r, c->partial, &np, st));
+        HIPCHK(c, launch_tensor<T>(V, c->op - 1, MODE_RESID, u, f, r, partial, &np, st));
     } else if (c->op == 3 || c->op == 4) {
         // the scalar nodal or primitive-mixed form (the scaled residual's grids)
-        HIPCHK(c, launch_scalar_form<T>(V, corr<T>(c, l), c->op - 2, MODE_RESID, c->mix_mask, u, f, r, c->partial,
+        HIPCHK(c, launch_scalar_form<T>(V, corr<T>(c, l), c->op - 2, MODE_RESID, c->mix_mask, u, f, r, partial,
                                         &np, st));
     } else {
-        HIPCHK(c, launch_scaled<T>(V, MODE_RESID, u, f, r, c->partial, &np, st));
+        HIPCHK(c, launch_scaled<T>(V, MODE_RESID, u, f, r, partial, &np, st));
         CorrView<T> C = corr<T>(c, l);
-        HIPCHK(c, launch_correction<T>(V, C, MODE_RESID, u, r, c->partial + np, st));
+        HIPCHK(c, launch_correction<T>(V, C, MODE_RESID, u, r, partial + np, st));
         if (C.n_rows) np += (C.n_rows + BLOCK - 1) / BLOCK;
     }
     if (norm) {
-        HIPCHK(c, launch_reduce(c->partial, np, 0, c->dscalar, st));
-        HIPCHK(c, hipMemcpyAsync(c->hscalar, c->dscalar, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(c, launch_reduce(partial, np, 0, dscalar, st));
+        HIPCHK(c, hipMemcpyAsync(c->hscalar, dscalar, sizeof(double), hipMemcpyDeviceToHost, st));
         HIPCHK(c, hipStreamSynchronize(st));
         *norm = std::sqrt(std::max(0.0, c->hscalar[0]));
     }
@@ -1851,13 +2009,17 @@ hhg_status hhg_create_macro(const double *vert_xyz, int32_t n_vert, const int32_
         double E0[NTYPE][4][4];
         if (!type_matrices(tp, t, 1, E0)) { delete c; return fail(nullptr, HHG_EMESH, "tet %d is degenerate", t); }
     }
+    {
+        const std::string why = conformity_error(tp.X, tp.tet, tp.nv, tp.nt, tp.edges, tp.faces, tp.f_val);
+        if (!why.empty()) { delete c; return fail(nullptr, HHG_EMESH, "non-conforming macro mesh: %s", why.c_str()); }
+    }
     c->lv.resize(max_level + 1);
     hhg_status s = HHG_OK;
     for (int l = 0; l <= max_level && s == HHG_OK; ++l) s = build_level(c, l);
     if (s == HHG_OK) {
         int64_t pc = 1024;
         for (int l = 0; l <= max_level; ++l) {
-            const Level &L = c->lv[l];
+            Level &L = c->lv[l];
             const int64_t bp2 = (L.n_bnd + BLOCK - 1) / BLOCK;
             const int64_t gm = std::max({(int64_t)tp.nt * ((L.n_items + 3) / 4 + bp2),
                                          (int64_t)tp.nt * ((L.n_items2 + 3) / 4 + bp2),
@@ -1866,7 +2028,8 @@ hhg_status hhg_create_macro(const double *vert_xyz, int32_t n_vert, const int32_
                                          (int64_t)tp.nt * (L.n_items2f + (L.n_bnd + 63) / 64),
                                          (int64_t)tp.nt * (L.n_itemsL + (L.n_bnd + 511) / 512)});
             const int64_t gv = (std::max((int64_t)tp.nt * L.bpt, gm) + 7) / 8 * 8;
-            pc = std::max(pc, gv + (L.n_shared + BLOCK - 1) / BLOCK + (L.n_slots + BLOCK - 1) / BLOCK + 8);
+            L.partial_bound = gv + (L.n_shared + BLOCK - 1) / BLOCK + (L.n_slots + BLOCK - 1) / BLOCK + 8;
+            pc = std::max(pc, L.partial_bound);
         }
         c->partial_cap = pc;
         s = dalloc(c, &c->partial, pc);
@@ -2085,12 +2248,11 @@ hhg_status hhg_read_timing(hhg_ctx c, double *ms_total, int64_t *launches)
 {
     if (!c || !ms_total || !launches) return HHG_EINVAL;
     double tot = 0.0;
-    if (c->tev_used > 0) {
-        HIPCHK(c, hipEventRecord(c->tev[1], c->tev_stream));
-        HIPCHK(c, hipEventSynchronize(c->tev[1]));
+    for (size_t q = 0; q < c->tev_used; ++q) {
+        HIPCHK(c, hipEventSynchronize(c->tev[2 * q + 1]));
         float ms = 0.0f;
-        HIPCHK(c, hipEventElapsedTime(&ms, c->tev[0], c->tev[1]));
-        tot = ms;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->tev[2 * q], c->tev[2 * q + 1]));
+        tot += ms;
     }
     *ms_total = tot;
     *launches = (int64_t)c->tev_used;
@@ -2345,34 +2507,61 @@ hhg_status solve_impl(hhg_ctx c, int32_t level, hhg_solve_mode mode, int32_t pre
     std::vector<double> hist;
     int fallback = 0;
     bool use_learned = mode == HHG_SOLVE_LEARNED;
+    const LearnedState &LS = c->learned;
+    // the plain cycle's contraction, measured once from the same iterate as
+    // a learned cycle (cycle LEARNED_PROBE_CYCLE), when a margin is set
+    const bool probe = use_learned && LS.plain_margin > 0.0;
+    double q_plain = -1.0;
+    bool probe_pending = false;  // the last cycle was the probe's learned one
     if (use_learned && !L.ubak) TRY(dalloc(c, &L.ubak, L.n_slots));
+    if (probe && !L.uprobe) TRY(dalloc(c, &L.uprobe, L.n_slots));
     for (int it = 0;; ++it) {
         TRY(residual_t<double>(c, level, f, u, L.r64, &nr, st));
         hist.push_back(nr / nf);
-        // fallback: a learned cycle must contract at least by the accepted
-        // rate and keep the residual finite; otherwise its result is
-        // discarded and the solve continues with Chebyshev smoothing
+        // fallback: a learned cycle must keep the residual finite, contract
+        // at least by the accepted rate and, once the plain cycle's
+        // contraction is known, by no less than margin x that contraction;
+        // otherwise its result is replaced (by the probe's plain result after
+        // the probe, else by the iterate before the cycle) and the solve
+        // continues with Chebyshev smoothing
         if (use_learned && it >= 1) {
             const double q = hist[it] / hist[it - 1];
-            if (!std::isfinite(nr) || !(q <= c->learned.fallback_rate)) {
+            double bound = LS.fallback_rate;
+            if (q_plain > 0.0) bound = std::min(bound, LS.plain_margin * q_plain);
+            if (!std::isfinite(nr) || !(q <= bound)) {
                 use_learned = false;
                 fallback = 1;
-                HIPCHK(c, hipMemcpyAsync(u, L.ubak, L.n_slots * sizeof(double), hipMemcpyDeviceToDevice, st));
+                HIPCHK(c, hipMemcpyAsync(u, probe_pending ? L.uprobe : L.ubak, L.n_slots * sizeof(double),
+                                         hipMemcpyDeviceToDevice, st));
                 TRY(residual_t<double>(c, level, f, u, L.r64, &nr, st));
                 hist.back() = nr / nf;
             }
         }
+        probe_pending = false;
         if (!std::isfinite(nr)) break;
         if (hist.back() <= tol || it >= max_iter) break;
         if (mode == HHG_SOLVE_F64) {
             TRY(vcycle_run<double>(c, level, f, u, pre, post, HHG_CHEBYSHEV, st));
         } else {
+            HIPCHK(c, launch_convert<double, float>(L.r64, L.f32, L.n_slots, st));
+            if (use_learned && probe && it == LEARNED_PROBE_CYCLE) {
+                // the plain cycle from this iterate, into uprobe
+                HIPCHK(c, launch_fill<float>(L.u32, 0.0f, L.n_slots, st));
+                TRY(vcycle_run<float>(c, level, L.f32, L.u32, pre, post, HHG_CHEBYSHEV, st));
+                HIPCHK(c, hipMemcpyAsync(L.uprobe, u, L.n_slots * sizeof(double), hipMemcpyDeviceToDevice, st));
+                HIPCHK(c, launch_add_f32_to_f64(L.uprobe, L.u32, L.n_slots, st));
+            }
             if (use_learned)
                 HIPCHK(c, hipMemcpyAsync(L.ubak, u, L.n_slots * sizeof(double), hipMemcpyDeviceToDevice, st));
-            HIPCHK(c, launch_convert<double, float>(L.r64, L.f32, L.n_slots, st));
             HIPCHK(c, launch_fill<float>(L.u32, 0.0f, L.n_slots, st));
             TRY(vcycle_run<float>(c, level, L.f32, L.u32, pre, post, use_learned ? HHG_LEARNED : HHG_CHEBYSHEV, st));
             HIPCHK(c, launch_add_f32_to_f64(u, L.u32, L.n_slots, st));
+            if (use_learned && probe && it == LEARNED_PROBE_CYCLE) {
+                double np = 0.0;
+                TRY(residual_t<double>(c, level, f, L.uprobe, L.r64, &np, st));
+                q_plain = (np / nf) / hist[it];
+                probe_pending = true;
+            }
         }
     }
     HIPCHK(c, hipStreamSynchronize(st));
@@ -2507,10 +2696,13 @@ hhg_status hhg_learned_set_weights(hhg_ctx c, const float *w, int64_t n)
     return HHG_OK;
 }
 
-hhg_status hhg_learned_set_fallback(hhg_ctx c, double max_rate)
+hhg_status hhg_learned_set_fallback(hhg_ctx c, double max_rate, double plain_margin)
 {
     if (!c || !(max_rate > 0.0)) return fail(c, HHG_EINVAL, "fallback rate must be positive");
+    if (!(plain_margin >= 0.0) || !std::isfinite(plain_margin))
+        return fail(c, HHG_EINVAL, "plain-cycle margin must be finite and >= 0");
     c->learned.fallback_rate = max_rate;
+    c->learned.plain_margin = plain_margin;
     return HHG_OK;
 }
 

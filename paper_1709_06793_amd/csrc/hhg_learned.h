@@ -9,11 +9,15 @@
 namespace hhg {
 
 constexpr int LN_IN = 32, LN_H = 16;
+// the cycle of a learned solve at which the plain cycle's contraction is
+// measured from the same iterate
+constexpr int LEARNED_PROBE_CYCLE = 2;
 constexpr int LN_NPARAM = LN_H * LN_IN + LN_H + LN_H * LN_H + LN_H + LN_H + 1;  // 817
 
 struct LearnedState {
     bool ready = false;
     double fallback_rate = 1.0;     // largest accepted per-cycle residual ratio
+    double plain_margin = 1.05;     // largest accepted ratio to the plain cycle's contraction (0: off)
     double omega = 2.0 / 3.0;       // damping of the Jacobi part of the step
     unsigned short *wbf = nullptr;  // BF16 parameters (817)
     float *w32 = nullptr;           // FP32 copy uploaded by the caller

@@ -87,7 +87,7 @@ def load():
         "hhg_solve_tensor": [P, I32, I32, I32, I32, I32, D, I32, P, P, P, P],
         "hhg_solve_form": [P, I32, I32, I32, I32, I32, I32, D, I32, P, P, P, P],
         "hhg_learned_set_weights": [P, P, I64],
-        "hhg_learned_set_fallback": [P, D],
+        "hhg_learned_set_fallback": [P, D, D],
         "hhg_learned_forward": [P, I32, P, P, P],
         "hhg_learned_backward": [P, I32, P, P, P, P],
         "hhg_learned_loss_grad": [P, I32, P, P, P, P, P],
@@ -120,6 +120,35 @@ def _dtype_code(t):
     if t.dtype == torch.float32:
         return F32
     raise TypeError("vectors must be float64 or float32 torch tensors")
+
+
+def check_vectors(sizes, level, vecs, n="n_slots", dtype=None, require_cuda=True):
+    """Validate vector arguments before any pointer reaches the library: torch
+    tensors, on the GPU, contiguous, one dtype (float64 or float32, or the one
+    given), and exactly sizes(level)[n] elements each.  Returns the dtype
+    code.  Raises HHGError(EINVAL) otherwise: a wrong-sized or wrong-typed
+    buffer would make the kernels read or write out of bounds."""
+    import torch
+    want = sizes[n]
+    dt = None
+    for v in vecs:
+        if not isinstance(v, torch.Tensor):
+            raise HHGError(EINVAL, f"level {level}: vectors must be torch tensors, got {type(v).__name__}")
+        if require_cuda and not v.is_cuda:
+            raise HHGError(EINVAL, f"level {level}: vectors must live on the GPU")
+        if not v.is_contiguous():
+            raise HHGError(EINVAL, f"level {level}: vectors must be contiguous")
+        if v.numel() != want:
+            raise HHGError(EINVAL, f"level {level}: vector has {v.numel()} elements, expected {want} ({n})")
+        if v.dtype not in (torch.float64, torch.float32):
+            raise HHGError(EINVAL, f"level {level}: vectors must be float64 or float32, got {v.dtype}")
+        if dt is None:
+            dt = v.dtype
+        elif v.dtype != dt:
+            raise HHGError(EINVAL, f"level {level}: mixed dtypes {dt} and {v.dtype}")
+    if dtype is not None and dt != dtype:
+        raise HHGError(EINVAL, f"level {level}: vectors must be {dtype}, got {dt}")
+    return F64 if dt == torch.float64 else F32
 
 
 def _stream():
@@ -160,9 +189,23 @@ class Context:
 
     # ---- sizes and layout
     def sizes(self, level):
-        a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
-        self._check(load().hhg_vector_size(self._h, level, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
-        return dict(n_slots=a.value, n_unknowns=b.value, n_nodes=c.value)
+        cache = self.__dict__.setdefault("_sizes", {})
+        if level not in cache:
+            a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+            self._check(load().hhg_vector_size(self._h, level, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+            cache[level] = dict(n_slots=a.value, n_unknowns=b.value, n_nodes=c.value)
+        return dict(cache[level])
+
+    def _vecs(self, level, *vecs, n="n_slots", dtype=None):
+        return check_vectors(self.sizes(level), level, vecs, n=n, dtype=dtype)
+
+    def _f32(self):
+        import torch
+        return torch.float32
+
+    def _f64(self):
+        import torch
+        return torch.float64
 
     def node_coords(self, level):
         n = self.sizes(level)["n_nodes"]
@@ -178,23 +221,30 @@ class Context:
 
     def to_canonical(self, level, v):
         import torch
+        dt = self._vecs(level, v)
         out = torch.empty(self.sizes(level)["n_nodes"], dtype=v.dtype, device=v.device)
-        self._check(load().hhg_to_canonical(self._h, level, _dtype_code(v), _ptr(v), _ptr(out), _stream()))
+        self._check(load().hhg_to_canonical(self._h, level, dt, _ptr(v), _ptr(out), _stream()))
         return out
 
     def from_canonical(self, level, v):
         import torch
+        dt = self._vecs(level, v, n="n_nodes")
         out = torch.zeros(self.sizes(level)["n_slots"], dtype=v.dtype, device=v.device)
-        self._check(load().hhg_from_canonical(self._h, level, _dtype_code(v), _ptr(v), _ptr(out), _stream()))
+        self._check(load().hhg_from_canonical(self._h, level, dt, _ptr(v), _ptr(out), _stream()))
         return out
 
     # ---- coefficient and solver data
     def set_coefficient(self, k):
         """Finest-level nodal k, canonical order (numpy float64 or a torch tensor)."""
+        nn = self.sizes(self.max_level)["n_nodes"]
         if isinstance(k, np.ndarray):
             k = np.ascontiguousarray(k, dtype=np.float64)
+            if k.size != nn:
+                raise HHGError(EINVAL, f"coefficient has {k.size} values, expected {nn}")
             self._check(load().hhg_set_coefficient(self._h, _ptr(k), 0, _stream()))
         else:
+            check_vectors(self.sizes(self.max_level), self.max_level, (k,), n="n_nodes",
+                          dtype=self._f64(), require_cuda=False)
             self._check(load().hhg_set_coefficient(self._h, _ptr(k), 1 if k.is_cuda else 0, _stream()))
 
     def set_coarse_level(self, level):
@@ -207,7 +257,8 @@ class Context:
 
     # ---- operators
     def apply_scaled(self, level, u, y):
-        self._check(load().hhg_apply_scaled(self._h, level, _dtype_code(u), _ptr(u), _ptr(y), _stream()))
+        dt = self._vecs(level, u, y)
+        self._check(load().hhg_apply_scaled(self._h, level, dt, _ptr(u), _ptr(y), _stream()))
         return y
 
     def set_timing(self, enable):
@@ -220,53 +271,66 @@ class Context:
         return ms.value, n.value
 
     def apply_mixed(self, level, u, y, nodal_primitives=PRIM_VERTICES | PRIM_EDGES):
-        self._check(load().hhg_apply_mixed(self._h, level, _dtype_code(u), int(nodal_primitives), _ptr(u), _ptr(y),
+        dt = self._vecs(level, u, y)
+        self._check(load().hhg_apply_mixed(self._h, level, dt, int(nodal_primitives), _ptr(u), _ptr(y),
                                            _stream()))
         return y
 
     def set_tensor_coefficient(self, k6):
         """k6: (6, n_nodes) component fields at the finest level (numpy or a
         contiguous float64 device tensor), canonical node order."""
+        nn = self.sizes(self.max_level)["n_nodes"]
+        if tuple(k6.shape) != (6, nn):
+            raise HHGError(EINVAL, f"tensor coefficient has shape {tuple(k6.shape)}, expected (6, {nn})")
         if isinstance(k6, np.ndarray):
             a = np.ascontiguousarray(k6, dtype=np.float64)
             self._check(load().hhg_set_tensor_coefficient(self._h, _ptr(a), 0, _stream()))
         else:
             t = k6.contiguous()
+            if t.dtype != self._f64():
+                raise HHGError(EINVAL, f"tensor coefficient must be float64, got {t.dtype}")
             self._check(load().hhg_set_tensor_coefficient(self._h, _ptr(t), 1 if t.is_cuda else 0, _stream()))
 
     def apply_tensor(self, level, u, y):
-        self._check(load().hhg_apply_tensor(self._h, level, _dtype_code(u), _ptr(u), _ptr(y), _stream()))
+        dt = self._vecs(level, u, y)
+        self._check(load().hhg_apply_tensor(self._h, level, dt, _ptr(u), _ptr(y), _stream()))
         return y
 
     def apply_tensor_nodal(self, level, u, y):
-        self._check(load().hhg_apply_tensor_nodal(self._h, level, _dtype_code(u), _ptr(u), _ptr(y), _stream()))
+        dt = self._vecs(level, u, y)
+        self._check(load().hhg_apply_tensor_nodal(self._h, level, dt, _ptr(u), _ptr(y), _stream()))
         return y
 
     def store_stencils(self, level):
         self._check(load().hhg_store_stencils(self._h, level))
 
     def apply_stored(self, level, u, y):
-        self._check(load().hhg_apply_stored(self._h, level, _dtype_code(u), _ptr(u), _ptr(y), _stream()))
+        dt = self._vecs(level, u, y)
+        self._check(load().hhg_apply_stored(self._h, level, dt, _ptr(u), _ptr(y), _stream()))
         return y
 
     def apply_nodal(self, level, u, y):
-        self._check(load().hhg_apply_nodal(self._h, level, _dtype_code(u), _ptr(u), _ptr(y), _stream()))
+        dt = self._vecs(level, u, y)
+        self._check(load().hhg_apply_nodal(self._h, level, dt, _ptr(u), _ptr(y), _stream()))
         return y
 
     def residual(self, level, f, u, r, norm=False):
         nv = ctypes.c_double()
-        self._check(load().hhg_residual(self._h, level, _dtype_code(u), _ptr(f), _ptr(u), _ptr(r),
+        dt = self._vecs(level, f, u, r)
+        self._check(load().hhg_residual(self._h, level, dt, _ptr(f), _ptr(u), _ptr(r),
                                         ctypes.byref(nv) if norm else None, _stream()))
         return nv.value if norm else r
 
     def smooth(self, level, f, u, sweeps, smoother=JACOBI, omega=2.0 / 3.0):
-        self._check(load().hhg_smooth(self._h, level, _dtype_code(u), smoother, sweeps, omega,
+        dt = self._vecs(level, f, u)
+        self._check(load().hhg_smooth(self._h, level, dt, smoother, sweeps, omega,
                                       _ptr(f), _ptr(u), _stream()))
         return u
 
     def vcycle(self, level, f, u, pre=2, post=2, smoother=CHEBYSHEV, rel_res=False):
         rr = ctypes.c_double()
-        self._check(load().hhg_vcycle(self._h, level, _dtype_code(u), pre, post, smoother, _ptr(f),
+        dt = self._vecs(level, f, u)
+        self._check(load().hhg_vcycle(self._h, level, dt, pre, post, smoother, _ptr(f),
                                       _ptr(u), ctypes.byref(rr) if rel_res else None, _stream()))
         return rr.value if rel_res else u
 
@@ -275,6 +339,7 @@ class Context:
         self._check(load().hhg_set_graphs(self._h, int(bool(enable))))
 
     def solve(self, level, f, u, mode=SOLVE_F64, tol=1e-8, max_iter=100, pre=2, post=2):
+        self._vecs(level, f, u, dtype=self._f64())
         st = SolveStats()
         s = self._check(load().hhg_solve(self._h, level, mode, pre, post, tol, max_iter, _ptr(f), _ptr(u),
                                          ctypes.byref(st), _stream()))
@@ -285,6 +350,7 @@ class Context:
         """hhg_solve_tensor: the tensor operator with every component scaled
         (form "scaled") or nodally integrated (form "nodal")."""
         fc = {"scaled": 0, "nodal": 1}[form]
+        self._vecs(level, f, u, dtype=self._f64())
         st = SolveStats()
         s = self._check(load().hhg_solve_tensor(self._h, level, fc, mode, pre, post, tol, max_iter, _ptr(f), _ptr(u),
                                                 ctypes.byref(st), _stream()))
@@ -297,6 +363,7 @@ class Context:
         ("nodal") or primitive-mixed ("mixed", nodal rows on
         nodal_primitives) operator."""
         fc = {"scaled": 0, "nodal": 1, "mixed": 2}[form]
+        self._vecs(level, f, u, dtype=self._f64())
         st = SolveStats()
         s = self._check(load().hhg_solve_form(self._h, level, fc, nodal_primitives, mode, pre, post, tol, max_iter,
                                               _ptr(f), _ptr(u), ctypes.byref(st), _stream()))
@@ -306,21 +373,28 @@ class Context:
     # ---- learned correction
     def learned_set_weights(self, w):
         w = np.ascontiguousarray(w, dtype=np.float32)
+        if w.size != LEARNED_NPARAM:
+            raise HHGError(EINVAL, f"{w.size} parameters, expected {LEARNED_NPARAM}")
         self._check(load().hhg_learned_set_weights(self._h, _ptr(w), w.size))
 
     def learned_forward(self, level, r, c_out):
+        self._vecs(level, r, c_out, dtype=self._f32())
         self._check(load().hhg_learned_forward(self._h, level, _ptr(r), _ptr(c_out), _stream()))
         return c_out
 
     def learned_backward(self, level, r, g):
+        self._vecs(level, r, g, dtype=self._f32())
         dw = np.zeros(LEARNED_NPARAM, dtype=np.float32)
         self._check(load().hhg_learned_backward(self._h, level, _ptr(r), _ptr(g), _ptr(dw), _stream()))
         return dw
 
-    def learned_set_fallback(self, max_rate):
-        self._check(load().hhg_learned_set_fallback(self._h, float(max_rate)))
+    def learned_set_fallback(self, max_rate=1.0, plain_margin=1.05):
+        """Reject a learned cycle whose residual ratio exceeds max_rate or
+        plain_margin x the plain cycle's ratio (0 turns that test off)."""
+        self._check(load().hhg_learned_set_fallback(self._h, float(max_rate), float(plain_margin)))
 
     def learned_loss_grad(self, level, r, e):
+        self._vecs(level, r, e, dtype=self._f32())
         dw = np.zeros(LEARNED_NPARAM, dtype=np.float32)
         loss = ctypes.c_double()
         self._check(load().hhg_learned_loss_grad(self._h, level, _ptr(r), _ptr(e), ctypes.byref(loss),
@@ -328,6 +402,8 @@ class Context:
         return loss.value, dw
 
     def training_pair(self, level, f, u, u_star, r_out, e_out):
+        self._vecs(level, f, u, u_star, dtype=self._f64())
+        self._vecs(level, r_out, e_out, dtype=self._f32())
         self._check(load().hhg_training_pair(self._h, level, _ptr(f), _ptr(u), _ptr(u_star), _ptr(r_out),
                                              _ptr(e_out), _stream()))
 

@@ -83,27 +83,38 @@ class Context2D:
 
     def set_coefficient(self, k):
         k = np.ascontiguousarray(k, dtype=np.float64)
+        nn = self.sizes()["n_nodes"]
+        if k.size != nn:
+            raise HHGError(-1, f"coefficient has {k.size} values, expected {nn}")
         self._check(load().hhg2d_set_coefficient(self._h, _ptr(k)))
 
     def vector(self, dtype=None):
         import torch
         return torch.zeros(self.sizes()["n_slots"], dtype=dtype or torch.float64, device="cuda")
 
+    def _vecs(self, *vecs, n="n_slots"):
+        from .hhg import check_vectors
+        return check_vectors(self.sizes(), self.level, vecs, n=n)
+
     def from_canonical(self, v):
+        dt = self._vecs(v, n="n_nodes")
         out = self.vector(v.dtype)
-        self._check(load().hhg2d_from_canonical(self._h, _dtype_code(v), _ptr(v.contiguous()), _ptr(out), _stream()))
+        self._check(load().hhg2d_from_canonical(self._h, dt, _ptr(v), _ptr(out), _stream()))
         return out
 
     def to_canonical(self, v):
         import torch
+        dt = self._vecs(v)
         out = torch.empty(self.sizes()["n_nodes"], dtype=v.dtype, device="cuda")
-        self._check(load().hhg2d_to_canonical(self._h, _dtype_code(v), _ptr(v), _ptr(out), _stream()))
+        self._check(load().hhg2d_to_canonical(self._h, dt, _ptr(v), _ptr(out), _stream()))
         return out
 
     def apply_scaled(self, u, y):
-        self._check(load().hhg2d_apply_scaled(self._h, _dtype_code(u), _ptr(u), _ptr(y), _stream()))
+        dt = self._vecs(u, y)
+        self._check(load().hhg2d_apply_scaled(self._h, dt, _ptr(u), _ptr(y), _stream()))
         return y
 
     def apply_nodal(self, u, y):
-        self._check(load().hhg2d_apply_nodal(self._h, _dtype_code(u), _ptr(u), _ptr(y), _stream()))
+        dt = self._vecs(u, y)
+        self._check(load().hhg2d_apply_nodal(self._h, dt, _ptr(u), _ptr(y), _stream()))
         return y

@@ -130,11 +130,12 @@ def evaluate(ctx, f, level, w, torch, tol=1e-8, max_iter=200):
     u = ctx.vector(level)
     res["chebyshev"] = ctx.solve(level, f, u, mode=hhg.SOLVE_MIXED, tol=tol, max_iter=max_iter)
     # the learned solve runs with the library's default fallback (a cycle that
-    # does not reduce the residual switches the solve to Chebyshev); the
-    # network-off reference never falls back
-    for name, wv, rate in (("learned", w, 1.0), ("network_off", np.zeros_like(w), 1e30)):
+    # does not reduce the residual, or contracts worse than 1.05 x the plain
+    # cycle measured from the same iterate, switches the solve to Chebyshev);
+    # the network-off reference never falls back
+    for name, wv, rate, margin in (("learned", w, 1.0, 1.05), ("network_off", np.zeros_like(w), 1e30, 0.0)):
         ctx.learned_set_weights(wv)
-        ctx.learned_set_fallback(rate)
+        ctx.learned_set_fallback(rate, margin)
         u = ctx.vector(level)
         res[name] = ctx.solve(level, f, u, mode=hhg.SOLVE_LEARNED, tol=tol, max_iter=max_iter)
     return res

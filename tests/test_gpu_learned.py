@@ -1,13 +1,14 @@
 """Learned smoothing correction on the GPU (through the C ABI) against the CPU
 reference network, and what training buys.
 
-Tolerances: the kernels round features and first-layer activations to BF16
-exactly where the reference does, but accumulate in FP32 on the matrix cores
-in their own order; a rounding of an activation near a BF16 tie can then land
-one BF16 step (2^-8 relative) away.  Such flips are rare (a few per thousand
-nodes), so the outputs agree to ~1e-4 in norm and to a few 1e-3 of the
-largest output element-wise; gradients are sums over nodes and agree to
-~1e-4 in norm.
+Tolerances: the features are formed exactly as the reference forms them
+(the same FP32 operations, one rounding each), so their BF16 roundings agree.
+The matrix products accumulate in FP32 in the matrix cores' order, the
+reference rounds the exact sum once; a first-layer activation within a few
+FP32 ulps of a BF16 rounding midpoint can then round to the neighbouring BF16
+value (2^-8 relative).  The forward test separates those nodes: elsewhere
+outputs agree to 1e-5; the few nodes with such a tie only to the looser bar.
+Gradients are sums over nodes and agree to ~1e-4 in norm (bar 1e-3).
 """
 import numpy as np
 import pytest
@@ -33,6 +34,21 @@ def _weights(seed):
     w[800:816] = rng.normal(0, 0.5, 16)
     w[816] = 0.05
     return w.astype(np.float32)
+
+
+def _bf16_tie_nodes(w, cache):
+    """Nodes with a first-layer pre-activation z within 2^-19 S of a BF16
+    rounding midpoint, S = sum_j |W1_ij x_j| + |b1_i|: summing the 32 products
+    and the bias in FP32 in any order errs by at most ~32 ulps of S, so only
+    such activations may round to the neighbouring BF16 value on the matrix
+    cores."""
+    W1, b1 = LN.unpack(LN.bf16(w))[:2]
+    S = np.abs(cache["xb"]) @ np.abs(W1).T + np.abs(b1)
+    a = np.maximum(np.asarray(cache["z1"], dtype=np.float32), 0).astype(np.float32)
+    lo = (a.view(np.uint32) & np.uint32(0xFFFF0000)).view(np.float32).astype(np.float64)
+    e = np.floor(np.log2(np.where(lo > 0, lo, 1.0)))
+    mid = lo + 2.0 ** (e - 8)                      # half a BF16 step (8 significant bits)
+    return ((lo > 0) & (np.abs(a - mid) <= 2.0 ** -19 * S)).any(axis=1)
 
 
 def _setup(mesh_fn, level, seed=0):
@@ -64,14 +80,106 @@ def test_forward_and_backward_match_reference(mesh_fn, level):
     others = np.setdiff1d(np.arange(om.n_nodes), nodes)
     assert np.all(got[others] == 0.0)
     err = got[nodes] - ref
-    assert np.linalg.norm(err) <= 5e-4 * np.linalg.norm(ref), np.linalg.norm(err) / np.linalg.norm(ref)
-    assert np.abs(err).max() <= 2e-2 * np.abs(ref).max()
+    tie = _bf16_tie_nodes(w, cache)
+    print(f"nodes {len(nodes)}, with a first-layer BF16 tie {int(tie.sum())}", flush=True)
+    assert tie.mean() <= 0.2
+    clean = ~tie
+    scale = np.abs(ref).max()
+    assert np.abs(err[clean]).max() <= 1e-5 * scale, np.abs(err[clean]).max() / scale
+    assert np.linalg.norm(err[clean]) <= 1e-5 * np.linalg.norm(ref[clean])
+    assert np.abs(err).max() <= 2e-2 * scale
     # backward: gradient of sum_i g_i c_i
     g = uniform_vector(om.n_nodes, seed=9).astype(np.float32)
     gd = ctx.from_canonical(level, torch.tensor(g, device="cuda"))
     dw = ctx.learned_backward(level, rd, gd)
     dref = LN.backward(w, cache, g[nodes])
     assert np.linalg.norm(dw - dref) <= 1e-3 * np.linalg.norm(dref), np.linalg.norm(dw - dref) / np.linalg.norm(dref)
+
+
+@pytest.mark.parametrize("mesh_fn,level", [(kuhn_cube, 4), (unit_tet, 5)])
+def test_learned_smoothing_step_matches_oracle(mesh_fn, level):
+    """hhg_smooth(HHG_LEARNED): r = f - A u, u <- u + D^{-1}(2/3 r + s c) in
+    FP32, against the oracle's step (FP64 operator, features from r rounded to
+    FP32, the same BF16 network)."""
+    om, k, ctx, _ = _setup(mesh_fn, level)
+    w = _weights(3)
+    ctx.learned_set_weights(w)
+    op = O.make_operator(om, k, "scaled", modification=True)
+    f = uniform_vector(om.n_nodes, seed=21).astype(np.float32).astype(np.float64)
+    u = uniform_vector(om.n_nodes, seed=22).astype(np.float32).astype(np.float64)
+    f[om.dirichlet] = 0.0
+    u[om.dirichlet] = 0.0
+    fd = ctx.from_canonical(level, torch.tensor(f, device="cuda").float())
+    ud = ctx.from_canonical(level, torch.tensor(u, device="cuda").float())
+    nodes = LN.interior_nodes(om)
+    pos = LN.stencil_positions(om, nodes)
+    lk = np.log(k).astype(np.float32)
+    for sweep in range(2):
+        ref = LN.step(op, w, f, u, lk, pos, nodes)
+        ctx.smooth(level, fd, ud, 1, hhg.LEARNED)
+        got = ctx.to_canonical(level, ud).cpu().numpy().astype(np.float64)
+        du_ref, du_got = ref - u, got - u
+        rel = np.linalg.norm(du_got - du_ref) / np.linalg.norm(du_ref)
+        print(f"sweep {sweep}: relative error of the update {rel:.2e}", flush=True)
+        assert rel <= 1e-4
+        assert np.abs(du_got - du_ref).max() <= 2e-3 * np.abs(du_ref).max()
+        u = got     # both sides continue from the GPU's FP32 iterate
+    # the C ABI's FP64 path refuses the learned smoother
+    with pytest.raises(hhg.HHGError):
+        ctx.smooth(level, ctx.vector(level), ctx.vector(level), 1, hhg.LEARNED)
+
+
+def test_learned_vcycle_matches_oracle():
+    """One V(2,2) cycle with learned smoothing on the finest level (FP32)
+    against the oracle's cycle with the same steps (FP64, Chebyshev below)."""
+    X, T = kuhn_cube()
+    level, coarse = 4, 2
+    kfun = lambda x: lognormal_k(x, lognormal_params(5, 1.0, 0.2))
+    mg = O.Multigrid(X, T, level, coarse, kfun=kfun, modification=True)
+    om = mg.meshes[level]
+    k = kfun(om.xyz)
+    ctx = hhg.Context(X, T, level)
+    ctx.set_coefficient(k)
+    ctx.set_coarse_level(coarse)
+    w = _weights(4)
+    ctx.learned_set_weights(w)
+    f = uniform_vector(om.n_nodes, seed=23).astype(np.float32).astype(np.float64)
+    f[om.dirichlet] = 0.0
+    nodes = LN.interior_nodes(om)
+    pos = LN.stencil_positions(om, nodes)
+    ref = LN.vcycle(mg, w, f, np.zeros(om.n_nodes), np.log(k).astype(np.float32), pos, nodes)
+    fd = ctx.from_canonical(level, torch.tensor(f, device="cuda").float())
+    ud = ctx.vector(level, torch.float32)
+    ctx.vcycle(level, fd, ud, 2, 2, hhg.LEARNED)
+    got = ctx.to_canonical(level, ud).cpu().numpy().astype(np.float64)
+    rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    print(f"learned V-cycle: relative error {rel:.2e}", flush=True)
+    assert rel <= 2e-4
+
+
+def test_loss_gradient_matches_oracle():
+    """hhg_learned_loss_grad: the loss and dL/dw that training consumes,
+    against the oracle's loss_and_grad (FP64 operator, backward() chained)."""
+    level = 4
+    om, k, ctx, _ = _setup(kuhn_cube, level)
+    w = _weights(2)
+    ctx.learned_set_weights(w)
+    op = O.make_operator(om, k, "scaled", modification=True)
+    e = uniform_vector(om.n_nodes, seed=4)
+    e[om.dirichlet] = 0.0
+    e = e.astype(np.float32).astype(np.float64)
+    r = op.apply(e).astype(np.float32).astype(np.float64)
+    rd = ctx.from_canonical(level, torch.tensor(r, device="cuda").float())
+    ed = ctx.from_canonical(level, torch.tensor(e, device="cuda").float())
+    loss, dw = ctx.learned_loss_grad(level, rd, ed)
+    nodes = LN.interior_nodes(om)
+    pos = LN.stencil_positions(om, nodes)
+    ref_loss, ref_dw = LN.loss_and_grad(op, w, r, e, np.log(k).astype(np.float32), pos, nodes)
+    print(f"loss {loss:.6e} ref {ref_loss:.6e}", flush=True)
+    assert loss == pytest.approx(ref_loss, rel=2e-4)
+    rel = np.linalg.norm(dw - ref_dw) / np.linalg.norm(ref_dw)
+    print(f"dL/dw relative error {rel:.2e}", flush=True)
+    assert rel <= 1e-3
 
 
 def test_training_loss_matches_reference():
@@ -115,7 +223,7 @@ def test_training_reduces_loss_and_fallback_recovers():
     ctx, pairs, f = data[0]
     # trained network: converges
     ctx.learned_set_weights(w)
-    ctx.learned_set_fallback(1e30)
+    ctx.learned_set_fallback(1e30, 0.0)
     u = ctx.vector(level)
     st = ctx.solve(level, f, u, mode=hhg.SOLVE_LEARNED, tol=1e-8, max_iter=100)
     print("trained", st, flush=True)
@@ -124,12 +232,39 @@ def test_training_reduces_loss_and_fallback_recovers():
     bad = w.copy()
     bad[800:817] = 1e4
     ctx.learned_set_weights(bad)
-    ctx.learned_set_fallback(0.9)
+    ctx.learned_set_fallback(0.9, 0.0)
     u = ctx.vector(level)
     st = ctx.solve(level, f, u, mode=hhg.SOLVE_LEARNED, tol=1e-8, max_iter=100)
     print("corrupted", st, flush=True)
     assert st["fallback"] == 1 and st["status"] == hhg.WFALLBACK
     assert st["rel_residual"] <= 1e-8
+
+
+def test_fallback_fires_when_learned_cycles_contract_worse_than_plain():
+    """A zero network output leaves damped-Jacobi learned cycles: they
+    contract, but worse than Chebyshev cycles.  The plain-cycle probe must
+    switch such a solve to Chebyshev (and keep the probe's plain result); with
+    the probe off, the same solve runs on with the weaker cycles."""
+    level = 5
+    ctx, f, _ = LT.make_field_context(level, 1000, kuhn_cube, torch)
+    ctx.learned_set_weights(np.zeros(LN.NPARAM, dtype=np.float32))
+    ctx.learned_set_fallback(1.0, 1.05)
+    u = ctx.vector(level)
+    st = ctx.solve(level, f, u, mode=hhg.SOLVE_LEARNED, tol=1e-8, max_iter=100)
+    print("probe on", st, flush=True)
+    assert st["fallback"] == 1 and st["status"] == hhg.WFALLBACK
+    assert st["rel_residual"] <= 1e-8
+    ctx.learned_set_fallback(1.0, 0.0)
+    u = ctx.vector(level)
+    st_off = ctx.solve(level, f, u, mode=hhg.SOLVE_LEARNED, tol=1e-8, max_iter=100)
+    print("probe off", st_off, flush=True)
+    assert st_off["fallback"] == 0 and st_off["rel_residual"] <= 1e-8
+    assert st["iterations"] < st_off["iterations"]
+    u = ctx.vector(level)
+    st_plain = ctx.solve(level, f, u, mode=hhg.SOLVE_MIXED, tol=1e-8, max_iter=100)
+    assert st["iterations"] <= st_plain["iterations"] + 1
+    with pytest.raises(hhg.HHGError):
+        ctx.learned_set_fallback(1.0, -1.0)
 
 
 def test_learned_smoother_gains_over_network_off():
