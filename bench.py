@@ -83,33 +83,143 @@ def lognormal_on_device(xyz, prm, torch):
     return lognormal_k_torch(xyz, prm, torch)
 
 
-def cpu_baseline(level=7, seconds=8.0):
-    """The oracle as it stands on this host: CSR assembly of the scaled operator
-    on the unit tet at `level` (one eighth of the GPU workload at level 7), then
-    SpMV repeated for about `seconds`.  scipy's CSR SpMV uses one thread."""
-    from hhg_inputs import unit_tet, lognormal_params, lognormal_k
+def host_description():
+    """nproc, the CPU model (lscpu) and the threads the oracle may use: the
+    box's CPU share (at most 16 threads for one GPU) whatever os.cpu_count()
+    shows."""
+    import subprocess
+    try:
+        nproc = int(subprocess.run(["nproc"], capture_output=True, text=True).stdout.strip())
+    except Exception:
+        nproc = os.cpu_count()
+    model = "unknown"
+    try:
+        for line in subprocess.run(["lscpu"], capture_output=True, text=True).stdout.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except Exception:
+        pass
+    threads = max(1, min(len(os.sched_getaffinity(0)), 16, nproc))
+    return {"nproc": nproc, "os_cpu_count": os.cpu_count(), "cpu_model": model, "threads": threads}
+
+
+def cpu_baseline(host):
+    """The oracle as it stands on this host's cores.
+
+    * Matvec: the oracle's CSR assembly of the scaled operator on the unit
+      tet at level 8 (the GPU workload: 2,731,135 unknowns, 15 entries per
+      row), then the oracle's plain C CSR product (OpenMP, static schedule
+      over rows) on all threads of the machine's CPU share: 20 untimed products,
+      200 timed, median; and on one thread (20 timed).
+    * Time to solution: the oracle's multigrid (scipy CSR products, one
+      thread; V(2,2), Chebyshev, P1 transfer, dense coarse solve) on the
+      6-tet cube at level 6 (250,047 unknowns), smooth k, b = M I_h f, from
+      u = 0 to a 1e-8 relative residual; its solution continued to 1e-12
+      is the reference the GPU's level-6 solves are compared with."""
+    from hhg_inputs import unit_tet, kuhn_cube, lognormal_params, lognormal_k, smooth_k, manufactured_f
     from oracle import oracle as O
     X, T = unit_tet()
     t0 = time.perf_counter()
-    m = O.Mesh(X, T, level)
-    prm = lognormal_params(1, 1.0, 0.1)
-    k = lognormal_k(m.xyz, prm)
+    m = O.Mesh(X, T, 8)
+    k = lognormal_k(m.xyz, lognormal_params(1, 1.0, 0.1))
     op = O.make_operator(m, k, "scaled")
     t_asm = time.perf_counter() - t0
-    x = np.random.default_rng(0).uniform(-1, 1, op.A.shape[0])
-    n = 0
-    t0 = time.perf_counter()
-    while time.perf_counter() - t0 < seconds:
-        op.A @ x
-        n += 1
-    dt = (time.perf_counter() - t0) / n
     nu = op.A.shape[0]
-    return {"value": nu / dt / 1e9, "unit": "GDoF/s", "cores": 1, "kind": "oracle",
-            "sample": f"unit tet level {level} ({nu} unknowns, 1/8 of the GPU workload): oracle CSR SpMV "
-                      f"(scipy, 1 thread), {n} reps; CSR assembly from k took {t_asm:.1f} s "
-                      f"({nu / t_asm / 1e9:.2e} GDoF/s if assembly is counted)",
-            "host_threads_available": os.cpu_count()}
+    th = host["threads"]
+    times = O.spmv_bench(op, th, warm=20, reps=200)
+    t1 = O.spmv_bench(op, 1, warm=2, reps=20)
+    gd = nu / float(np.median(times)) / 1e9
+    gd1 = nu / float(np.median(t1)) / 1e9
+    nnz = op.A.nnz
+    del op, m, k
+    log(f"bench: oracle CSR SpMV {gd:.3f} GDoF/s on {th} threads, {gd1:.3f} on 1")
+    # multigrid time to solution, C3 level 6
+    X6, T6 = kuhn_cube()
+    t0 = time.perf_counter()
+    mg = O.Multigrid(X6, T6, 6, 2, kfun=smooth_k, modification=True)
+    mesh = mg.meshes[6]
+    b = O.assemble_mass(mesh) @ manufactured_f(mesh.xyz)
+    b[mesh.dirichlet] = 0.0
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    u, hist = mg.solve(b, tol=1e-8, maxit=100)
+    t_solve = time.perf_counter() - t0
+    uref = u.copy()
+    op6 = mg.ops[6]
+    nb = np.linalg.norm(b[mesh.unknowns])
+    for _ in range(40):
+        if np.linalg.norm(op6.residual(b, uref)[mesh.unknowns]) <= 1e-12 * nb:
+            break
+        uref = mg.vcycle(6, b, uref)
+    out = {"value": round(gd, 4), "unit": "GDoF/s", "cores": th, "kind": "oracle",
+           "sample": f"unit tet level 8 ({nu} unknowns, {nnz} stored entries; the GPU workload itself): the "
+                     f"oracle's CSR matrix of the scaled operator (assembled in {t_asm:.1f} s by its element "
+                     f"loops), plain C CSR product with OpenMP on {th} threads, median of 200 after 20 "
+                     f"untimed; {nu * 200 / gd / 1e9:.1f} s of products",
+           "single_thread_gdofs": round(gd1, 4),
+           "host": host,
+           "multigrid_c3_level6": {
+               "unknowns": int(len(mesh.unknowns)), "seconds_to_1e-8": round(t_solve, 3),
+               "setup_seconds": round(t_setup, 2), "iterations": len(hist) - 1,
+               "rel_residual": float(f"{hist[-1]:.3g}"),
+               "threads": 1,
+               "note": "oracle multigrid, scipy CSR products (one thread), V(2,2) Chebyshev, from u = 0"}}
+    return out, (mesh.xyz, uref)
 
+
+def c3_solves(hhg, torch, oracle_ref=None):
+    """The 6-tet Kuhn cube at levels 5-8 with smooth k and the manufactured
+    solution u* = sin(pi x) sin(pi y) sin(pi z), b = M I_h f (consistent mass
+    on the Freudenthal grid): FP64 and FP32-in-FP64 multigrid, V(2,2)
+    Chebyshev, from u = 0 to a 1e-8 relative residual.  Each record states
+    the discretisation error (discrete nodal L2 error against u*) and, at
+    level 6, the error against the oracle's solution of the same system."""
+    from hhg_inputs import kuhn_cube, smooth_k, manufactured_u, manufactured_f, kuhn_cube_mass_rhs
+    X, T = kuhn_cube()
+    out = {"cycle": "V(2,2)", "tol": 1e-8}
+    prev = None
+    for level in (5, 6, 7, 8):
+        log(f"bench: C3 level {level}")
+        ctx = hhg.Context(X, T, level)
+        xyz, dirichlet = ctx.node_coords(level)
+        ctx.set_coefficient(smooth_k(xyz))
+        b = kuhn_cube_mass_rhs(xyz, level, manufactured_f)
+        b[dirichlet] = 0.0
+        fd = ctx.from_canonical(level, torch.tensor(b, device="cuda"))
+        ustar = manufactured_u(xyz)
+        h = 0.5 ** level
+        rec = {"unknowns": ctx.sizes(level)["n_unknowns"]}
+        for name, mode in (("f64", hhg.SOLVE_F64), ("mixed", hhg.SOLVE_MIXED)):
+            best = None
+            for _ in range(2):
+                u = ctx.vector(level)
+                torch.cuda.synchronize()
+                st = ctx.solve(level, fd, u, mode=mode, tol=1e-8, max_iter=100)
+                if best is None or st["seconds"] < best["seconds"]:
+                    best, ub = st, u
+            uh = ctx.to_canonical(level, ub).cpu().numpy()
+            e = uh - ustar
+            r = {k2: (float(f"{v:.4g}") if isinstance(v, float) else v) for k2, v in best.items()}
+            r["nodal_l2_error"] = float(f"{np.sqrt(h ** 3 * np.sum(e[~dirichlet] ** 2)):.5g}")
+            if oracle_ref is not None and level == 6:
+                oxyz, ouref = oracle_ref
+                # match nodes by coordinates (both sides number nodes their own way)
+                key = lambda x: np.rint(x * 2 ** level).astype(np.int64) @ np.array([1, 1 << 10, 1 << 20])
+                order_o = np.argsort(key(oxyz))
+                order_g = np.argsort(key(xyz))
+                a, c = uh[order_g], ouref[order_o]
+                r["error_vs_oracle_solution"] = float(f"{np.linalg.norm(a - c) / np.linalg.norm(c):.3g}")
+            rec[name] = r
+            log(f"bench: C3 level {level} {name}: {r}")
+        if prev is not None:
+            rec["nodal_l2_eoc"] = round(float(np.log2(prev / rec["f64"]["nodal_l2_error"])), 3)
+        prev = rec["f64"]["nodal_l2_error"]
+        out[f"level{level}"] = rec
+        ctx.close()
+        del ctx, fd, u, ub
+        torch.cuda.empty_cache()
+    return out
 
 
 def kuhn48_applies(hhg, torch, steps, solves=True, applies=True):
@@ -219,7 +329,7 @@ def learned_solves(hhg, torch):
     fd = ctx.from_canonical(level, torch.tensor(f, device="cuda"))
     w, meta = LT.load_weights()
     ctx.learned_set_weights(w)
-    ctx.learned_set_fallback(1.0)
+    ctx.learned_set_fallback(1.0, 1.05)
     out = {"unknowns": ctx.sizes(level)["n_unknowns"], "field_seed": 1000,
            "sigma": round(prm["sigma"], 4), "corr_len": round(prm["corr_len"], 4), "tol": 1e-8}
     for name, mode in (("learned", hhg.SOLVE_LEARNED), ("chebyshev_mixed", hhg.SOLVE_MIXED),
@@ -379,6 +489,7 @@ def main():
                     help="only the scalar operator comparison (6-tet cube, level 8, ten V(3,3) cycles)")
     ap.add_argument("--tensor-solves", action="store_true",
                     help="only the tensor-operator solves (12-tet cube, level 8)")
+    ap.add_argument("--c3-solves", action="store_true", help="only the 6-tet cube solves at levels 5-8")
     ap.add_argument("--k48-solves", action="store_true",
                     help="only run the 48-tet level-8 V-cycle solves (profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -416,6 +527,9 @@ def main():
     if args.k48_solves:
         print(json.dumps(kuhn48_applies(hhg, torch, args.steps, solves=True, applies=False)))
         return
+    if args.c3_solves:
+        print(json.dumps(c3_solves(hhg, torch)))
+        return
 
     # ---------------- main workload: unit tet, level 8, lognormal k
     level = 8
@@ -435,14 +549,33 @@ def main():
     log(f"bench: unknowns {nu}, timing {args.steps} applies")
     ms = time_op(lambda: ctx.apply_scaled(level, u64, y64), args.steps, args.warmup, torch)
     value = nu / (ms * 1e-3) / 1e9
-    # the interior kernel: HIP events the library records on the stream it
-    # runs on, over a second timed loop of the same applies (the unit tet has
-    # no inter-tet rows and no modified edges, so each apply is this kernel)
+    # the interior kernel, timed by HIP events the library records around it
+    # on the stream it runs on (the unit tet has no inter-tet rows and no
+    # modified edges, so each apply is this one kernel): (a) back to back, as
+    # the timed steps run, with the 69 MB working set resident in the 256 MB
+    # last-level cache; (b) with a 1 GiB read between launches, so that the
+    # kernel reads u and k from HBM: the roofline figure.  The flush is a read
+    # (a sum over the buffer), so the caches hold clean lines and the kernel
+    # pays for no write-back of the flush's own data.
     ctx.set_timing(True)
     time_op(lambda: ctx.apply_scaled(level, u64, y64), args.steps, 0, torch)
     k_ms_tot, k_n = ctx.read_timing()
+    k_ms_warm = k_ms_tot / k_n
+    flush = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    for q in range(args.steps):
+        flush.sum()
+        ctx.apply_scaled(level, u64, y64)
+    torch.cuda.synchronize()
+    k_ms_tot, k_n = ctx.read_timing()
     ctx.set_timing(False)
     k_ms = k_ms_tot / k_n
+    # measured copy roof: a 1 GiB device-to-device copy (reads and writes)
+    dst = torch.empty_like(flush)
+    copy_ms = time_op(lambda: dst.copy_(flush), 10, 2, torch)
+    copy_gbs = 2 * flush.numel() * 8 / (copy_ms * 1e-3) / 1e9
+    del flush, dst
+    torch.cuda.empty_cache()
     achieved = BYTES_PER_DOF["f64"] * nu / (k_ms * 1e-3) / 1e9
     n_mod = ctx.level_info(level)["n_modified"]
     traffic = measured_traffic()
@@ -454,14 +587,25 @@ def main():
         "config": {"workload": "unit macro tet (0,0,0),(1,0,0),(0,1,0),(0,0,1), level 8 "
                                f"({sz['n_slots']} slots, {nu} unknowns), lognormal k (32 Fourier modes, "
                                "sigma 1, correlation length 0.1, seed 1), u ~ U[-1,1]: one FP64 "
-                               "scaled-stencil apply per step",
+                               "scaled-stencil apply per step, applies back to back (the 69 MB working set "
+                               "stays in the 256 MB last-level cache between steps)",
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
+                     "traffic_counter": "FETCH_SIZE + WRITE_SIZE per launch (L2 to fabric: what HBM serves "
+                                        "when the last-level cache holds none of the inputs), scaled by the copy "
+                                        "calibration; null when taken on other kernel sources",
                      "kernel": "k_march2<double, MODE_APPLY, scaled> (interior rows, two per lane; the unit "
                                "tet has no inter-tet rows)",
+                     "timing": "mean duration per launch from HIP events around each launch, a 1 GiB read "
+                               "between launches (inputs read from HBM)",
                      "kernel_ms": round(k_ms, 5),
+                     "kernel_ms_back_to_back": round(k_ms_warm, 5),
+                     "frac_back_to_back": round(BYTES_PER_DOF["f64"] * nu / (k_ms_warm * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                                4),
+                     "copy_roof_gbs": round(copy_gbs, 1),
+                     "frac_of_copy_roof": round(achieved / copy_gbs, 4),
                      "algorithmic_bytes_per_launch": BYTES_PER_DOF["f64"] * nu,
                      "other_kernels": ("none" if n_mod == 0 else
                                        f"k_correction<double> ({n_mod} modified edges) once per apply")},
@@ -476,27 +620,48 @@ def main():
         msn32 = time_op(lambda: ctx.apply_nodal(level, u32, y32), args.steps, args.warmup, torch)
         r64 = ctx.vector(level)
         msr = time_op(lambda: ctx.residual(level, y64, u64, r64), args.steps, args.warmup, torch)
+        # FP32 interior kernel with a 1 GiB read between launches
+        flush = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        ctx.set_timing(True)
+        for q in range(args.steps):
+            flush.sum()
+            ctx.apply_scaled(level, u32, y32)
+        torch.cuda.synchronize()
+        k32_tot, k32_n = ctx.read_timing()
+        ctx.set_timing(False)
+        del flush
+        k32_ms = k32_tot / k32_n
         extra["unit_tet_l8"] = {
             "scaled_f64_gdofs": round(value, 2), "scaled_f32_gdofs": round(nu / ms32 / 1e6, 2),
             "nodal_f64_gdofs": round(nu / msn / 1e6, 2), "nodal_f32_gdofs": round(nu / msn32 / 1e6, 2),
             "scaled_over_nodal_f64": round(msn / ms, 3), "scaled_over_nodal_f32": round(msn32 / ms32, 3),
             "residual_f64_gdofs": round(nu / msr / 1e6, 2),
-            "scaled_f32_hbm_frac": round(BYTES_PER_DOF["f32"] * nu / ms32 / 1e6 / HBM_PEAK_GBS, 4),
-            "note": "working set (69 MB FP64) fits the 256 MB Infinity Cache"}
+            "scaled_f32_frac_back_to_back": round(BYTES_PER_DOF["f32"] * nu / ms32 / 1e6 / HBM_PEAK_GBS, 4),
+            "scaled_f32_kernel_ms_cold": round(k32_ms, 5),
+            "scaled_f32_hbm_frac_cold": round(BYTES_PER_DOF["f32"] * nu / k32_ms / 1e6 / HBM_PEAK_GBS, 4),
+            "note": "back-to-back rates: the working set (69 MB FP64) stays in the 256 MB last-level cache; "
+                    "'cold': kernel duration with a 1 GiB read between launches (inputs from HBM)"}
         del ctx, u64, y64, u32, y32, r64
         torch.cuda.empty_cache()
 
+        cpu_out, oracle_ref = (None, None)
+        if not args.no_cpu:
+            log("bench: CPU oracle baseline")
+            cpu_out, oracle_ref = cpu_baseline(host_description())
+        extra["c3_6tet"] = c3_solves(hhg, torch, oracle_ref)
         extra["kuhn48_l8"] = kuhn48_applies(hhg, torch, args.steps, solves=True)
         extra["learned_l8"] = learned_solves(hhg, torch)
         extra["forms_6tet_l8"] = scalar_form_solves(hhg, torch)
         extra["square2d_l11"] = applies_2d(torch, args.steps)
         extra["tensor_cube12_l8"] = tensor_solves(hhg, torch)
-    out["extra"] = extra
-    if not args.no_cpu:
-        log("bench: CPU oracle baseline")
-        out["cpu_baseline"] = cpu_baseline()
     else:
-        out["cpu_baseline"] = None
+        cpu_out = None
+        if not args.no_cpu:
+            log("bench: CPU oracle baseline")
+            cpu_out, _ = cpu_baseline(host_description())
+    out["extra"] = extra
+    out["cpu_baseline"] = cpu_out
     print(json.dumps(out))
 
 

@@ -9,11 +9,12 @@ from .meshes import (unit_tet, regular_tet, flat_tet, kuhn_cube, kuhn_cube_2x2x2
                      obtuse_triangle, square_right4, square_nondelaunay8, MESHES2D)
 from .fields import (smooth_k, cosine_k, lognormal_params, lognormal_k, lognormal_k_torch, sigmoid_k,
                      TENSOR_DIRS, tensor_K, tensor_fields, tensor_fields_torch,
-                     polynomial_tensor_K, polynomial_tensor_fields_torch, affine_k, uniform_vector, manufactured_u, manufactured_f)
+                     polynomial_tensor_K, polynomial_tensor_fields_torch, affine_k, uniform_vector, manufactured_u, manufactured_f,
+                     kuhn_cube_mass_rhs)
 
 __all__ = ["unit_tet", "regular_tet", "flat_tet", "kuhn_cube", "kuhn_cube_2x2x2", "cube12", "MESHES",
            "obtuse_triangle", "square_right4", "square_nondelaunay8", "MESHES2D",
            "smooth_k", "cosine_k", "lognormal_params", "lognormal_k", "lognormal_k_torch", "sigmoid_k",
            "TENSOR_DIRS", "tensor_K", "tensor_fields", "tensor_fields_torch", "polynomial_tensor_K",
            "polynomial_tensor_fields_torch", "affine_k",
-           "uniform_vector", "manufactured_u", "manufactured_f"]
+           "uniform_vector", "manufactured_u", "manufactured_f", "kuhn_cube_mass_rhs"]

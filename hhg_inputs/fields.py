@@ -181,3 +181,43 @@ def manufactured_f(xyz):
     gu = p * np.stack([cx * sy * sz, sx * cy * sz, sx * sy * cz], axis=1)
     lap_u = -3 * p * p * sx * sy * sz
     return -(np.sum(gk * gu, axis=1) + k * lap_u)
+
+
+def _freudenthal_mass_stencil():
+    """Consistent P1 mass-matrix stencil of the Freudenthal triangulation of a
+    grid of unit cubes (each cube cut into the 6 tetrahedra along the monotone
+    paths from its lower to its upper corner), in units of the cube volume:
+    {offset: sum over tets holding the origin and the offset of |t|/20
+    (1 + delta)}, |t| = 1/6."""
+    import itertools
+    st = {}
+    for c in itertools.product((-1, 0), repeat=3):
+        for perm in itertools.permutations(range(3)):
+            p = list(c)
+            path = [tuple(p)]
+            for ax in perm:
+                p[ax] += 1
+                path.append(tuple(p))
+            if (0, 0, 0) not in path:
+                continue
+            for v in path:
+                st[v] = st.get(v, 0.0) + (2.0 if v == (0, 0, 0) else 1.0) / 20.0 / 6.0
+    return st
+
+
+def kuhn_cube_mass_rhs(xyz, level, f):
+    """b = M I_h f for the 6-tet Kuhn unit cube at `level` (the Freudenthal
+    triangulation of the (2^level)^3 grid), at the nodes xyz (any order):
+    f sampled on the grid, then the consistent mass stencil, h^3 per cube.
+    Nodes on the boundary get the same formula (callers zero Dirichlet
+    rows)."""
+    n = 2 ** level
+    g = np.arange(n + 1) / n
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    F = f(np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)).reshape(n + 1, n + 1, n + 1)
+    Fp = np.pad(F, 1)
+    B = np.zeros_like(F)
+    for (a, b, c), w in _freudenthal_mass_stencil().items():
+        B += w * Fp[1 + a:n + 2 + a, 1 + b:n + 2 + b, 1 + c:n + 2 + c]
+    idx = np.rint(np.asarray(xyz) * n).astype(np.int64)
+    return B[idx[:, 0], idx[:, 1], idx[:, 2]] / float(n) ** 3

@@ -35,14 +35,18 @@ import scipy.sparse as sp
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle_topo.c")
 _LIB = os.path.join(_HERE, "liboracle_topo.so")
+_CSR_SRC = os.path.join(_HERE, "oracle_csr.c")
+_CSR_LIB = os.path.join(_HERE, "liboracle_csr.so")
 
 
 def build(force=False):
-    """Compile oracle_topo.c with gcc into liboracle_topo.so (in-tree)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", _SRC, "-o", tmp])
-        os.replace(tmp, _LIB)
+    """Compile oracle_topo.c and oracle_csr.c (OpenMP) with gcc into in-tree
+    shared libraries."""
+    for src, lib, extra in ((_SRC, _LIB, []), (_CSR_SRC, _CSR_LIB, ["-fopenmp"])):
+        if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(src):
+            tmp = lib + ".tmp"
+            subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared"] + extra + [src, "-o", tmp])
+            os.replace(tmp, lib)
     return _LIB
 
 
@@ -700,6 +704,50 @@ def errors(mesh, uh, uexact, grad_exact, chunk=200000):
 
 # ---------------------------------------------------------------- CSR SpMV (C)
 def spmv_timing_matrix(op):
-    """Plain CSR arrays (int32 indices) of the reduced operator for timing."""
+    """Plain CSR arrays (int64 row pointers, int32 column indices) of the
+    reduced operator for timing."""
     A = op.A
-    return A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data
+    return A.indptr.astype(np.int64), A.indices.astype(np.int32), np.ascontiguousarray(A.data)
+
+
+_csr = None
+
+
+def _csr_lib():
+    global _csr
+    if _csr is None:
+        build()
+        L = ctypes.CDLL(_CSR_LIB)
+        P, I64, I32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+        L.csr_spmv.argtypes = [I64, P, P, P, P, P, I32]
+        L.csr_spmv.restype = None
+        L.csr_spmv_bench.argtypes = [I64, P, P, P, P, P, I32, I32, I32, P]
+        L.csr_spmv_bench.restype = None
+        L.csr_max_threads.restype = I32
+        _csr = L
+    return _csr
+
+
+def spmv_threaded(op, x, threads):
+    """A x over the unknowns (vector on all nodes, Dirichlet entries 0) by the
+    threaded C CSR product; equals op.apply(x) (same summation order)."""
+    ip, ix, dv = spmv_timing_matrix(op)
+    xu = np.ascontiguousarray(x[op.mesh.unknowns], dtype=np.float64)
+    yu = np.empty_like(xu)
+    _csr_lib().csr_spmv(len(xu), _p(ip), _p(ix), _p(dv), _p(xu), _p(yu), int(threads))
+    y = np.zeros(op.mesh.n_nodes)
+    y[op.mesh.unknowns] = yu
+    return y
+
+
+def spmv_bench(op, threads, warm=20, reps=200, seed=0):
+    """Seconds of each of `reps` threaded CSR products with the reduced
+    operator (after `warm` untimed ones), on a uniform random vector."""
+    ip, ix, dv = spmv_timing_matrix(op)
+    n = len(ip) - 1
+    x = np.random.default_rng(seed).uniform(-1, 1, n)
+    y = np.empty(n)
+    times = np.empty(reps)
+    _csr_lib().csr_spmv_bench(n, _p(ip), _p(ix), _p(dv), _p(x), _p(y), int(threads), int(warm), int(reps),
+                              _p(times))
+    return times

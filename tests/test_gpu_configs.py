@@ -75,6 +75,36 @@ def test_c3_rates_from_gpu_solutions():
     assert abs(eoc_nd[-1] - 2.0) < 0.15
 
 
+def test_c3_nodal_rates_at_levels_7_and_8():
+    """C3 at its largest levels: GPU multigrid solutions (FP64, V(2,2), 1e-8)
+    on the 6-tet cube with b = M I_h f (consistent mass, on the Freudenthal
+    grid), nodal L2 error against u* = sin sin sin; the error falls as h^2
+    (Lemma 3.1) from level 6 to 7 to 8."""
+    from hhg_inputs import kuhn_cube_mass_rhs
+    X, T = kuhn_cube()
+    nodal = []
+    for level in (6, 7, 8):
+        ctx = hhg.Context(X, T, level)
+        xyz, dirichlet = ctx.node_coords(level)
+        ctx.set_coefficient(smooth_k(xyz))
+        b = kuhn_cube_mass_rhs(xyz, level, manufactured_f)
+        b[dirichlet] = 0.0
+        u = ctx.vector(level)
+        st = ctx.solve(level, ctx.from_canonical(level, _dev(b)), u, mode=hhg.SOLVE_F64, tol=1e-8, max_iter=100)
+        print(f"C3 level {level}: {st}", flush=True)
+        assert st["rel_residual"] <= 1e-8 and st["status"] == 0
+        uh = ctx.to_canonical(level, u).cpu().numpy()
+        e = uh - manufactured_u(xyz)
+        h = 1.0 / 2 ** level
+        nodal.append(np.sqrt(h ** 3 * np.sum(e[~dirichlet] ** 2)))
+        ctx.close()
+        del ctx, u, uh, e, b, xyz
+        torch.cuda.empty_cache()
+    eoc = [np.log2(a / c) for a, c in zip(nodal, nodal[1:])]
+    print("nodal L2 errors", nodal, "eoc", eoc, flush=True)
+    assert all(abs(x - 2.0) < 0.1 for x in eoc), eoc
+
+
 def _c4_k(x):
     return lognormal_k(x, lognormal_params(2, 1.5, 0.05))
 

@@ -511,6 +511,21 @@ def test_c2_full_size_sampled_rows():
         scale = np.abs(ref).max()
         assert np.abs(got[nodes] - ref).max() <= TOL64 * scale, kind
         assert np.all(got[om.dirichlet] == 0.0)
+    # FP32 applies (the bench's FP32 configuration) on the same rows, against
+    # the oracle on the FP32-rounded u and k: FP32 arithmetic only
+    u32 = u.astype(np.float32).astype(np.float64)
+    k32 = k.astype(np.float32).astype(np.float64)
+    ud32 = ctx.from_canonical(level, _dev(u32).float())
+    for kind in ("scaled", "nodal"):
+        y = ctx.vector(level, torch.float32)
+        (ctx.apply_scaled if kind == "scaled" else ctx.apply_nodal)(level, ud32, y)
+        got = ctx.to_canonical(level, y).cpu().numpy().astype(np.float64)
+        ref = O.apply_rows(om, k32, u32, nodes, kind)
+        scale = np.abs(ref).max()
+        err = np.abs(got[nodes] - ref).max() / scale
+        print(f"C2 FP32 {kind}: max sampled-row error {err:.2e} of the largest row", flush=True)
+        assert err <= 2e-6, kind
+        assert np.all(got[om.dirichlet] == 0.0)
     assert ctx.level_info(level)["n_modified"] == 0
     one = ctx.from_canonical(level, _dev(np.where(om.dirichlet, 0.0, 1.0)))
     interior = ~om.dirichlet & ~_touches_boundary(om)

@@ -490,3 +490,37 @@ def test_mass_matrix_is_the_exact_l2_product():
         q2 = O.errors(m, u + v, zero, gzero)["L2"] ** 2
         q3 = O.errors(m, u - v, zero, gzero)["L2"] ** 2
         assert u @ (M @ v) == pytest.approx((q2 - q3) / 4, rel=1e-10, abs=1e-14)
+
+
+def test_threaded_csr_product_equals_the_assembled_operator():
+    """The C CSR product used to time the oracle gives op.apply's result
+    exactly (same per-row summation order) for 1 and several threads, and the
+    dense product up to rounding."""
+    X, T = kuhn_cube_2x2x2()
+    m = O.Mesh(X, T, 2)
+    k = lognormal_k(m.xyz, lognormal_params(1, 1.0, 0.1))
+    op = O.make_operator(m, k, "scaled", modification=True)
+    x = uniform_vector(m.n_nodes, seed=7)
+    x[m.dirichlet] = 0.0
+    ref = op.apply(x)
+    for th in (1, 3):
+        assert np.array_equal(O.spmv_threaded(op, x, th), ref)
+    dense = np.zeros(m.n_nodes)
+    dense[m.unknowns] = op.A.toarray() @ x[m.unknowns]
+    assert np.abs(ref - dense).max() <= 1e-14 * np.abs(dense).max()
+    t = O.spmv_bench(op, 2, warm=1, reps=3)
+    assert t.shape == (3,) and np.all(t > 0)
+
+
+def test_kuhn_cube_mass_rhs_matches_the_oracle_mass_matrix():
+    """The grid-stencil rhs b = M I_h f used for the 6-tet cube at large levels
+    equals the oracle's assembled consistent mass matrix times f on every
+    unknown (the refined Kuhn cube is the Freudenthal triangulation)."""
+    from hhg_inputs import kuhn_cube_mass_rhs
+    X, T = kuhn_cube()
+    for L in (2, 3):
+        m = O.Mesh(X, T, L)
+        want = O.assemble_mass(m) @ manufactured_f(m.xyz)
+        got = kuhn_cube_mass_rhs(m.xyz, L, manufactured_f)
+        u = m.unknowns
+        assert np.abs(got[u] - want[u]).max() <= 1e-13 * np.abs(want[u]).max()
