@@ -224,6 +224,20 @@ hhg_status hhg_apply_mixed(hhg_ctx ctx, int32_t level, hhg_dtype dtype, int32_t 
  * in double) and the stream is synchronised.  r may alias neither f nor u. */
 hhg_status hhg_residual(hhg_ctx ctx, int32_t level, hhg_dtype dtype, const void *f,
                         const void *u, void *r, double *norm2_out, void *stream);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * result as hhg_residual (scaled operator, r = f - A u and the optional norm),
+ * with the norm's per-block partials and its reduced value kept in a static
+ * device array of the library (8 MiB per GPU, held until the process ends)
+ * instead of the context's buffers.  Allocates nothing.  The context must
+ * have been created with its device current (hhg_create_macro looks up that
+ * device's copy of the array).  HHG_EINVAL when the level's reduction needs
+ * more than the array holds (more than about 1M blocks: beyond a 48-tet mesh
+ * at level 8).  All calls on one GPU share the array: calls that overlap in
+ * time on one GPU (different streams or threads) race and must not be
+ * issued.  Nothing in the array needs clearing between calls. */
+hhg_status hhg_residual_noalloc(hhg_ctx ctx, int32_t level, hhg_dtype dtype, const void *f,
+                                const void *u, void *r, double *norm2_out, void *stream);
 /* In-place smoothing of A u = f: `sweeps` steps of weighted Jacobi
  * u <- u + omega D^{-1}(f - A u) (HHG_JACOBI), or a Chebyshev polynomial of
  * degree `sweeps` in D^{-1}A on [0.1, 1] x lambda_max (HHG_CHEBYSHEV; omega

@@ -15,6 +15,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <string>
 #include <unordered_map>
@@ -461,6 +462,9 @@ struct CoarseInv {
 
 struct hhg_ctx_s {
     Topology topo;
+    // the device's copy of the allocation-free entry point's static scratch
+    // array (resolved at creation, with the device current)
+    double *noalloc_scratch = nullptr;
     int max_level = 0, coarse = 0;
     uint32_t flags = 0;
     hipStream_t stream = nullptr;
@@ -513,6 +517,45 @@ struct hhg_ctx_s {
     std::vector<hipEvent_t> tev;  // start/end pairs
     size_t tev_used = 0;          // pairs recorded
 };
+
+// Scratch of hhg_residual_noalloc: the residual norm's per-block partials
+// (from element NOALLOC_PARTIAL_AT on) and the reduced value (element 0).
+// Each GPU holds its own copy from the library's load until the process
+// ends.  Host code must not use the array's name as a device address: the
+// device address comes from hipGetSymbolAddress, once per device.
+constexpr int64_t NOALLOC_SCRATCH_DOUBLES = int64_t(1) << 20;  // 8 MiB
+constexpr int64_t NOALLOC_PARTIAL_AT = 32;                      // 256-byte aligned
+static __device__ __align__(256) double scratch[NOALLOC_SCRATCH_DOUBLES];
+
+namespace {
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_noalloc_mu;
+double *g_noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// the current device's address of `scratch` (looked up on the first call
+// for that device, then kept); nullptr with *err set on failure
+double *noalloc_scratch_address(hipError_t *err)
+{
+    int dev = -1;
+    *err = hipGetDevice(&dev);
+    if (*err != hipSuccess) return nullptr;
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) {
+        *err = hipErrorInvalidDevice;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void *p = nullptr;
+        *err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (*err != hipSuccess || !p) return nullptr;
+        g_noalloc_ptr[dev] = static_cast<double *>(p);
+    }
+    *err = hipSuccess;
+    return g_noalloc_ptr[dev];
+}
+
+}  // namespace
 
 namespace {
 
@@ -2044,6 +2087,16 @@ hhg_status hhg_create_macro(const double *vert_xyz, int32_t n_vert, const int32_
         return s;
     }
     c->coarse = default_coarse(c);
+    {
+        hipError_t e = hipSuccess;
+        c->noalloc_scratch = noalloc_scratch_address(&e);
+        if (!c->noalloc_scratch) {
+            const hhg_status st = fail(c, HHG_EHIP, "scratch symbol lookup failed: %s", hipGetErrorString(e));
+            g_create_error = c->err;
+            hhg_destroy(c);
+            return st;
+        }
+    }
     *out = c;
     return HHG_OK;
 }
@@ -2431,6 +2484,31 @@ hhg_status hhg_residual(hhg_ctx c, int32_t level, hhg_dtype dt, const void *f, c
     if (dt == HHG_F64) return residual_t<double>(c, level, (const double *)f, (const double *)u, (double *)r, norm2_out, st);
     if (dt == HHG_F32) return residual_t<float>(c, level, (const float *)f, (const float *)u, (float *)r, norm2_out, st);
     return fail(c, HHG_EINVAL, "bad dtype");
+}
+
+hhg_status hhg_residual_noalloc(hhg_ctx c, int32_t level, hhg_dtype dt, const void *f, const void *u, void *r,
+                                double *norm2_out, void *stream)
+{
+    TRY(check_level(c, level));
+    NEED_K(c);
+    if (!f || !u || !r || r == u || r == f) return fail(c, HHG_EINVAL, "bad vectors");
+    if (dt != HHG_F64 && dt != HHG_F32) return fail(c, HHG_EINVAL, "bad dtype");
+    if (!c->noalloc_scratch) return fail(c, HHG_ESTATE, "no scratch address for this context's device");
+    const int64_t need = NOALLOC_PARTIAL_AT + c->lv[level].partial_bound;
+    if (need > NOALLOC_SCRATCH_DOUBLES)
+        return fail(c, HHG_EINVAL,
+                    "level %d needs %lld scratch values for its residual norm; the static scratch holds %lld",
+                    level, (long long)need, (long long)NOALLOC_SCRATCH_DOUBLES);
+    hipStream_t st = pick(c, stream);
+    // every block partial the reduction reads is written by this call's
+    // kernels first, so nothing in the scratch needs clearing
+    double *const partial = c->noalloc_scratch + NOALLOC_PARTIAL_AT;
+    double *const value = c->noalloc_scratch;
+    if (dt == HHG_F64)
+        return residual_t<double>(c, level, (const double *)f, (const double *)u, (double *)r, norm2_out, st,
+                                  partial, value);
+    return residual_t<float>(c, level, (const float *)f, (const float *)u, (float *)r, norm2_out, st, partial,
+                             value);
 }
 
 hhg_status hhg_smooth(hhg_ctx c, int32_t level, hhg_dtype dt, hhg_smoother sm, int32_t sweeps, double omega,

@@ -27,7 +27,7 @@ EINVAL, EMESH, ECOEF, EHIP, ESTATE, ENOMEM = -1, -2, -3, -4, -5, -6
 EXPORTS = [
     "hhg_create_macro", "hhg_destroy", "hhg_last_error", "hhg_vector_size", "hhg_node_coords",
     "hhg_to_canonical", "hhg_from_canonical", "hhg_set_coefficient", "hhg_set_coarse_level",
-    "hhg_level_info", "hhg_apply_scaled", "hhg_set_graphs", "hhg_set_timing", "hhg_read_timing", "hhg_set_kernel_variant", "hhg_apply_nodal", "hhg_apply_mixed", "hhg_store_stencils", "hhg_apply_stored", "hhg_set_tensor_coefficient", "hhg_apply_tensor", "hhg_apply_tensor_nodal", "hhg_residual", "hhg_smooth",
+    "hhg_level_info", "hhg_apply_scaled", "hhg_residual_noalloc", "hhg_set_graphs", "hhg_set_timing", "hhg_read_timing", "hhg_set_kernel_variant", "hhg_apply_nodal", "hhg_apply_mixed", "hhg_store_stencils", "hhg_apply_stored", "hhg_set_tensor_coefficient", "hhg_apply_tensor", "hhg_apply_tensor_nodal", "hhg_residual", "hhg_smooth",
     "hhg_vcycle", "hhg_solve", "hhg_solve_tensor", "hhg_solve_form", "hhg_learned_set_weights", "hhg_learned_set_fallback",
     "hhg_learned_forward", "hhg_learned_backward", "hhg_learned_loss_grad", "hhg_training_pair",
     "hhg_adam_update",
@@ -81,6 +81,7 @@ def load():
         "hhg_apply_tensor_nodal": [P, I32, I32, P, P, P],
         "hhg_apply_stored": [P, I32, I32, P, P, P],
         "hhg_residual": [P, I32, I32, P, P, P, P, P],
+        "hhg_residual_noalloc": [P, I32, I32, P, P, P, P, P],
         "hhg_smooth": [P, I32, I32, I32, I32, D, P, P, P],
         "hhg_vcycle": [P, I32, I32, I32, I32, I32, P, P, P, P],
         "hhg_solve": [P, I32, I32, I32, I32, D, I32, P, P, P, P],
@@ -319,6 +320,15 @@ class Context:
         dt = self._vecs(level, f, u, r)
         self._check(load().hhg_residual(self._h, level, dt, _ptr(f), _ptr(u), _ptr(r),
                                         ctypes.byref(nv) if norm else None, _stream()))
+        return nv.value if norm else r
+
+    def residual_noalloc(self, level, f, u, r, norm=False):
+        """hhg_residual_noalloc: hhg_residual without any device allocation
+        (the norm's scratch is the library's static per-GPU array)."""
+        nv = ctypes.c_double()
+        dt = self._vecs(level, f, u, r)
+        self._check(load().hhg_residual_noalloc(self._h, level, dt, _ptr(f), _ptr(u), _ptr(r),
+                                                ctypes.byref(nv) if norm else None, _stream()))
         return nv.value if norm else r
 
     def smooth(self, level, f, u, sweeps, smoother=JACOBI, omega=2.0 / 3.0):
