@@ -224,12 +224,16 @@ def c3_solves(hhg, torch, oracle_ref=None):
 
 def kuhn48_applies(hhg, torch, steps, solves=True, applies=True):
     """HBM-resident working set: 48 Kuhn tets, level 8 (133M unknowns): apply
-    throughputs and/or multigrid time to solution."""
+    throughputs and/or multigrid time to solution.  The solves use coarse
+    coefficients averaged geometrically from the finest level
+    (HHG_FLAG_COARSE_K_GEOMETRIC: the field is rough) and the default coarse
+    level (3: 3375 unknowns); solves with k sampled at the coarse nodes are
+    reported beside them."""
     from hhg_inputs import kuhn_cube_2x2x2, lognormal_params
     level = 8
     log("bench: 48-tet cube level 8")
     X, T = kuhn_cube_2x2x2()
-    ctx = hhg.Context(X, T, level)
+    ctx = hhg.Context(X, T, level, hhg.FLAG_COARSE_K_GEOMETRIC)
     xyz, dirichlet = ctx.node_coords(level)
     prm2 = lognormal_params(2, 1.5, 0.05)
     k = lognormal_on_device(xyz, prm2, torch)
@@ -296,16 +300,38 @@ def kuhn48_applies(hhg, torch, steps, solves=True, applies=True):
             "mixed_vertices_edges_f64_gdofs": round(nu48 / m5 / 1e6, 2),
             "mixed_vertices_edges_f32_gdofs": round(nu48 / m6 / 1e6, 2)})
     if solves:
-        res = {}
-        for name, mode, tol in (("f64", hhg.SOLVE_F64, 1e-8), ("mixed", hhg.SOLVE_MIXED, 1e-8),
-                                ("f64_1e-10", hhg.SOLVE_F64, 1e-10), ("mixed_1e-10", hhg.SOLVE_MIXED, 1e-10)):
-            uu = ctx.vector(level)
-            torch.cuda.synchronize()
-            st = ctx.solve(level, f64, uu, mode=mode, tol=tol, max_iter=200)
-            res[name] = {k2: (float(f"{v:.4g}") if isinstance(v, float) else v) for k2, v in st.items()}
-            log(f"bench: solve {name}: {st}")
-            del uu
+        def run_solves(c, cases):
+            res = {}
+            for name, mode, tol in cases:
+                best = None
+                for _ in range(2):
+                    uu = c.vector(level)
+                    torch.cuda.synchronize()
+                    st = c.solve(level, f64, uu, mode=mode, tol=tol, max_iter=200)
+                    if best is None or st["seconds"] < best["seconds"]:
+                        best = st
+                    del uu
+                res[name] = {k2: (float(f"{v:.4g}") if isinstance(v, float) else v) for k2, v in best.items()}
+                log(f"bench: solve {name}: {best}")
+            return res
+        res = run_solves(ctx, (("f64", hhg.SOLVE_F64, 1e-8), ("mixed", hhg.SOLVE_MIXED, 1e-8),
+                               ("f64_1e-10", hhg.SOLVE_F64, 1e-10), ("mixed_1e-10", hhg.SOLVE_MIXED, 1e-10)))
+        res["coarse_level"] = ctx.level_info(level)["coarse_level"]
+        res["coarse_k"] = "geometric full-weighting averages"
         out["vcycle_solves"] = res
+        del ctx
+        torch.cuda.empty_cache()
+        # the same solves with k sampled at the coarse nodes
+        ctx = hhg.Context(X, T, level)
+        xyz2, _ = ctx.node_coords(level)
+        k = lognormal_on_device(xyz2, lognormal_params(2, 1.5, 0.05), torch)
+        del xyz2
+        ctx.set_coefficient(k)
+        del k
+        res2 = run_solves(ctx, (("f64_1e-10", hhg.SOLVE_F64, 1e-10), ("mixed_1e-10", hhg.SOLVE_MIXED, 1e-10)))
+        res2["coarse_level"] = ctx.level_info(level)["coarse_level"]
+        res2["coarse_k"] = "sampled at the coarse nodes"
+        out["vcycle_solves_sampled_coarse_k"] = res2
     del ctx, f64, y, f32
     torch.cuda.empty_cache()
     return out
@@ -343,14 +369,58 @@ def learned_solves(hhg, torch):
                 best = st
         out[name] = {k2: (float(f"{v:.4g}") if isinstance(v, float) else v) for k2, v in best.items()}
         log(f"bench: {name}: {best}")
-    ev = meta.get("evaluation", {}).get("summary")
-    if ev:
-        out["held_out_32_fields"] = {k2: {"mean_iterations": v["mean_iterations"],
-                                          "mean_seconds": round(v["mean_seconds"], 5)}
-                                     for k2, v in ev.items() if isinstance(v, dict)}
-        out["held_out_32_fields"]["source"] = ("evaluation record stored with the shipped weights "
-                                               "(python -m paper_1709_06793_amd.learned_train eval), "
-                                               "not re-timed in this run")
+    del ctx
+    torch.cuda.empty_cache()
+    return out
+
+
+def learned_held_out(hhg, torch, seeds=range(1000, 1032)):
+    """The 32 held-out learned-smoother fields (seeds 1000-1031: sigma ~
+    U(0.5, 2), correlation length ~ U(0.05, 0.3)) on the 6-tet cube at level
+    8, re-timed in this run: time to a 1e-8 relative residual with the
+    learned smoother (shipped weights, default fallback), plain Chebyshev
+    FP32-in-FP64 and plain FP64; one solve each per field."""
+    from hhg_inputs import kuhn_cube, lognormal_params
+    from paper_1709_06793_amd import learned_train as LT
+    level = 8
+    log("bench: learned smoother on 32 held-out fields, 6-tet cube level 8")
+    X, T = kuhn_cube()
+    ctx = hhg.Context(X, T, level)
+    xyz, dirichlet = ctx.node_coords(level)
+    w, _ = LT.load_weights()
+    cols = {name: {"iterations": [], "seconds": [], "fallback": [], "rho": []}
+            for name in ("learned", "chebyshev_mixed", "chebyshev_f64")}
+    dmask = torch.tensor(dirichlet, device="cuda")
+    for seed in seeds:
+        prm = lognormal_params(seed)
+        ctx.set_coefficient(lognormal_on_device(xyz, prm, torch))
+        f = torch.tensor(prm["rng"].uniform(-1, 1, xyz.shape[0]), device="cuda")
+        f[dmask] = 0.0
+        fd = ctx.from_canonical(level, f)
+        ctx.learned_set_weights(w)
+        ctx.learned_set_fallback(1.0, 1.05)
+        for name, mode in (("learned", hhg.SOLVE_LEARNED), ("chebyshev_mixed", hhg.SOLVE_MIXED),
+                           ("chebyshev_f64", hhg.SOLVE_F64)):
+            u = ctx.vector(level)
+            torch.cuda.synchronize()
+            st = ctx.solve(level, fd, u, mode=mode, tol=1e-8, max_iter=200)
+            if st["rel_residual"] > 1e-8:
+                raise RuntimeError(f"field {seed} {name}: no convergence {st}")
+            for key in cols[name]:
+                cols[name][key].append(st[key])
+    out = {"fields": len(list(seeds)), "unknowns": ctx.sizes(level)["n_unknowns"], "tol": 1e-8}
+    for name, c in cols.items():
+        out[name] = {"mean_iterations": round(float(np.mean(c["iterations"])), 3),
+                     "mean_seconds": round(float(np.mean(c["seconds"])), 5),
+                     "median_rho": round(float(np.median(c["rho"])), 4),
+                     "fallbacks": int(np.sum(c["fallback"]))}
+    li, ci = np.array(cols["learned"]["iterations"]), np.array(cols["chebyshev_mixed"]["iterations"])
+    ls, cs = np.array(cols["learned"]["seconds"]), np.array(cols["chebyshev_mixed"]["seconds"])
+    out["learned_fewer_cycles_than_chebyshev"] = int((li < ci).sum())
+    out["learned_faster_than_chebyshev_mixed"] = int((ls < cs).sum())
+    out["learned_faster_than_f64"] = int((ls < np.array(cols["chebyshev_f64"]["seconds"])).sum())
+    log(f"bench: held-out fields: {out}")
+    ctx.close()
     del ctx
     torch.cuda.empty_cache()
     return out
@@ -490,6 +560,7 @@ def main():
     ap.add_argument("--tensor-solves", action="store_true",
                     help="only the tensor-operator solves (12-tet cube, level 8)")
     ap.add_argument("--c3-solves", action="store_true", help="only the 6-tet cube solves at levels 5-8")
+    ap.add_argument("--held-out", action="store_true", help="only the 32 held-out learned-smoother fields")
     ap.add_argument("--k48-solves", action="store_true",
                     help="only run the 48-tet level-8 V-cycle solves (profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -529,6 +600,9 @@ def main():
         return
     if args.c3_solves:
         print(json.dumps(c3_solves(hhg, torch)))
+        return
+    if args.held_out:
+        print(json.dumps(learned_held_out(hhg, torch)))
         return
 
     # ---------------- main workload: unit tet, level 8, lognormal k
@@ -652,6 +726,7 @@ def main():
         extra["c3_6tet"] = c3_solves(hhg, torch, oracle_ref)
         extra["kuhn48_l8"] = kuhn48_applies(hhg, torch, args.steps, solves=True)
         extra["learned_l8"] = learned_solves(hhg, torch)
+        extra["learned_held_out_l8"] = learned_held_out(hhg, torch)
         extra["forms_6tet_l8"] = scalar_form_solves(hhg, torch)
         extra["square2d_l11"] = applies_2d(torch, args.steps)
         extra["tensor_cube12_l8"] = tensor_solves(hhg, torch)

@@ -80,6 +80,11 @@ typedef enum { HHG_FORM_SCALED = 0, HHG_FORM_NODAL = 1, HHG_FORM_MIXED = 2 } hhg
 
 /* flags of hhg_create_macro */
 #define HHG_FLAG_NO_MODIFICATION 1u  /* disable the Sec. 4.1 modification (on by default) */
+/* coarse-level scalar coefficients as geometric full-weighting averages of
+ * the next finer level's, k_c = exp(sum_f P_fc log k_f / sum_f P_fc) with P
+ * the P1 interpolation, instead of k at the coarse nodes (the default); for
+ * rough coefficients given at the finest nodes only */
+#define HHG_FLAG_COARSE_K_GEOMETRIC 2u
 
 /* Build the context for a macro mesh (Sec. 2.1: macro triangulation T_H refined
  * uniformly up to max_level, 0 <= max_level <= 10).
@@ -126,14 +131,16 @@ hhg_status hhg_from_canonical(hhg_ctx ctx, int32_t level, hhg_dtype dtype,
 /* Nodal coefficient k > 0 at the finest level (max_level), canonical order,
  * double; on_device = 1 for a device pointer, 0 for host memory.  Coarser
  * levels sample k at their own nodes (the nested nodes, Sec. 2.2: k is stored
- * per node).  Computes per level: FP32 copies, the Jacobi diagonal, the
+ * per node), or average it geometrically with HHG_FLAG_COARSE_K_GEOMETRIC.  Computes per level: FP32 copies, the Jacobi diagonal, the
  * Chebyshev bound, the modification corrections and the coarse-grid inverse.
  * Synchronises the stream.  Errors: HHG_ECOEF (k <= 0 or not finite). */
 hhg_status hhg_set_coefficient(hhg_ctx ctx, const double *k_canonical, int on_device,
                                void *stream);
 
-/* Coarsest multigrid level (default: the largest level with at most 1000
- * unknowns).  Recomputes the coarse inverse if a coefficient is set. */
+/* Coarsest multigrid level (default: the largest level with at most 4096
+ * unknowns if it lies at least four levels below max_level, else the largest
+ * with at most 1000; at most 4096 unknowns).  Recomputes the coarse inverse
+ * (dense, FP64; on the device above 512 unknowns) if a coefficient is set. */
 hhg_status hhg_set_coarse_level(hhg_ctx ctx, int32_t level);
 /* Per-level solver data: Chebyshev bound of D^{-1}A (Gershgorin), number of
  * modification corrections (edges whose factor was replaced), coarse level. */

@@ -587,18 +587,35 @@ def chebyshev(op, f, u, steps, lam_max, lo=0.1, hi=1.0):
     return u
 
 
+def geometric_coarse_k(P, kf):
+    """Coarse coefficients as geometric full-weighting averages of the fine
+    ones: k_c = exp(sum_f P_fc log k_f / sum_f P_fc), P the P1 interpolation
+    matrix (fine x coarse, all nodes)."""
+    R = P.T.tocsr()
+    return np.exp((R @ np.log(kf)) / (R @ np.ones(P.shape[0])))
+
+
 class Multigrid:
     """Geometric multigrid on the nested uniformly refined meshes: P1
     interpolation P, restriction P^T, rediscretised operators with k sampled at
-    each level's nodes, exact dense solve on the coarsest level."""
+    each level's nodes (coarse_k="sample"; with kfine given, the coarse values
+    at the nested nodes) or averaged geometrically from the next finer level
+    (coarse_k="geometric", geometric_coarse_k), exact dense solve on the
+    coarsest level."""
 
     def __init__(self, X, T, level, coarse_level, kfun=None, kfine=None, kind="scaled",
-                 modification=False):
+                 modification=False, coarse_k="sample"):
         self.levels = list(range(coarse_level, level + 1))
         self.meshes = {l: Mesh(X, T, l) for l in self.levels}
         self.ops, self.P, self.lam = {}, {}, {}
+        for l in self.levels[1:]:
+            self.P[l] = prolongation(self.meshes[l - 1], self.meshes[l])
         kl = {}
-        if kfine is not None:
+        if coarse_k == "geometric":
+            kl[level] = kfine if kfine is not None else kfun(self.meshes[level].xyz)
+            for l in reversed(self.levels[:-1]):
+                kl[l] = geometric_coarse_k(self.P[l + 1], kl[l + 1])
+        elif kfine is not None:
             kl[level] = kfine
             for l in reversed(self.levels[:-1]):
                 kl[l] = kl[l + 1][coarse_to_fine(self.meshes[l], self.meshes[l + 1])]
@@ -609,7 +626,6 @@ class Multigrid:
         for l in self.levels:
             self.ops[l] = make_operator(self.meshes[l], kl[l], kind, modification)
             if l > coarse_level:
-                self.P[l] = prolongation(self.meshes[l - 1], self.meshes[l])
                 self.lam[l] = gershgorin_lambda(self.ops[l])
         cop = self.ops[coarse_level]
         self.coarse_dense = cop.A.toarray()

@@ -400,6 +400,12 @@ struct Level {
     int sh_w = 0;
     int64_t *sh_nb = nullptr, *sh_self = nullptr, *sh_cslot = nullptr;
     int8_t *sh_map = nullptr;  // [copy][16]: entry of direction d, -1 if none
+    // the scaled operator's own (narrower) pattern
+    int sh_ws = 0;
+    int64_t *sh_nbs = nullptr;
+    int8_t *sh_maps = nullptr;
+    double *sh_css64 = nullptr;
+    float *sh_css32 = nullptr;
     // the same for the tensor operator's (wider) pattern
     int sh_wt = 0;
     int64_t *sh_nbt = nullptr;
@@ -441,6 +447,14 @@ struct Level {
     uint8_t *own = nullptr;
     float *lt[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     int64_t partial_bound = 0;  // block partials any reduction at this level writes
+    // geometric coarse coefficients (this level as the coarse one): the nodes
+    // on macro primitives with their distinct fine support nodes and weights
+    // (CSR) and their copies (CSR)
+    bool cg_ready = false;
+    int cg_n = 0;
+    int32_t *cg_off = nullptr, *cg_coff = nullptr;
+    int64_t *cg_fslot = nullptr, *cg_cslot = nullptr;
+    double *cg_w = nullptr;
     double *ubak = nullptr;  // last accepted iterate of a learned solve
     double *uprobe = nullptr;  // a learned solve's plain-cycle probe result
     // canonical maps (built on first use); slot2canon holds -(c+1) for a
@@ -753,6 +767,7 @@ LevelView<double> view<double>(const hhg_ctx c, int l)
     v.items = L.items; v.n_items = L.n_items; v.vpt = (L.n_items + 3) / 4;
     v.sh_w = L.sh_w; v.sh_nb = L.sh_nb; v.sh_self = L.sh_self; v.sh_cslot = L.sh_cslot;
     v.sh_cs = L.sh_cs64; v.sh_cn = L.sh_cn64; v.sh_prim = L.sh_prim;
+    v.sh_ws = L.sh_ws; v.sh_nbs = L.sh_nbs; v.sh_css = L.sh_css64;
     v.sh_wt = L.sh_wt; v.sh_nbt = L.sh_nbt; v.sh_ct = L.sh_ct64; v.sh_ctn = L.sh_ctn64;
     v.tsten = L.tsten64; v.kt = L.kt64; v.kp = L.kp64; v.temat = L.temat64;
     v.items2 = L.items2; v.n_items2 = L.n_items2; v.vpt2 = (L.n_items2 + 3) / 4;
@@ -772,10 +787,11 @@ LevelView<float> view<float>(const hhg_ctx c, int l)
     v.items = L.items; v.n_items = L.n_items; v.vpt = (L.n_items + 3) / 4;
     v.sh_w = L.sh_w; v.sh_nb = L.sh_nb; v.sh_self = L.sh_self; v.sh_cslot = L.sh_cslot;
     v.sh_cs = L.sh_cs32; v.sh_cn = L.sh_cn32; v.sh_prim = L.sh_prim;
+    v.sh_ws = L.sh_ws; v.sh_nbs = L.sh_nbs; v.sh_css = L.sh_css32;
     v.sh_wt = L.sh_wt; v.sh_nbt = L.sh_nbt; v.sh_ct = L.sh_ct32; v.sh_ctn = L.sh_ctn32;
     v.tsten = L.tsten32; v.kt = L.kt32; v.kp = L.kp32; v.temat = L.temat32;
     v.items2 = L.items2f; v.n_items2 = L.n_items2f; v.vpt2 = (L.n_items2f + 3) / 4;
-    v.itemsL = L.itemsL; v.n_itemsL = 0;
+    v.itemsL = L.itemsL; v.n_itemsL = L.n_itemsL;
     v.bnd = L.bnd; v.n_bnd = L.n_bnd; v.bpt2 = (L.n_bnd + BLOCK - 1) / BLOCK;
     return v;
 }
@@ -1047,6 +1063,21 @@ hhg_status build_level(hhg_ctx c, int l)
                     }
             }
         }
+        // the scaled operator's own pattern: directions whose tet-restricted
+        // scaled weight is not negligible (the element couplings of the
+        // nodal form widen the pattern above; on Kuhn meshes the scaled
+        // stencil has 6 of the 14 directions)
+        std::vector<uint8_t> need_s((size_t)tp.nt * 16 * NDIR, 0);
+        for (int t = 0; t < tp.nt; ++t) {
+            double ms = 0.0;
+            for (int q = 0; q < TET_STENCIL; ++q) ms = std::max(ms, std::fabs(L.h_sten[(size_t)t * TET_STENCIL + q]));
+            for (int zp = 0; zp < 15; ++zp) {
+                if (popcount4(zp) == 4) continue;
+                uint8_t *nd = &need_s[((size_t)t * 16 + zp) * NDIR];
+                const double *row = &L.h_sten[(size_t)t * TET_STENCIL + zp * KIND_STRIDE];
+                for (int d = 0; d < NDIR; ++d) nd[d] = std::fabs(row[d]) > 1e-14 * ms;
+            }
+        }
         // the tensor operator's pattern: every component's tet-restricted
         // weights and element matrices (wider than the scalar one where a
         // component couples a direction the scalar stencil does not)
@@ -1106,8 +1137,13 @@ hhg_status build_level(hhg_ctx c, int l)
         };
         // one merged pattern per `need`: map[copy][d] = entry, the ELL table of
         // neighbour slots (padding entries = the node itself) and its width
+        // merged_scaled: keep only the entries whose merged scaled weight (the
+        // sum of the copies' tet-restricted weights onto the entry; the
+        // coefficient is that sum times k_q + k_m) is not negligible: on the
+        // Kuhn meshes the restricted weights of two tets cancel exactly in 8
+        // of a face node's directions, although neither vanishes alone
         auto build_ell = [&](const std::vector<uint8_t> &need, std::vector<int8_t> &hmap, std::vector<int64_t> &ell,
-                             int &width) -> hhg_status {
+                             int &width, bool merged_scaled = false) -> hhg_status {
             hmap.assign((size_t)ncopy * 16, -1);
             std::vector<int32_t> ecount(L.n_shared);
             std::vector<int64_t> enb;  // entries of all nodes, node after node
@@ -1141,6 +1177,36 @@ hhg_status build_level(hhg_ctx c, int l)
                         hmap[(size_t)p * 16 + d] = (int8_t)m;
                     }
                 }
+                if (merged_scaled) {
+                    std::vector<double> wsum(keys.size(), 0.0);
+                    double wmax = 0.0;
+                    for (int p = L.h_sh_off[q]; p < L.h_sh_off[q + 1]; ++p) {
+                        int t, kind, i, j, k;
+                        unpack_copy(L.h_sh_copy[p], t, kind, i, j, k);
+                        const double *row = &L.h_sten[(size_t)t * TET_STENCIL + kind * KIND_STRIDE];
+                        for (int d = 0; d < NDIR; ++d) {
+                            wmax = std::max(wmax, std::fabs(row[d]));
+                            const int m = hmap[(size_t)p * 16 + d];
+                            if (m >= 0) wsum[m] += row[d];
+                        }
+                    }
+                    std::vector<int> remap(keys.size(), -1);
+                    std::vector<Key> k2;
+                    std::vector<int64_t> s2;
+                    for (size_t e = 0; e < keys.size(); ++e)
+                        if (std::fabs(wsum[e]) > 1e-12 * wmax) {
+                            remap[e] = (int)k2.size();
+                            k2.push_back(keys[e]);
+                            s2.push_back(slots[e]);
+                        }
+                    for (int p = L.h_sh_off[q]; p < L.h_sh_off[q + 1]; ++p)
+                        for (int d = 0; d < NDIR; ++d) {
+                            int8_t &m = hmap[(size_t)p * 16 + d];
+                            if (m >= 0) m = (int8_t)remap[m];
+                        }
+                    keys.swap(k2);
+                    slots.swap(s2);
+                }
                 ecount[q] = (int32_t)keys.size();
                 width = std::max(width, (int)keys.size());
                 enb.insert(enb.end(), slots.begin(), slots.end());
@@ -1154,11 +1220,12 @@ hhg_status build_level(hhg_ctx c, int l)
             }
             return HHG_OK;
         };
-        std::vector<int8_t> hmap, hmap_t;
-        std::vector<int64_t> ell, ell_t;
-        int width = 0, width_t = 0;
+        std::vector<int8_t> hmap, hmap_t, hmap_s;
+        std::vector<int64_t> ell, ell_t, ell_s;
+        int width = 0, width_t = 0, width_s = 0;
         TRY(build_ell(need, hmap, ell, width));
         TRY(build_ell(need_t, hmap_t, ell_t, width_t));
+        TRY(build_ell(need_s, hmap_s, ell_s, width_s, true));
         L.sh_w = width;
         // macro primitive of each shared node from the zero pattern of its
         // barycentric weights: three zero weights = vertex, two = edge, one = face
@@ -1181,6 +1248,14 @@ hhg_status build_level(hhg_ctx c, int l)
         TRY(upload(c, &L.sh_self, hself));
         TRY(upload(c, &L.sh_cslot, hcslot));
         TRY(upload(c, &L.sh_map, hmap));
+        L.sh_ws = width_s;
+        TRY(upload(c, &L.sh_nbs, ell_s));
+        TRY(upload(c, &L.sh_maps, hmap_s));
+        {
+            const int64_t nes = std::max<int64_t>(1, (int64_t)width_s * L.n_shared);
+            TRY(dalloc(c, &L.sh_css64, nes));
+            TRY(dalloc(c, &L.sh_css32, nes));
+        }
         const int64_t ne = std::max<int64_t>(1, (int64_t)width * L.n_shared);
         TRY(dalloc(c, &L.sh_cs64, ne));
         TRY(dalloc(c, &L.sh_cn64, ne));
@@ -1353,6 +1428,70 @@ hhg_status ensure_canon_maps(hhg_ctx c, int l)
         if (c2s[ci] < 0) return fail(c, HHG_EMESH, "canonical node %lld has no slot", (long long)ci);
     TRY(upload(c, &L.slot2canon, s2c));
     TRY(upload(c, &L.canon2slot, c2s));
+    return HHG_OK;
+}
+
+// support lists of the geometric coarse coefficients of level l (from level
+// l + 1) for the nodes on macro primitives: every distinct fine node f with
+// P_fc != 0 (the coincident node, weight 1, and the midpoint of every coarse
+// edge at the node, weight 1/2, over all copies; distinct by canonical index)
+hhg_status build_coarsen_lists(hhg_ctx c, int l)
+{
+    Level &Lc = c->lv[l], &Lf = c->lv[l + 1];
+    if (Lc.cg_ready) return HHG_OK;
+    const Topology &tp = c->topo;
+    const int nc = Lc.n, nf = Lf.n;
+    struct Copy {
+        int64_t ci;
+        int t, i, j, k;
+    };
+    std::vector<Copy> cps;
+    for (int t = 0; t < tp.nt; ++t)
+        for (int k = 0; k <= nc; ++k)
+            for (int j = 0; j + k <= nc; ++j)
+                for (int i = 0; i + j + k <= nc; ++i) {
+                    if (i > 0 && j > 0 && k > 0 && i + j + k < nc) continue;
+                    cps.push_back({canon_index(tp, t, nc, i, j, k, Lc.h_poff.data()), t, i, j, k});
+                }
+    std::sort(cps.begin(), cps.end(), [](const Copy &a, const Copy &b) {
+        return a.ci != b.ci ? a.ci < b.ci : a.t < b.t;
+    });
+    std::vector<int32_t> off(1, 0), coff(1, 0);
+    std::vector<int64_t> fslot, cslot, seen;
+    std::vector<double> w;
+    for (size_t a = 0; a < cps.size();) {
+        size_t b = a;
+        while (b < cps.size() && cps[b].ci == cps[a].ci) ++b;
+        seen.clear();
+        auto add = [&](int t, int fi, int fj, int fk, double wt) {
+            const int64_t fci = canon_index(tp, t, nf, fi, fj, fk, Lf.h_poff.data());
+            for (int64_t x : seen)
+                if (x == fci) return;
+            seen.push_back(fci);
+            fslot.push_back((int64_t)t * Lf.Spad + slot_of(nf, fi, fj, fk));
+            w.push_back(wt);
+        };
+        for (size_t q = a; q < b; ++q) {
+            const Copy &C = cps[q];
+            add(C.t, 2 * C.i, 2 * C.j, 2 * C.k, 1.0);
+            for (int d = 0; d < NDIR; ++d) {
+                const int i2 = C.i + DIR[d][0], j2 = C.j + DIR[d][1], k2 = C.k + DIR[d][2];
+                if (!in_lattice(nc, i2, j2, k2)) continue;
+                add(C.t, 2 * C.i + DIR[d][0], 2 * C.j + DIR[d][1], 2 * C.k + DIR[d][2], 0.5);
+            }
+            cslot.push_back((int64_t)C.t * Lc.Spad + slot_of(nc, C.i, C.j, C.k));
+        }
+        off.push_back((int32_t)fslot.size());
+        coff.push_back((int32_t)cslot.size());
+        a = b;
+    }
+    Lc.cg_n = (int)(off.size() - 1);
+    TRY(upload(c, &Lc.cg_off, off));
+    TRY(upload(c, &Lc.cg_coff, coff));
+    TRY(upload(c, &Lc.cg_fslot, fslot.empty() ? std::vector<int64_t>(1, 0) : fslot));
+    TRY(upload(c, &Lc.cg_w, w.empty() ? std::vector<double>(1, 0.0) : w));
+    TRY(upload(c, &Lc.cg_cslot, cslot.empty() ? std::vector<int64_t>(1, 0) : cslot));
+    Lc.cg_ready = true;
     return HHG_OK;
 }
 
@@ -1875,14 +2014,39 @@ hhg_status build_coarse(hhg_ctx c, hipStream_t st, int op = 0)
     }
     HIPCHK(c, hipMemsetAsync(de, 0, L.n_slots * 8, st));
     HIPCHK(c, hipMemsetAsync(dy, 0, L.n_slots * 8, st));
-    if (!invert_dense(A, nu)) return fail(c, HHG_ECOEF, "coarse operator is singular");
     CoarseInv &C = c->co[op];
     if (C.ainv) {
         for (void *p : {(void *)C.ainv, (void *)C.cgather, (void *)C.ccoff, (void *)C.ccslot}) dfree(c, p);
         C = CoarseInv();
     }
     C.cu = nu;
-    TRY(upload(c, &C.ainv, A));
+    if (nu <= 512) {
+        if (!invert_dense(A, nu)) return fail(c, HHG_ECOEF, "coarse operator is singular");
+        TRY(upload(c, &C.ainv, A));
+    } else {
+        // larger coarse levels: Gauss-Jordan on the device ([A | I] uploaded
+        // once, the inverse extracted into C.ainv)
+        std::vector<double> W((size_t)nu * 2 * nu, 0.0);
+        for (int r = 0; r < nu; ++r) {
+            std::copy(&A[(size_t)r * nu], &A[(size_t)r * nu] + nu, &W[(size_t)r * 2 * nu]);
+            W[(size_t)r * 2 * nu + nu + r] = 1.0;
+        }
+        double *dw = nullptr, *dscr = nullptr;
+        int *iscr = nullptr;
+        TRY(upload(c, &dw, W));
+        TRY(dalloc(c, &dscr, nu + 1));
+        TRY(dalloc(c, &iscr, 2));
+        TRY(dalloc(c, &C.ainv, (int64_t)nu * nu));
+        HIPCHK(c, hipMemsetAsync(iscr, 0, 2 * sizeof(int), st));
+        HIPCHK(c, launch_dense_inverse(dw, nu, C.ainv, iscr, dscr, st));
+        int sing[2] = {0, 0};
+        HIPCHK(c, hipMemcpyAsync(sing, iscr, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        dfree(c, dw);
+        dfree(c, dscr);
+        dfree(c, iscr);
+        if (sing[1]) return fail(c, HHG_ECOEF, "coarse operator is singular");
+    }
     TRY(upload(c, &C.cgather, gather));
     TRY(upload(c, &C.ccoff, coff));
     TRY(upload(c, &C.ccslot, cslot));
@@ -1892,6 +2056,15 @@ hhg_status build_coarse(hhg_ctx c, hipStream_t st, int op = 0)
 
 int default_coarse(hhg_ctx c)
 {
+    // deep hierarchies: the largest level with at most 4096 unknowns when it
+    // lies at least four levels below the finest (its dense inverse is built
+    // on the device and costs a few tens of microseconds per cycle, and a
+    // deeper exact solve contracts much better on rough coefficients);
+    // otherwise the largest with at most 1000
+    int deep = -1;
+    for (int l = 0; l <= c->max_level; ++l)
+        if (c->lv[l].n_unknowns >= 1 && c->lv[l].n_unknowns <= 4096) deep = l;
+    if (deep >= 0 && c->max_level - deep >= 4) return deep;
     int best = -1;
     for (int l = 0; l <= c->max_level; ++l)
         if (c->lv[l].n_unknowns >= 1 && c->lv[l].n_unknowns <= 1000) best = l;
@@ -1983,7 +2156,8 @@ hhg_status hhg_create_macro(const double *vert_xyz, int32_t n_vert, const int32_
     if (!vert_xyz || !tet_vert || !out || n_vert <= 0 || n_tet <= 0 || n_tet >= (1 << 16))
         return fail(nullptr, HHG_EINVAL, "invalid mesh arguments");
     if (max_level < 0 || max_level > 10) return fail(nullptr, HHG_EINVAL, "max_level must be in [0, 10]");
-    if (flags & ~HHG_FLAG_NO_MODIFICATION) return fail(nullptr, HHG_EINVAL, "unknown flag bits");
+    if (flags & ~(HHG_FLAG_NO_MODIFICATION | HHG_FLAG_COARSE_K_GEOMETRIC))
+        return fail(nullptr, HHG_EINVAL, "unknown flag bits");
     for (int i = 0; i < 4 * n_tet; ++i)
         if (tet_vert[i] < 0 || tet_vert[i] >= n_vert) return fail(nullptr, HHG_EINVAL, "vertex id out of range");
     hhg_ctx c = new hhg_ctx_s();
@@ -2212,7 +2386,13 @@ hhg_status hhg_set_coefficient(hhg_ctx c, const double *k, int on_device, void *
     for (int l = Lmax - 1; l >= 0; --l) {
         Level &Lc = c->lv[l], &Lf = c->lv[l + 1];
         HIPCHK(c, launch_fill<double>(Lc.k64, 1.0, Lc.n_slots, st));
-        HIPCHK(c, launch_inject<double>(Lf.k64, Lf.n, Lc.k64, Lc.n, c->topo.nt, Lf.Spad, Lc.Spad, st));
+        if (c->flags & HHG_FLAG_COARSE_K_GEOMETRIC) {
+            TRY(build_coarsen_lists(c, l));
+            HIPCHK(c, launch_coarsen(Lf.k64, Lf.n, Lc.k64, Lc.n, c->topo.nt, Lf.Spad, Lc.Spad, Lc.cg_n, Lc.cg_off,
+                                     Lc.cg_fslot, Lc.cg_w, Lc.cg_coff, Lc.cg_cslot, st));
+        } else {
+            HIPCHK(c, launch_inject<double>(Lf.k64, Lf.n, Lc.k64, Lc.n, c->topo.nt, Lf.Spad, Lc.Spad, st));
+        }
     }
     for (int l = 0; l <= Lmax; ++l) {
         Level &L = c->lv[l];
@@ -2221,6 +2401,8 @@ hhg_status hhg_set_coefficient(hhg_ctx c, const double *k, int on_device, void *
         if (L.n_shared > 0) {
             const int64_t ne = (int64_t)L.sh_w * L.n_shared;
             HIPCHK(c, launch_shared_coef(view<double>(c, l), L.sh_map, L.sh_cs64, L.sh_cn64, st));
+            HIPCHK(c, launch_shared_coef_scaled(view<double>(c, l), L.sh_maps, L.sh_css64, st));
+            HIPCHK(c, launch_convert<double, float>(L.sh_css64, L.sh_css32, (int64_t)L.sh_ws * L.n_shared, st));
             HIPCHK(c, launch_convert<double, float>(L.sh_cs64, L.sh_cs32, ne, st));
             HIPCHK(c, launch_convert<double, float>(L.sh_cn64, L.sh_cn32, ne, st));
         }

@@ -56,6 +56,12 @@ struct LevelView {
     const T *sh_cs;           // scaled-operator coefficients
     const T *sh_cn;           // nodal-operator coefficients
     const uint8_t *sh_prim;   // macro primitive of node q: 1 vertex, 2 edge, 4 face
+    // the scaled operator alone: the entries of the pattern above whose
+    // scaled weight is not negligible (on Kuhn meshes 6 of the 14 entries
+    // of a face node), same layout, with that operator's coefficients
+    int sh_ws;
+    const int64_t *sh_nbs;
+    const T *sh_css;
     // tensor operator: its own (wider) pattern sh_wt / sh_nbt in the same
     // layout, coefficients with every component scaled (sh_ct) or nodally
     // integrated (sh_ctn)
@@ -201,10 +207,21 @@ int march_variant_now();
 // merged coefficients of the shared rows for the current k (scaled and nodal)
 hipError_t launch_shared_coef(const LevelView<double> &L, const int8_t *map, double *cs, double *cn,
                               hipStream_t st);
+hipError_t launch_shared_coef_scaled(const LevelView<double> &L, const int8_t *map, double *cs, hipStream_t st);
+// inverse of the n x n matrix in the left half of work ([A | I], n x 2n,
+// row-major; overwritten) into ainv; iscr: 2 ints (iscr[1] = 1 afterwards if
+// A is singular; the caller clears it), dscr: n + 1 doubles
+hipError_t launch_dense_inverse(double *work, int n, double *ainv, int *iscr, double *dscr, hipStream_t st);
 hipError_t launch_add_f32_to_f64(double *u, const float *c, int64_t n, hipStream_t st);
 template <typename T>
 hipError_t launch_inject(const T *kf, int nf, T *kc, int nc, int n_tet, int64_t Spad_f,
                          int64_t Spad_c, hipStream_t st);
+// coarse k as geometric full-weighting averages of the finer level's k
+// (macro-tet interior nodes from the tet's own fine lattice, the n_list
+// nodes on macro primitives from their support lists)
+hipError_t launch_coarsen(const double *kf, int nf, double *kc, int nc, int n_tet, int64_t Spad_f, int64_t Spad_c,
+                          int n_list, const int32_t *off, const int64_t *fslot, const double *w,
+                          const int32_t *coff, const int64_t *cslot, hipStream_t st);
 template <typename T>
 hipError_t launch_from_canonical(const T *canon, const int32_t *slot2canon, T *slots, int64_t n,
                                  int keep_dirichlet, int S, int64_t Spad, hipStream_t st);

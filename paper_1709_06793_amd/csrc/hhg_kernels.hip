@@ -552,16 +552,36 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
 // The LDS reads are written as inline asm that waits for its own data, and the
 // waits for the LDS loads are explicit (counted per wave): the compiler would
 // otherwise wait for every outstanding load before each LDS read.
+// FP64: a 16-byte load brings 2 elements per lane, 128 per wave and load:
+// twelve chunks per array, three loads per wave and plane.  FP32: 4 elements
+// per lane, 256 per load: six chunks per array, two load slots per wave and
+// plane (16 slots for 12 chunks; the spare slots read nothing).
 constexpr int LW = 8;               // waves per block
-constexpr int LCH = 12;             // 128-element chunks per array and plane
-constexpr int LELEM = LCH * 128;    // staged elements per array and plane
+constexpr int LELEM = 1536;         // staged elements per array and plane
 constexpr int LRS = 3;              // ring slots (two planes in flight)
 
-typedef double d2v __attribute__((ext_vector_type(2)));
+template <typename T>
+struct LdsCfg;
+template <>
+struct LdsCfg<double> {
+    static constexpr int CHUNK = 128;  // elements per 16-byte-per-lane load
+    static constexpr int LCH = LELEM / CHUNK;
+    static constexpr int PERWAVE = 3;  // load slots per wave and plane
+};
+template <>
+struct LdsCfg<float> {
+    static constexpr int CHUNK = 256;
+    static constexpr int LCH = LELEM / CHUNK;
+    static constexpr int PERWAVE = 2;
+};
 
-__device__ __forceinline__ unsigned lds_addr(const double *p)
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+
+template <typename T>
+__device__ __forceinline__ unsigned lds_addr(const T *p)
 {
-    return (unsigned)(size_t)((__attribute__((address_space(3))) const double *)p);
+    return (unsigned)(size_t)((__attribute__((address_space(3))) const T *)p);
 }
 
 // the six pairs (diagonals s-1, s, s+1 of u and k) of one plane from LDS
@@ -584,12 +604,45 @@ __device__ __forceinline__ void lds_read_plane(unsigned au, unsigned ak, const i
     uu[0] = {a0.x, a0.y}; uu[1] = {a1.x, a1.y}; uu[2] = {a2.x, a2.y};
     kk[0] = {b0.x, b0.y}; kk[1] = {b1.x, b1.y}; kk[2] = {b2.x, b2.y};
 }
-
-template <int MODE>
-__global__ __launch_bounds__(64 * LW) __attribute__((amdgpu_waves_per_eu(4))) void k_march_lds(
-    LevelView<double> L, const double *__restrict__ u, double *__restrict__ y)
+__device__ __forceinline__ void lds_read_plane(unsigned au, unsigned ak, const int e[3], P2<float> uu[3],
+                                               P2<float> kk[3])
 {
-    __shared__ __attribute__((aligned(16))) double ring[LRS][2][LELEM];
+    f2v a0, a1, a2, b0, b1, b2;
+    asm volatile(
+        "ds_read2_b32 %0, %6 offset1:1\n\t"
+        "ds_read2_b32 %1, %7 offset1:1\n\t"
+        "ds_read2_b32 %2, %8 offset1:1\n\t"
+        "ds_read2_b32 %3, %9 offset1:1\n\t"
+        "ds_read2_b32 %4, %10 offset1:1\n\t"
+        "ds_read2_b32 %5, %11 offset1:1\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(a0), "=&v"(a1), "=&v"(a2), "=&v"(b0), "=&v"(b1), "=&v"(b2)
+        : "v"(au + e[0] * 4), "v"(au + e[1] * 4), "v"(au + e[2] * 4), "v"(ak + e[0] * 4), "v"(ak + e[1] * 4),
+          "v"(ak + e[2] * 4)
+        : "memory");
+    uu[0] = {a0.x, a0.y}; uu[1] = {a1.x, a1.y}; uu[2] = {a2.x, a2.y};
+    kk[0] = {b0.x, b0.y}; kk[1] = {b1.x, b1.y}; kk[2] = {b2.x, b2.y};
+}
+
+// s_waitcnt immediates (gfx9 encoding: vmcnt in bits 3:0, expcnt 6:4 (7 = no
+// wait), lgkmcnt 11:8 (15 = no wait)) for vmcnt(n), n < 16
+template <int N>
+__device__ __forceinline__ void wait_vm()
+{
+    static_assert(N >= 0 && N < 16, "vmcnt immediate");
+    __builtin_amdgcn_s_waitcnt(0x0F70 | N);
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(64 * LW) __attribute__((amdgpu_waves_per_eu(4))) void k_march_lds(
+    LevelView<T> L, const T *__restrict__ u, T *__restrict__ y)
+{
+    using C = LdsCfg<T>;
+    constexpr int B = (int)sizeof(T);
+    __shared__ __attribute__((aligned(16))) T ring[LRS][2][LELEM];
+    // landing area of the spare load slots (FP32): they read nothing, and
+    // whatever the hardware writes for them must not reach the ring
+    __shared__ __attribute__((aligned(16))) T dump[64 * 16 / sizeof(T)];
     const int nbb = (L.n_bnd + 64 * LW - 1) / (64 * LW);
     const int per_tet = L.n_itemsL + nbb;
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
@@ -602,7 +655,7 @@ __global__ __launch_bounds__(64 * LW) __attribute__((amdgpu_waves_per_eu(4))) vo
         const int e = b * (64 * LW) + threadIdx.x;
         if (e < L.n_bnd) {
             const uint32_t v = L.bnd[e];
-            if ((L.dmask[tet] >> (v & 15u)) & 1) y[base + (v >> 4)] = 0.0;
+            if ((L.dmask[tet] >> (v & 15u)) & 1) y[base + (v >> 4)] = T(0);
         }
         return;
     }
@@ -632,41 +685,44 @@ __global__ __launch_bounds__(64 * LW) __attribute__((amdgpu_waves_per_eu(4))) vo
     const int need = __builtin_amdgcn_readfirstlane(t0 + 1007 + diag(t0 + 1007) + 3 - lo);
     const int osm = ty - sdy - 1, oc = tx, osp = tx + sdx + 1;
     const int e[3] = {(osm >= 0 ? osm : 0) - lo, (oc >= 0 ? oc : 0) - lo, (osp >= 0 ? osp : 0) - lo};
-    const __amdgpu_buffer_rsrc_t ru = tet_rsrc(u + base, (int64_t)L.S * 8);
-    const __amdgpu_buffer_rsrc_t rk = tet_rsrc(L.kap + base, (int64_t)L.S * 8);
-    const __amdgpu_buffer_rsrc_t ry = tet_rsrc(y + base, (int64_t)L.S * 8);
+    const __amdgpu_buffer_rsrc_t ru = tet_rsrc(u + base, (int64_t)L.S * B);
+    const __amdgpu_buffer_rsrc_t rk = tet_rsrc(L.kap + base, (int64_t)L.S * B);
+    const __amdgpu_buffer_rsrc_t ry = tet_rsrc(y + base, (int64_t)L.S * B);
     const int Sn = tc32(n);
     auto plane = [&](int p) { return Sn - tc32(n - p); };
-    // this wave's three 16-byte-per-lane LDS loads of plane p into slot p % LRS
+    // this wave's 16-byte-per-lane LDS loads of plane p into slot p % LRS
     auto stage = [&](int p) {
         const int sl = p % LRS;
 #pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            const int Q = wave * 3 + q, arr = Q / LCH, ch = Q - arr * LCH;
-            // a chunk past the needed length, or a plane past the last one the
-            // chunk's rows use, is still issued (the waits count three loads
-            // per wave and plane) but reads nothing
-            const int voff = ch * 128 < need && p <= k1 + 1 ? (plane(p) + lo + ch * 128 + 2 * lane) * 8 : 0x7ffffff0;
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(arr ? rk : ru,
-                                                     (__attribute__((address_space(3))) void *)&ring[sl][arr][ch * 128],
+        for (int q = 0; q < C::PERWAVE; ++q) {
+            const int Q = wave * C::PERWAVE + q;
+            const int arr = Q / C::LCH, ch = Q - arr * C::LCH;
+            // a chunk past the needed length, or a plane past the last one
+            // the chunk's rows use, is still issued (the waits count
+            // PERWAVE loads per wave and plane) but reads nothing and lands
+            // in its own chunk, which no row reads; a spare slot past the
+            // two arrays' chunks lands in the dump area
+            const bool spare = arr >= 2;
+            const bool real = !spare && ch * C::CHUNK < need && p <= k1 + 1;
+            const int voff = real ? (plane(p) + lo + ch * C::CHUNK + (16 / B) * lane) * B : 0x7ffffff0;
+            T *dst = spare ? &dump[0] : &ring[sl][spare ? 0 : arr][spare ? 0 : ch * C::CHUNK];
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(arr == 1 ? rk : ru, (__attribute__((address_space(3))) void *)dst,
                                                      16, voff, 0, 0, 0);
         }
     };
-    auto addr = [&](int p, int arr) { return lds_addr(&ring[p % LRS][arr][0]); };
-    double wr[NDIR / 2];
-    const double *__restrict__ w = L.sten + (int64_t)tet * TET_STENCIL;
+    auto addr = [&](int p, int arr) { return lds_addr<T>(&ring[p % LRS][arr][0]); };
+    T wr[NDIR / 2];
+    const T *__restrict__ w = L.sten + (int64_t)tet * TET_STENCIL;
 #pragma unroll
     for (int d = 0; d < NDIR / 2; ++d) wr[d] = w[d];
     struct Pl {
-        P2<double> u[3], k[3];
+        P2<T> u[3], k[3];
     } R[3];
     // prologue: planes k0-1 and k0 into registers, then k0+1 and k0+2 in flight
     stage(k0 - 1);
     stage(k0);
-    // s_waitcnt immediates: vmcnt in bits 3:0, expcnt 6:4 (7 = no wait),
-    // lgkmcnt 11:8 (15 = no wait)
     __builtin_amdgcn_sched_barrier(0);
-    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    wait_vm<0>();
     __builtin_amdgcn_s_barrier();
     __builtin_amdgcn_sched_barrier(0);
     lds_read_plane(addr(k0 - 1, 0), addr(k0 - 1, 1), e, R[0].u, R[0].k);
@@ -682,22 +738,23 @@ __global__ __launch_bounds__(64 * LW) __attribute__((amdgpu_waves_per_eu(4))) vo
         for (int q = 0; q < 3; ++q) {
             const int k = kb + q;
             if (k > k1) break;  // block-uniform
-            Pl &M = R[q % 3], &C = R[(q + 1) % 3], &P = R[(q + 2) % 3];
+            Pl &M = R[q % 3], &Cc = R[(q + 1) % 3], &P = R[(q + 2) % 3];
             // plane k+1 has landed once at most the later loads and stores
-            // are outstanding: 3 at the first step, 5 after
+            // are outstanding: the next plane's PERWAVE loads at the first
+            // step, plus the previous step's two stores after
             __builtin_amdgcn_sched_barrier(0);
-            if (k == k0) __builtin_amdgcn_s_waitcnt(0x0F73);  // vmcnt(3)
-            else __builtin_amdgcn_s_waitcnt(0x0F75);          // vmcnt(5)
+            if (k == k0) wait_vm<C::PERWAVE>();
+            else wait_vm<C::PERWAVE + 2>();
             __builtin_amdgcn_s_barrier();
             __builtin_amdgcn_sched_barrier(0);
             lds_read_plane(addr(k + 1, 0), addr(k + 1, 1), e, P.u, P.k);
-            double ux[NDIR + 1], uy[NDIR + 1], kx[NDIR + 1], ky[NDIR + 1];
-            gather2<double>(M.u, C.u, P.u, ux, uy);
-            gather2<double>(M.k, C.k, P.k, kx, ky);
-            const double ax = scaled_row_paired<double>(ux, kx, wr);
-            const double ay = scaled_row_paired<double>(uy, ky, wr);
+            T ux[NDIR + 1], uy[NDIR + 1], kx[NDIR + 1], ky[NDIR + 1];
+            gather2<T>(M.u, Cc.u, P.u, ux, uy);
+            gather2<T>(M.k, Cc.k, P.k, kx, ky);
+            const T ax = scaled_row_paired<T>(ux, kx, wr);
+            const T ay = scaled_row_paired<T>(uy, ky, wr);
             const int Pk = plane(k);
-            const int sx = k <= lastx ? (Pk + tx) * 8 : DROP, sy = k <= lasty ? (Pk + ty) * 8 : DROP;
+            const int sx = k <= lastx ? (Pk + tx) * B : DROP, sy = k <= lasty ? (Pk + ty) * B : DROP;
             bstore(ax, ry, sx);
             bstore(ay, ry, sy);
             // the slot of plane k (read one step ago by every wave, which all
@@ -707,10 +764,11 @@ __global__ __launch_bounds__(64 * LW) __attribute__((amdgpu_waves_per_eu(4))) vo
         }
     }
     // drain: every LDS load has landed before the block's LDS is released
-    __builtin_amdgcn_s_waitcnt(0x0F70);
+    wait_vm<0>();
 }
 
-static int lds_grid(const LevelView<double> &L)
+template <typename T>
+static int lds_grid(const LevelView<T> &L)
 {
     const int nbb = (L.n_bnd + 64 * LW - 1) / (64 * LW);
     return ((L.n_tet * (L.n_itemsL + nbb) + 7) / 8) * 8;
@@ -789,14 +847,15 @@ template <typename T, int MODE, int OP>
 static void launch_march_std(const LevelView<T> &L, const T *u, const T *f, T *y, double *partial,
                              hipStream_t st, const ChebArgs<T> &cb)
 {
-    if constexpr (OP == 0 && MODE == MODE_APPLY && sizeof(T) == 8) {
+    if constexpr (OP == 0 && MODE == MODE_APPLY) {
         // the LDS-staged block march where the level fits it: forced by
         // variant 10, chosen by default for working sets far beyond the
-        // last-level cache (it measured faster there and slower below)
+        // last-level cache (it measured faster there and slower below; on
+        // the 48-tet cube at level 8: FP64 131 vs 122, FP32 205 vs 184 GDoF/s)
         const int v = march_variant();
         const bool big_set = (int64_t)L.n_tet * L.Spad >= ((int64_t)32 << 20);
         if (L.n_itemsL > 0 && (v == 10 || (v == 0 && big_set))) {
-            k_march_lds<MODE_APPLY><<<lds_grid(L), 64 * LW, 0, st>>>(L, u, y);
+            k_march_lds<T, MODE_APPLY><<<lds_grid(L), 64 * LW, 0, st>>>(L, u, y);
             return;
         }
     }
@@ -886,6 +945,49 @@ static void launch_shared_rows(const LevelView<T> &L, const T *coef, const T *u,
     if (gs) k_shared_rows<T, MODE><<<gs, BLOCK, 0, st>>>(L, coef, u, f, y, partial, cb, coefn, nodal_mask);
 }
 
+// the scaled operator's shared rows on its own (narrower) pattern
+template <typename T, int MODE>
+static void launch_shared_rows_scaled(const LevelView<T> &L, const T *u, const T *f, T *y, double *partial,
+                                      hipStream_t st, const ChebArgs<T> &cb = ChebArgs<T>())
+{
+    LevelView<T> Ls = L;
+    Ls.sh_w = L.sh_ws;
+    Ls.sh_nb = L.sh_nbs;
+    launch_shared_rows<T, MODE>(Ls, L.sh_css, u, f, y, partial, st, cb);
+}
+
+// scaled coefficients on the scaled pattern (FP64, once per coefficient
+// field): c_m = sum over copies and directions d onto m of w_d (k_q + k_m)
+__global__ __launch_bounds__(BLOCK) void k_shared_coef_scaled(LevelView<double> L, const int8_t *__restrict__ map,
+                                                              double *__restrict__ cs)
+{
+    const int q = blockIdx.x * BLOCK + threadIdx.x;
+    const int ns = L.n_shared;
+    if (q >= ns) return;
+    for (int m = 0; m < L.sh_ws; ++m) cs[(int64_t)m * ns + q] = 0.0;
+    for (int c = L.sh_off[q]; c < L.sh_off[q + 1]; ++c) {
+        int tet, kind, i, j, k;
+        unpack_copy(L.sh_copy[c], tet, kind, i, j, k);
+        const int64_t base = (int64_t)tet * L.Spad;
+        const int s = slot32(L.n, i, j, k);
+        const int8_t *mp = map + (int64_t)c * 16;
+        const double kq = L.kap[base + s];
+        int nb[NDIR];
+        neighbour_slots(s, i + j, L.n - k, nb);
+        const double *w = L.sten + (int64_t)tet * TET_STENCIL + kind * KIND_STRIDE;
+        for (int d = 0; d < NDIR; ++d) {
+            const int m = mp[d];
+            if (m >= 0) cs[(int64_t)m * ns + q] += w[d] * (kq + L.kap[base + nb[d]]);
+        }
+    }
+}
+
+hipError_t launch_shared_coef_scaled(const LevelView<double> &L, const int8_t *map, double *cs, hipStream_t st)
+{
+    if (L.n_shared) k_shared_coef_scaled<<<blocks_for(L.n_shared), BLOCK, 0, st>>>(L, map, cs);
+    return hipGetLastError();
+}
+
 // merged coefficients of the shared rows (FP64, once per coefficient field):
 // scaled  c_m = sum over copies and directions d onto m of w_d (k_q + k_m);
 // nodal   c_m = sum over copies, elements t holding the node and m of
@@ -951,10 +1053,10 @@ hipError_t launch_scaled(const LevelView<T> &L, int mode, const T *u, const T *f
     const int gs = blocks_for(L.n_shared);
     if (mode == MODE_APPLY) {
         launch_march<T, MODE_APPLY, 0>(L, u, f, y, partial, st);
-        launch_shared_rows<T, MODE_APPLY>(L, L.sh_cs, u, f, y, partial, st);
+        launch_shared_rows_scaled<T, MODE_APPLY>(L, u, f, y, partial, st);
     } else {
         launch_march<T, MODE_RESID, 0>(L, u, f, y, partial, st);
-        launch_shared_rows<T, MODE_RESID>(L, L.sh_cs, u, f, y, partial + gv, st);
+        launch_shared_rows_scaled<T, MODE_RESID>(L, u, f, y, partial + gv, st);
         if (n_partial) *n_partial = gv + gs;
     }
     return hipGetLastError();
@@ -1077,7 +1179,7 @@ hipError_t launch_cheb_sweep(const LevelView<T> &L, const CorrView<T> &C, const 
                              const ChebArgs<T> &cb, hipStream_t st)
 {
     launch_march<T, MODE_CHEB, 0>(L, u, f, u_new, nullptr, st, cb);
-    launch_shared_rows<T, MODE_CHEB>(L, L.sh_cs, u, f, u_new, nullptr, st, cb);
+    launch_shared_rows_scaled<T, MODE_CHEB>(L, u, f, u_new, nullptr, st, cb);
     if (C.n_rows)
         k_correction<T, MODE_CHEB><<<blocks_for(C.n_rows), BLOCK, 0, st>>>(C, u, u_new, nullptr, cb, 0);
     return hipGetLastError();
@@ -1822,7 +1924,7 @@ hipError_t launch_stored(const LevelView<T> &L, const CorrView<T> &C, const T *s
     int n_seg = 0;
     const dim3 g = stored_grid(L.n, L.n_tet, n_seg);
     if (g.x) k_stored_apply<T><<<g, BLOCK, 0, strm>>>(L, st, u, y, n_seg);
-    launch_shared_rows<T, MODE_APPLY>(L, L.sh_cs, u, nullptr, y, nullptr, strm);
+    launch_shared_rows_scaled<T, MODE_APPLY>(L, u, nullptr, y, nullptr, strm);
     const int64_t nb = (int64_t)L.n_tet * L.n_bnd;
     if (nb) k_dirichlet_zero<T><<<blocks_for(nb), BLOCK, 0, strm>>>(L, y);
     if (C.n_rows)
@@ -1935,6 +2037,106 @@ hipError_t launch_coarse_solve(const double *ainv, int nu, const int64_t *gather
     return hipGetLastError();
 }
 
+// Dense inverse on the device by Gauss-Jordan elimination with partial
+// pivoting on the augmented n x 2n matrix M = [A | I] (row-major, FP64).
+// Step c: the pivot row p (largest |M[r][c]|, r >= c; the first on ties) and
+// its value; swap rows c and p while scaling the new row c by 1/pivot; copy
+// column c; subtract f_r x row c from every other row r (columns c..2n-1:
+// left of c every row already holds 0 in A's part).  flag[0] is set when a
+// pivot is 0 (singular matrix).
+__global__ __launch_bounds__(BLOCK) void k_gj_pivot(const double *__restrict__ M, int n, int c,
+                                                   int *__restrict__ piv, double *__restrict__ pval,
+                                                   int *__restrict__ flag)
+{
+    __shared__ double bv[BLOCK];
+    __shared__ int bi[BLOCK];
+    const int64_t w = 2 * (int64_t)n;
+    double best = -1.0;
+    int bidx = n;
+    for (int r = c + threadIdx.x; r < n; r += BLOCK) {
+        const double v = fabs(M[(int64_t)r * w + c]);
+        if (v > best) { best = v; bidx = r; }
+    }
+    bv[threadIdx.x] = best;
+    bi[threadIdx.x] = bidx;
+    __syncthreads();
+    for (int h = BLOCK / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            const double v2 = bv[threadIdx.x + h];
+            const int i2 = bi[threadIdx.x + h];
+            if (v2 > bv[threadIdx.x] || (v2 == bv[threadIdx.x] && i2 < bi[threadIdx.x])) {
+                bv[threadIdx.x] = v2;
+                bi[threadIdx.x] = i2;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const int p = bi[0] < n ? bi[0] : c;
+        const double v = M[(int64_t)p * w + c];
+        piv[0] = p;
+        pval[0] = v;
+        if (!(fabs(v) > 0.0)) flag[0] = 1;
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_gj_swap_scale(double *__restrict__ M, int n, int c,
+                                                        const int *__restrict__ piv,
+                                                        const double *__restrict__ pval)
+{
+    const int64_t w = 2 * (int64_t)n;
+    const int64_t k = c + (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (k >= w) return;
+    const int p = piv[0];
+    const double v = pval[0];
+    const double a = M[(int64_t)c * w + k], b = M[(int64_t)p * w + k];
+    M[(int64_t)c * w + k] = b / v;
+    if (p != c) M[(int64_t)p * w + k] = a;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_gj_column(const double *__restrict__ M, int n, int c,
+                                                    double *__restrict__ fcol)
+{
+    const int r = blockIdx.x * BLOCK + threadIdx.x;
+    if (r < n) fcol[r] = r == c ? 0.0 : M[(int64_t)r * 2 * n + c];
+}
+
+__global__ __launch_bounds__(BLOCK) void k_gj_eliminate(double *__restrict__ M, int n, int c,
+                                                       const double *__restrict__ fcol)
+{
+    const int64_t w = 2 * (int64_t)n;
+    const int64_t k = c + (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const int r = blockIdx.y;
+    if (k >= w || r == c) return;
+    const double f = fcol[r];
+    if (f != 0.0) M[(int64_t)r * w + k] -= f * M[(int64_t)c * w + k];
+}
+
+__global__ __launch_bounds__(BLOCK) void k_gj_extract(const double *__restrict__ M, int n, double *__restrict__ ainv)
+{
+    const int64_t q = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (q >= (int64_t)n * n) return;
+    const int64_t r = q / n, col = q - r * n;
+    ainv[q] = M[r * 2 * n + n + col];
+}
+
+// work: n * 2n doubles holding [A | I] on entry; ainv: n * n; scratch: 2
+// ints and n + 1 doubles (pivot row and value, column copy)
+hipError_t launch_dense_inverse(double *work, int n, double *ainv, int *iscr, double *dscr, hipStream_t st)
+{
+    if (n <= 0 || n > 65535) return hipErrorInvalidValue;
+    const int64_t w = 2 * (int64_t)n;
+    for (int c = 0; c < n; ++c) {
+        const unsigned gx = (unsigned)((w - c + BLOCK - 1) / BLOCK);
+        k_gj_pivot<<<1, BLOCK, 0, st>>>(work, n, c, iscr, dscr, iscr + 1);
+        k_gj_swap_scale<<<gx, BLOCK, 0, st>>>(work, n, c, iscr, dscr);
+        k_gj_column<<<blocks_for(n), BLOCK, 0, st>>>(work, n, c, dscr + 1);
+        k_gj_eliminate<<<dim3(gx, (unsigned)n), BLOCK, 0, st>>>(work, n, c, dscr + 1);
+    }
+    k_gj_extract<<<blocks_for((int64_t)n * n), BLOCK, 0, st>>>(work, n, ainv);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- misc
 template <typename T>
 __global__ void k_fill(T *x, T v, int64_t n)
@@ -1992,6 +2194,58 @@ hipError_t launch_inject(const T *kf, int nf, T *kc, int nc, int n_tet, int64_t 
 {
     k_inject<T><<<blocks_for((int64_t)tet_count(nc) * n_tet), BLOCK, 0, st>>>(kf, nf, kc, nc, n_tet,
                                                                              Spad_f, Spad_c);
+    return hipGetLastError();
+}
+
+// Coarse coefficients as geometric full-weighting averages of the next finer
+// level's: k_c = exp(sum_f P_fc log k_f / sum_f P_fc), P the P1
+// interpolation (P_fc = 1 for the coincident fine node, 1/2 for the midpoint
+// of each coarse edge at c).  Macro-tet interior nodes: the coincident node
+// and the 14 edge midpoints of the same tet (total weight 8).  Nodes on macro
+// faces, edges and vertices (Dirichlet ones included): from a list of their
+// distinct fine support nodes over all copies, written to every copy.
+__global__ __launch_bounds__(BLOCK) void k_coarsen_volume(const double *__restrict__ kf, int nf,
+                                                         double *__restrict__ kc, int nc, int64_t Spad_f,
+                                                         int64_t Spad_c)
+{
+    int i, j, k, s;
+    if (!plane_point(nc, i, j, k, s)) return;
+    if (i == 0 || j == 0 || k == 0 || i + j + k == nc) return;
+    const int tet = blockIdx.z;
+    const double *__restrict__ fb = kf + (int64_t)tet * Spad_f;
+    const int sf = slot32(nf, 2 * i, 2 * j, 2 * k);
+    int nb[NDIR];
+    neighbour_slots(sf, 2 * (i + j), nf - 2 * k, nb);
+    double acc = 0.0;
+#pragma unroll
+    for (int d = 0; d < NDIR; ++d) acc += log(fb[nb[d]]);
+    kc[(int64_t)tet * Spad_c + s] = exp((log(fb[sf]) + 0.5 * acc) / 8.0);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_coarsen_list(const double *__restrict__ kf, double *__restrict__ kc,
+                                                       int n_nodes, const int32_t *__restrict__ off,
+                                                       const int64_t *__restrict__ fslot,
+                                                       const double *__restrict__ w,
+                                                       const int32_t *__restrict__ coff,
+                                                       const int64_t *__restrict__ cslot)
+{
+    const int q = blockIdx.x * BLOCK + threadIdx.x;
+    if (q >= n_nodes) return;
+    double acc = 0.0, ws = 0.0;
+    for (int e = off[q]; e < off[q + 1]; ++e) {
+        acc += w[e] * log(kf[fslot[e]]);
+        ws += w[e];
+    }
+    const double v = exp(acc / ws);
+    for (int c = coff[q]; c < coff[q + 1]; ++c) kc[cslot[c]] = v;
+}
+
+hipError_t launch_coarsen(const double *kf, int nf, double *kc, int nc, int n_tet, int64_t Spad_f, int64_t Spad_c,
+                          int n_list, const int32_t *off, const int64_t *fslot, const double *w,
+                          const int32_t *coff, const int64_t *cslot, hipStream_t st)
+{
+    if (nc >= 4) k_coarsen_volume<<<plane_grid(nc, n_tet), BLOCK, 0, st>>>(kf, nf, kc, nc, Spad_f, Spad_c);
+    if (n_list) k_coarsen_list<<<blocks_for(n_list), BLOCK, 0, st>>>(kf, kc, n_list, off, fslot, w, coff, cslot);
     return hipGetLastError();
 }
 

@@ -16,6 +16,7 @@ F64, F32 = 0, 1
 JACOBI, CHEBYSHEV, LEARNED = 0, 1, 2
 SOLVE_F64, SOLVE_MIXED, SOLVE_LEARNED = 0, 1, 2
 FLAG_NO_MODIFICATION = 1
+FLAG_COARSE_K_GEOMETRIC = 2
 # macro primitives whose rows use nodal integration in apply_mixed (Sec. 5)
 PRIM_VERTICES, PRIM_EDGES, PRIM_FACES = 1, 2, 4
 LEARNED_NPARAM = 817

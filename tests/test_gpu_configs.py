@@ -244,5 +244,17 @@ def test_c5_shipped_weights_on_held_out_field():
     ctx, f, prm = LT.make_field_context(5, 1005, kuhn_cube, torch)
     res = LT.evaluate(ctx, f, 5, w, torch)
     print("C5 held-out field 1005 at level 5:", res, flush=True)
-    assert res["learned"]["rel_residual"] <= 1e-8 and res["learned"]["fallback"] == 0
-    assert res["learned"]["iterations"] < res["network_off"]["iterations"]
+    # with the default fallback (learned cycles must contract within 1.05 x
+    # the plain cycle measured from the same iterate) the solve converges and
+    # is never much worse than plain Chebyshev
+    assert res["learned"]["rel_residual"] <= 1e-8
+    assert res["learned"]["iterations"] <= res["chebyshev"]["iterations"] + 1
+    # the network alone (no comparison with the plain cycle): converges
+    # without falling back and beats the same cycles with the network off
+    ctx.learned_set_weights(w)
+    ctx.learned_set_fallback(1.0, 0.0)
+    u = ctx.vector(5)
+    st = ctx.solve(5, f, u, mode=hhg.SOLVE_LEARNED, tol=1e-8, max_iter=200)
+    print("network alone:", st, flush=True)
+    assert st["fallback"] == 0 and st["rel_residual"] <= 1e-8
+    assert st["iterations"] < res["network_off"]["iterations"]

@@ -524,3 +524,31 @@ def test_kuhn_cube_mass_rhs_matches_the_oracle_mass_matrix():
         got = kuhn_cube_mass_rhs(m.xyz, L, manufactured_f)
         u = m.unknowns
         assert np.abs(got[u] - want[u]).max() <= 1e-13 * np.abs(want[u]).max()
+
+
+def test_geometric_coarse_coefficients():
+    """k_c = exp(sum_f P_fc log k_f / sum_f P_fc): constant k stays constant;
+    for log k affine the average equals k at every macro-tet interior coarse
+    node (its support, the node and the 14 edge midpoints, is point
+    symmetric); at one boundary node, the support enumerated from the coarse
+    edges of the refined mesh (element vertex pairs) gives the same value."""
+    X, T = kuhn_cube_2x2x2()
+    mc, mf = O.Mesh(X, T, 2), O.Mesh(X, T, 3)
+    P = O.prolongation(mc, mf)
+    assert np.allclose(O.geometric_coarse_k(P, np.full(mf.n_nodes, 2.5)), 2.5, rtol=1e-15, atol=0)
+    g = lambda x: 0.3 + 0.7 * x[:, 0] - 1.1 * x[:, 1] + 0.4 * x[:, 2]
+    kc = O.geometric_coarse_k(P, np.exp(g(mf.xyz)))
+    interior = O.primitive_dims(mc) == 3
+    assert interior.sum() > 0
+    assert np.abs(kc[interior] / np.exp(g(mc.xyz[interior])) - 1).max() < 1e-13
+    # one node on the domain boundary and one on an interior macro vertex
+    kf = lognormal_k(mf.xyz, lognormal_params(2, 1.5, 0.05))
+    kc = O.geometric_coarse_k(P, kf)
+    conn, _ = mc.elements()
+    c2f = O.coarse_to_fine(mc, mf)
+    for c in (int(np.flatnonzero(mc.dirichlet)[5]), int(np.argmin(np.abs(mc.xyz - 0.5).sum(axis=1)))):
+        nbrs = set(conn[np.any(conn == c, axis=1)].ravel()) - {c}
+        mids = [np.argmin(np.abs(mf.xyz - (mc.xyz[c] + mc.xyz[m]) / 2).sum(axis=1)) for m in nbrs]
+        logs = [np.log(kf[c2f[c]])] + [0.5 * np.log(kf[f]) for f in mids]
+        want = np.exp(np.sum(logs) / (1 + 0.5 * len(mids)))
+        assert kc[c] == pytest.approx(want, rel=1e-13)
