@@ -2136,9 +2136,8 @@ hhg_status learned_smooth_t<float>(hhg_ctx c, int l, int sweeps, const float *f,
     Level &L = c->lv[l];
     for (int s = 0; s < sweeps; ++s) {
         TRY(residual_t<float>(c, l, f, u, L.r32, nullptr, st));
-        HIPCHK(c, launch_learned_forward_full(view<float>(c, l), c->learned, L.r32, L.logk32, nullptr,
-                                              L.lt[0], nullptr, st));
-        HIPCHK(c, launch_learned_update(u, L.r32, L.lt[0], L.invd32, (float)c->learned.omega, L.n_slots, st));
+        HIPCHK(c, launch_learned_step(view<float>(c, l), c->learned, L.r32, L.logk32, u, L.invd32,
+                                      (float)c->learned.omega, st));
     }
     return HHG_OK;
 }

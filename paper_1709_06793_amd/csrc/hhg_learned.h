@@ -38,6 +38,9 @@ int learned_bwd_blocks(const LevelView<float> &L);
 hipError_t launch_learned_backward(const LevelView<float> &L, const LearnedState &S,
                                    const float *r, const float *logk, const float *g,
                                    hipStream_t st);
+// the learned smoothing step in one pass: u += D^{-1}(omega r + s c(r, k))
+hipError_t launch_learned_step(const LevelView<float> &L, const LearnedState &S, const float *r, const float *logk,
+                               float *u, const float *invd, float omega, hipStream_t st);
 hipError_t launch_learned_update(float *u, const float *r, const float *sc, const float *invd,
                                  float omega, int64_t n, hipStream_t st);
 hipError_t launch_learned_err(const float *e, const float *r, const float *sc, const float *invd,

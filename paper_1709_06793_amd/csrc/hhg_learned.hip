@@ -115,12 +115,17 @@ __device__ __forceinline__ void node_features(const LevelView<float> &L, const f
 // features, the wave stages them in LDS as BF16 and evaluates the network
 // for its 64 lanes in four groups of 16 on the matrix cores.  Extra blocks
 // write 0 to every slot on the tet's boundary.
+// With u given (the learned smoothing step), the kernel also applies
+// u <- u + D^{-1}(omega r + s c) at every slot of the lattice (c = 0 on the
+// tet's boundary slots), so no separate update pass runs.
 __global__ __launch_bounds__(BLOCK) void k_learned_fwd_march(LevelView<float> L, const float *__restrict__ r,
                                                              const float *__restrict__ logk,
                                                              const unsigned short *__restrict__ wbf,
                                                              float *__restrict__ c_out,
                                                              float *__restrict__ sc_out,
-                                                             float *__restrict__ s_out)
+                                                             float *__restrict__ s_out,
+                                                             float *__restrict__ u,
+                                                             const float *__restrict__ invd, float omega)
 {
     constexpr int NS = 4;
     // bf16 features of a lane's node: 16 words, rows 18 words apart (the
@@ -142,6 +147,7 @@ __global__ __launch_bounds__(BLOCK) void k_learned_fwd_march(LevelView<float> L,
             if (c_out) c_out[sl] = 0.0f;
             if (sc_out) sc_out[sl] = 0.0f;
             if (s_out) s_out[sl] = 0.0f;
+            if (u) u[sl] += invd[sl] * (omega * r[sl] + 0.0f);
         }
         return;
     }
@@ -168,6 +174,8 @@ __global__ __launch_bounds__(BLOCK) void k_learned_fwd_march(LevelView<float> L,
     const __amdgpu_buffer_rsrc_t rc = tet_rsrc(c_out ? c_out + base : r + base, c_out ? bytes : 0);
     const __amdgpu_buffer_rsrc_t rsc = tet_rsrc(sc_out ? sc_out + base : r + base, sc_out ? bytes : 0);
     const __amdgpu_buffer_rsrc_t rs = tet_rsrc(s_out ? s_out + base : r + base, s_out ? bytes : 0);
+    const __amdgpu_buffer_rsrc_t ru = tet_rsrc(u ? u + base : r + base, u ? bytes : 0);
+    const __amdgpu_buffer_rsrc_t rid = tet_rsrc(u ? invd + base : r + base, u ? bytes : 0);
     const int vo[3] = {t >= 0 ? t - sd : 0, t >= 0 ? t : 0, t >= 0 ? t + sd + 1 : 0};
     const int Sn = tc32(n);
     auto plane = [&](int p) { return Sn - tc32(n - p); };
@@ -200,6 +208,13 @@ __global__ __launch_bounds__(BLOCK) void k_learned_fwd_march(LevelView<float> L,
         for (int q = 0; q < NS; ++q) {
             const int k = kb + q;
             MPlane<float> &M = R[q % NS], &C = R[(q + 1) % NS], &P = R[(q + 2) % NS];
+            const bool live = k <= lastk;
+            const int so = live ? (plane(k) + vo[1]) * 4 : DROP;
+            // the node's iterate and inverse diagonal, issued before the
+            // feature and network work that hides their latency (an empty
+            // range reads 0 when there is no update)
+            const float u_old = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(ru, so, 0, 0));
+            const float id = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rid, so, 0, 0));
             mplane_shift_mid(C);
             mplane_shift_up(P);
             // node first, then the neighbours in DIR order
@@ -250,11 +265,11 @@ __global__ __launch_bounds__(BLOCK) void k_learned_fwd_march(LevelView<float> L,
             }
             __builtin_amdgcn_wave_barrier();
             const float c = cs[threadIdx.x];
-            const bool live = k <= lastk;
-            const int so = live ? (plane(k) + vo[1]) * 4 : DROP;
+            const float scv = c * scale;
             bstore(c, rc, so);
-            bstore(c * scale, rsc, so);
+            bstore(scv, rsc, so);
             bstore(scale, rs, so);
+            bstore(u_old + id * (omega * rp[0] + scv), ru, so);
             mplane_load<float, MODE_APPLY>(M, rr, rl, rr, vo, plane(k - 1 + NS));
             __builtin_amdgcn_sched_barrier(0);
         }
@@ -271,7 +286,15 @@ template <>
 hipError_t launch_learned_forward<float>(const LevelView<float> &L, const LearnedState &S,
                                          const float *r, const float *logk, float *c, hipStream_t st)
 {
-    k_learned_fwd_march<<<fwd_grid(L), BLOCK, 0, st>>>(L, r, logk, S.wbf, c, nullptr, nullptr);
+    k_learned_fwd_march<<<fwd_grid(L), BLOCK, 0, st>>>(L, r, logk, S.wbf, c, nullptr, nullptr, nullptr, nullptr,
+                                                        0.0f);
+    return hipGetLastError();
+}
+
+hipError_t launch_learned_step(const LevelView<float> &L, const LearnedState &S, const float *r, const float *logk,
+                               float *u, const float *invd, float omega, hipStream_t st)
+{
+    k_learned_fwd_march<<<fwd_grid(L), BLOCK, 0, st>>>(L, r, logk, S.wbf, nullptr, nullptr, nullptr, u, invd, omega);
     return hipGetLastError();
 }
 
@@ -279,7 +302,7 @@ hipError_t launch_learned_forward_full(const LevelView<float> &L, const LearnedS
                                        const float *r, const float *logk, float *c, float *sc,
                                        float *s, hipStream_t st)
 {
-    k_learned_fwd_march<<<fwd_grid(L), BLOCK, 0, st>>>(L, r, logk, S.wbf, c, sc, s);
+    k_learned_fwd_march<<<fwd_grid(L), BLOCK, 0, st>>>(L, r, logk, S.wbf, c, sc, s, nullptr, nullptr, 0.0f);
     return hipGetLastError();
 }
 

@@ -529,6 +529,38 @@ def test_geometric_coarse_coefficients_match_oracle(mesh_fn, level, coarse):
         assert _rel(got, u) <= 1e-11, (it, _rel(got, u))
 
 
+def test_device_coarse_inverse_matches_dense_solve():
+    """Coarse levels above 512 unknowns are inverted on the device
+    (Gauss-Jordan with partial pivoting): the 6-tet cube's level 4 (3375
+    unknowns) as the coarse level, its solve against numpy's dense solve of
+    the oracle's matrix (with the modification), and a V(2,2) cycle from
+    level 5 against the oracle's cycle with the same coarse level."""
+    X, T = kuhn_cube()
+    level, coarse = 5, 4
+    kfun = lambda x: lognormal_k(x, lognormal_params(6, 1.0, 0.15))
+    mg = O.Multigrid(X, T, level, coarse, kfun=kfun, modification=True)
+    ctx = hhg.Context(X, T, level)
+    ctx.set_coefficient(kfun(mg.meshes[level].xyz))
+    ctx.set_coarse_level(coarse)
+    mc = mg.meshes[coarse]
+    assert len(mc.unknowns) == 3375
+    f = uniform_vector(mc.n_nodes, seed=31)
+    f[mc.dirichlet] = 0.0
+    uc = ctx.vector(coarse)
+    ctx.vcycle(coarse, ctx.from_canonical(coarse, _dev(f)), uc, 2, 2, hhg.CHEBYSHEV)
+    got = ctx.to_canonical(coarse, uc).cpu().numpy()
+    ref = mg.coarse_solve(f)
+    assert _rel(got, ref) <= 1e-11, _rel(got, ref)
+    om = mg.meshes[level]
+    f = uniform_vector(om.n_nodes, seed=32)
+    f[om.dirichlet] = 0.0
+    ud = ctx.vector(level)
+    ctx.vcycle(level, ctx.from_canonical(level, _dev(f)), ud, 2, 2, hhg.CHEBYSHEV)
+    ref = mg.vcycle(level, f, np.zeros(om.n_nodes))
+    got = ctx.to_canonical(level, ud).cpu().numpy()
+    assert _rel(got, ref) <= 1e-11, _rel(got, ref)
+
+
 def test_geometric_coarse_coefficients_contract_faster_on_rough_k():
     """On the 48-tet cube with the rough lognormal field (sigma 1.5,
     correlation length 0.05), geometric coarse coefficients need fewer cycles
