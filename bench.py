@@ -545,6 +545,60 @@ def tensor_solves(hhg, torch):
     return out
 
 
+def blending_solves(hhg, torch, levels=(3, 4, 5, 6, 7)):
+    """The blending example of Sec. 7.4 on one GPU: the half cylinder mantle's
+    reference box in 80 Kuhn blocks (480 tets), coefficient (1 + z) K with K
+    from the mapping, the manufactured solution made zero on the boundary,
+    b = M I_h f; V(3,3) to a 1e-8 relative residual (as in that example) with
+    every tensor component scaled and with every component nodally
+    integrated, FP64 (best of two runs).  Per level: unknowns, nodal L2 error
+    against u*, its order, the multigrid rate and the times."""
+    from hhg_inputs import (CYLINDER_BOX, cylinder_reference_box, kuhn_box_mass_rhs, cylinder_tensor_fields_torch,
+                            cylinder_u, cylinder_f)
+    blocks = (1, 8, 10)
+    X, T = cylinder_reference_box(blocks)
+    lo, hi = CYLINDER_BOX
+    out = {"macro_tets": int(T.shape[0]), "cycle": "V(3,3)", "tol": 1e-8, "precision": "f64"}
+    prev = {}
+    for level in levels:
+        log(f"bench: blending level {level}")
+        ctx = hhg.Context(X, T, level)
+        xyz, dirichlet = ctx.node_coords(level)
+        ctx.set_tensor_coefficient(cylinder_tensor_fields_torch(xyz, torch))
+        b = kuhn_box_mass_rhs(xyz, level, cylinder_f, blocks, lo, hi)
+        b[dirichlet] = 0.0
+        fd = ctx.from_canonical(level, torch.tensor(b, device="cuda"))
+        del b
+        ustar = cylinder_u(xyz)
+        vol = float(np.prod((np.asarray(hi) - np.asarray(lo)) / (np.asarray(blocks) * 2 ** level)))
+        rec = {"unknowns": ctx.sizes(level)["n_unknowns"]}
+        for form in ("nodal", "scaled"):
+            best, ub = None, None
+            for _ in range(2):
+                u = ctx.vector(level)
+                torch.cuda.synchronize()
+                st = ctx.solve_tensor(level, fd, u, form=form, mode=hhg.SOLVE_F64, tol=1e-8, max_iter=100,
+                                      pre=3, post=3)
+                if best is None or st["seconds"] < best["seconds"]:
+                    best, ub = st, u
+            e = ctx.to_canonical(level, ub).cpu().numpy() - ustar
+            r = {"error": float(f"{np.sqrt(vol * np.sum(e[~dirichlet] ** 2)):.4g}"),
+                 "rho": round(best["rho"], 3), "iterations": best["iterations"],
+                 "seconds": float(f"{best['seconds']:.4g}"), "status": best["status"]}
+            if form in prev:
+                r["eoc"] = round(float(np.log2(prev[form] / r["error"])), 3)
+            prev[form] = r["error"]
+            rec[form] = r
+            log(f"bench: blending level {level} {form}: {r}")
+            del ub, u
+        rec["relative_tts"] = round(rec["scaled"]["seconds"] / rec["nodal"]["seconds"], 3)
+        out[f"level{level}"] = rec
+        ctx.close()
+        del ctx, fd, xyz, ustar
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -561,6 +615,7 @@ def main():
                     help="only the tensor-operator solves (12-tet cube, level 8)")
     ap.add_argument("--c3-solves", action="store_true", help="only the 6-tet cube solves at levels 5-8")
     ap.add_argument("--held-out", action="store_true", help="only the 32 held-out learned-smoother fields")
+    ap.add_argument("--blending", action="store_true", help="only the blending example's solves (Sec. 7.4)")
     ap.add_argument("--k48-solves", action="store_true",
                     help="only run the 48-tet level-8 V-cycle solves (profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -603,6 +658,9 @@ def main():
         return
     if args.held_out:
         print(json.dumps(learned_held_out(hhg, torch)))
+        return
+    if args.blending:
+        print(json.dumps(blending_solves(hhg, torch)))
         return
 
     # ---------------- main workload: unit tet, level 8, lognormal k
@@ -746,6 +804,7 @@ def main():
         extra["forms_6tet_l8"] = scalar_form_solves(hhg, torch)
         extra["square2d_l11"] = applies_2d(torch, args.steps)
         extra["tensor_cube12_l8"] = tensor_solves(hhg, torch)
+        extra["blending_cylinder"] = blending_solves(hhg, torch)
     else:
         cpu_out = None
         if not args.no_cpu:

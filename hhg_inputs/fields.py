@@ -221,3 +221,124 @@ def kuhn_cube_mass_rhs(xyz, level, f):
         B += w * Fp[1 + a:n + 2 + a, 1 + b:n + 2 + b, 1 + c:n + 2 + c]
     idx = np.rint(np.asarray(xyz) * n).astype(np.int64)
     return B[idx[:, 0], idx[:, 1], idx[:, 2]] / float(n) ** 3
+
+
+# ---------------------------------------------------------------- blending example
+# The half cylinder mantle of Sec. 7.4 on its reference box (r1, r2) x (0, pi)
+# x (0, z1), warped by w(z) = 0.2 sin(pi z / z1): with the mapping Phi from
+# the physical to the reference domain, the Laplacian becomes -div(K grad u)
+# with K = (D Phi)(D Phi)^T / |det D Phi| at x = Phi^{-1}(xh), here times the
+# material parameter 1 + z.
+CYL_R1, CYL_R2, CYL_Z1, CYL_WARP = 0.8, 1.0, 4.0, 0.2
+
+
+def cylinder_warp(z, lib=np):
+    """w(z), w'(z), w''(z) of the warp w(z) = 0.2 sin(pi z / z1)."""
+    k = np.pi / CYL_Z1
+    return CYL_WARP * lib.sin(k * z), CYL_WARP * k * lib.cos(k * z), -CYL_WARP * k * k * lib.sin(k * z)
+
+
+def cylinder_mapping_K(xyz, lib=np):
+    """K = (D Phi)(D Phi)^T / |det D Phi| at the reference points xyz (n, 3, 3):
+    with r = x - w(z) the physical radius and p = w'(z),
+    K = r [[p^2 + 1, 0, p], [0, 1 / r^2, 0], [p, 0, 1]]."""
+    x, z = xyz[:, 0], xyz[:, 2]
+    w, p, _ = cylinder_warp(z, lib)
+    r = x - w
+    zero = 0 * r
+    rows = [[r * (p * p + 1), zero, r * p], [zero, 1 / r, zero], [r * p, zero, r]]
+    return lib.stack([lib.stack(q, 1) for q in rows], 1)
+
+
+def cylinder_phi_inverse(xyz):
+    """Phi^{-1}: reference (radius + warp, angle, height) -> physical (x, y, z)."""
+    w, _, _ = cylinder_warp(xyz[:, 2])
+    r = xyz[:, 0] - w
+    return np.stack([r * np.cos(xyz[:, 1]), r * np.sin(xyz[:, 1]), xyz[:, 2]], axis=1)
+
+
+def cylinder_phi(xp):
+    """Phi: physical (x, y, z) -> reference (sqrt(x^2 + y^2) + w(z), arccos(x / sqrt(x^2 + y^2)), z)."""
+    rho = np.hypot(xp[:, 0], xp[:, 1])
+    w, _, _ = cylinder_warp(xp[:, 2])
+    return np.stack([rho + w, np.arccos(xp[:, 0] / rho), xp[:, 2]], axis=1)
+
+
+def cylinder_tensor(xyz, lib=np):
+    """The coefficient of the blending example: (1 + z) K (n, 3, 3)."""
+    return (1 + xyz[:, 2])[:, None, None] * cylinder_mapping_K(xyz, lib)
+
+
+def cylinder_tensor_fields_torch(xyz, torch, device="cuda", chunk=1 << 22):
+    """tensor_fields(cylinder_tensor(xyz)) with torch on `device` in chunks
+    (FP64); returns a (6, n) device tensor."""
+    x = torch.as_tensor(xyz, dtype=torch.float64, device=device)
+    n = x.shape[0]
+    out = torch.empty((6, n), dtype=torch.float64, device=device)
+    for c0 in range(0, n, chunk):
+        K = cylinder_tensor(x[c0:c0 + chunk], torch)
+        for i in range(3):
+            out[i, c0:c0 + chunk] = K[:, i, i] - sum(K[:, i, j] for j in range(3) if j != i)
+        out[3, c0:c0 + chunk] = K[:, 0, 1]
+        out[4, c0:c0 + chunk] = K[:, 0, 2]
+        out[5, c0:c0 + chunk] = K[:, 1, 2]
+    return out
+
+
+def _cylinder_factors(xyz):
+    """u = A(x) B(y) C(z) with A = sin(pi (x - r1) / (r2 - r1)),
+    B = sin(4 y), C = sin(pi z / z1) exp(z / 2), and their first two derivatives."""
+    x, y, z = xyz[:, 0], xyz[:, 1], xyz[:, 2]
+    c = np.pi / (CYL_R2 - CYL_R1)
+    A, A1 = np.sin(c * (x - CYL_R1)), c * np.cos(c * (x - CYL_R1))
+    A2 = -c * c * A
+    B, B1 = np.sin(4 * y), 4 * np.cos(4 * y)
+    B2 = -16 * B
+    k, e = np.pi / CYL_Z1, np.exp(z / 2)
+    C = np.sin(k * z) * e
+    C1 = k * np.cos(k * z) * e + C / 2
+    C2 = -k * k * C + C1 - C / 4
+    return A, A1, A2, B, B1, B2, C, C1, C2
+
+
+def cylinder_u(xyz):
+    """Manufactured solution on the reference box, zero on its boundary:
+    sin(pi (x - r1) / (r2 - r1)) sin(4 y) sin(pi z / z1) exp(z / 2)."""
+    A, _, _, B, _, _, C, _, _ = _cylinder_factors(xyz)
+    return A * B * C
+
+
+def cylinder_f(xyz):
+    """f = -div((1 + z) K grad u) for cylinder_u, written out: with a = 1 + z,
+    r = x - w(z), p = w'(z), q = w''(z) and the flux F = a K grad u,
+    F_x = a r ((p^2 + 1) u_x + p u_z), F_y = (a / r) u_y, F_z = a r (p u_x + u_z)."""
+    A, A1, A2, B, B1, B2, C, C1, C2 = _cylinder_factors(xyz)
+    ux, uxx, uyy = A1 * B * C, A2 * B * C, A * B2 * C
+    uz, uzz, uxz = A * B * C1, A * B * C2, A1 * B * C1
+    x, z = xyz[:, 0], xyz[:, 2]
+    w, p, q = cylinder_warp(z)
+    r, a = x - w, 1 + z
+    dFx = a * ((p * p + 1) * ux + p * uz) + a * r * ((p * p + 1) * uxx + p * uxz)
+    dFy = a / r * uyy
+    dFz = (r - a * p) * (p * ux + uz) + a * r * (q * ux + p * uxz + uzz)
+    return -(dFx + dFy + dFz)
+
+
+def kuhn_box_mass_rhs(xyz, level, f, nblocks, lo, hi):
+    """b = M I_h f for kuhn_box(nblocks, lo, hi) at `level` (the Freudenthal
+    triangulation of the grid of nblocks * 2^level cells per axis) at the
+    nodes xyz (any order): f sampled on the grid, then the consistent mass
+    stencil, one cell volume per cube.  Boundary nodes get the same formula
+    (callers zero Dirichlet rows)."""
+    lo, hi = np.asarray(lo, dtype=np.float64), np.asarray(hi, dtype=np.float64)
+    N = np.asarray(nblocks) * 2 ** level
+    h = (hi - lo) / N
+    g = [lo[d] + h[d] * np.arange(N[d] + 1) for d in range(3)]
+    X, Y, Z = np.meshgrid(*g, indexing="ij")
+    F = f(np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)).reshape(X.shape)
+    Fp = np.pad(F, 1)
+    B = np.zeros_like(F)
+    for (a, b, c), wt in _freudenthal_mass_stencil().items():
+        B += wt * Fp[1 + a:N[0] + 2 + a, 1 + b:N[1] + 2 + b, 1 + c:N[2] + 2 + c]
+    idx = np.rint((np.asarray(xyz) - lo) / h).astype(np.int64)
+    return B[idx[:, 0], idx[:, 1], idx[:, 2]] * float(np.prod(h))

@@ -60,6 +60,33 @@ def kuhn_cube_2x2x2():
     return X, np.array(T, dtype=np.int32)
 
 
+def kuhn_box(nblocks, lo, hi):
+    """The box [lo, hi] cut into nx x ny x nz equal blocks, each into its 6
+    Kuhn tetrahedra (as kuhn_cube, along every block's lo -> hi diagonal, so
+    the mesh is conforming and its uniform refinement is the Freudenthal
+    triangulation of the fine grid)."""
+    nx, ny, nz = nblocks
+    g = [np.linspace(lo[d], hi[d], nb + 1) for d, nb in enumerate((nx, ny, nz))]
+    X = np.array([[g[0][a], g[1][b], g[2][c]] for c in range(nz + 1) for b in range(ny + 1)
+                  for a in range(nx + 1)], dtype=np.float64)
+    vid = lambda a, b, c: a + (nx + 1) * (b + (ny + 1) * c)
+    T = []
+    for oz, oy, ox in itertools.product(range(nz), range(ny), range(nx)):
+        T += _kuhn_tets(lambda a, b, c: vid(ox + a, oy + b, oz + c))
+    return X, np.array(T, dtype=np.int32)
+
+
+# reference domain of the paper's blending example (Sec. 7.4): radius
+# (r1, r2) = (0.8, 1.0), angle (0, pi), height (0, z1), z1 = 4
+CYLINDER_BOX = ((0.8, 0.0, 0.0), (1.0, np.pi, 4.0))
+
+
+def cylinder_reference_box(nblocks=(1, 8, 10)):
+    """The reference box of the half cylinder mantle of Sec. 7.4 in Kuhn
+    blocks (default 80 blocks = 480 tets of 0.2 x 0.39 x 0.4)."""
+    return kuhn_box(nblocks, *CYLINDER_BOX)
+
+
 def cube12():
     """Unit cube split into 12 tetrahedra around one interior macro vertex at
     (0.5, 0.5, 0.5): every cube face is cut along a diagonal into two
