@@ -11,6 +11,9 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          # no packed-FP32 instructions (some of their forms have given silently
          # wrong results on this hardware)
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # matrix-core results in ordinary VGPRs (no accumulation-register
+         # copies after each product in the learned-correction kernels)
+         "-mllvm", "-amdgpu-mfma-vgpr-form",
          "-I", os.path.join(ROOT, "include")]
 
 

@@ -248,17 +248,20 @@ __global__ __launch_bounds__(BLOCK) void k_learned_fwd_march(LevelView<float> L,
                 bf16x4 xlo, xhi;
                 __builtin_memcpy(&xlo, &lo, 8);
                 __builtin_memcpy(&xhi, &hi, 8);
-                f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+                // the biases start the accumulators (one FP32 sum of the
+                // products and the bias, as the reference's single rounding
+                // bounds it)
+                f32x4 acc = {b1v[0], b1v[1], b1v[2], b1v[3]};
                 acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1lo, xlo, acc, 0, 0, 0);
                 acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1hi, xhi, acc, 0, 0, 0);
-                const uint2 hp = make_uint2(pack_bf16(fmaxf(acc[0] + b1v[0], 0.0f), fmaxf(acc[1] + b1v[1], 0.0f)),
-                                            pack_bf16(fmaxf(acc[2] + b1v[2], 0.0f), fmaxf(acc[3] + b1v[3], 0.0f)));
+                const uint2 hp = make_uint2(pack_bf16(fmaxf(acc[0], 0.0f), fmaxf(acc[1], 0.0f)),
+                                            pack_bf16(fmaxf(acc[2], 0.0f), fmaxf(acc[3], 0.0f)));
                 bf16x4 h1;
                 __builtin_memcpy(&h1, &hp, 8);
-                f32x4 acc2 = {0.0f, 0.0f, 0.0f, 0.0f};
+                f32x4 acc2 = {b2v[0], b2v[1], b2v[2], b2v[3]};
                 acc2 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2, h1, acc2, 0, 0, 0);
                 float part = 0.0f;
-                for (int q2 = 0; q2 < 4; ++q2) part += w3v[q2] * fmaxf(acc2[q2] + b2v[q2], 0.0f);
+                for (int q2 = 0; q2 < 4; ++q2) part += w3v[q2] * fmaxf(acc2[q2], 0.0f);
                 part += __shfl_xor(part, 16, 64);
                 part += __shfl_xor(part, 32, 64);
                 if (lane < 16) cs[wave * 64 + g * 16 + lane] = part + b3;
