@@ -399,6 +399,7 @@ struct Level {
     uint64_t *sh_copy = nullptr;
     int sh_w = 0;
     int64_t *sh_nb = nullptr, *sh_self = nullptr, *sh_cslot = nullptr;
+    uint32_t *sh_nb32 = nullptr, *sh_self32 = nullptr, *sh_cslot32 = nullptr, *sh_nbs32 = nullptr;
     int8_t *sh_map = nullptr;  // [copy][16]: entry of direction d, -1 if none
     // the scaled operator's own (narrower) pattern
     int sh_ws = 0;
@@ -768,6 +769,7 @@ LevelView<double> view<double>(const hhg_ctx c, int l)
     v.sh_w = L.sh_w; v.sh_nb = L.sh_nb; v.sh_self = L.sh_self; v.sh_cslot = L.sh_cslot;
     v.sh_cs = L.sh_cs64; v.sh_cn = L.sh_cn64; v.sh_prim = L.sh_prim;
     v.sh_ws = L.sh_ws; v.sh_nbs = L.sh_nbs; v.sh_css = L.sh_css64;
+    v.sh_nb32 = L.sh_nb32; v.sh_self32 = L.sh_self32; v.sh_cslot32 = L.sh_cslot32; v.sh_nbs32 = L.sh_nbs32;
     v.sh_wt = L.sh_wt; v.sh_nbt = L.sh_nbt; v.sh_ct = L.sh_ct64; v.sh_ctn = L.sh_ctn64;
     v.tsten = L.tsten64; v.kt = L.kt64; v.kp = L.kp64; v.temat = L.temat64;
     v.items2 = L.items2; v.n_items2 = L.n_items2; v.vpt2 = (L.n_items2 + 3) / 4;
@@ -788,6 +790,7 @@ LevelView<float> view<float>(const hhg_ctx c, int l)
     v.sh_w = L.sh_w; v.sh_nb = L.sh_nb; v.sh_self = L.sh_self; v.sh_cslot = L.sh_cslot;
     v.sh_cs = L.sh_cs32; v.sh_cn = L.sh_cn32; v.sh_prim = L.sh_prim;
     v.sh_ws = L.sh_ws; v.sh_nbs = L.sh_nbs; v.sh_css = L.sh_css32;
+    v.sh_nb32 = L.sh_nb32; v.sh_self32 = L.sh_self32; v.sh_cslot32 = L.sh_cslot32; v.sh_nbs32 = L.sh_nbs32;
     v.sh_wt = L.sh_wt; v.sh_nbt = L.sh_nbt; v.sh_ct = L.sh_ct32; v.sh_ctn = L.sh_ctn32;
     v.tsten = L.tsten32; v.kt = L.kt32; v.kp = L.kp32; v.temat = L.temat32;
     v.items2 = L.items2f; v.n_items2 = L.n_items2f; v.vpt2 = (L.n_items2f + 3) / 4;
@@ -1250,6 +1253,15 @@ hhg_status build_level(hhg_ctx c, int l)
         TRY(upload(c, &L.sh_map, hmap));
         L.sh_ws = width_s;
         TRY(upload(c, &L.sh_nbs, ell_s));
+        if ((uint64_t)tp.nt * (uint64_t)L.Spad <= UINT32_MAX) {
+            auto narrow = [](const std::vector<int64_t> &a) {
+                return std::vector<uint32_t>(a.begin(), a.end());
+            };
+            TRY(upload(c, &L.sh_nb32, narrow(ell)));
+            TRY(upload(c, &L.sh_self32, narrow(hself)));
+            TRY(upload(c, &L.sh_cslot32, narrow(hcslot)));
+            TRY(upload(c, &L.sh_nbs32, narrow(ell_s)));
+        }
         TRY(upload(c, &L.sh_maps, hmap_s));
         {
             const int64_t nes = std::max<int64_t>(1, (int64_t)width_s * L.n_shared);

@@ -53,6 +53,10 @@ struct LevelView {
     const int64_t *sh_nb;     // global slot (tet * Spad + slot) of the neighbour
     const int64_t *sh_self;   // global slot of the node's first copy
     const int64_t *sh_cslot;  // global slot of every copy (sh_off order)
+    // the same three (and sh_nbs below) as 32-bit slots when every global
+    // slot of the level fits (null otherwise): the row kernel then streams 4
+    // instead of 8 bytes per index
+    const uint32_t *sh_nb32, *sh_self32, *sh_cslot32, *sh_nbs32;
     const T *sh_cs;           // scaled-operator coefficients
     const T *sh_cn;           // nodal-operator coefficients
     const uint8_t *sh_prim;   // macro primitive of node q: 1 vertex, 2 edge, 4 face

@@ -895,24 +895,26 @@ static void launch_march_std(const LevelView<T> &L, const T *u, const T *f, T *y
 // the sum of the tet-restricted stencils of all copies).  The merged
 // coefficients are built once per coefficient field (k_shared_coef); a row
 // is then sum_m c_m (u_m - u_q), written to every copy of the node.
-template <typename T, int MODE>
-__global__ __launch_bounds__(BLOCK) void k_shared_rows(LevelView<T> L, const T *__restrict__ coef,
-                                                        const T *__restrict__ u, const T *__restrict__ f,
-                                                        T *__restrict__ y, double *__restrict__ partial,
-                                                        ChebArgs<T> cb, const T *__restrict__ coefn, int nodal_mask)
+template <typename T, int MODE, typename IX>
+__global__ __launch_bounds__(BLOCK) void k_shared_rows(LevelView<T> L, const IX *__restrict__ nbs,
+                                                        const IX *__restrict__ selfs, const IX *__restrict__ cslots,
+                                                        const T *__restrict__ coef, const T *__restrict__ u,
+                                                        const T *__restrict__ f, T *__restrict__ y,
+                                                        double *__restrict__ partial, ChebArgs<T> cb,
+                                                        const T *__restrict__ coefn, int nodal_mask)
 {
     const int q = blockIdx.x * BLOCK + threadIdx.x;
     const int ns = L.n_shared;
     double sq = 0.0;
     if (q < ns) {
-        const int64_t self = L.sh_self[q];
+        const int64_t self = (int64_t)selfs[q];
         const T u0 = u[self];
         // primitive-mixed operator: the nodal coefficients on the chosen primitives
         const T *__restrict__ cp = nodal_mask && (L.sh_prim[q] & nodal_mask) ? coefn : coef;
         T acc = T(0);
         for (int m = 0; m < L.sh_w; ++m) {
             const int64_t e = (int64_t)m * ns + q;
-            acc += cp[e] * (u[L.sh_nb[e]] - u0);
+            acc += cp[e] * (u[(int64_t)nbs[e]] - u0);
         }
         T out = acc;
         if (MODE == MODE_RESID) {
@@ -923,11 +925,11 @@ __global__ __launch_bounds__(BLOCK) void k_shared_rows(LevelView<T> L, const T *
             const T r = f[self] - acc;
             const T dn = (cb.first ? T(0) : cb.c_old * cb.d[self]) + cb.c_r * cb.invd[self] * r;
             for (int c = L.sh_off[q]; c < L.sh_off[q + 1]; ++c) {
-                cb.d[L.sh_cslot[c]] = dn;
-                y[L.sh_cslot[c]] = u0 + dn;
+                cb.d[(int64_t)cslots[c]] = dn;
+                y[(int64_t)cslots[c]] = u0 + dn;
             }
         } else {
-            for (int c = L.sh_off[q]; c < L.sh_off[q + 1]; ++c) y[L.sh_cslot[c]] = out;
+            for (int c = L.sh_off[q]; c < L.sh_off[q + 1]; ++c) y[(int64_t)cslots[c]] = out;
         }
     }
     if (MODE == MODE_RESID) {
@@ -936,13 +938,21 @@ __global__ __launch_bounds__(BLOCK) void k_shared_rows(LevelView<T> L, const T *
     }
 }
 
+// 32-bit slot lists when the level has them (and the pattern in L.sh_nb is
+// the one they mirror: the tensor pattern clears sh_nb32)
 template <typename T, int MODE>
 static void launch_shared_rows(const LevelView<T> &L, const T *coef, const T *u, const T *f, T *y,
                                double *partial, hipStream_t st, const ChebArgs<T> &cb = ChebArgs<T>(),
                                const T *coefn = nullptr, int nodal_mask = 0)
 {
     const int gs = blocks_for(L.n_shared);
-    if (gs) k_shared_rows<T, MODE><<<gs, BLOCK, 0, st>>>(L, coef, u, f, y, partial, cb, coefn, nodal_mask);
+    if (!gs) return;
+    if (L.sh_nb32)
+        k_shared_rows<T, MODE, uint32_t><<<gs, BLOCK, 0, st>>>(L, L.sh_nb32, L.sh_self32, L.sh_cslot32, coef, u, f,
+                                                               y, partial, cb, coefn, nodal_mask);
+    else
+        k_shared_rows<T, MODE, int64_t><<<gs, BLOCK, 0, st>>>(L, L.sh_nb, L.sh_self, L.sh_cslot, coef, u, f, y,
+                                                              partial, cb, coefn, nodal_mask);
 }
 
 // the scaled operator's shared rows on its own (narrower) pattern
@@ -953,6 +963,7 @@ static void launch_shared_rows_scaled(const LevelView<T> &L, const T *u, const T
     LevelView<T> Ls = L;
     Ls.sh_w = L.sh_ws;
     Ls.sh_nb = L.sh_nbs;
+    Ls.sh_nb32 = L.sh_nbs32;
     launch_shared_rows<T, MODE>(Ls, L.sh_css, u, f, y, partial, st, cb);
 }
 
@@ -1886,6 +1897,7 @@ hipError_t launch_tensor_shared_coef(const LevelView<double> &L, const int8_t *m
     LevelView<double> Lt = L;
     Lt.sh_w = L.sh_wt;
     Lt.sh_nb = L.sh_nbt;
+    Lt.sh_nb32 = nullptr;
     if (L.n_shared) k_tensor_shared_coef<<<blocks_for(L.n_shared), BLOCK, 0, st>>>(Lt, map, cs, cn);
     return hipGetLastError();
 }
@@ -1957,6 +1969,7 @@ hipError_t launch_tensor(const LevelView<T> &L, int form, int mode, const T *u, 
     LevelView<T> Lt = L;  // the tensor pattern
     Lt.sh_w = L.sh_wt;
     Lt.sh_nb = L.sh_nbt;
+    Lt.sh_nb32 = nullptr;
     const T *coef = form == 0 ? L.sh_ct : L.sh_ctn;
     if (resid) launch_shared_rows<T, MODE_RESID>(Lt, coef, u, f, y, partial + gi, st);
     else launch_shared_rows<T, MODE_APPLY>(Lt, coef, u, f, y, nullptr, st);
