@@ -633,12 +633,53 @@ __device__ __forceinline__ void wait_vm()
     __builtin_amdgcn_s_waitcnt(0x0F70 | N);
 }
 
+// row values of one plane (two rows per lane): f, and for the smoother the
+// direction d and D^-1 at x and y
+template <typename T>
+struct LdsRow {
+    P2<T> f, d, id;
+};
+
+// one 16-byte (FP64) or 8-byte (FP32) load of a lane's two row values
+template <typename T>
+__device__ __forceinline__ P2<T> load_pair(__amdgpu_buffer_rsrc_t r, int off)
+{
+    if constexpr (sizeof(T) == 8) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+        unsigned long long lo = ((unsigned long long)v[1] << 32) | v[0], hi = ((unsigned long long)v[3] << 32) | v[2];
+        P2<T> o;
+        __builtin_memcpy(&o.x, &lo, 8);
+        __builtin_memcpy(&o.y, &hi, 8);
+        return o;
+    } else {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+        return {__uint_as_float(v[0]), __uint_as_float(v[1])};
+    }
+}
+
+// block sum of an 8-wave block, the result in thread 0
+__device__ __forceinline__ double block_reduce_lw(double v)
+{
+    __shared__ double red[LW];
+    v = warp_sum(v);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    if (l == 0) red[w] = v;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int q = 1; q < LW; ++q) v += red[q];
+    return v;
+}
+
 template <typename T, int MODE>
 __global__ __launch_bounds__(64 * LW) __attribute__((amdgpu_waves_per_eu(4))) void k_march_lds(
-    LevelView<T> L, const T *__restrict__ u, T *__restrict__ y)
+    LevelView<T> L, const T *__restrict__ u, const T *__restrict__ f, T *__restrict__ y,
+    double *__restrict__ partial, ChebArgs<T> cb)
 {
     using C = LdsCfg<T>;
     constexpr int B = (int)sizeof(T);
+    // row loads per plane (f; f, d, D^-1) and stores per step (y; d, u_new)
+    constexpr int RL = MODE == MODE_APPLY ? 0 : MODE == MODE_RESID ? 1 : 3;
+    constexpr int ST = MODE == MODE_CHEB ? 4 : 2;
     __shared__ __attribute__((aligned(16))) T ring[LRS][2][LELEM];
     // landing area of the spare load slots (FP32): they read nothing, and
     // whatever the hardware writes for them must not reach the ring
@@ -646,7 +687,10 @@ __global__ __launch_bounds__(64 * LW) __attribute__((amdgpu_waves_per_eu(4))) vo
     const int nbb = (L.n_bnd + 64 * LW - 1) / (64 * LW);
     const int per_tet = L.n_itemsL + nbb;
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
-    if (lb >= L.n_tet * per_tet) return;  // whole block
+    if (lb >= L.n_tet * per_tet) {  // whole block
+        if (MODE == MODE_RESID && threadIdx.x == 0) partial[blockIdx.x] = 0.0;
+        return;
+    }
     const int tet = lb / per_tet;
     int b;
     const bool marching = march_block(lb - tet * per_tet, L.n_itemsL, nbb, b);
@@ -657,6 +701,7 @@ __global__ __launch_bounds__(64 * LW) __attribute__((amdgpu_waves_per_eu(4))) vo
             const uint32_t v = L.bnd[e];
             if ((L.dmask[tet] >> (v & 15u)) & 1) y[base + (v >> 4)] = T(0);
         }
+        if (MODE == MODE_RESID && threadIdx.x == 0) partial[blockIdx.x] = 0.0;
         return;
     }
     const uint2 it = L.itemsL[b];
@@ -688,8 +733,12 @@ __global__ __launch_bounds__(64 * LW) __attribute__((amdgpu_waves_per_eu(4))) vo
     const __amdgpu_buffer_rsrc_t ru = tet_rsrc(u + base, (int64_t)L.S * B);
     const __amdgpu_buffer_rsrc_t rk = tet_rsrc(L.kap + base, (int64_t)L.S * B);
     const __amdgpu_buffer_rsrc_t ry = tet_rsrc(y + base, (int64_t)L.S * B);
+    const __amdgpu_buffer_rsrc_t rf = tet_rsrc(MODE != MODE_APPLY ? f + base : u + base, (int64_t)L.S * B);
+    const __amdgpu_buffer_rsrc_t rd = tet_rsrc(MODE == MODE_CHEB ? cb.d + base : u + base, (int64_t)L.S * B);
+    const __amdgpu_buffer_rsrc_t ri = tet_rsrc(MODE == MODE_CHEB ? cb.invd + base : u + base, (int64_t)L.S * B);
     const int Sn = tc32(n);
     auto plane = [&](int p) { return Sn - tc32(n - p); };
+    constexpr int DROP = 0x7ffffff0;
     // this wave's 16-byte-per-lane LDS loads of plane p into slot p % LRS
     auto stage = [&](int p) {
         const int sl = p % LRS;
@@ -704,10 +753,21 @@ __global__ __launch_bounds__(64 * LW) __attribute__((amdgpu_waves_per_eu(4))) vo
             // two arrays' chunks lands in the dump area
             const bool spare = arr >= 2;
             const bool real = !spare && ch * C::CHUNK < need && p <= k1 + 1;
-            const int voff = real ? (plane(p) + lo + ch * C::CHUNK + (16 / B) * lane) * B : 0x7ffffff0;
+            const int voff = real ? (plane(p) + lo + ch * C::CHUNK + (16 / B) * lane) * B : DROP;
             T *dst = spare ? &dump[0] : &ring[sl][spare ? 0 : arr][spare ? 0 : ch * C::CHUNK];
             __builtin_amdgcn_raw_ptr_buffer_load_lds(arr == 1 ? rk : ru, (__attribute__((address_space(3))) void *)dst,
                                                      16, voff, 0, 0, 0);
+        }
+    };
+    // the row values of plane p (RL loads; a plane without a row reads nothing)
+    auto rowload = [&](int p, LdsRow<T> &v) {
+        if constexpr (RL > 0) {
+            const int off = (p <= lastx || p <= lasty) ? (plane(p) + tx) * B : DROP;
+            v.f = load_pair<T>(rf, off);
+            if constexpr (RL == 3) {
+                v.d = load_pair<T>(rd, off);
+                v.id = load_pair<T>(ri, off);
+            }
         }
     };
     auto addr = [&](int p, int arr) { return lds_addr<T>(&ring[p % LRS][arr][0]); };
@@ -718,7 +778,10 @@ __global__ __launch_bounds__(64 * LW) __attribute__((amdgpu_waves_per_eu(4))) vo
     struct Pl {
         P2<T> u[3], k[3];
     } R[3];
-    // prologue: planes k0-1 and k0 into registers, then k0+1 and k0+2 in flight
+    LdsRow<T> RV[3];
+    double sq = 0.0;
+    // prologue: planes k0-1 and k0 into registers, then k0+1 and k0+2 in
+    // flight, then the row values of plane k0
     stage(k0 - 1);
     stage(k0);
     __builtin_amdgcn_sched_barrier(0);
@@ -732,19 +795,23 @@ __global__ __launch_bounds__(64 * LW) __attribute__((amdgpu_waves_per_eu(4))) vo
     __builtin_amdgcn_sched_barrier(0);
     stage(k0 + 1);
     stage(k0 + 2);
-    constexpr int DROP = 0x7ffffff0;
+    rowload(k0, RV[0]);
+    __builtin_amdgcn_sched_barrier(0);
     for (int kb = k0; kb <= k1; kb += 3) {
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
             const int k = kb + q;
             if (k > k1) break;  // block-uniform
             Pl &M = R[q % 3], &Cc = R[(q + 1) % 3], &P = R[(q + 2) % 3];
+            const LdsRow<T> &rv = RV[q % 3];
             // plane k+1 has landed once at most the later loads and stores
-            // are outstanding: the next plane's PERWAVE loads at the first
-            // step, plus the previous step's two stores after
+            // are outstanding: at the first step the next plane's PERWAVE
+            // loads and this plane's row loads; later the previous step's row
+            // loads (of this plane), stores and plane loads, issued in that
+            // order
             __builtin_amdgcn_sched_barrier(0);
-            if (k == k0) wait_vm<C::PERWAVE>();
-            else wait_vm<C::PERWAVE + 2>();
+            if (k == k0) wait_vm<C::PERWAVE + RL>();
+            else wait_vm<RL + ST + C::PERWAVE>();
             __builtin_amdgcn_s_barrier();
             __builtin_amdgcn_sched_barrier(0);
             lds_read_plane(addr(k + 1, 0), addr(k + 1, 1), e, P.u, P.k);
@@ -754,17 +821,41 @@ __global__ __launch_bounds__(64 * LW) __attribute__((amdgpu_waves_per_eu(4))) vo
             const T ax = scaled_row_paired<T>(ux, kx, wr);
             const T ay = scaled_row_paired<T>(uy, ky, wr);
             const int Pk = plane(k);
-            const int sx = k <= lastx ? (Pk + tx) * B : DROP, sy = k <= lasty ? (Pk + ty) * B : DROP;
-            bstore(ax, ry, sx);
-            bstore(ay, ry, sy);
+            const bool lx = k <= lastx, ly = k <= lasty;
+            const int sx = lx ? (Pk + tx) * B : DROP, sy = ly ? (Pk + ty) * B : DROP;
+            // the next plane's row values, before this step's stores
+            rowload(k + 1, RV[(q + 1) % 3]);
+            __builtin_amdgcn_sched_barrier(0);
+            if constexpr (MODE == MODE_APPLY) {
+                bstore(ax, ry, sx);
+                bstore(ay, ry, sy);
+            } else if constexpr (MODE == MODE_RESID) {
+                const T rx = rv.f.x - ax, rr = rv.f.y - ay;
+                bstore(rx, ry, sx);
+                bstore(rr, ry, sy);
+                sq += (lx ? (double)rx * (double)rx : 0.0) + (ly ? (double)rr * (double)rr : 0.0);
+            } else {
+                const T rx = rv.f.x - ax, rr = rv.f.y - ay;
+                const T dx = (cb.first ? T(0) : cb.c_old * rv.d.x) + cb.c_r * rv.id.x * rx;
+                const T dy = (cb.first ? T(0) : cb.c_old * rv.d.y) + cb.c_r * rv.id.y * rr;
+                bstore(dx, rd, sx);
+                bstore(dy, rd, sy);
+                bstore(Cc.u[1].x + dx, ry, sx);
+                bstore(Cc.u[1].y + dy, ry, sy);
+            }
             // the slot of plane k (read one step ago by every wave, which all
             // passed this step's barrier) takes plane k+3
+            __builtin_amdgcn_sched_barrier(0);
             stage(k + 3);
             __builtin_amdgcn_sched_barrier(0);
         }
     }
     // drain: every LDS load has landed before the block's LDS is released
     wait_vm<0>();
+    if constexpr (MODE == MODE_RESID) {
+        sq = block_reduce_lw(sq);
+        if (threadIdx.x == 0) partial[blockIdx.x] = sq;
+    }
 }
 
 template <typename T>
@@ -808,10 +899,27 @@ int set_march_variant(int v)
 template <typename T>
 static inline bool two_rows(int v) { return v == 6 || v == 8 || v == 9 || (v == 0 && sizeof(T) == 8); }
 
+// the LDS-staged block march where the level fits it: forced by variant 10,
+// chosen by default for working sets far beyond the last-level cache (it
+// measured faster there and slower below; on the 48-tet cube at level 8 the
+// FP64 apply 131 vs 122, the FP32 apply 205 vs 184 GDoF/s).  Residual and
+// smoother sweeps use it in FP32 (the FP64 kernel's registers hold no row
+// values beyond the apply's).
+template <typename T, int MODE>
+static bool use_lds(const LevelView<T> &L)
+{
+    if (L.n_itemsL <= 0) return false;
+    if (MODE != MODE_APPLY && sizeof(T) == 8) return false;
+    const int v = march_variant();
+    const bool big_set = (int64_t)L.n_tet * L.Spad >= ((int64_t)32 << 20);
+    return v == 10 || (v == 0 && big_set);
+}
+
 // blocks of the interior launch (one partial sum each in residual mode)
 template <typename T>
 static int march_blocks(const LevelView<T> &L)
 {
+    if (use_lds<T, MODE_RESID>(L)) return lds_grid(L);
     const int v = march_variant();
     if (v == 9) return ((L.n_tet * march2_blocks_per_tet<1>(L.n_items2, L.n_bnd) + 7) / 8) * 8;
     return two_rows<T>(v) ? march_grid(L.n_tet, L.vpt2, L.bpt2) : march_grid(L.n_tet, L.vpt, L.bpt2);
@@ -834,6 +942,8 @@ static void launch_march(const LevelView<T> &L, const T *u, const T *f, T *y, do
             const int g2 = march_grid(L.n_tet, L.vpt2, L.bpt2);
             if (march_variant() == 6) k_march2<T, MODE_CHEB, 0, 0, 3><<<g2, BLOCK, 0, st>>>(L, u, f, y, partial, cb);
             else k_march2<T, MODE_CHEB, 0, 1, 2><<<g2, BLOCK, 0, st>>>(L, u, f, y, partial, cb);
+        } else if (use_lds<T, MODE_CHEB>(L)) {
+            k_march_lds<T, MODE_CHEB><<<lds_grid(L), 64 * LW, 0, st>>>(L, u, f, y, partial, cb);
         } else {
             k_march<T, MODE_CHEB, 0, 1, 8, 1><<<march_grid(L.n_tet, L.vpt, L.bpt2), BLOCK, 0, st>>>(L, u, f, y,
                                                                                                    partial, cb);
@@ -847,15 +957,9 @@ template <typename T, int MODE, int OP>
 static void launch_march_std(const LevelView<T> &L, const T *u, const T *f, T *y, double *partial,
                              hipStream_t st, const ChebArgs<T> &cb)
 {
-    if constexpr (OP == 0 && MODE == MODE_APPLY) {
-        // the LDS-staged block march where the level fits it: forced by
-        // variant 10, chosen by default for working sets far beyond the
-        // last-level cache (it measured faster there and slower below; on
-        // the 48-tet cube at level 8: FP64 131 vs 122, FP32 205 vs 184 GDoF/s)
-        const int v = march_variant();
-        const bool big_set = (int64_t)L.n_tet * L.Spad >= ((int64_t)32 << 20);
-        if (L.n_itemsL > 0 && (v == 10 || (v == 0 && big_set))) {
-            k_march_lds<T, MODE_APPLY><<<lds_grid(L), 64 * LW, 0, st>>>(L, u, y);
+    if constexpr (OP == 0 && (MODE == MODE_APPLY || (MODE == MODE_RESID && sizeof(T) == 4))) {
+        if (use_lds<T, MODE>(L)) {
+            k_march_lds<T, MODE><<<lds_grid(L), 64 * LW, 0, st>>>(L, u, f, y, partial, cb);
             return;
         }
     }

@@ -119,6 +119,53 @@ def test_apply_fp32_kernel_variants(mesh_fn, level, variant):
     assert d <= 2e-6
 
 
+@pytest.mark.parametrize("mesh_fn,level", [(unit_tet, 5), (kuhn_cube_2x2x2, 3), (flat_tet, 4), (kuhn_cube, 6)])
+def test_fp32_lds_residual_and_chebyshev(mesh_fn, level):
+    """The LDS-staged block march in the FP32 residual (with its block norms)
+    and the fused Chebyshev sweep, forced (variant 10), with the modification
+    on: the residual against the oracle's on the FP32-rounded u, f and k
+    (2e-6 of the largest of |f| and |Au|) and its norm against the default
+    kernel's; three sweeps against the default kernel's (1e-5) and a
+    FP32-in-FP64 solve to 1e-10 against the default kernel's solution."""
+    om, k, u, ctx = _setup(mesh_fn, level, kfun=lambda x: lognormal_k(x, lognormal_params(3, 1.5, 0.1)))
+    f = uniform_vector(om.n_nodes, seed=17)
+    f[om.dirichlet] = 0.0
+    u32, f32, k32 = (a.astype(np.float32).astype(np.float64) for a in (u, f, k))
+    mods, _ = O.modification_factors(om, k)
+    op32 = O.Operator(om, O.assemble(om, k32, "scaled", mods=mods))
+    Au = op32.apply(u32)
+    ref = f32 - Au
+    ref[om.dirichlet] = 0.0
+    ud, fd = ctx.from_canonical(level, _dev(u32).float()), ctx.from_canonical(level, _dev(f32).float())
+    out = {}
+    try:
+        for v in (0, 10):
+            hhg.set_kernel_variant(v)
+            r = ctx.vector(level, torch.float32)
+            nrm = ctx.residual(level, fd, ud, r, norm=True)
+            w = ud.clone()
+            ctx.smooth(level, fd, w, 3, hhg.CHEBYSHEV)
+            x = ctx.vector(level)
+            st = ctx.solve(level, ctx.from_canonical(level, _dev(f)), x, mode=hhg.SOLVE_MIXED, tol=1e-10,
+                           max_iter=80)
+            out[v] = (ctx.to_canonical(level, r).cpu().numpy().astype(np.float64), nrm,
+                      ctx.to_canonical(level, w).cpu().numpy().astype(np.float64), st,
+                      ctx.to_canonical(level, x).cpu().numpy())
+    finally:
+        hhg.set_kernel_variant(0)
+    r10, n10, w10, st10, x10 = out[10]
+    r0, n0, w0, st0, x0 = out[0]
+    scale = max(np.abs(f32).max(), np.abs(Au).max())
+    err = np.abs(r10 - ref).max() / scale
+    print(f"FP32 LDS residual: max error {err:.2e}; norms {n10:.6e} {n0:.6e}", flush=True)
+    assert err <= 2e-6
+    assert np.all(r10[om.dirichlet] == 0.0)
+    assert n10 == pytest.approx(n0, rel=1e-5)
+    assert np.linalg.norm(w10 - w0) <= 1e-5 * np.linalg.norm(w0)
+    assert st10["status"] == 0 and st10["rel_residual"] <= 1e-10
+    assert np.linalg.norm(x10 - x0) <= 1e-8 * np.linalg.norm(x0)
+
+
 MIX = [(3, (0, 1)), (7, (0, 1, 2)), (4, (2,)), (1, (0,)), (0, ())]
 
 
