@@ -904,14 +904,16 @@ static inline bool two_rows(int v) { return v == 6 || v == 8 || v == 9 || (v == 
 // measured faster there and slower below; on the 48-tet cube at level 8 the
 // FP64 apply 131 vs 122, the FP32 apply 205 vs 184 GDoF/s).  Residual and
 // smoother sweeps use it in FP32 (the FP64 kernel's registers hold no row
-// values beyond the apply's).
+// values beyond the apply's) from 8M slots on, where their five arrays no
+// longer fit the last-level cache (the 6-tet cube at level 8, 17M slots:
+// FP32-in-FP64 solves 8% faster).
 template <typename T, int MODE>
 static bool use_lds(const LevelView<T> &L)
 {
     if (L.n_itemsL <= 0) return false;
     if (MODE != MODE_APPLY && sizeof(T) == 8) return false;
     const int v = march_variant();
-    const bool big_set = (int64_t)L.n_tet * L.Spad >= ((int64_t)32 << 20);
+    const bool big_set = (int64_t)L.n_tet * L.Spad >= ((int64_t)(MODE == MODE_APPLY ? 32 : 8) << 20);
     return v == 10 || (v == 0 && big_set);
 }
 
