@@ -473,6 +473,7 @@ struct CoarseInv {
     int64_t *cgather = nullptr;
     int32_t *ccoff = nullptr;
     int64_t *ccslot = nullptr;
+    double *cf = nullptr;  // the gathered right-hand side (cu values)
 };
 
 struct hhg_ctx_s {
@@ -1684,7 +1685,7 @@ hhg_status coarse_solve_t(hhg_ctx c, const T *f, T *u, hipStream_t st)
     Level &L = c->lv[c->coarse];
     const CoarseInv &C = c->co[c->op];
     HIPCHK(c, launch_fill<T>(u, T(0), L.n_slots, st));
-    HIPCHK(c, launch_coarse_solve<T>(C.ainv, C.cu, C.cgather, C.ccoff, C.ccslot, f, u, st));
+    HIPCHK(c, launch_coarse_solve<T>(C.ainv, C.cu, C.cgather, C.ccoff, C.ccslot, f, u, C.cf, st));
     return HHG_OK;
 }
 
@@ -2028,7 +2029,8 @@ hhg_status build_coarse(hhg_ctx c, hipStream_t st, int op = 0)
     HIPCHK(c, hipMemsetAsync(dy, 0, L.n_slots * 8, st));
     CoarseInv &C = c->co[op];
     if (C.ainv) {
-        for (void *p : {(void *)C.ainv, (void *)C.cgather, (void *)C.ccoff, (void *)C.ccslot}) dfree(c, p);
+        for (void *p : {(void *)C.ainv, (void *)C.cgather, (void *)C.ccoff, (void *)C.ccslot, (void *)C.cf})
+            dfree(c, p);
         C = CoarseInv();
     }
     C.cu = nu;
@@ -2062,6 +2064,7 @@ hhg_status build_coarse(hhg_ctx c, hipStream_t st, int op = 0)
     TRY(upload(c, &C.cgather, gather));
     TRY(upload(c, &C.ccoff, coff));
     TRY(upload(c, &C.ccslot, cslot));
+    TRY(dalloc(c, &C.cf, std::max(nu, 1)));
     HIPCHK(c, hipStreamSynchronize(st));
     return HHG_OK;
 }

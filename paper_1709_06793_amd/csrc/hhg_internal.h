@@ -199,7 +199,7 @@ hipError_t launch_prolong_add(const LevelView<T> &Lc, const LevelView<T> &Lf, co
 template <typename T>
 hipError_t launch_coarse_solve(const double *ainv, int nu, const int64_t *gather,
                                const int32_t *copy_off, const int64_t *copy_slot, const T *f, T *u,
-                               hipStream_t st);
+                               double *fc, hipStream_t st);
 template <typename T>
 hipError_t launch_fill(T *x, T v, int64_t n, hipStream_t st);
 template <typename Ti, typename To>

@@ -2129,18 +2129,36 @@ template hipError_t launch_store_stencils<float>(const LevelView<double> &, floa
 // u[copies of row r] = sum_c Ainv[r][c] f[gather[c]] in FP64 (u zeroed
 // before): one wave per row, lanes stride over the columns (coalesced row
 // reads), wave-wide sum
+// the coarse right-hand side gathered once (one slot per coarse unknown) in FP64
 template <typename T>
-__global__ __launch_bounds__(64) void k_coarse(const double *__restrict__ ainv, int nu,
-                                               const int64_t *__restrict__ gather,
-                                               const int32_t *__restrict__ coff,
-                                               const int64_t *__restrict__ cslot,
-                                               const T *__restrict__ f, T *__restrict__ u)
+__global__ __launch_bounds__(BLOCK) void k_coarse_gather(const int64_t *__restrict__ gather, const T *__restrict__ f,
+                                                          double *__restrict__ fc, int nu)
 {
-    const int r = blockIdx.x;
-    const int lane = threadIdx.x;
+    const int c = blockIdx.x * BLOCK + threadIdx.x;
+    if (c < nu) fc[c] = (double)f[gather[c]];
+}
+
+// u = A^-1 f on the coarse level: one wave per row (four per block), the row
+// streamed against the gathered right-hand side with two independent sums
+// per lane, the result written to every copy of the node
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_coarse(const double *__restrict__ ainv, int nu,
+                                                  const double *__restrict__ fc,
+                                                  const int32_t *__restrict__ coff,
+                                                  const int64_t *__restrict__ cslot, T *__restrict__ u)
+{
+    const int r = blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (r >= nu) return;  // whole wave
     const double *row = ainv + (int64_t)r * nu;
-    double acc = 0.0;
-    for (int c = lane; c < nu; c += 64) acc += row[c] * (double)f[gather[c]];
+    double a0 = 0.0, a1 = 0.0;
+    int c = lane;
+    for (; c + 64 < nu; c += 128) {
+        a0 += row[c] * fc[c];
+        a1 += row[c + 64] * fc[c + 64];
+    }
+    if (c < nu) a0 += row[c] * fc[c];
+    double acc = a0 + a1;
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
     if (lane == 0)
@@ -2150,9 +2168,11 @@ __global__ __launch_bounds__(64) void k_coarse(const double *__restrict__ ainv, 
 template <typename T>
 hipError_t launch_coarse_solve(const double *ainv, int nu, const int64_t *gather,
                                const int32_t *copy_off, const int64_t *copy_slot, const T *f, T *u,
-                               hipStream_t st)
+                               double *fc, hipStream_t st)
 {
-    if (nu > 0) k_coarse<T><<<nu, 64, 0, st>>>(ainv, nu, gather, copy_off, copy_slot, f, u);
+    if (nu <= 0) return hipSuccess;
+    k_coarse_gather<T><<<blocks_for(nu), BLOCK, 0, st>>>(gather, f, fc, nu);
+    k_coarse<T><<<(nu + BLOCK / 64 - 1) / (BLOCK / 64), BLOCK, 0, st>>>(ainv, nu, fc, copy_off, copy_slot, u);
     return hipGetLastError();
 }
 
@@ -2446,7 +2466,7 @@ hipError_t launch_positive_check(const double *k, int64_t n, int *bad, hipStream
                                               const T *, T *, hipStream_t);                        \
     template hipError_t launch_coarse_solve<T>(const double *, int, const int64_t *,               \
                                                const int32_t *, const int64_t *, const T *, T *,   \
-                                               hipStream_t);                                       \
+                                               double *, hipStream_t);                             \
     template hipError_t launch_fill<T>(T *, T, int64_t, hipStream_t);                              \
     template hipError_t launch_inject<T>(const T *, int, T *, int, int, int64_t, int64_t,          \
                                          hipStream_t);                                             \
