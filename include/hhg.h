@@ -264,19 +264,22 @@ hhg_status hhg_vcycle(hhg_ctx ctx, int32_t level, hhg_dtype dtype, int32_t pre, 
                       void *stream);
 
 typedef struct {
-    int32_t iterations;        /* outer iterations (V-cycles) performed */
+    int32_t iterations;        /* V-cycles performed (at most max_iter) */
     int32_t fallback;          /* learned smoother fell back (1) or not (0) */
     double rel_residual;       /* final |f - A u| / |f| in FP64 */
-    double rho;                /* asymptotic rate (r_last / r_5)^(1/(last-5)), or the mean rate */
+    double rho;                /* rate per V-cycle from the first FP64 residual after five
+                                  cycles to the last, or the mean rate */
     double seconds;            /* wall time of the solve loop */
 } hhg_solve_stats;
 
-/* Solve A u = f at `level` to |f - A u| / |f| <= tol (FP64 residual):
+/* Solve A u = f at `level` to |f - A u| / |f| <= tol (FP64 residual, checked
+ * after every refinement step):
  *   HHG_SOLVE_F64     FP64 V(pre,post) Chebyshev cycles;
- *   HHG_SOLVE_MIXED   FP64 residual, one FP32 V-cycle on the correction,
+ *   HHG_SOLVE_MIXED   FP64 residual, two FP32 V-cycles on the correction,
  *                     FP64 update (iterative refinement);
- *   HHG_SOLVE_LEARNED as MIXED with the learned smoother on the finest level,
- *                     falling back to Chebyshev when the contraction worsens.
+ *   HHG_SOLVE_LEARNED FP64 residual, one FP32 V-cycle with the learned smoother
+ *                     on the finest level, FP64 update; falls back to Chebyshev
+ *                     when the contraction worsens.
  * f, u: FP64 device slot vectors; u holds the start value and the result.
  * Returns HHG_WFALLBACK (> 0) if the learned smoother fell back. */
 hhg_status hhg_solve(hhg_ctx ctx, int32_t level, hhg_solve_mode mode, int32_t pre, int32_t post,

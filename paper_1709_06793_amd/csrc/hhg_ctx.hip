@@ -2779,6 +2779,13 @@ hhg_status solve_impl(hhg_ctx c, int32_t level, hhg_solve_mode mode, int32_t pre
     TRY(residual_t<double>(c, level, f, L.d64, L.r64, &nf, st));
     if (!(nf > 0.0)) nf = 1.0;
     std::vector<double> hist;
+    std::vector<int> cyc;  // V-cycles done before each entry of hist
+    int cycles = 0;
+    // FP32 V-cycles per refinement step: two in the plain mixed mode (the FP64
+    // residual, its conversion and the correction's update then run once per
+    // two cycles); one with the learned smoother, whose fallback judges each
+    // cycle's contraction
+    const int inner = mode == HHG_SOLVE_MIXED ? 2 : 1;
     int fallback = 0;
     bool use_learned = mode == HHG_SOLVE_LEARNED;
     const LearnedState &LS = c->learned;
@@ -2792,6 +2799,7 @@ hhg_status solve_impl(hhg_ctx c, int32_t level, hhg_solve_mode mode, int32_t pre
     for (int it = 0;; ++it) {
         TRY(residual_t<double>(c, level, f, u, L.r64, &nr, st));
         hist.push_back(nr / nf);
+        cyc.push_back(cycles);
         // fallback: a learned cycle must keep the residual finite, contract
         // at least by the accepted rate and, once the plain cycle's
         // contraction is known, by no less than margin x that contraction;
@@ -2813,9 +2821,10 @@ hhg_status solve_impl(hhg_ctx c, int32_t level, hhg_solve_mode mode, int32_t pre
         }
         probe_pending = false;
         if (!std::isfinite(nr)) break;
-        if (hist.back() <= tol || it >= max_iter) break;
+        if (hist.back() <= tol || cycles >= max_iter) break;
         if (mode == HHG_SOLVE_F64) {
             TRY(vcycle_run<double>(c, level, f, u, pre, post, HHG_CHEBYSHEV, st));
+            ++cycles;
         } else {
             HIPCHK(c, launch_convert<double, float>(L.r64, L.f32, L.n_slots, st));
             if (use_learned && probe && it == LEARNED_PROBE_CYCLE) {
@@ -2828,7 +2837,9 @@ hhg_status solve_impl(hhg_ctx c, int32_t level, hhg_solve_mode mode, int32_t pre
             if (use_learned)
                 HIPCHK(c, hipMemcpyAsync(L.ubak, u, L.n_slots * sizeof(double), hipMemcpyDeviceToDevice, st));
             HIPCHK(c, launch_fill<float>(L.u32, 0.0f, L.n_slots, st));
-            TRY(vcycle_run<float>(c, level, L.f32, L.u32, pre, post, use_learned ? HHG_LEARNED : HHG_CHEBYSHEV, st));
+            for (int m = 0; m < inner && cycles < max_iter; ++m, ++cycles)
+                TRY(vcycle_run<float>(c, level, L.f32, L.u32, pre, post, use_learned ? HHG_LEARNED : HHG_CHEBYSHEV,
+                                      st));
             HIPCHK(c, launch_add_f32_to_f64(u, L.u32, L.n_slots, st));
             if (use_learned && probe && it == LEARNED_PROBE_CYCLE) {
                 double np = 0.0;
@@ -2841,14 +2852,17 @@ hhg_status solve_impl(hhg_ctx c, int32_t level, hhg_solve_mode mode, int32_t pre
     HIPCHK(c, hipStreamSynchronize(st));
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (stats) {
+        // rho per V-cycle, from the first residual after five cycles (else
+        // the initial one) to the last
         const int n = (int)hist.size() - 1;
-        stats->iterations = n;
+        int j = 0;
+        while (j < n && cyc[j] < 5) ++j;
+        if (cyc[n] - cyc[j] <= 0) j = 0;
+        stats->iterations = cycles;
         stats->fallback = fallback;
         stats->rel_residual = hist.back();
         stats->seconds = secs;
-        if (n > 5) stats->rho = std::pow(hist[n] / hist[5], 1.0 / (n - 5));
-        else if (n > 0) stats->rho = std::pow(hist[n] / hist[0], 1.0 / n);
-        else stats->rho = 0.0;
+        stats->rho = cyc[n] > cyc[j] ? std::pow(hist[n] / hist[j], 1.0 / (cyc[n] - cyc[j])) : 0.0;
     }
     return fallback ? HHG_WFALLBACK : HHG_OK;
 }
