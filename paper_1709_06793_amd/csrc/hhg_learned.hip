@@ -77,6 +77,10 @@ __device__ __forceinline__ unsigned int pack_bf16(float a, float b)
     return u;
 }
 
+// max(x, 0) as one integer max on the bit pattern: a negative float is a
+// negative integer, so every finite x maps to its ReLU (-0 to +0)
+__device__ __forceinline__ float relu(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
+
 // features of slot s (interior node assumed): 32 values and the scale
 __device__ __forceinline__ void node_features(const LevelView<float> &L, const float *__restrict__ r,
                                               const float *__restrict__ logk, int64_t base, int s,
@@ -240,31 +244,51 @@ __global__ __launch_bounds__(BLOCK) void k_learned_fwd_march(LevelView<float> L,
             for (int w2 = 0; w2 < 8; ++w2)
                 mine[w2] = make_uint2(pack_bf16(x[4 * w2], x[4 * w2 + 1]), pack_bf16(x[4 * w2 + 2], x[4 * w2 + 3]));
             __builtin_amdgcn_wave_barrier();
+            // the four groups of 16 nodes interleaved (operand reads, then
+            // each layer's products for all groups, then the reductions), so
+            // that no product or cross-lane exchange waits for its own
+            // predecessor alone; the biases start the accumulators (one FP32
+            // sum of the products and the bias, as the reference's single
+            // rounding bounds it)
+            bf16x4 xlo[4], xhi[4];
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
-                const int node = wave * 64 + g * 16 + row;
-                const uint2 *src = reinterpret_cast<const uint2 *>(xs + node * XW);
+                const uint2 *src = reinterpret_cast<const uint2 *>(xs + (wave * 64 + g * 16 + row) * XW);
                 const uint2 lo = src[lane >> 4], hi = src[4 + (lane >> 4)];
-                bf16x4 xlo, xhi;
-                __builtin_memcpy(&xlo, &lo, 8);
-                __builtin_memcpy(&xhi, &hi, 8);
-                // the biases start the accumulators (one FP32 sum of the
-                // products and the bias, as the reference's single rounding
-                // bounds it)
-                f32x4 acc = {b1v[0], b1v[1], b1v[2], b1v[3]};
-                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1lo, xlo, acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1hi, xhi, acc, 0, 0, 0);
-                const uint2 hp = make_uint2(pack_bf16(fmaxf(acc[0], 0.0f), fmaxf(acc[1], 0.0f)),
-                                            pack_bf16(fmaxf(acc[2], 0.0f), fmaxf(acc[3], 0.0f)));
+                __builtin_memcpy(&xlo[g], &lo, 8);
+                __builtin_memcpy(&xhi[g], &hi, 8);
+            }
+            f32x4 acc[4];
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                acc[g] = f32x4{b1v[0], b1v[1], b1v[2], b1v[3]};
+                acc[g] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1lo, xlo[g], acc[g], 0, 0, 0);
+            }
+#pragma unroll
+            for (int g = 0; g < 4; ++g) acc[g] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1hi, xhi[g], acc[g], 0, 0, 0);
+            f32x4 acc2[4];
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const uint2 hp = make_uint2(pack_bf16(relu(acc[g][0]), relu(acc[g][1])),
+                                            pack_bf16(relu(acc[g][2]), relu(acc[g][3])));
                 bf16x4 h1;
                 __builtin_memcpy(&h1, &hp, 8);
-                f32x4 acc2 = {b2v[0], b2v[1], b2v[2], b2v[3]};
-                acc2 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2, h1, acc2, 0, 0, 0);
-                float part = 0.0f;
-                for (int q2 = 0; q2 < 4; ++q2) part += w3v[q2] * fmaxf(acc2[q2], 0.0f);
-                part += __shfl_xor(part, 16, 64);
-                part += __shfl_xor(part, 32, 64);
-                if (lane < 16) cs[wave * 64 + g * 16 + lane] = part + b3;
+                acc2[g] = f32x4{b2v[0], b2v[1], b2v[2], b2v[3]};
+                acc2[g] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2, h1, acc2[g], 0, 0, 0);
+            }
+            float part[4];
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                part[g] = 0.0f;
+                for (int q2 = 0; q2 < 4; ++q2) part[g] += w3v[q2] * relu(acc2[g][q2]);
+            }
+#pragma unroll
+            for (int g = 0; g < 4; ++g) part[g] += __shfl_xor(part[g], 16, 64);
+#pragma unroll
+            for (int g = 0; g < 4; ++g) part[g] += __shfl_xor(part[g], 32, 64);
+            if (lane < 16) {
+#pragma unroll
+                for (int g = 0; g < 4; ++g) cs[wave * 64 + g * 16 + lane] = part[g] + b3;
             }
             __builtin_amdgcn_wave_barrier();
             const float c = cs[threadIdx.x];
