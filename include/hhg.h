@@ -281,6 +281,7 @@ typedef struct {
  *                     on the finest level, FP64 update; falls back to Chebyshev
  *                     when the contraction worsens.
  * f, u: FP64 device slot vectors; u holds the start value and the result.
+ * A residual that is not finite ends the solve (stats->rel_residual holds it).
  * Returns HHG_WFALLBACK (> 0) if the learned smoother fell back. */
 hhg_status hhg_solve(hhg_ctx ctx, int32_t level, hhg_solve_mode mode, int32_t pre, int32_t post,
                      double tol, int32_t max_iter, const double *f, double *u,

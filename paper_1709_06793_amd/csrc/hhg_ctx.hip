@@ -1563,7 +1563,9 @@ hhg_status residual_t(hhg_ctx c, int l, const T *f, const T *u, T *r, double *no
         HIPCHK(c, launch_reduce(partial, np, 0, dscalar, st));
         HIPCHK(c, hipMemcpyAsync(c->hscalar, dscalar, sizeof(double), hipMemcpyDeviceToHost, st));
         HIPCHK(c, hipStreamSynchronize(st));
-        *norm = std::sqrt(std::max(0.0, c->hscalar[0]));
+        // a NaN sum stays NaN (std::max would turn it into 0, a converged solve)
+        const double v = c->hscalar[0];
+        *norm = std::isnan(v) ? v : std::sqrt(std::max(0.0, v));
     }
     return HHG_OK;
 }

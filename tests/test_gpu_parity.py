@@ -653,6 +653,21 @@ def test_solve_reaches_tolerance_and_oracle_solution(mode):
     assert _rel(got, ref) <= 1e-8, _rel(got, ref)
 
 
+def test_solve_stops_on_a_non_finite_residual():
+    """A NaN in the right-hand side gives a NaN residual norm, which ends the
+    solve and is reported as such (not as a zero residual)."""
+    om, k, u, ctx = _setup(kuhn_cube, 4)
+    f = uniform_vector(om.n_nodes, seed=2)
+    f[om.dirichlet] = 0.0
+    f[om.unknowns[len(om.unknowns) // 2]] = np.nan
+    fd = ctx.from_canonical(4, _dev(f))
+    r = ctx.vector(4)
+    assert np.isnan(ctx.residual(4, fd, ctx.vector(4), r, norm=True))
+    for mode in (hhg.SOLVE_F64, hhg.SOLVE_MIXED):
+        st = ctx.solve(4, fd, ctx.vector(4), mode=mode, tol=1e-8, max_iter=20)
+        assert np.isnan(st["rel_residual"]) and st["iterations"] == 0, st
+
+
 def test_c2_full_size_sampled_rows():
     """Unit tet level 8 (2.86M nodes), lognormal k (sigma 1, l_c 0.1, seed 1),
     u from the same stream: 400 sampled rows of the scaled and nodal applies
