@@ -31,7 +31,13 @@ def flat_tet():
 
 def _kuhn_tets(vid):
     """Six Kuhn tetrahedra of a cube whose corner (a,b,c) in {0,1}^3 has id
-    vid(a,b,c); each is ordered along its monotone path 0 -> e_p -> e_p+e_q -> 1."""
+    vid(a,b,c), one per monotone path p0 = 0 -> p1 = e_p -> p2 = e_p+e_q ->
+    p3 = 1, with vertices in the order (p2, p3, p0, p1).  That order refines
+    exactly as the path order does (the octahedra are cut between the
+    midpoints of p0p2 and p1p3 either way, so the refined cube is the
+    Freudenthal lattice), and the two faces through the cube's diagonal p0p3,
+    shared with the neighbouring tets, lie opposite the first and the last
+    vertex."""
     tets = []
     for perm in itertools.permutations(range(3)):
         p = [0, 0, 0]
@@ -39,7 +45,7 @@ def _kuhn_tets(vid):
         for ax in perm:
             p[ax] = 1
             path.append(vid(*p))
-        tets.append(path)
+        tets.append([path[2], path[3], path[0], path[1]])
     return tets
 
 

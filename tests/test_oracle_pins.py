@@ -552,3 +552,25 @@ def test_geometric_coarse_coefficients():
         logs = [np.log(kf[c2f[c]])] + [0.5 * np.log(kf[f]) for f in mids]
         want = np.exp(np.sum(logs) / (1 + 0.5 * len(mids)))
         assert kc[c] == pytest.approx(want, rel=1e-13)
+
+
+def test_kuhn_vertex_order_refines_as_the_path_order():
+    """The Kuhn tets are listed in the vertex order (p2, p3, p0, p1) of their
+    monotone path p0 -> p3; Bey's refinement in that order cuts every
+    octahedron between the same midpoints as in path order, so the refined
+    meshes coincide (the same set of elements, as coordinate sets, at levels
+    1-3) and the faces through the cube diagonal lie opposite the first and
+    last vertex."""
+    for fn in (kuhn_cube, kuhn_cube_2x2x2):
+        X, T = fn()
+        path = T[:, [2, 3, 0, 1]]
+        d = X[path[:, 1:]] - X[path[:, :-1]]
+        assert np.allclose(np.abs(d).sum(axis=2), 1.0 / (2 if fn is kuhn_cube_2x2x2 else 1))
+        for L in (1, 2, 3):
+            sets = []
+            for TT in (T, path):
+                m = O.Mesh(X, TT, L)
+                conn, _ = m.elements()
+                P = np.rint(m.xyz[conn] * 2 ** (L + 1)).astype(np.int64)
+                sets.append({tuple(sorted(map(tuple, e))) for e in P})
+            assert sets[0] == sets[1], (fn.__name__, L)
