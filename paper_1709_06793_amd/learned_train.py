@@ -123,17 +123,17 @@ def mean_loss(data, level, w):
     return tot / n
 
 
-def evaluate(ctx, f, level, w, torch, tol=1e-8, max_iter=200):
+def evaluate(ctx, f, level, w, torch, tol=1e-8, max_iter=200, margin=1.05):
     """FP32-in-FP64 solves with the learned smoother, with the network off
-    (damped Jacobi steps) and with plain Chebyshev; returns the stats dicts."""
+    (damped Jacobi steps) and with plain Chebyshev; returns the stats dicts.
+    The learned solve runs with the library's fallback (a cycle that does not
+    reduce the residual switches the solve to Chebyshev, and with margin > 0
+    so does one that contracts worse than margin x the plain cycle measured
+    from the same iterate); the network-off reference never falls back."""
     res = {}
     u = ctx.vector(level)
     res["chebyshev"] = ctx.solve(level, f, u, mode=hhg.SOLVE_MIXED, tol=tol, max_iter=max_iter)
-    # the learned solve runs with the library's default fallback (a cycle that
-    # does not reduce the residual, or contracts worse than 1.05 x the plain
-    # cycle measured from the same iterate, switches the solve to Chebyshev);
-    # the network-off reference never falls back
-    for name, wv, rate, margin in (("learned", w, 1.0, 1.05), ("network_off", np.zeros_like(w), 1e30, 0.0)):
+    for name, wv, rate, margin in (("learned", w, 1.0, margin), ("network_off", np.zeros_like(w), 1e30, 0.0)):
         ctx.learned_set_weights(wv)
         ctx.learned_set_fallback(rate, margin)
         u = ctx.vector(level)

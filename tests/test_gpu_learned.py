@@ -269,14 +269,18 @@ def test_fallback_fires_when_learned_cycles_contract_worse_than_plain():
 
 def test_learned_smoother_gains_over_network_off():
     """Trained on fields at level 5, evaluated on held-out fields at level 6:
-    fewer V-cycles to 1e-8 than the same smoother with the network switched off."""
+    fewer V-cycles to 1e-8 than the same smoother with the network switched
+    off.  Both solves keep the divergence-only fallback, so that the count
+    compares the network itself (with the plain-cycle probe a solve may switch
+    to Chebyshev, which on field 1001 takes more cycles than damped Jacobi;
+    the probe has its own test)."""
     data = LT.generate_samples(5, list(range(100, 108)), kuhn_cube, torch, cycles=4)
     w, hist = LT.train(data, 5, epochs=8, lr=3e-3)
     print("train history", hist, flush=True)
     gains = []
     for seed in (1000, 1001):
         ctx, f, _ = LT.make_field_context(6, seed, kuhn_cube, torch)
-        res = LT.evaluate(ctx, f, 6, w, torch)
+        res = LT.evaluate(ctx, f, 6, w, torch, margin=0.0)
         print(seed, res, flush=True)
         assert res["learned"]["rel_residual"] <= 1e-8
         gains.append(res["network_off"]["iterations"] - res["learned"]["iterations"])
