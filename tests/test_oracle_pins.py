@@ -574,3 +574,35 @@ def test_kuhn_vertex_order_refines_as_the_path_order():
                 P = np.rint(m.xyz[conn] * 2 ** (L + 1)).astype(np.int64)
                 sets.append({tuple(sorted(map(tuple, e))) for e in P})
             assert sets[0] == sets[1], (fn.__name__, L)
+
+
+def test_cube12_orientation_keeps_the_refinement():
+    """cube12 lists its tets in the orders chosen by
+    orient_for_contiguous_faces; each keeps the tet's vertex pairs {v0, v2},
+    {v1, v3} at positions {0, 2} and {1, 3}, so the refined mesh equals that
+    of the positively oriented listing (identical element sets at levels
+    1-3), and 11 of the 18 shared faces lie opposite positions 0 or 3 in both
+    tets (6 before)."""
+    from hhg_inputs.meshes import cube12_oriented_positive
+    X, T = cube12()
+    X0, P = cube12_oriented_positive()
+    assert np.array_equal(X, X0)
+    for a, b in zip(T, P):
+        pairs = lambda t: {frozenset((int(t[0]), int(t[2]))), frozenset((int(t[1]), int(t[3])))}
+        assert pairs(a) == pairs(b)
+    for L in (1, 2, 3):
+        sets = []
+        for TT in (T, P):
+            m = O.Mesh(X, TT, L)
+            conn, _ = m.elements()
+            Q = np.rint(m.xyz[conn] * 2 ** (L + 1)).astype(np.int64)
+            sets.append({tuple(sorted(map(tuple, e))) for e in Q})
+        assert sets[0] == sets[1], L
+
+    def contiguous_shared(TT):
+        faces = {}
+        for t in range(len(TT)):
+            for q in range(4):
+                faces.setdefault(tuple(sorted(np.delete(TT[t], q))), []).append(q)
+        return sum(1 for v in faces.values() if len(v) == 2 and all(q in (0, 3) for q in v))
+    assert contiguous_shared(T) == 11 and contiguous_shared(P) == 6
