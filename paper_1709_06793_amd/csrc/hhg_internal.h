@@ -110,6 +110,10 @@ enum ApplyMode { MODE_APPLY = 0, MODE_RESID = 1, MODE_CHEB = 2 };
 // d <- c_old d + c_r D^{-1} r (d taken as 0 when `first`) and u_new = u + d
 template <typename T>
 struct ChebArgs {
+    // direction of the fused sweep: read only at a row's own slot (interior
+    // rows) or at the first copy of a shared node (the inter-tet and
+    // modification rows both take sh_off order), so a shared node's other
+    // copies of d are not kept up to date
     T *d = nullptr;
     const T *invd = nullptr;
     T c_old = T(0), c_r = T(0);

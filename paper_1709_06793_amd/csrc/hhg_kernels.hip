@@ -1030,10 +1030,8 @@ __global__ __launch_bounds__(BLOCK) void k_shared_rows(LevelView<T> L, const IX 
         if (MODE == MODE_CHEB) {
             const T r = f[self] - acc;
             const T dn = (cb.first ? T(0) : cb.c_old * cb.d[self]) + cb.c_r * cb.invd[self] * r;
-            for (int c = L.sh_off[q]; c < L.sh_off[q + 1]; ++c) {
-                cb.d[(int64_t)cslots[c]] = dn;
-                y[(int64_t)cslots[c]] = u0 + dn;
-            }
+            cb.d[self] = dn;  // d is read at the first copy only
+            for (int c = L.sh_off[q]; c < L.sh_off[q + 1]; ++c) y[(int64_t)cslots[c]] = u0 + dn;
         } else {
             for (int c = L.sh_off[q]; c < L.sh_off[q + 1]; ++c) y[(int64_t)cslots[c]] = out;
         }
@@ -1209,10 +1207,8 @@ __global__ __launch_bounds__(BLOCK) void k_correction(CorrView<T> C, const T *__
         if (MODE == MODE_CHEB) {
             const T delta = cb.c_r * cb.invd[p0] * acc;
             const T dn = cb.d[p0] - delta, un = y[p0] - delta;
-            for (int p = C.p_off[q]; p < C.p_off[q + 1]; ++p) {
-                cb.d[C.p_slot[p]] = dn;
-                y[C.p_slot[p]] = un;
-            }
+            cb.d[p0] = dn;  // d is read at the first copy only
+            for (int p = C.p_off[q]; p < C.p_off[q + 1]; ++p) y[C.p_slot[p]] = un;
         } else {
             const T old = y[p0];
             const T nw = MODE == MODE_APPLY ? old + acc : old - acc;
