@@ -681,9 +681,10 @@ def main():
     log(f"bench: unknowns {nu}, timing {args.steps} applies")
     ms = time_op(lambda: ctx.apply_scaled(level, u64, y64), args.steps, args.warmup, torch)
     value = nu / (ms * 1e-3) / 1e9
-    # the interior kernel, timed by HIP events the library records around it
-    # on the stream it runs on (the unit tet has no inter-tet rows and no
-    # modified edges, so each apply is this one kernel): (a) back to back, as
+    # the interior kernel, timed by a pair of HIP events that its launch
+    # stamps on the stream it runs on (hipExtLaunchKernel: dispatch to
+    # completion, no separate event commands; the unit tet has no inter-tet
+    # rows and no modified edges, so each apply is this one kernel): (a) back to back, as
     # the timed steps run, with the 69 MB working set resident in the 256 MB
     # last-level cache; (b) with a 1 GiB read between launches, so that the
     # kernel reads u and k from HBM: the roofline figure.  The flush is a read
@@ -744,8 +745,9 @@ def main():
                                         "calibration; null when taken on other kernel sources",
                      "kernel": "k_march2<double, MODE_APPLY, scaled> (interior rows, two per lane; the unit "
                                "tet has no inter-tet rows)",
-                     "timing": "mean duration per launch from HIP events around each launch, a 1 GiB read "
-                               "between launches (inputs read from HBM)",
+                     "timing": "mean duration per launch from the HIP event pair each launch stamps on its "
+                               "stream (hipExtLaunchKernel), a 1 GiB read between launches (inputs read from "
+                               "HBM); the copies are timed with events recorded around them",
                      "kernel_ms": round(k_ms, 5),
                      "kernel_ms_back_to_back": round(k_ms_warm, 5),
                      "frac_back_to_back": round(BYTES_PER_DOF["f64"] * nu / (k_ms_warm * 1e-3) / 1e9 / HBM_PEAK_GBS,

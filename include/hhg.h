@@ -153,13 +153,16 @@ hhg_status hhg_level_info(hhg_ctx ctx, int32_t level, double *lambda_max,
 hhg_status hhg_apply_scaled(hhg_ctx ctx, int32_t level, hhg_dtype dtype,
                             const void *u, void *y, void *stream);
 /* Instrumentation (not part of the method): while enabled, every
- * hhg_apply_scaled records a HIP event on its stream right before its stencil
- * kernels and one right after them (the Sec. 4.1 correction kernel, if any,
- * is outside the pair).  hhg_read_timing synchronises on the recorded events
- * and returns the summed start-to-end times in ms (the stencil kernels'
- * durations, whatever else the stream runs between applies) and the number of
- * timed applies, and clears the record.  Enabling or disabling also clears
- * it. */
+ * hhg_apply_scaled times its stencil kernels with a pair of HIP events that
+ * the launches themselves stamp (hipExtLaunchKernel on its stream: the start
+ * at the first kernel's dispatch, the stop at the last kernel's completion;
+ * the Sec. 4.1 correction kernel, if any, is outside the pair; a level without
+ * stencil kernels gives an empty window).  hhg_read_timing synchronises on the
+ * recorded events and returns the summed start-to-end times in ms (the stencil
+ * kernels' durations, whatever else the stream runs between applies) and the
+ * number of timed applies, and clears the record.  Enabling or disabling also
+ * clears it.  Not for applies issued concurrently from several host threads
+ * on one context. */
 /* enable != 0: V-cycles inside hhg_solve, hhg_solve_form and
  * hhg_solve_tensor run as captured HIP graphs on a stream of the context
  * (each distinct level, cycle shape, operator, precision and vector pair is

@@ -1514,17 +1514,25 @@ hhg_status apply_scaled_t(hhg_ctx c, int l, const T *u, T *y, hipStream_t st)
 {
     LevelView<T> V = view<T>(c, l);
     if (c->timing) {
-        // an event pair around this apply's stencil kernels (events pooled;
-        // the pool grows on the first timed applies)
+        // an event pair spanning this apply's stencil kernels, stamped by the
+        // launches themselves (events pooled; the pool grows on the first
+        // timed applies).  A level without stencil kernels records an empty
+        // window.
         const size_t q = 2 * c->tev_used;
         while (c->tev.size() < q + 2) {
             hipEvent_t e;
             HIPCHK(c, hipEventCreate(&e));
             c->tev.push_back(e);
         }
-        HIPCHK(c, hipEventRecord(c->tev[q], st));
-        HIPCHK(c, launch_scaled<T>(V, MODE_APPLY, u, nullptr, y, nullptr, nullptr, st));
-        HIPCHK(c, hipEventRecord(c->tev[q + 1], st));
+        set_launch_events(c->tev[q], c->tev[q + 1]);
+        const hipError_t e = launch_scaled<T>(V, MODE_APPLY, u, nullptr, y, nullptr, nullptr, st);
+        const bool none = launch_events_unused();
+        set_launch_events(nullptr, nullptr);
+        HIPCHK(c, e);
+        if (none) {
+            HIPCHK(c, hipEventRecord(c->tev[q], st));
+            HIPCHK(c, hipEventRecord(c->tev[q + 1], st));
+        }
         ++c->tev_used;
     } else {
         HIPCHK(c, launch_scaled<T>(V, MODE_APPLY, u, nullptr, y, nullptr, nullptr, st));

@@ -212,6 +212,12 @@ hipError_t launch_convert(const Ti *in, To *out, int64_t n, hipStream_t st);
 int set_march_variant(int v);
 // the interior kernels' variant in force (0 = per precision and size)
 int march_variant_now();
+// timed applies: the stencil launches of the calling thread take these
+// events (start at the first kernel's dispatch, stop at the last kernel's
+// completion) until they are cleared with nullptrs; true while the start
+// event has not been taken by a launch
+void set_launch_events(hipEvent_t start, hipEvent_t stop);
+bool launch_events_unused();
 // merged coefficients of the shared rows for the current k (scaled and nodal)
 hipError_t launch_shared_coef(const LevelView<double> &L, const int8_t *map, double *cs, double *cn,
                               hipStream_t st);

@@ -15,6 +15,7 @@
 // Dirichlet slots.  Marching grids are remapped so that each of the 8 XCDs
 // walks one contiguous eighth of the work items (neighbouring diagonals of
 // the same planes then meet in that XCD's L2).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdlib>
@@ -893,6 +894,30 @@ int set_march_variant(int v)
     return 0;
 }
 
+// Timed applies (instrumentation of hhg_apply_scaled): while events are set,
+// the launches of launch_march_std and launch_shared_rows go through
+// hipExtLaunchKernel, which takes the start time from the first kernel's own
+// dispatch and the stop time from the completion of each kernel it is given
+// (the last one's counts), so the pair spans the apply's kernels and no
+// separate event command.
+struct LaunchEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+static thread_local LaunchEvents t_launch_ev;
+void set_launch_events(hipEvent_t start, hipEvent_t stop) { t_launch_ev = LaunchEvents{start, stop}; }
+bool launch_events_unused() { return t_launch_ev.start != nullptr; }
+
+template <typename... P, typename... A>
+static void launch_k(void (*kernel)(P...), dim3 grid, dim3 block, hipStream_t st, const A &...args)
+{
+    if (t_launch_ev.stop) {
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, st, t_launch_ev.start, t_launch_ev.stop, 0, args...);
+        t_launch_ev.start = nullptr;
+    } else {
+        hipLaunchKernelGGL(kernel, grid, block, 0, st, args...);
+    }
+}
+
 // scaled rows: variants 6, 8, 9 run two rows per lane, 1-5 and 7 one per
 // lane; the default (0) runs FP64 two per lane and FP32 one per lane with
 // shifts recomputed at each use (variant 1), the fastest of each measured
@@ -961,7 +986,7 @@ static void launch_march_std(const LevelView<T> &L, const T *u, const T *f, T *y
 {
     if constexpr (OP == 0 && (MODE == MODE_APPLY || (MODE == MODE_RESID && sizeof(T) == 4))) {
         if (use_lds<T, MODE>(L)) {
-            k_march_lds<T, MODE><<<lds_grid(L), 64 * LW, 0, st>>>(L, u, f, y, partial, cb);
+            launch_k(k_march_lds<T, MODE>, lds_grid(L), 64 * LW, st, L, u, f, y, partial, cb);
             return;
         }
     }
@@ -969,13 +994,13 @@ static void launch_march_std(const LevelView<T> &L, const T *u, const T *f, T *y
         const int v = march_variant();
         if (two_rows<T>(v)) {
             const int g2 = march_grid(L.n_tet, L.vpt2, L.bpt2);
-            if (v == 6) k_march2<T, MODE, OP, 0, 3><<<g2, BLOCK, 0, st>>>(L, u, f, y, partial, cb);
-            else if (v == 8) k_march2<T, MODE, OP, 2, 2><<<g2, BLOCK, 0, st>>>(L, u, f, y, partial, cb);
+            if (v == 6) launch_k(k_march2<T, MODE, OP, 0, 3>, g2, BLOCK, st, L, u, f, y, partial, cb);
+            else if (v == 8) launch_k(k_march2<T, MODE, OP, 2, 2>, g2, BLOCK, st, L, u, f, y, partial, cb);
             else if (v == 9) {
                 const int g1 = ((L.n_tet * march2_blocks_per_tet<1>(L.n_items2, L.n_bnd) + 7) / 8) * 8;
-                k_march2<T, MODE, OP, 1, 2, 1><<<g1, 64, 0, st>>>(L, u, f, y, partial, cb);
+                launch_k(k_march2<T, MODE, OP, 1, 2, 1>, g1, 64, st, L, u, f, y, partial, cb);
             }
-            else k_march2<T, MODE, OP, 1, 2><<<g2, BLOCK, 0, st>>>(L, u, f, y, partial, cb);
+            else launch_k(k_march2<T, MODE, OP, 1, 2>, g2, BLOCK, st, L, u, f, y, partial, cb);
             return;
         }
     }
@@ -988,12 +1013,12 @@ static void launch_march_std(const LevelView<T> &L, const T *u, const T *f, T *y
     int v = march_variant();
     if (v == 0 && OP == 0 && sizeof(T) == 4) v = 1;
     switch (v) {
-    case 1: k_march<T, MODE, OP, 1, big ? 3 : (f64 ? 5 : 8), 1><<<g, BLOCK, 0, st>>>(L, u, f, y, partial, cb); break;
-    case 2: k_march<T, MODE, OP, 2, W4, 0><<<g, BLOCK, 0, st>>>(L, u, f, y, partial, cb); break;
-    case 3: k_march<T, MODE, OP, 2, big ? 3 : (f64 ? 4 : 6), 1><<<g, BLOCK, 0, st>>>(L, u, f, y, partial, cb); break;
-    case 4: k_march<T, MODE, OP, 0, 8, 1><<<g, BLOCK, 0, st>>>(L, u, f, y, partial, cb); break;
-    case 5: k_march<T, MODE, OP, 0, big ? 5 : 6, 0><<<g, BLOCK, 0, st>>>(L, u, f, y, partial, cb); break;
-    default: k_march<T, MODE, OP, 1, W4, 0><<<g, BLOCK, 0, st>>>(L, u, f, y, partial, cb); break;
+    case 1: launch_k(k_march<T, MODE, OP, 1, big ? 3 : (f64 ? 5 : 8), 1>, g, BLOCK, st, L, u, f, y, partial, cb); break;
+    case 2: launch_k(k_march<T, MODE, OP, 2, W4, 0>, g, BLOCK, st, L, u, f, y, partial, cb); break;
+    case 3: launch_k(k_march<T, MODE, OP, 2, big ? 3 : (f64 ? 4 : 6), 1>, g, BLOCK, st, L, u, f, y, partial, cb); break;
+    case 4: launch_k(k_march<T, MODE, OP, 0, 8, 1>, g, BLOCK, st, L, u, f, y, partial, cb); break;
+    case 5: launch_k(k_march<T, MODE, OP, 0, big ? 5 : 6, 0>, g, BLOCK, st, L, u, f, y, partial, cb); break;
+    default: launch_k(k_march<T, MODE, OP, 1, W4, 0>, g, BLOCK, st, L, u, f, y, partial, cb); break;
     }
 }
 
@@ -1052,11 +1077,11 @@ static void launch_shared_rows(const LevelView<T> &L, const T *coef, const T *u,
     const int gs = blocks_for(L.n_shared);
     if (!gs) return;
     if (L.sh_nb32)
-        k_shared_rows<T, MODE, uint32_t><<<gs, BLOCK, 0, st>>>(L, L.sh_nb32, L.sh_self32, L.sh_cslot32, coef, u, f,
-                                                               y, partial, cb, coefn, nodal_mask);
+        launch_k(k_shared_rows<T, MODE, uint32_t>, gs, BLOCK, st, L, L.sh_nb32, L.sh_self32, L.sh_cslot32, coef, u,
+                 f, y, partial, cb, coefn, nodal_mask);
     else
-        k_shared_rows<T, MODE, int64_t><<<gs, BLOCK, 0, st>>>(L, L.sh_nb, L.sh_self, L.sh_cslot, coef, u, f, y,
-                                                              partial, cb, coefn, nodal_mask);
+        launch_k(k_shared_rows<T, MODE, int64_t>, gs, BLOCK, st, L, L.sh_nb, L.sh_self, L.sh_cslot, coef, u, f, y,
+                 partial, cb, coefn, nodal_mask);
 }
 
 // the scaled operator's shared rows on its own (narrower) pattern
