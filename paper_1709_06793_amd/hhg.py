@@ -154,7 +154,13 @@ def check_vectors(sizes, level, vecs, n="n_slots", dtype=None, require_cuda=True
 
 
 def _stream():
+    """Handle of torch's current stream on the current device (the raw
+    accessors avoid building a Stream object on every call)."""
     import torch
+    raw = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+    dev = getattr(torch._C, "_cuda_getDevice", None)
+    if raw is not None and dev is not None:
+        return ctypes.c_void_p(raw(dev()))
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
@@ -190,16 +196,19 @@ class Context:
         return s
 
     # ---- sizes and layout
-    def sizes(self, level):
+    def _size_table(self, level):
         cache = self.__dict__.setdefault("_sizes", {})
         if level not in cache:
             a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
             self._check(load().hhg_vector_size(self._h, level, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
             cache[level] = dict(n_slots=a.value, n_unknowns=b.value, n_nodes=c.value)
-        return dict(cache[level])
+        return cache[level]
+
+    def sizes(self, level):
+        return dict(self._size_table(level))
 
     def _vecs(self, level, *vecs, n="n_slots", dtype=None):
-        return check_vectors(self.sizes(level), level, vecs, n=n, dtype=dtype)
+        return check_vectors(self._size_table(level), level, vecs, n=n, dtype=dtype)
 
     def _f32(self):
         import torch

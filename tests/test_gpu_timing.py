@@ -56,3 +56,27 @@ def test_timed_applies_lie_inside_the_calls_and_change_nothing(mesh_fn, level, d
         assert np.isfinite(t_in) and t_in > 0.0
         assert t_in <= t_out + 2e-3, (t_in, t_out)  # 2 us for the two clocks' rounding
     assert torch.equal(y0, y1)
+
+
+def test_calls_go_to_torchs_current_stream():
+    """The binding passes the handle of torch's current stream (default
+    priority side stream here): an apply issued inside `torch.cuda.stream`
+    runs there and gives the default stream's result."""
+    X, T = kuhn_cube()
+    level = 4
+    ctx = hhg.Context(X, T, level)
+    xyz, dirichlet = ctx.node_coords(level)
+    ctx.set_coefficient(smooth_k(xyz))
+    u = uniform_vector(len(xyz), seed=4)
+    u[dirichlet] = 0.0
+    uv = ctx.from_canonical(level, torch.tensor(u, device="cuda"))
+    y0, y1 = ctx.vector(level), ctx.vector(level)
+    assert (hhg._stream().value or 0) == torch.cuda.current_stream().cuda_stream
+    ctx.apply_scaled(level, uv, y0)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        assert (hhg._stream().value or 0) == s.cuda_stream != torch.cuda.default_stream().cuda_stream
+        ctx.apply_scaled(level, uv, y1)
+    s.synchronize()
+    assert torch.equal(y0, y1)
