@@ -41,8 +41,6 @@ hipError_t launch_learned_backward(const LevelView<float> &L, const LearnedState
 // the learned smoothing step in one pass: u += D^{-1}(omega r + s c(r, k))
 hipError_t launch_learned_step(const LevelView<float> &L, const LearnedState &S, const float *r, const float *logk,
                                float *u, const float *invd, float omega, hipStream_t st);
-hipError_t launch_learned_update(float *u, const float *r, const float *sc, const float *invd,
-                                 float omega, int64_t n, hipStream_t st);
 hipError_t launch_learned_err(const float *e, const float *r, const float *sc, const float *invd,
                               float omega, float *e1, int64_t n, hipStream_t st);
 hipError_t launch_learned_lossgrad(const float *ae1, const float *s, const float *invd,

@@ -441,23 +441,6 @@ hipError_t launch_learned_backward(const LevelView<float> &L, const LearnedState
     return hipGetLastError();
 }
 
-// ---------------------------------------------------------------- smoothing update
-// u += D^{-1} (omega r + s c): damped Jacobi plus the learned correction
-// (sc = s c is 0 where the network is not applied)
-__global__ void k_learned_update(float *__restrict__ u, const float *__restrict__ r,
-                                 const float *__restrict__ sc, const float *__restrict__ invd,
-                                 float omega, int64_t n)
-{
-    const int64_t q = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (q < n) u[q] += invd[q] * (omega * r[q] + sc[q]);
-}
-hipError_t launch_learned_update(float *u, const float *r, const float *sc, const float *invd,
-                                 float omega, int64_t n, hipStream_t st)
-{
-    k_learned_update<<<(int)((n + BLOCK - 1) / BLOCK), BLOCK, 0, st>>>(u, r, sc, invd, omega, n);
-    return hipGetLastError();
-}
-
 // training: e1 = e - D^{-1}(omega r + s c)
 __global__ void k_learned_err(const float *__restrict__ e, const float *__restrict__ r,
                               const float *__restrict__ sc, const float *__restrict__ invd,
