@@ -5,7 +5,8 @@ import numpy as np
 import pytest
 
 from hhg_inputs import (lognormal_params, lognormal_k, lognormal_k_torch, tensor_K, tensor_fields,
-                        tensor_fields_torch, polynomial_tensor_K, polynomial_tensor_fields_torch, TENSOR_DIRS)
+                        tensor_fields_torch, polynomial_tensor_K, polynomial_tensor_fields_torch, TENSOR_DIRS,
+                        kuhn_cube, kuhn_cube_2x2x2, cube12)
 
 torch = pytest.importorskip("torch")
 
@@ -55,3 +56,29 @@ def test_2d_macro_meshes_are_conforming_and_counter_clockwise():
         assert max(count.values()) <= 2, name
         # the boundary edges close into the outline of the domain (Euler: V - E + F = 1)
         assert X.shape[0] - len(count) + T.shape[0] == 1, name
+
+
+def _faces_contiguous_in_both(T):
+    """Shared macro faces and how many of them lie on contiguous slot runs in
+    both their tets.  In the slot layout (planes k, anti-diagonals s = i + j,
+    index i; i, j, k the weights of the tet's vertices 1..3) the runs are the
+    plane k = 0 (the face opposite the last vertex) and the last anti-diagonal
+    of every plane, where vertex 0's weight is 0 (the face opposite the first
+    vertex)."""
+    faces = {}
+    for tet in np.asarray(T):
+        for q in range(4):
+            faces.setdefault(tuple(sorted(np.delete(tet, q))), []).append(q)
+    shared = [qs for qs in faces.values() if len(qs) == 2]
+    return sum(all(q in (0, 3) for q in qs) for qs in shared), len(shared)
+
+
+@pytest.mark.parametrize("mesh_fn,want", [(kuhn_cube, (6, 6)), (kuhn_cube_2x2x2, (48, 72)), (cube12, (11, 18))])
+def test_shared_faces_on_contiguous_slot_runs(mesh_fn, want):
+    """The listed vertex orders put the counted shared faces on contiguous runs
+    in both tets; a tet has two such faces, so no listing gets more than one
+    per tet (the 6- and 48-tet cubes reach that bound)."""
+    X, T = mesh_fn()
+    got = _faces_contiguous_in_both(T)
+    assert got == want
+    assert got[0] <= len(T)
